@@ -1,0 +1,587 @@
+/*
+ * FP64 CPU oracle of the hybrid time-domain LISA response (arXiv:2505.09600).
+ *
+ * TEST INFRASTRUCTURE ONLY (see tdi_oracle.h).  Written from the paper's
+ * definitions, in their order and notation, for a reader to check by eye:
+ *   - source triad and polarisation rotation          Sec. II.A, Eqs. (hplus_ssb, hcross_ssb)
+ *   - antenna patterns and link projection            Sec. II.A, Eqs. (H, xi_plus, xi_cross)
+ *   - single-link response and propagation delays     Sec. II.B, Eqs. (yslr, delta_s, delta_r)
+ *   - Michelson X 1.5 / 2.0, delays evaluated at t    Sec. II.B, Eqs. (X1.5, X2.0)
+ *   - low-frequency response (central differences)    Sec. III, Eqs. (yslr_strain_derivatives,
+ *                                                     X15_with_strain_derivatives,
+ *                                                     X20_with_strain_derivatives);
+ *                                                     App. B, Eqs. (X15_nonequal_timedelays,
+ *                                                     X20_nonequal_timedelays)
+ *   - sigmoid hybrid                                  Sec. IV, Eqs. (sigmoid, hybridized_xs)
+ * Readings where the paper is silent or inconsistent are listed in the design doc
+ * of the repository; each is restated at its point of use below.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp (no fast-math, no FMA contraction).
+ */
+#include "tdi_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_C 299792458.0   /* speed of light, m/s */
+#define ORC_PI 3.14159265358979323846
+
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+/* ---------------------------------------------------------------------------
+ * Links.  Sec. II.B: link l joins sender s and receiver r, |l| is the index of
+ * the spacecraft opposite the link and sgn(l) = eps_{s |l| r}.
+ * ------------------------------------------------------------------------- */
+static int levi_civita(int a, int b, int c) {
+  if (a == b || b == c || a == c) return 0;
+  if ((a == 1 && b == 2 && c == 3) || (a == 2 && b == 3 && c == 1) || (a == 3 && b == 1 && c == 2))
+    return 1;
+  return -1;
+}
+
+void orc_link_ends(int l, int* s, int* r) {
+  int a = l > 0 ? l : -l;
+  int o1 = a % 3 + 1, o2 = (a + 1) % 3 + 1;     /* the two spacecraft other than |l| */
+  if (levi_civita(o1, a, o2) == (l > 0 ? 1 : -1)) { *s = o1; *r = o2; }
+  else { *s = o2; *r = o1; }
+}
+
+/* link label -> slot in the 6-arrays: +1,+2,+3,-1,-2,-3 */
+static int link_slot(int l) { return l > 0 ? l - 1 : 2 - l; }
+
+/* Cyclic relabelling 1->2->3->1 applied c times (Y: c = 1, Z: c = 2), sign kept. */
+static int rotate_link(int l, int c) {
+  int a = l > 0 ? l : -l;
+  int b = (a - 1 + c) % 3 + 1;
+  return l > 0 ? b : -b;
+}
+
+/* ---------------------------------------------------------------------------
+ * Triad (Sec. II.A).  k = -e_r, u = -e_phi, v = -e_theta with beta = pi/2 - theta
+ * and lambda = phi.  The printed components carry two sign slips (k_z and u_y)
+ * that contradict both the stated definitions and orthonormality; the
+ * definitions are used.
+ * ------------------------------------------------------------------------- */
+void orc_triad(double beta, double lam, double k[3], double u[3], double v[3]) {
+  double cb = cos(beta), sb = sin(beta), cl = cos(lam), sl = sin(lam);
+  k[0] = -cb * cl; k[1] = -cb * sl; k[2] = -sb;
+  u[0] = sl;       u[1] = -cl;      u[2] = 0.0;
+  v[0] = -sb * cl; v[1] = -sb * sl; v[2] = cb;
+}
+
+/* ---------------------------------------------------------------------------
+ * Orbits.  The paper uses an equal-arm analytic orbit (Sec. II.B) without
+ * printing it; the first-order-in-eccentricity analytic form of its cited
+ * reference is used: alpha = Omega t + kappa0, beta_i = 2 pi (i-1)/3 + lambda0,
+ * e = L / (2 sqrt(3) R).  FROZEN takes the positions at t_freeze.
+ * ------------------------------------------------------------------------- */
+void orc_positions(const orc_orbit* o, double t, double R[3][3]) {
+  double tt = (o->kind == ORC_ORBIT_FROZEN) ? o->t_freeze : t;
+  double e = o->L / (2.0 * sqrt(3.0) * o->R);
+  double alpha = o->omega * tt + o->kappa0;
+  for (int i = 0; i < 3; ++i) {
+    double b = 2.0 * ORC_PI * (double)i / 3.0 + o->lambda0;
+    R[i][0] = o->R * cos(alpha) + 0.5 * e * o->R * (cos(2.0 * alpha - b) - 3.0 * cos(b));
+    R[i][1] = o->R * sin(alpha) + 0.5 * e * o->R * (sin(2.0 * alpha - b) - 3.0 * sin(b));
+    R[i][2] = -sqrt(3.0) * e * o->R * cos(alpha - b);
+  }
+}
+
+/* Light time T_l(t) = L_l(t)/c: photon received by r at t, emitted by s at
+ * t - T; fixed-point iteration T <- |R_r(t) - R_s(t - T)| / c from L/c.
+ * FROZEN: equal constant arms, T = L/c. */
+double orc_light_time(const orc_orbit* o, int l, double t) {
+  if (o->kind == ORC_ORBIT_FROZEN) return o->L / ORC_C;
+  int s, r;
+  orc_link_ends(l, &s, &r);
+  double Rr[3][3], Rs[3][3];
+  orc_positions(o, t, Rr);
+  double T = o->L / ORC_C;
+  for (int it = 0; it < 12; ++it) {
+    orc_positions(o, t - T, Rs);
+    double d[3] = {Rr[r - 1][0] - Rs[s - 1][0], Rr[r - 1][1] - Rs[s - 1][1],
+                   Rr[r - 1][2] - Rs[s - 1][2]};
+    double Tn = sqrt(dot3(d, d)) / ORC_C;
+    double dT = Tn - T;
+    T = Tn;
+    if (fabs(dT) <= 4e-15) break;
+  }
+  return T;
+}
+
+/* Geometry at time t (Sec. II.A/B): n_l is the photon direction
+ * (R_r(t) - R_s(t - T_l)) / (c T_l); xi+ = (u.n)^2 - (v.n)^2, xi_x = 2 (u.n)(v.n);
+ * delta_s = T_l + k.R_s(t)/c, delta_r = k.R_r(t)/c (Eqs. delta_s, delta_r). */
+void orc_geometry(const orc_orbit* o, double beta, double lam, double t, orc_geom* g) {
+  static const int L6[6] = {1, 2, 3, -1, -2, -3};
+  double k[3], u[3], v[3];
+  orc_triad(beta, lam, k, u, v);
+  orc_positions(o, t, g->R);
+  for (int a = 0; a < 6; ++a) {
+    int l = L6[a], s, r;
+    orc_link_ends(l, &s, &r);
+    double T = orc_light_time(o, l, t);
+    double Re[3][3];
+    orc_positions(o, t - T, Re);
+    double nn[3];
+    for (int i = 0; i < 3; ++i) nn[i] = (g->R[r - 1][i] - Re[s - 1][i]) / (ORC_C * T);
+    double un = dot3(u, nn), vn = dot3(v, nn);
+    g->T[a] = T;
+    for (int i = 0; i < 3; ++i) g->n[a][i] = nn[i];
+    g->xi_p[a] = un * un - vn * vn;
+    g->xi_c[a] = 2.0 * un * vn;
+    g->kn[a] = dot3(k, nn);
+    g->ds[a] = T + dot3(k, g->R[s - 1]) / ORC_C;
+    g->dr[a] = dot3(k, g->R[r - 1]) / ORC_C;
+    if (a < 3) g->mu[a] = (dot3(k, g->R[s - 1]) + dot3(k, g->R[r - 1])) / (2.0 * ORC_C);
+  }
+}
+
+/* ---------------------------------------------------------------------------
+ * Fractional delay.  A delay d (s) at output sample k is read at grid position
+ * k - d/dt = i0 + x with i0 = k - ceil(d/dt), x in [0, 1).  The absolute time
+ * t_k - d is never formed.
+ * ------------------------------------------------------------------------- */
+void orc_split(int64_t k, double d, double dt, int64_t* i0, double* x) {
+  double q = d / dt;
+  double m = ceil(q);
+  *i0 = k - (int64_t)m;
+  *x = m - q;
+}
+
+/* Lagrange interpolation with N taps (degree N-1) on the nodes
+ * j = -N/2+1 .. N/2 around i0: l_j(x) = prod_{m != j} (x - m)/(j - m).
+ * Written as a product of ratios so that x = 0 returns s[i0] exactly. */
+void orc_lagrange_weights(double x, int N, double* w) {
+  int jlo = -N / 2 + 1;
+  for (int a = 0; a < N; ++a) {
+    int j = jlo + a;
+    double p = 1.0;
+    for (int b = 0; b < N; ++b) {
+      int m = jlo + b;
+      if (m == j) continue;
+      p *= (x - (double)m) / (double)(j - m);
+    }
+    w[a] = p;
+  }
+}
+
+double orc_lagrange(const double* s, int64_t n, int64_t i0, double x, int N) {
+  double w[64];
+  orc_lagrange_weights(x, N, w);
+  int jlo = -N / 2 + 1;
+  double acc = 0.0;
+  for (int a = 0; a < N; ++a) {
+    int64_t i = i0 + jlo + a;
+    if (i >= 0 && i < n) acc += w[a] * s[i];   /* zero outside the series */
+  }
+  return acc;
+}
+
+/* ---------------------------------------------------------------------------
+ * Central finite-difference stencils of derivative order m and accuracy p
+ * (the numerical derivatives of Sec. III).  Coefficients over offsets
+ * -h..h, numerator / denominator.
+ * ------------------------------------------------------------------------- */
+static int stencil_coeffs(int m, int p, double* num, double* den) {
+  if (m == 1 && p == 2) { double c[] = {-1, 0, 1}; memcpy(num, c, sizeof c); *den = 2; return 1; }
+  if (m == 1 && p == 4) { double c[] = {1, -8, 0, 8, -1}; memcpy(num, c, sizeof c); *den = 12; return 2; }
+  if (m == 2 && p == 2) { double c[] = {1, -2, 1}; memcpy(num, c, sizeof c); *den = 1; return 1; }
+  if (m == 2 && p == 4) { double c[] = {-1, 16, -30, 16, -1}; memcpy(num, c, sizeof c); *den = 12; return 2; }
+  if (m == 3 && p == 2) { double c[] = {-1, 2, 0, -2, 1}; memcpy(num, c, sizeof c); *den = 2; return 2; }
+  if (m == 3 && p == 4) { double c[] = {1, -8, 13, 0, -13, 8, -1}; memcpy(num, c, sizeof c); *den = 8; return 3; }
+  return -1;
+}
+
+static double stencil_at(const double* h, int64_t n, int64_t i, const double* num, int hw, double scale) {
+  double acc = 0.0;
+  for (int s = -hw; s <= hw; ++s) {
+    int64_t j = i + s;
+    if (j >= 0 && j < n) acc += num[s + hw] * h[j];
+  }
+  return acc / scale;
+}
+
+void orc_stencil(const double* h, int64_t n, int m, int p, double dt, double* g) {
+  double num[7], den;
+  int hw = stencil_coeffs(m, p, num, &den);
+  if (hw < 0) { for (int64_t i = 0; i < n; ++i) g[i] = NAN; return; }
+  double scale = den * pow(dt, (double)m);
+  for (int64_t i = 0; i < n; ++i) g[i] = stencil_at(h, n, i, num, hw, scale);
+}
+
+/* ---------------------------------------------------------------------------
+ * TDI term lists, transcribed from Eqs. (X1.5) and (X2.0): each term is
+ * sign * y_link(t - sum of the listed delays), with every L evaluated at t.
+ * Links: y_{1-32} is l = -3, y_{231} is l = +3, y_{123} is l = +2,
+ * y_{3-21} is l = -2.  Y and Z follow by cyclic relabelling.
+ * ------------------------------------------------------------------------- */
+typedef struct { int sign, link, nd, d[7]; } orc_term;
+
+static const orc_term X15_TERMS[8] = {
+    {+1, -3, 3, {-2, +2, +3}},
+    {-1, -3, 1, {+3}},
+    {+1, +3, 2, {+2, -2}},
+    {-1, +3, 0, {0}},
+    {+1, +2, 1, {-2}},
+    {-1, +2, 3, {-2, -3, +3}},
+    {+1, -2, 0, {0}},
+    {-1, -2, 2, {-3, +3}},
+};
+
+static const orc_term X20_EXTRA_TERMS[8] = {
+    {+1, -3, 5, {-2, +2, +3, +3, -3}},
+    {-1, -3, 7, {+3, +3, -3, -2, -2, +2, +2}},
+    {+1, +3, 4, {-2, +2, +3, -3}},
+    {-1, +3, 6, {+3, -3, -2, -2, +2, +2}},
+    {+1, +2, 7, {-2, -2, +2, +3, +3, -3, -3}},
+    {-1, +2, 5, {+3, -3, -2, -2, +2}},
+    {+1, -2, 6, {-2, +2, +3, +3, -3, -3}},
+    {-1, -2, 4, {+3, -3, -2, +2}},
+};
+
+static int n_terms(int gen) { return gen == 20 ? 16 : 8; }
+static const orc_term* term_at(int t) { return t < 8 ? &X15_TERMS[t] : &X20_EXTRA_TERMS[t - 8]; }
+
+/* ---------------------------------------------------------------------------
+ * Evaluation context: h_SSB, lazily filled link series y and LFA derivative
+ * series g (each entry computed at most once).
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  const orc_config* c;
+  const orc_orbit* o;
+  const orc_source* s;
+  int64_t n;
+  double* hp_ssb;
+  double* hc_ssb;
+  double* y;          /* 6 * n */
+  unsigned char* y_ok;
+  double* gp;
+  double* gc;
+  unsigned char* g_ok;
+  int m;              /* LFA derivative order */
+} orc_ctx;
+
+static void ctx_init(orc_ctx* x, const orc_config* c, const orc_orbit* o, const orc_source* s,
+                     int64_t n, const double* hp, const double* hc) {
+  x->c = c; x->o = o; x->s = s; x->n = n;
+  x->hp_ssb = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  x->hc_ssb = (double*)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+  /* Eqs. (hplus_ssb, hcross_ssb): rotation by the polarisation angle. */
+  double c2 = cos(2.0 * s->psi), s2 = sin(2.0 * s->psi);
+  for (int64_t i = 0; i < n; ++i) {
+    x->hp_ssb[i] = hp[i] * c2 - hc[i] * s2;
+    x->hc_ssb[i] = hp[i] * s2 + hc[i] * c2;
+  }
+  x->y = NULL; x->y_ok = NULL; x->gp = NULL; x->gc = NULL; x->g_ok = NULL;
+  x->m = (c->tdi_gen == 20) ? 3 : 2;
+}
+
+static void ctx_free(orc_ctx* x) {
+  free(x->hp_ssb); free(x->hc_ssb); free(x->y); free(x->y_ok);
+  free(x->gp); free(x->gc); free(x->g_ok);
+}
+
+static double t_of(const orc_ctx* x, int64_t k) { return x->s->t0 + (double)k * x->s->dt; }
+
+/* Stage 1 at grid sample i, Eq. (yslr) with Eq. (H): for each link,
+ * y = [H_l(t - delta_s) - H_l(t - delta_r)] / (2 (1 - k.n)), where H_l at a
+ * retarded time uses the antenna patterns at the reception time t_i and the
+ * N-tap Lagrange value of h_SSB. */
+static void stage1_at(orc_ctx* x, int64_t i, double y6[6]) {
+  orc_geom g;
+  orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, i), &g);
+  int N = x->c->taps;
+  double dt = x->s->dt;
+  for (int a = 0; a < 6; ++a) {
+    int64_t i0; double fx;
+    orc_split(i, g.ds[a], dt, &i0, &fx);
+    double Hs = g.xi_p[a] * orc_lagrange(x->hp_ssb, x->n, i0, fx, N) +
+                g.xi_c[a] * orc_lagrange(x->hc_ssb, x->n, i0, fx, N);
+    orc_split(i, g.dr[a], dt, &i0, &fx);
+    double Hr = g.xi_p[a] * orc_lagrange(x->hp_ssb, x->n, i0, fx, N) +
+                g.xi_c[a] * orc_lagrange(x->hc_ssb, x->n, i0, fx, N);
+    y6[a] = (Hs - Hr) / (2.0 * (1.0 - g.kn[a]));
+  }
+}
+
+static void ensure_y_alloc(orc_ctx* x) {
+  if (x->y) return;
+  size_t n = (size_t)(x->n > 0 ? x->n : 1);
+  x->y = (double*)malloc(sizeof(double) * 6 * n);
+  x->y_ok = (unsigned char*)calloc(n, 1);
+}
+
+static void ensure_y_range(orc_ctx* x, int64_t lo, int64_t hi) {
+  ensure_y_alloc(x);
+  if (lo < 0) lo = 0;
+  if (hi > x->n) hi = x->n;
+  for (int64_t i = lo; i < hi; ++i) {
+    if (x->y_ok[i]) continue;
+    double y6[6];
+    stage1_at(x, i, y6);
+    for (int a = 0; a < 6; ++a) x->y[(size_t)a * x->n + i] = y6[a];
+    x->y_ok[i] = 1;
+  }
+}
+
+static int in_parallel(void) {
+#ifdef _OPENMP
+  return omp_in_parallel();
+#else
+  return 1;
+#endif
+}
+
+/* Fill y for every grid index >= lo (in parallel when not nested). */
+static void fill_y_from(orc_ctx* x, int64_t lo) {
+  ensure_y_alloc(x);
+  int64_t n = x->n;
+  if (lo < 0) lo = 0;
+#pragma omp parallel for schedule(static) if (n - lo > 4096 && !in_parallel())
+  for (int64_t i = lo; i < n; ++i) {
+    if (x->y_ok[i]) continue;
+    double y6[6];
+    stage1_at(x, i, y6);
+    for (int a = 0; a < 6; ++a) x->y[(size_t)a * n + i] = y6[a];
+    x->y_ok[i] = 1;
+  }
+}
+
+static double lagrange_y(orc_ctx* x, int slot, int64_t i0, double fx) {
+  int N = x->c->taps;
+  ensure_y_range(x, i0 - N / 2 + 1, i0 + N / 2 + 1);
+  return orc_lagrange(x->y + (size_t)slot * x->n, x->n, i0, fx, N);
+}
+
+/* Stage 2 at output sample k, Eqs. (X1.5)/(X2.0): all delays L_l -> c T_l(t_k);
+ * a term's delays are summed first, then split.  If absterms is non-null the
+ * sum of |term| per channel is returned there as well. */
+static void full_at(orc_ctx* x, int64_t k, double out[3], double* absterms) {
+  orc_geom g;
+  orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, k), &g);
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0, aabs = 0.0;
+    for (int t = 0; t < n_terms(x->c->tdi_gen); ++t) {
+      const orc_term* tm = term_at(t);
+      double d = 0.0;
+      for (int q = 0; q < tm->nd; ++q) d += g.T[link_slot(rotate_link(tm->d[q], c))];
+      int64_t i0; double fx;
+      orc_split(k, d, x->s->dt, &i0, &fx);
+      double v = lagrange_y(x, link_slot(rotate_link(tm->link, c)), i0, fx);
+      acc += (double)tm->sign * v;
+      aabs += fabs(v);
+    }
+    out[c] = acc;
+    if (absterms) absterms[c] = aabs;
+  }
+}
+
+/* LFA derivative series g_m = D^(m)_p [h_SSB] on the grid, zero outside. */
+static void ensure_g_alloc(orc_ctx* x) {
+  if (x->gp) return;
+  size_t n = (size_t)(x->n > 0 ? x->n : 1);
+  x->gp = (double*)malloc(sizeof(double) * n);
+  x->gc = (double*)malloc(sizeof(double) * n);
+  x->g_ok = (unsigned char*)calloc(n, 1);
+}
+
+static void ensure_g_range(orc_ctx* x, int64_t lo, int64_t hi) {
+  ensure_g_alloc(x);
+  if (lo < 0) lo = 0;
+  if (hi > x->n) hi = x->n;
+  double num[7], den;
+  int hw = stencil_coeffs(x->m, x->c->stencil_order, num, &den);
+  double scale = den * pow(x->s->dt, (double)x->m);
+  for (int64_t i = lo; i < hi; ++i) {
+    if (x->g_ok[i]) continue;
+    x->gp[i] = stencil_at(x->hp_ssb, x->n, i, num, hw, scale);
+    x->gc[i] = stencil_at(x->hc_ssb, x->n, i, num, hw, scale);
+    x->g_ok[i] = 1;
+  }
+}
+
+static void fill_g_all(orc_ctx* x) {
+  ensure_g_alloc(x);
+  ensure_g_range(x, 0, x->n);
+}
+
+/* Xi_l(k; d) = xi+_l(t_k) I_N[g+](k - d/dt) + xi_x_l(t_k) I_N[g_x](k - d/dt). */
+static double Xi(orc_ctx* x, const orc_geom* g, int l, int64_t k, double d) {
+  int N = x->c->taps;
+  int64_t i0; double fx;
+  orc_split(k, d, x->s->dt, &i0, &fx);
+  ensure_g_range(x, i0 - N / 2 + 1, i0 + N / 2 + 1);
+  int a = link_slot(l);
+  return g->xi_p[a] * orc_lagrange(x->gp, x->n, i0, fx, N) +
+         g->xi_c[a] * orc_lagrange(x->gc, x->n, i0, fx, N);
+}
+
+/* LFA at output sample k.  The single-link LFA of Eq. (yslr_strain_derivatives),
+ * y_l(t) = -(T_l/2) [xi+ h+'(t - T_l/2 - mu_l) + xi_x hx'(...)], with
+ * mu_l = k.(R_s + R_r)/(2c), substituted into Eqs. (X15_nonequal_timedelays)
+ * and (X20_nonequal_timedelays) (T_i = L_i/c, positive-index links, geometry at
+ * t_k, derivatives of the delays and antenna patterns dropped as in App. B):
+ *   X1.5 = -2 T2 T3        [Xi_2^(2)(k; T2+T3+mu_2)     - Xi_3^(2)(k; T2+T3+mu_3)]
+ *   X2.0 = -4 T2 T3 (T2+T3) [Xi_2^(3)(k; 2(T2+T3)+mu_2) - Xi_3^(3)(k; 2(T2+T3)+mu_3)]
+ * where Xi^(m) interpolates the m-th strain derivative taken on the grid by a
+ * central stencil (derivative first, then fractional delay).  Equal arms set
+ * every T_i to L/c.  Y, Z: links (2,3) -> (3,1) -> (1,2). */
+static void lfa_at(orc_ctx* x, int64_t k, double out[3]) {
+  orc_geom g;
+  orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, k), &g);
+  for (int c = 0; c < 3; ++c) {
+    int la = (c + 1) % 3 + 1, lb = (c + 2) % 3 + 1;
+    double Ta = x->c->equal_arms ? x->o->L / ORC_C : g.T[la - 1];
+    double Tb = x->c->equal_arms ? x->o->L / ORC_C : g.T[lb - 1];
+    double pref, d;
+    if (x->c->tdi_gen == 20) { pref = -4.0 * Ta * Tb * (Ta + Tb); d = 2.0 * (Ta + Tb); }
+    else { pref = -2.0 * Ta * Tb; d = Ta + Tb; }
+    out[c] = pref * (Xi(x, &g, la, k, d + g.mu[la - 1]) - Xi(x, &g, lb, k, d + g.mu[lb - 1]));
+  }
+}
+
+/* Hybrid weights and windows, Eqs. (sigmoid, hybridized_xs), in sample units:
+ * z = (k - k_H)/sigma, w+ = 1/(1+e^z), w- = 1/(1+e^-z); LFA part where
+ * k - k_H <= T/2, full part where k - k_H >= -T/2 (both inclusive, weights
+ * applied everywhere).  k_H = (t_Hyb - t0)/dt. */
+static void output_at(orc_ctx* x, int64_t k, double out[3]) {
+  int mode = x->c->mode;
+  if (mode == ORC_FULL) { full_at(x, k, out, NULL); return; }
+  if (mode == ORC_LFA) { lfa_at(x, k, out); return; }
+  double kH = (x->s->t_hyb - x->s->t0) / x->s->dt;
+  double rel = (double)k - kH;
+  double z = rel / x->c->sigma_samples;
+  double wp = 1.0 / (1.0 + exp(z));
+  double wm = 1.0 / (1.0 + exp(-z));
+  double r[3] = {0.0, 0.0, 0.0};
+  if (rel <= 0.5 * x->c->T_samples) {
+    double a[3];
+    lfa_at(x, k, a);
+    for (int c = 0; c < 3; ++c) r[c] += wp * a[c];
+  }
+  if (rel >= -0.5 * x->c->T_samples) {
+    double b[3];
+    full_at(x, k, b, NULL);
+    for (int c = 0; c < 3; ++c) r[c] += wm * b[c];
+  }
+  for (int c = 0; c < 3; ++c) out[c] = r[c];
+}
+
+/* First grid index of y that the full part can read, or n if none: the full
+ * part starts at k_H - T/2 and a TDI 2.0 term reaches back at most seven arm
+ * light times (bounded generously by ten L/c) plus N/2 taps. */
+static int64_t first_y_needed(const orc_ctx* x) {
+  if (x->c->mode == ORC_FULL) return 0;
+  if (x->c->mode == ORC_LFA) return x->n;
+  double kH = (x->s->t_hyb - x->s->t0) / x->s->dt;
+  double k0 = kH - 0.5 * x->c->T_samples;
+  if (!(k0 <= (double)(x->n - 1))) return x->n;       /* also catches NaN */
+  if (k0 < 0.0) return 0;
+  double back = 10.0 * x->o->L / ORC_C / x->s->dt + x->c->taps / 2 + 2;
+  double lo = floor(k0 - back);
+  return lo < 0.0 ? 0 : (int64_t)lo;
+}
+
+/* ---------------------------------------------------------------------------
+ * Public entry points.
+ * ------------------------------------------------------------------------- */
+void orc_links(const orc_config* c, const orc_orbit* o, const orc_source* s,
+               int64_t n, const double* hp, const double* hc, double* y) {
+  orc_ctx x;
+  ctx_init(&x, c, o, s, n, hp, hc);
+  fill_y_from(&x, 0);
+  memcpy(y, x.y, sizeof(double) * 6 * (size_t)n);
+  ctx_free(&x);
+}
+
+void orc_tdi_combine(int gen, int N, int64_t n, double dt, const double* y,
+                     const double* T, double* X, double* Y, double* Z) {
+  double* outs[3] = {X, Y, Z};
+#pragma omp parallel for schedule(static) if (n > 4096 && !in_parallel())
+  for (int64_t k = 0; k < n; ++k) {
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0.0;
+      for (int t = 0; t < n_terms(gen); ++t) {
+        const orc_term* tm = term_at(t);
+        double d = 0.0;
+        for (int q = 0; q < tm->nd; ++q) d += T[(size_t)link_slot(rotate_link(tm->d[q], c)) * n + k];
+        int64_t i0; double fx;
+        orc_split(k, d, dt, &i0, &fx);
+        acc += (double)tm->sign *
+               orc_lagrange(y + (size_t)link_slot(rotate_link(tm->link, c)) * n, n, i0, fx, N);
+      }
+      outs[c][k] = acc;
+    }
+  }
+}
+
+void orc_response(const orc_config* c, const orc_orbit* o, const orc_source* s,
+                  int64_t n, const double* hp, const double* hc,
+                  double* X, double* Y, double* Z) {
+  if (n <= 0) return;
+  orc_ctx x;
+  ctx_init(&x, c, o, s, n, hp, hc);
+  int64_t ylo = first_y_needed(&x);
+  if (ylo < n) fill_y_from(&x, ylo);
+  if (c->mode != ORC_FULL) fill_g_all(&x);
+#pragma omp parallel for schedule(static) if (n > 4096 && !in_parallel())
+  for (int64_t k = 0; k < n; ++k) {
+    double r[3];
+    output_at(&x, k, r);
+    X[k] = r[0]; Y[k] = r[1]; Z[k] = r[2];
+  }
+  ctx_free(&x);
+}
+
+void orc_response_at(const orc_config* c, const orc_orbit* o, const orc_source* s,
+                     int64_t n, const double* hp, const double* hc,
+                     int64_t nk, const int64_t* ks, double* X, double* Y, double* Z) {
+  orc_ctx x;
+  ctx_init(&x, c, o, s, n, hp, hc);
+  for (int64_t q = 0; q < nk; ++q) {
+    double r[3];
+    output_at(&x, ks[q], r);
+    X[q] = r[0]; Y[q] = r[1]; Z[q] = r[2];
+  }
+  ctx_free(&x);
+}
+
+void orc_response_batch(const orc_config* c, const orc_orbit* o, int64_t n_sources,
+                        const orc_source* src, const int64_t* offsets,
+                        const double* hp, const double* hc,
+                        double* X, double* Y, double* Z) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n_sources; ++i) {
+    int64_t a = offsets[i], b = offsets[i + 1];
+    orc_response(c, o, &src[i], b - a, hp + a, hc + a, X + a, Y + a, Z + a);
+  }
+}
+
+void orc_full_terms_absmax(const orc_config* c, const orc_orbit* o, const orc_source* s,
+                           int64_t n, const double* hp, const double* hc, double* absmax3) {
+  orc_ctx x;
+  ctx_init(&x, c, o, s, n, hp, hc);
+  fill_y_from(&x, 0);
+  absmax3[0] = absmax3[1] = absmax3[2] = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    double r[3], a[3];
+    full_at(&x, k, r, a);
+    for (int q = 0; q < 3; ++q) if (a[q] > absmax3[q]) absmax3[q] = a[q];
+  }
+  ctx_free(&x);
+}
