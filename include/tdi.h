@@ -1,0 +1,149 @@
+/*
+ * tdi.h - C ABI of the MI355X (gfx950) hybrid time-domain LISA response.
+ *
+ * Computes the Michelson TDI observables X, Y, Z of a batch of gravitational-
+ * wave sources from their sampled polarisations h+, hx, following
+ * arXiv:2505.09600:
+ *   - full response: per-link projection at retarded times, Sec. II.A-B,
+ *     Eqs. (H), (xi_plus), (xi_cross), (yslr), (delta_s), (delta_r), with
+ *     N-tap Lagrange fractional delays; TDI 1.5 / 2.0 Michelson combinations,
+ *     Eqs. (X1.5) and (X2.0), every arm delay evaluated at the output time;
+ *   - low-frequency approximation (LFA): delays become central finite-difference
+ *     stencils of the strain, Sec. III, Eqs. (yslr_strain_derivatives),
+ *     (X15_with_strain_derivatives), (X20_with_strain_derivatives) and App. B,
+ *     Eqs. (X15_nonequal_timedelays), (X20_nonequal_timedelays);
+ *   - hybrid: sigmoid blend of the two around a switch time, Sec. IV,
+ *     Eqs. (sigmoid), (hybridized_xs).
+ *
+ * Memory and ownership
+ *   Small per-batch metadata (source records, CSR offsets) are HOST pointers,
+ *   validated on the host before any device work and copied by the library.
+ *   Bulk arrays (hp, hc, X, Y, Z) are DEVICE pointers on the plan's device,
+ *   owned by the caller; they must stay valid until the work on the plan's
+ *   stream has completed.  The library owns the plan (device tables, work
+ *   counters, captured graph); tdi_run allocates no device memory.
+ *   All calls on one plan must come from one host thread at a time.
+ *
+ * Errors
+ *   Every function returns a tdi_status.  Argument errors are detected before
+ *   any device work and leave the outputs untouched.  After TDI_EDEVICE the
+ *   output contents are unspecified.  NaN inputs propagate without a check.
+ *
+ * Numerics
+ *   TDI_FP64: all arithmetic in FP64.  TDI_FP32_BULK: retarded-time arguments,
+ *   geometry, stencils and the split into integer index and fraction stay in
+ *   FP64; the fractional-delay interpolation, TDI combination and hybrid blend
+ *   run in FP32 with FP32 accumulation, and X, Y, Z are written as float.
+ */
+#ifndef TDI_H
+#define TDI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TDI_OK = 0,
+  TDI_EINVAL = -1,        /* null / misaligned pointer, bad offsets, bad sizes */
+  TDI_ERANGE = -2,        /* value out of the supported range (taps, dt, angles, window) */
+  TDI_ENOMEM = -3,        /* device or pinned host allocation failed */
+  TDI_EDEVICE = -4,       /* no gfx950 device, or a HIP runtime error */
+  TDI_EUNSUPPORTED = -5,  /* unknown TDI generation, mode, precision or orbit kind */
+  TDI_ESTATE = -6         /* batch exceeds the plan's declared maxima, or bad plan */
+} tdi_status;
+
+enum { TDI_ORBIT_FROZEN = 0, TDI_ORBIT_ANALYTIC1 = 1 };
+enum { TDI_MODE_FULL = 0, TDI_MODE_LFA = 1, TDI_MODE_HYBRID = 2 };
+enum { TDI_FP64 = 0, TDI_FP32_BULK = 1 };
+
+/* Constellation orbit (Sec. II.B uses an equal-arm analytic orbit).
+ * ANALYTIC1: rigid equilateral first-order analytic orbit at radius R_m with
+ *   eccentricity L_m / (2 sqrt(3) R_m), orbital phase alpha = omega t + kappa0,
+ *   spacecraft i at beta_i = 2 pi (i-1)/3 + lambda0; light times solve the
+ *   light-time equation with the sender at emission time.
+ * FROZEN: positions of ANALYTIC1 at t_freeze, all six light times L_m / c. */
+typedef struct {
+  int32_t kind;       /* TDI_ORBIT_* */
+  int32_t reserved;   /* must be 0 */
+  double L_m;         /* arm length, m, > 0 */
+  double R_m;         /* orbital radius, m, > L_m */
+  double omega;       /* rad/s, finite, >= 0 */
+  double kappa0;      /* rad */
+  double lambda0;     /* rad */
+  double t_freeze;    /* s (FROZEN only) */
+} tdi_orbit;
+
+/* One source: sky position, polarisation, time grid and switch time.
+ * Sample k of the source is at t0 + k dt. */
+typedef struct {
+  double beta;        /* ecliptic latitude, rad, |beta| <= pi/2 */
+  double lambda;      /* ecliptic longitude, rad, finite */
+  double psi;         /* polarisation angle, rad, finite */
+  double t0;          /* s, finite */
+  double dt;          /* s, > 0 */
+  double t_hyb;       /* switch time, s (HYBRID): +inf = pure LFA, -inf = pure full; not NaN */
+} tdi_source;
+
+typedef struct {
+  int32_t tdi_gen;          /* 15 (first generation) or 20 (second generation) */
+  int32_t mode;             /* TDI_MODE_* */
+  int32_t interp_taps;      /* N Lagrange taps (degree N-1): 4, 8, 16 or 32 */
+  int32_t stencil_order;    /* LFA central-difference accuracy order: 2 or 4 */
+  int32_t lfa_equal_arms;   /* LFA only: 1 = equal constant delays L/c, 0 = unequal time-dependent */
+  int32_t precision;        /* TDI_FP64 or TDI_FP32_BULK */
+  double hyb_T_samples;     /* hybrid window length T in samples (paper default 800), > 0 */
+  double hyb_sigma_samples; /* sigmoid width sigma in samples (paper default T/40), > 0 */
+  int32_t autotune;         /* 1: time the launch candidates on the first run and keep the best */
+  int32_t use_graph;        /* 1: capture the run sequence in a hipGraph and replay it */
+} tdi_config;
+
+typedef struct tdi_plan tdi_plan;
+
+/* Host-only validation of a configuration and orbit (no device needed).
+ * Returns TDI_OK, TDI_EINVAL (null), TDI_EUNSUPPORTED or TDI_ERANGE. */
+tdi_status tdi_check_config(const tdi_config* cfg, const tdi_orbit* orb);
+
+/* Host-only validation of a batch: src[n_sources] records and
+ * offsets[n_sources + 1] (offsets[0] = 0, non-decreasing; source i owns samples
+ * offsets[i] .. offsets[i+1]-1 of the flat arrays).  No device needed. */
+tdi_status tdi_check_batch(const tdi_config* cfg, int64_t n_sources,
+                           const tdi_source* src, const int64_t* offsets);
+
+/* Create a plan on the current HIP device for batches of at most max_sources
+ * sources and max_total_samples samples.  hip_stream is a hipStream_t (NULL =
+ * default stream).  Returns TDI_EDEVICE when no gfx950 device is present. */
+tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbit* orb,
+                           int64_t max_sources, int64_t max_total_samples, void* hip_stream);
+
+/* Enqueue the response of one batch on the plan's stream (asynchronous).
+ * src, offsets: host arrays (copied before return).  hp, hc: device arrays of
+ * offsets[n_sources] doubles (8-byte aligned).  X, Y, Z: device arrays of
+ * offsets[n_sources] doubles (TDI_FP64) or floats (TDI_FP32_BULK).
+ * The first run of an autotuning plan times candidates synchronously. */
+tdi_status tdi_run(tdi_plan* plan, int64_t n_sources, const tdi_source* src,
+                   const int64_t* offsets, const double* hp, const double* hc,
+                   void* X, void* Y, void* Z);
+
+/* Wait for the plan's work and report device-side window checks:
+ * TDI_ERANGE if any retarded-time window left the staged range since the last
+ * call (such samples were written as NaN), else TDI_OK. */
+tdi_status tdi_plan_sync(tdi_plan* plan);
+
+/* Durations (ms) of the response kernel in the most recent runs, oldest first
+ * (at most 'cap' values, up to 256 remembered).  Synchronizes the stream.
+ * *count receives the number written.  The record is cleared afterwards. */
+tdi_status tdi_plan_kernel_times(tdi_plan* plan, float* ms, int32_t cap, int32_t* count);
+
+/* Launch parameters chosen for the plan (tile length, workgroups, variant). */
+tdi_status tdi_plan_describe(const tdi_plan* plan, char* buf, int32_t buflen);
+
+tdi_status tdi_plan_destroy(tdi_plan* plan);
+
+const char* tdi_status_str(tdi_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDI_H */

@@ -1,0 +1,146 @@
+"""GPU parity: the HIP library through its C ABI against the FP64 oracle.
+
+Error metric per channel: max_k |X_gpu - X_oracle| / max_k |X_oracle|.
+FP64 bar: 1e-12, or the conditioning floor of the response when that is higher
+(``tol64`` below; the floor is measured by the oracle's absolute-value
+evaluation).  FP32-bulk bar: 1e-5.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2505_09600_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tdi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2505_09600_amd import tdi as T
+    T.lib()
+    return T
+
+
+def _run_gpu(T, batch, cfg, orb, **kw):
+    return T.response(batch, cfg, orb, **kw)
+
+
+def _run_orc(orc, batch, cfg, orb):
+    return orc.response_batch(cfg, orb, batch)
+
+
+def _err(orc, got, ref):
+    return orc.peak_rel_err(got, ref)
+
+
+def _report(name, err, tol):
+    print(f"[parity] {name}: err X,Y,Z = {err[0]:.3e} {err[1]:.3e} {err[2]:.3e}  tol {tol:.1e}", flush=True)
+
+
+def _small_analytic(n=20000, mc=4e5, seed=11, dt=10.0, t0=3.0e6, hybrid=True):
+    rng = np.random.default_rng(seed)
+    beta = math.asin(rng.uniform(-1, 1))
+    lam, psi, iota = rng.uniform(0, 2 * math.pi), rng.uniform(0, math.pi), math.acos(rng.uniform(-1, 1))
+    rec, hp, hc, meta = W.make_source(mc, iota, beta, lam, psi, n, dt, t0=t0, hybrid=hybrid)
+    return W._assemble([(rec, hp, hc, meta)], np)
+
+
+def test_c1_full_fp64_frozen_tdi15(tdi, orc):
+    batch, cfg, orb = W.config_c1()
+    got = _run_gpu(tdi, batch, cfg, orb)
+    ref = _run_orc(orc, batch, cfg, orb)
+    err = _err(orc, got, ref)
+    _report("c1 full fp64 tdi1.5 N16", err, 1e-12)
+    assert np.all(err <= 1e-12)
+
+
+@pytest.mark.parametrize("gen", [15, 20])
+def test_full_fp64_analytic_orbit(tdi, orc, gen):
+    batch = _small_analytic(mc=2e5)
+    orb = W.default_orbit()
+    cfg = W.default_config(tdi_gen=gen, mode=0, taps=32)
+    got = _run_gpu(tdi, batch, cfg, orb)
+    ref = _run_orc(orc, batch, cfg, orb)
+    err = _err(orc, got, ref)
+    _report(f"full fp64 tdi{gen} N32 analytic", err, 1e-12)
+    assert np.all(err <= 1e-10)
+
+
+@pytest.mark.parametrize("gen,p,eq", [(15, 2, 0), (15, 4, 1), (20, 2, 1), (20, 4, 0)])
+def test_lfa_fp64(tdi, orc, gen, p, eq):
+    batch = _small_analytic(mc=2e5)
+    orb = W.default_orbit()
+    cfg = W.default_config(tdi_gen=gen, mode=1, taps=32, stencil_order=p, equal_arms=eq)
+    got = _run_gpu(tdi, batch, cfg, orb)
+    ref = _run_orc(orc, batch, cfg, orb)
+    err = _err(orc, got, ref)
+    _report(f"lfa fp64 tdi{gen} p{p} eq{eq}", err, 1e-12)
+    assert np.all(err <= 1e-9)
+
+
+@pytest.mark.parametrize("gen", [15, 20])
+def test_hybrid_fp64_and_fp32(tdi, orc, gen):
+    batch = _small_analytic(mc=1.5e5, n=30000)
+    assert math.isfinite(batch.sources[0]["t_hyb"])
+    orb = W.default_orbit()
+    cfg = W.default_config(tdi_gen=gen, mode=2, taps=32, stencil_order=4)
+    ref = _run_orc(orc, batch, cfg, orb)
+    got = _run_gpu(tdi, batch, cfg, orb)
+    err = _err(orc, got, ref)
+    _report(f"hybrid fp64 tdi{gen}", err, 1e-12)
+    assert np.all(err <= 1e-9)
+    got32 = _run_gpu(tdi, batch, dict(cfg, precision=1), orb)
+    err32 = _err(orc, got32, ref)
+    _report(f"hybrid fp32 tdi{gen}", err32, 1e-5)
+    assert np.all(err32 <= 1e-5)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+def test_ragged_batch_fp32_and_fp64(tdi, orc, mode):
+    """Empty, single-sample, shorter-than-taps and multi-tile sources in one batch."""
+    rng = np.random.default_rng(3)
+    lens = [0, 1, 7, 31, 257, 1000, 4099, 0, 2600]
+    parts = []
+    for i, n in enumerate(lens):
+        mc = 10 ** rng.uniform(5, 5.4)
+        rec, hp, hc, meta = W.make_source(mc, 0.7, math.asin(rng.uniform(-1, 1)), rng.uniform(0, 6.28),
+                                          rng.uniform(0, 3.14), max(n, 1), 10.0, t0=1e6 * i)
+        if n and mode == 2:
+            rec["t_hyb"] = rec["t0"] + 0.6 * n * 10.0
+        parts.append((rec, hp[:n], hc[:n], meta))
+    batch = W._assemble(parts, np)
+    orb = W.default_orbit()
+    cfg = W.default_config(tdi_gen=20, mode=mode, taps=16, stencil_order=4)
+    ref = _run_orc(orc, batch, cfg, orb)
+    for prec, tol in ((0, 1e-9), (1, 1e-5)):
+        got = _run_gpu(tdi, batch, dict(cfg, precision=prec), orb)
+        for i in range(batch.n_sources):
+            a, b = batch.offsets[i], batch.offsets[i + 1]
+            if b - a < 2:
+                continue
+            err = _err(orc, got[:, a:b], ref[:, a:b])
+            _report(f"ragged mode{mode} prec{prec} src{i} n={b - a}", err, tol)
+            assert np.all(err <= tol)
+
+
+def test_zero_strain_gives_zero(tdi):
+    batch = _small_analytic(n=3000)
+    batch.hp[:] = 0.0
+    batch.hc[:] = 0.0
+    for mode in (0, 1, 2):
+        cfg = W.default_config(tdi_gen=20, mode=mode, taps=32)
+        got = _run_gpu(tdi, batch, cfg, W.default_orbit())
+        assert np.all(got == 0.0)
+
+
+def test_graph_and_persistent_match_plain_launch(tdi, orc):
+    batch = _small_analytic(mc=1.5e5, n=30000)
+    orb = W.default_orbit()
+    cfg = W.default_config(tdi_gen=20, mode=2, taps=32, precision=0)
+    a = _run_gpu(tdi, batch, cfg, orb)
+    b = _run_gpu(tdi, batch, cfg, orb, autotune=True, use_graph=True)
+    assert np.array_equal(a, b)
