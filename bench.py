@@ -1,0 +1,231 @@
+#!/usr/bin/env python3
+"""Benchmark: batched FP32-bulk hybrid TDI 2.0 X,Y,Z on one MI355X.
+
+Workload: 512 sources, lengths log-uniform in 2^18..2^22 samples at dt = 10 s
+(7.26e8 samples in total), seeded uniform sky, polarisation and inclination,
+log-uniform chirp mass 1e5..1e7 Msun, synthetic Newtonian chirps with ringdown
+(seed 1004); first-order analytic orbits; 32-tap Lagrange interpolation,
+4th-order LFA stencils, hybrid switch where f_GW L / c reaches 0.05,
+T = 800 dt, sigma = T / 40.  Inputs are generated in device memory before the
+timed region.  One step = one tdi_run over the whole batch (graph replay of the
+persistent LFA and full-response kernels).
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
+the response has no multi-GPU path in this build (sources would be sharded
+across GPUs without communication).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "TDI2 XYZ samples/s (batched, FP32-bulk vs FP64) at ≤1e-5 peak-rel error"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+BYTES_PER_SAMPLE_FP32 = 16 + 12       # read h+, hx (FP64), write X, Y, Z (FP32)
+BYTES_PER_SAMPLE_FP64 = 16 + 24
+TAPS = 32
+
+
+def lfa_flops_per_sample(taps: int) -> int:
+    """Algorithmic FP32 work of the LFA per output sample: six retarded reads,
+    each a two-component N-tap Lagrange interpolation counted as N weights
+    (4N flops) plus two N-tap dot products (4N flops)."""
+    return 6 * (4 * taps + 4 * taps)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("tdi_kernels.hip", "tdi_internal.h"):
+        with open(os.path.join(ROOT, "paper_2505_09600_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_hash: str):
+    """HBM bytes per sample from committed rocprofv3 PMC summaries, if they were
+    taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_lfa_c4_traffic.json")
+    if not os.path.exists(path):
+        return None
+    d = json.load(open(path))
+    if d.get("kernel_hash") != kernel_hash:
+        return None
+    return d
+
+
+def cpu_baseline(host_sub, cfg, orb, budget_s: float):
+    """The FP64 oracle on a bounded seeded sample of the same workload: seeded
+    random output indices of a seeded subset of the sources, evaluated with the
+    oracle's sampled-output entry point (OpenMP across sources)."""
+    import oracle
+    oracle.build(force=False)
+    threads = oracle.num_threads()
+    rng = np.random.default_rng(11)
+    lens = [int(host_sub.offsets[i + 1] - host_sub.offsets[i]) for i in range(host_sub.n_sources)]
+    # probe: per-output cost on one source
+    probe = host_sub.subset([0])
+    ks = [np.sort(rng.integers(0, lens[0], 256))]
+    t = time.perf_counter()
+    oracle.response_batch_at(cfg, orb, probe, ks)
+    per_out = (time.perf_counter() - t) / 256.0
+    m = int(max(64, budget_s * min(threads, host_sub.n_sources) / (host_sub.n_sources * per_out)))
+    ks = [np.sort(rng.integers(0, n, min(m, n))) for n in lens]
+    nout = int(sum(len(k) for k in ks))
+    t = time.perf_counter()
+    oracle.response_batch_at(cfg, orb, host_sub, ks)
+    el = time.perf_counter() - t
+    return {"value": nout / el, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nout} seeded-random output samples of {host_sub.n_sources} seeded-random sources "
+                      f"of the batch (FP64 hybrid TDI 2.0 oracle, sampled-output entry point), {el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n-sources", type=int, default=512)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--steps-only", action="store_true", help="only the timed hybrid steps (profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: only --gpus 1 is supported; the response has no multi-GPU path "
+              "(a batch would be sharded by source across GPUs with no communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2505_09600_amd import tdi
+    from paper_2505_09600_amd import workload as W
+
+    tdi.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    batch, cfg, orb = W.config_c4(n_sources=args.n_sources, xp=torch, device=dev)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    total = batch.total
+    print(f"[bench] workload: {batch.n_sources} sources, {total} samples, generated in {t_gen:.1f} s",
+          file=sys.stderr, flush=True)
+    hp, hc = batch.hp.contiguous(), batch.hc.contiguous()
+    src = tdi.make_sources(batch.sources)
+    n_full_region = sum(1 for r in batch.sources if math.isfinite(r["t_hyb"]))
+
+    cfg32 = dict(cfg, precision=1, mode=2, tdi_gen=20, taps=TAPS, stencil_order=4)
+    X = torch.empty(total, dtype=torch.float32, device=dev)
+    Y = torch.empty_like(X)
+    Z = torch.empty_like(X)
+    plan = tdi.Plan(cfg32, orb, batch.n_sources, total, autotune=True, use_graph=True)
+    print("[bench] warmup (first run autotunes)", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        plan.run(src, batch.offsets, hp, hc, X, Y, Z)
+    st = plan.sync()
+    if st != tdi.TDI_OK:
+        raise RuntimeError(f"window check failed during warmup: {tdi.tdi_status_str(st)}")
+    plan.kernel_times()                               # drop the warmup records
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plan.run(src, batch.offsets, hp, hc, X, Y, Z)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ktimes = plan.kernel_times()
+    st = plan.sync()
+    if st != tdi.TDI_OK:
+        raise RuntimeError(f"window check failed: {tdi.tdi_status_str(st)}")
+    launch = plan.describe()
+    finite = bool(torch.isfinite(X[:: max(1, total // 100000)]).all().item())
+    el = t1 - t0
+    value = total * args.steps / el
+    ms_step = 1e3 * el / args.steps
+    lfa_ms = float(np.mean([ktimes[2 * i] for i in range(len(ktimes) // 2)])) if ktimes else float("nan")
+    if args.steps_only:
+        print(json.dumps({"ms_per_step": ms_step, "kernel_ms": lfa_ms}), flush=True)
+        return
+    plan.close()
+
+    print(f"[bench] hybrid FP32-bulk: {ms_step:.2f} ms/step, kernel {lfa_ms:.2f} ms, launch {launch}",
+          file=sys.stderr, flush=True)
+    # FP64 plain full response on the same batch (the reference this path must beat)
+    ref = None
+    if not args.no_fp64_reference:
+        cfg64 = dict(cfg, precision=0, mode=0, tdi_gen=20, taps=TAPS, stencil_order=4)
+        X64 = torch.empty(total, dtype=torch.float64, device=dev)
+        Y64 = torch.empty_like(X64)
+        Z64 = torch.empty_like(X64)
+        p64 = tdi.Plan(cfg64, orb, batch.n_sources, total, autotune=True, use_graph=True)
+        p64.run(src, batch.offsets, hp, hc, X64, Y64, Z64)
+        p64.sync()
+        p64.kernel_times()
+        torch.cuda.synchronize()
+        r0 = time.perf_counter()
+        nref = 2
+        for _ in range(nref):
+            p64.run(src, batch.offsets, hp, hc, X64, Y64, Z64)
+        torch.cuda.synchronize()
+        r1 = time.perf_counter()
+        print(f"[bench] FP64 full reference: {1e3 * (r1 - r0) / nref:.2f} ms/step", file=sys.stderr, flush=True)
+        ref = {"value": total * nref / (r1 - r0), "unit": "samples/s",
+               "ms_per_step": 1e3 * (r1 - r0) / nref,
+               "config": "plain full response, FP64, TDI 2.0, same batch"}
+        p64.close()
+        del X64, Y64, Z64
+
+    flops = lfa_flops_per_sample(TAPS) * total
+    achieved_tflops = flops / (lfa_ms * 1e-3) / 1e12 if lfa_ms > 0 else float("nan")
+    achieved_gbs = BYTES_PER_SAMPLE_FP32 * total / (lfa_ms * 1e-3) / 1e9 if lfa_ms > 0 else float("nan")
+    khash = kernel_source_hash()
+    traffic = load_traffic(khash)
+    roof = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved_tflops / FP32_PEAK_TFLOPS,
+            "traffic": (traffic["bytes_per_launch"] if traffic else None),
+            "kernel": "k_lfa<32,float> (+ k_full in the same graph replay)",
+            "kernel_ms": lfa_ms,
+            "flops_per_sample": lfa_flops_per_sample(TAPS),
+            "hbm_achieved_gbs": achieved_gbs, "hbm_peak_gbs": HBM_PEAK_GBS,
+            "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
+            "hbm_bytes_per_sample": BYTES_PER_SAMPLE_FP32, "kernel_hash": khash}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        rng = np.random.default_rng(7)
+        order = rng.permutation(batch.n_sources)[:32]
+        host_sub = W.config_c4(n_sources=args.n_sources, only=[int(i) for i in order])[0]
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(host_sub, dict(cfg32, precision=0), orb, args.cpu_budget)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batched hybrid TDI 2.0, 512 sources, lengths log-uniform 2^18..2^22 at "
+                               "dt=10 s (seed 1004), FP32-bulk with FP64 delays and stencils",
+                   "n_sources": batch.n_sources, "total_samples": total, "taps": TAPS,
+                   "stencil_order": 4, "tdi": "2.0", "mode": "hybrid",
+                   "sources_with_full_region": n_full_region, "launch": launch,
+                   "outputs_finite": finite},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "fp64_full_reference": ref,
+        "speedup_vs_fp64_full": (value / ref["value"]) if ref else None,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

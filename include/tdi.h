@@ -131,16 +131,22 @@ tdi_status tdi_run(tdi_plan* plan, int64_t n_sources, const tdi_source* src,
  * call (such samples were written as NaN), else TDI_OK. */
 tdi_status tdi_plan_sync(tdi_plan* plan);
 
-/* Durations (ms) of the response kernel in the most recent runs, oldest first
- * (at most 'cap' values, up to 256 remembered).  Synchronizes the stream.
- * *count receives the number written.  The record is cleared afterwards. */
+/* Kernel durations (ms) of the most recent runs, oldest first, two values per
+ * run: the LFA kernel and the full-response kernel (a graph replay reports the
+ * whole replay as the first value and 0 as the second).  At most 'cap' values
+ * (up to 256 runs remembered); *count receives the number written.  Waits for
+ * the plan's work; the record is cleared afterwards. */
 tdi_status tdi_plan_kernel_times(tdi_plan* plan, float* ms, int32_t cap, int32_t* count);
 
-/* Launch parameters chosen for the plan (tile length, workgroups, variant). */
+/* Launch parameters chosen for the plan as a JSON object in buf (tile
+ * lengths, persistent grid sizes, graph use, compute units, tuned flag). */
 tdi_status tdi_plan_describe(const tdi_plan* plan, char* buf, int32_t buflen);
 
+/* Wait for the plan's outstanding work and release everything it owns
+ * (device tables, pinned staging, graph, events).  NULL returns TDI_EINVAL. */
 tdi_status tdi_plan_destroy(tdi_plan* plan);
 
+/* Static, human-readable description of a status code. */
 const char* tdi_status_str(tdi_status s);
 
 #ifdef __cplusplus

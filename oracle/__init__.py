@@ -88,6 +88,8 @@ def lib():
                                       C.c_int64, _D, _D, C.c_int64, _I64, _D, _D, _D]
         L.orc_response_batch.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.c_int64,
                                          C.POINTER(Source), _I64, _D, _D, _D, _D, _D]
+        L.orc_response_batch_at.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.c_int64,
+                                            C.POINTER(Source), _I64, _D, _D, _I64, _I64, _D, _D, _D]
         L.orc_full_terms_absmax.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.POINTER(Source),
                                             C.c_int64, _D, _D, _D]
         L.orc_num_threads.restype = C.c_int
@@ -221,6 +223,26 @@ def response_batch(cfg: dict, orbit: dict, batch):
     c, o = make_config(cfg), make_orbit(orbit)
     lib().orc_response_batch(C.byref(c), C.byref(o), batch.n_sources, srcs,
                              offs.ctypes.data_as(_I64), _dp(hp), _dp(hc), _dp(X), _dp(Y), _dp(Z))
+    return np.stack([X, Y, Z])
+
+
+def response_batch_at(cfg: dict, orbit: dict, batch, ks_per_source):
+    """Sampled outputs of a batch: ks_per_source[i] lists sample indices of source i.
+    Returns (3, sum of lengths) in the concatenated order (OpenMP across sources)."""
+    hp, hc = _f64(batch.hp), _f64(batch.hc)
+    lens = [len(k) for k in ks_per_source]
+    koffs = np.zeros(len(lens) + 1, dtype=np.int64)
+    koffs[1:] = np.cumsum(lens)
+    ks = np.ascontiguousarray(np.concatenate([np.asarray(k, dtype=np.int64) for k in ks_per_source])
+                              if lens else np.zeros(0, dtype=np.int64))
+    m = int(koffs[-1])
+    X, Y, Z = np.zeros(m), np.zeros(m), np.zeros(m)
+    srcs = (Source * max(1, batch.n_sources))(*[make_source(r) for r in batch.sources])
+    offs = np.ascontiguousarray(batch.offsets, dtype=np.int64)
+    c, o = make_config(cfg), make_orbit(orbit)
+    lib().orc_response_batch_at(C.byref(c), C.byref(o), batch.n_sources, srcs, offs.ctypes.data_as(_I64),
+                                _dp(hp), _dp(hc), koffs.ctypes.data_as(_I64), ks.ctypes.data_as(_I64),
+                                _dp(X), _dp(Y), _dp(Z))
     return np.stack([X, Y, Z])
 
 

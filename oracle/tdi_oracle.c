@@ -585,3 +585,15 @@ void orc_full_terms_absmax(const orc_config* c, const orc_orbit* o, const orc_so
   }
   ctx_free(&x);
 }
+
+void orc_response_batch_at(const orc_config* c, const orc_orbit* o, int64_t n_sources,
+                           const orc_source* src, const int64_t* offsets, const double* hp,
+                           const double* hc, const int64_t* k_offsets, const int64_t* ks,
+                           double* X, double* Y, double* Z) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n_sources; ++i) {
+    int64_t a = offsets[i], b = offsets[i + 1];
+    int64_t ka = k_offsets[i], kb = k_offsets[i + 1];
+    orc_response_at(c, o, &src[i], b - a, hp + a, hc + a, kb - ka, ks + ka, X + ka, Y + ka, Z + ka);
+  }
+}

@@ -105,6 +105,14 @@ void orc_response_batch(const orc_config* c, const orc_orbit* o, int64_t n_sourc
                         const double* hp, const double* hc,
                         double* X, double* Y, double* Z);
 
+/* Sampled outputs of a batch: source i is evaluated at the k_offsets[i] ..
+ * k_offsets[i+1]-1 entries of ks (sample indices within the source); results
+ * are written at the same positions of X, Y, Z.  OpenMP across sources. */
+void orc_response_batch_at(const orc_config* c, const orc_orbit* o, int64_t n_sources,
+                           const orc_source* src, const int64_t* offsets, const double* hp,
+                           const double* hc, const int64_t* k_offsets, const int64_t* ks,
+                           double* X, double* Y, double* Z);
+
 /* Per-channel condition number: max_k sum_terms |term_k| / max_k |X_k|. */
 void orc_full_terms_absmax(const orc_config* c, const orc_orbit* o, const orc_source* s,
                            int64_t n, const double* hp, const double* hc,

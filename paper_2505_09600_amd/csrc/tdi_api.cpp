@@ -1,9 +1,9 @@
 // Host runtime and C ABI of the hybrid time-domain LISA response (include/tdi.h).
 //
 // Responsibilities: argument validation (host only, before any device work),
-// plan construction (device tables, launch shape, optional hipGraph), per-run
-// upload of the small source table, kernel launches and timing records.  No
-// response arithmetic runs here; it is all in tdi_kernels.hip.
+// plan construction (device parameter block, launch shape, optional hipGraph),
+// per-run upload of the small source table, kernel launches and timing
+// records.  No response arithmetic runs here; it is all in tdi_kernels.hip.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -13,7 +13,6 @@
 #include <string.h>
 
 #include <algorithm>
-#include <string>
 #include <vector>
 
 #include "../../include/tdi.h"
@@ -24,9 +23,15 @@ namespace {
 constexpr double kC = 299792458.0;
 constexpr int kEventRing = 256;
 
-struct Candidate {
-  int tile;
-  int grid;          // 0 = one workgroup per tile (non-persistent)
+struct Launch {
+  int grid_lfa;      // 0 = one workgroup per tile
+  int grid_full;
+};
+
+struct Caps {
+  int g, hl, hf, y;
+  size_t lds_lfa, lds_full;
+  int goff;
 };
 
 }  // namespace
@@ -35,32 +40,31 @@ struct tdi_plan {
   tdi_config cfg;
   tdi_orbit orb;
   int64_t max_sources, max_total;
-  int device;
-  int n_cu;
+  int device, n_cu;
   hipStream_t user_stream;
   hipStream_t graph_stream;      // private stream used for capture and replay
   // device memory
-  void* d_run;                   // RunDesc + SrcDev[max_sources]
-  size_t run_bytes;
+  tdi::KParams* d_params;        // KParams followed by SrcDev[max_sources]
+  size_t params_bytes;
   int32_t* d_err;
-  uint32_t* d_counter;
-  // pinned staging for the per-run table
-  void* h_run;
+  uint32_t* d_counters;
+  // pinned staging image of the parameter block
+  tdi::KParams* h_params;
   hipEvent_t staged_free;        // recorded after the upload of the previous run
+  hipEvent_t handoff;            // orders the private stream after the caller's
   bool staged_pending;
   // launch choice
-  Candidate cand;
+  Launch launch;
   bool tuned;
   // graph
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
-  size_t graph_lds;
-  int graph_grid, graph_tile;
-  // timing
-  hipEvent_t ev_start[kEventRing], ev_stop[kEventRing];
-  int ev_count;                  // runs recorded since last read (capped)
-  int ev_head;
-  tdi::KParams kp;               // constant part of the kernel parameters
+  Launch graph_launch;
+  size_t graph_lds_lfa, graph_lds_full;
+  // timing: per recorded run, events before the LFA kernel, between the two
+  // kernels and after the full kernel (graph replays: before and after the graph)
+  hipEvent_t ev[kEventRing][3];
+  int ev_count, ev_head;
 };
 
 extern "C" {
@@ -91,6 +95,8 @@ tdi_status tdi_check_config(const tdi_config* c, const tdi_orbit* o) {
   if (N != 4 && N != 8 && N != 16 && N != 32) return TDI_ERANGE;
   if (c->stencil_order != 2 && c->stencil_order != 4) return TDI_ERANGE;
   if (c->lfa_equal_arms != 0 && c->lfa_equal_arms != 1) return TDI_ERANGE;
+  if (c->autotune != 0 && c->autotune != 1) return TDI_ERANGE;
+  if (c->use_graph != 0 && c->use_graph != 1) return TDI_ERANGE;
   if (!(c->hyb_T_samples > 0.0) || !is_fin(c->hyb_T_samples)) return TDI_ERANGE;
   if (!(c->hyb_sigma_samples > 0.0) || !is_fin(c->hyb_sigma_samples)) return TDI_ERANGE;
   if (!(o->L_m > 0.0) || !is_fin(o->L_m)) return TDI_ERANGE;
@@ -124,76 +130,105 @@ tdi_status tdi_check_batch(const tdi_config* c, int64_t n_sources, const tdi_sou
 
 namespace {
 
-// Worst-case staged window lengths (samples) for a tile of 'tile' outputs at
-// sampling step dt; the kernel re-checks the actual windows per tile.
-void window_caps(const tdi_config& c, const tdi_orbit& o, int tile, double dt,
-                 int& cap_g, int& cap_h, int& cap_y) {
+double move_rate(const tdi_orbit& o) {
+  const double e = o.L_m / (2.0 * sqrt(3.0) * o.R_m);
+  return o.R_m * o.omega * (1.0 + 2.0 * e) / kC + 1e-12;   // bound of |k.V| / c
+}
+
+double light_time_bound(const tdi_orbit& o) {
+  return o.L_m / kC * (1.0 + 4.0 * move_rate(o)) + 1e-9;
+}
+
+double stage2_bound(const tdi_config& c, const tdi_orbit& o) {
+  return (c.tdi_gen == 20 ? 7.0 : 3.0) * light_time_bound(o);
+}
+
+// Worst-case staged window lengths (samples) at sampling step dt; the kernels
+// recompute the actual windows per tile and check them against these.
+Caps window_caps(const tdi_config& c, const tdi_orbit& o, double dt) {
+  Caps k;
   const int N = c.interp_taps;
   const double Lc = o.L_m / kC;
-  const double e = o.L_m / (2.0 * sqrt(3.0) * o.R_m);
-  const double rate = o.R_m * o.omega * (1.0 + 2.0 * e) / kC + 1e-12;  // |k.V| / c bound
-  const double Tmax = Lc * (1.0 + 4.0 * rate) + 1e-9;
+  const double rate = move_rate(o);
+  const double Tmax = light_time_bound(o);
   const double Tmin = Lc * (1.0 - 4.0 * rate) - 1e-9;
-  const int hw = c.stencil_order == 4 ? 3 : 2;
+  const int hw = (c.tdi_gen == 20) ? (c.stencil_order == 4 ? 3 : 2) : (c.stencil_order == 4 ? 2 : 1);
   auto margin = [](double cnt) { return 2 + (int)ceil(4e-4 * cnt); };
   // LFA: the six delays D_c + mu_l spread over half an arm plus arm differences
   const double mult = c.tdi_gen == 20 ? 2.0 : 1.0;
-  const double spread_l = 0.5 * Lc * 1.02 + 2.0 * mult * (Tmax - Tmin) + 2.0 * rate * tile * dt;
-  cap_g = tile + (int)ceil(spread_l / dt) + N + 2 * margin(tile) + 4;
-  const int h_lfa = cap_g + 2 * hw;
+  const double spread_l = 0.5 * Lc * 1.02 + 2.0 * mult * (Tmax - Tmin) + 2.0 * rate * tdi::kTileLfa * dt;
+  k.g = tdi::kTileLfa + (int)ceil(spread_l / dt) + N + 2 * margin(tdi::kTileLfa) + 4;
+  k.hl = k.g + 2 * hw;
   // full: stage-2 delays reach back (7 or 3) light times
-  const double D2 = (c.tdi_gen == 20 ? 7.0 : 3.0) * Tmax;
-  cap_y = tile + (int)ceil(D2 / dt) + N + 2 * margin(tile) + 4;
-  // stage-1 delays: light time plus spacecraft separations along k
-  const double spread_f = Tmax + Lc * 1.02 + 2.0 * rate * cap_y * dt;
-  const int h_full = cap_y + (int)ceil(spread_f / dt) + N + 2 * margin(cap_y) + 4;
-  cap_h = std::max(h_lfa, h_full);
+  k.y = tdi::kTileFull + (int)ceil(stage2_bound(c, o) / dt) + N + 2 * margin(tdi::kTileFull) + 4;
+  // stage-1 delays: light time plus spacecraft separations along k, plus drift
+  const double spread_f = Tmax + Lc * 1.02 + 2.0 * rate * k.y * dt;
+  k.hf = k.y + (int)ceil(spread_f / dt) + N + 2 * margin(k.y) + 4;
+  const int fp32 = c.precision == TDI_FP32_BULK;
+  k.lds_lfa = tdi::lfa_lds_bytes(N, k.g, k.hl, fp32, &k.goff);
+  k.lds_full = tdi::full_lds_bytes(k.hf, k.y, fp32);
+  return k;
 }
 
-hipError_t upload_and_launch(tdi_plan* p, hipStream_t st, size_t copy_bytes, size_t lds,
-                             const Candidate& cd, bool record_events) {
-  hipError_t e = hipMemcpyAsync(p->d_run, p->h_run, copy_bytes, hipMemcpyHostToDevice, st);
-  if (e != hipSuccess) return e;
-  if (tdi::launch_reset(p->d_counter, p->d_err, 0, st) != 0) return hipErrorLaunchFailure;
-  tdi::KParams kp = p->kp;
-  kp.tile = cd.tile;
-  kp.persistent = cd.grid > 0 ? 1 : 0;
-  const tdi::RunDesc* rd = reinterpret_cast<const tdi::RunDesc*>(p->h_run);
-  int grid = cd.grid > 0 ? cd.grid : (int)std::max<int64_t>(1, rd->n_tiles);
-  if (record_events) hipEventRecord(p->ev_start[p->ev_head], st);
-  if (tdi::launch_main(kp, p->cfg.interp_taps, p->cfg.precision, grid, lds, st) != 0)
-    return hipErrorLaunchFailure;
-  if (record_events) {
-    hipEventRecord(p->ev_stop[p->ev_head], st);
-    p->ev_head = (p->ev_head + 1) % kEventRing;
-    if (p->ev_count < kEventRing) p->ev_count++;
-  }
-  return hipSuccess;
-}
-
-// Fill the pinned run table for one batch; returns the number of tiles.
-int64_t stage_batch(tdi_plan* p, int tile, int64_t n_sources, const tdi_source* src,
-                    const int64_t* offsets, const double* hp, const double* hc, void* X, void* Y,
-                    void* Z, int caps[3]) {
-  tdi::RunDesc* rd = reinterpret_cast<tdi::RunDesc*>(p->h_run);
-  tdi::SrcDev* sd = reinterpret_cast<tdi::SrcDev*>(rd + 1);
-  int64_t tiles = 0;
+// Fill the pinned parameter image for one batch (work lists of both kernels).
+void stage_batch(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
+                 const double* hp, const double* hc, void* X, void* Y, void* Z, const Caps& caps,
+                 const Launch& ln) {
+  tdi::KParams* kp = p->h_params;
+  tdi::SrcDev* sd = reinterpret_cast<tdi::SrcDev*>(kp + 1);
+  const tdi_config& c = p->cfg;
+  int64_t tl = 0, tf = 0;
   for (int64_t i = 0; i < n_sources; ++i) {
     const tdi_source& s = src[i];
     tdi::SrcDev& d = sd[i];
     d.beta = s.beta; d.lam = s.lambda; d.psi = s.psi; d.t0 = s.t0; d.dt = s.dt; d.t_hyb = s.t_hyb;
     d.off = offsets[i];
     d.n = offsets[i + 1] - offsets[i];
-    d.tile0 = tiles;
-    d.pad = 0;
-    tiles += (d.n + tile - 1) / tile;
+    // sample ranges of the two kernels; the kernels apply the exact window
+    // predicates per sample, these ranges only need to contain them
+    int64_t lb = 0, le = 0, fb = 0, fe = 0;
+    if (c.mode == TDI_MODE_FULL) {
+      fe = d.n;
+    } else if (c.mode == TDI_MODE_LFA) {
+      le = d.n;
+    } else {
+      const double kH = (s.t_hyb - s.t0) / s.dt;
+      const double lhi = kH + 0.5 * c.hyb_T_samples;     // LFA where k - kH <= T/2
+      const double flo = kH - 0.5 * c.hyb_T_samples;     // full where k - kH >= -T/2
+      le = !(lhi < (double)d.n) ? d.n : (lhi < 0.0 ? 0 : std::min<int64_t>(d.n, (int64_t)floor(lhi) + 2));
+      fb = !(flo > 0.0) ? 0 : (flo >= (double)d.n ? d.n : std::max<int64_t>(0, (int64_t)ceil(flo) - 2));
+      fe = d.n;
+    }
+    d.lfa_kb = lb; d.lfa_ke = le; d.lfa_t0 = tl;
+    d.full_kb = fb; d.full_ke = fe; d.full_t0 = tf;
+    if (le > lb) tl += (le - lb + tdi::kTileLfa - 1) / tdi::kTileLfa;
+    if (fe > fb) tf += (fe - fb + tdi::kTileFull - 1) / tdi::kTileFull;
   }
-  rd->n_src = n_sources;
-  rd->n_tiles = tiles;
-  rd->hp = hp; rd->hc = hc; rd->X = X; rd->Y = Y; rd->Z = Z;
-  rd->cap_g = caps[0]; rd->cap_h = caps[1]; rd->cap_y = caps[2];
-  rd->pad = 0;
-  return tiles;
+  kp->n_src = n_sources;
+  kp->n_tiles_lfa = tl;
+  kp->n_tiles_full = tf;
+  kp->hp = hp; kp->hc = hc; kp->X = X; kp->Y = Y; kp->Z = Z;
+  kp->cap_g = caps.g; kp->cap_hl = caps.hl; kp->cap_hf = caps.hf; kp->cap_y = caps.y;
+  kp->lfa_goff = caps.goff;
+  kp->persistent = (ln.grid_lfa > 0 ? 1 : 0) | (ln.grid_full > 0 ? 2 : 0);
+}
+
+hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& caps, const Launch& ln,
+                   int64_t tiles_lfa, int64_t tiles_full, int ev_slot) {
+  hipError_t e = hipMemcpyAsync(p->d_params, p->h_params, copy_bytes, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  if (tdi::launch_reset(p->d_counters, st) != 0) return hipErrorLaunchFailure;
+  const int taps = p->cfg.interp_taps, fp32 = p->cfg.precision;
+  if (ev_slot >= 0) hipEventRecord(p->ev[ev_slot][0], st);
+  const int gl = ln.grid_lfa > 0 ? ln.grid_lfa : (int)std::max<int64_t>(0, tiles_lfa);
+  if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, gl, caps.lds_lfa, st) != 0)
+    return hipErrorLaunchFailure;
+  if (ev_slot >= 0) hipEventRecord(p->ev[ev_slot][1], st);
+  const int gf = ln.grid_full > 0 ? ln.grid_full : (int)std::max<int64_t>(0, tiles_full);
+  if (gf > 0 && tdi::launch_full(p->d_params, taps, fp32, gf, caps.lds_full, st) != 0)
+    return hipErrorLaunchFailure;
+  if (ev_slot >= 0) hipEventRecord(p->ev[ev_slot][2], st);
+  return hipSuccess;
 }
 
 void destroy_graph(tdi_plan* p) {
@@ -201,6 +236,130 @@ void destroy_graph(tdi_plan* p) {
   if (p->graph) hipGraphDestroy(p->graph);
   p->graph_exec = nullptr;
   p->graph = nullptr;
+}
+
+// Capture (upload of the whole parameter block, counter reset, both
+// persistent kernels) once; replays pick up new batches from the block.
+bool capture_graph(tdi_plan* p, const Caps& caps, const Launch& ln) {
+  destroy_graph(p);
+  if (hipStreamBeginCapture(p->graph_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
+  hipError_t e = enqueue(p, p->graph_stream, p->params_bytes, caps, ln, 0, 0, -1);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(p->graph_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess || !g) {
+    if (g) hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return false;
+  }
+  p->graph = g;
+  if (hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
+    destroy_graph(p);
+    (void)hipGetLastError();
+    return false;
+  }
+  p->graph_launch = ln;
+  p->graph_lds_lfa = caps.lds_lfa;
+  p->graph_lds_full = caps.lds_full;
+  return true;
+}
+
+void advance_ring(tdi_plan* p) {
+  p->ev_head = (p->ev_head + 1) % kEventRing;
+  if (p->ev_count < kEventRing) p->ev_count++;
+}
+
+tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_source* src,
+                    const int64_t* offsets, const double* hp, const double* hc, void* X, void* Y,
+                    void* Z, bool record, bool allow_graph) {
+  double dt_min = INFINITY;
+  for (int64_t i = 0; i < n_sources; ++i)
+    if (offsets[i + 1] > offsets[i]) dt_min = std::min(dt_min, src[i].dt);
+  if (!isfinite(dt_min)) return TDI_OK;
+  const Caps caps = window_caps(p->cfg, p->orb, dt_min);
+  if (caps.lds_lfa > 65536 || caps.lds_full > 65536) return TDI_ERANGE;
+
+  // the previous upload must have left the pinned image before it is rewritten
+  if (p->staged_pending) {
+    if (hipEventSynchronize(p->staged_free) != hipSuccess) return TDI_EDEVICE;
+    p->staged_pending = false;
+  }
+  stage_batch(p, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
+  const int64_t tl = p->h_params->n_tiles_lfa, tf = p->h_params->n_tiles_full;
+  const size_t copy_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)n_sources;
+  const int slot = p->ev_head;
+
+  const bool graph = allow_graph && p->cfg.use_graph && ln.grid_lfa > 0 && ln.grid_full > 0;
+  if (graph) {
+    if (!p->graph_exec || p->graph_launch.grid_lfa != ln.grid_lfa ||
+        p->graph_launch.grid_full != ln.grid_full || p->graph_lds_lfa != caps.lds_lfa ||
+        p->graph_lds_full != caps.lds_full) {
+      if (!capture_graph(p, caps, ln)) return TDI_EDEVICE;
+    }
+    // replay on the private stream, ordered after the caller's stream and back
+    if (hipEventRecord(p->handoff, p->user_stream) != hipSuccess) return TDI_EDEVICE;
+    if (hipStreamWaitEvent(p->graph_stream, p->handoff, 0) != hipSuccess) return TDI_EDEVICE;
+    if (record) hipEventRecord(p->ev[slot][0], p->graph_stream);
+    if (hipGraphLaunch(p->graph_exec, p->graph_stream) != hipSuccess) return TDI_EDEVICE;
+    if (record) {
+      hipEventRecord(p->ev[slot][1], p->graph_stream);
+      hipEventRecord(p->ev[slot][2], p->graph_stream);
+      advance_ring(p);
+    }
+    hipEventRecord(p->staged_free, p->graph_stream);
+    p->staged_pending = true;
+    if (hipStreamWaitEvent(p->user_stream, p->staged_free, 0) != hipSuccess) return TDI_EDEVICE;
+    return TDI_OK;
+  }
+  hipError_t e = enqueue(p, p->user_stream, copy_bytes, caps, ln, tl, tf, record ? slot : -1);
+  if (e != hipSuccess) return TDI_EDEVICE;
+  hipEventRecord(p->staged_free, p->user_stream);
+  p->staged_pending = true;
+  if (record) advance_ring(p);
+  return TDI_OK;
+}
+
+void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
+              const double* hp, const double* hc, void* X, void* Y, void* Z) {
+  double dt_min = INFINITY;
+  for (int64_t i = 0; i < n_sources; ++i)
+    if (offsets[i + 1] > offsets[i]) dt_min = std::min(dt_min, src[i].dt);
+  if (!isfinite(dt_min)) return;
+  const Caps caps = window_caps(p->cfg, p->orb, dt_min);
+  const int ol = tdi::occupancy_lfa(p->cfg.interp_taps, p->cfg.precision, caps.lds_lfa);
+  const int of = tdi::occupancy_full(p->cfg.interp_taps, p->cfg.precision, caps.lds_full);
+  std::vector<Launch> cands;
+  cands.push_back({ol * p->n_cu, of * p->n_cu});
+  cands.push_back({0, 0});
+  if (ol > 1) cands.push_back({(ol / 2) * p->n_cu, of * p->n_cu});
+  cands.push_back({2 * ol * p->n_cu, 2 * of * p->n_cu});
+  hipEvent_t a, b;
+  hipEventCreate(&a);
+  hipEventCreate(&b);
+  float best = INFINITY;
+  Launch best_l = cands[0];
+  for (const Launch& ln : cands) {
+    float ms_sum = 0.0f;
+    bool ok = true;
+    for (int rep = 0; rep < 3 && ok; ++rep) {
+      hipEventRecord(a, p->user_stream);
+      if (run_with(p, ln, n_sources, src, offsets, hp, hc, X, Y, Z, false, false) != TDI_OK) ok = false;
+      hipEventRecord(b, p->user_stream);
+      if (hipEventSynchronize(b) != hipSuccess) ok = false;
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, a, b);
+      if (rep > 0) ms_sum += ms;
+    }
+    if (ok && ms_sum < best) {
+      best = ms_sum;
+      best_l = ln;
+    }
+  }
+  hipEventDestroy(a);
+  hipEventDestroy(b);
+  // graph replay needs persistent launches
+  if (p->cfg.use_graph && (best_l.grid_lfa == 0 || best_l.grid_full == 0)) best_l = cands[0];
+  p->launch = best_l;
+  p->tuned = true;
 }
 
 }  // namespace
@@ -221,6 +380,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return TDI_EDEVICE;
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TDI_EDEVICE;
+  if (tdi::set_constants() != 0) return TDI_EDEVICE;
 
   tdi_plan* p = (tdi_plan*)calloc(1, sizeof(tdi_plan));
   if (!p) return TDI_ENOMEM;
@@ -231,31 +391,31 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   p->device = dev;
   p->n_cu = prop.multiProcessorCount;
   p->user_stream = (hipStream_t)hip_stream;
-  p->run_bytes = sizeof(tdi::RunDesc) + sizeof(tdi::SrcDev) * (size_t)max_sources;
-  bool ok = hipMalloc(&p->d_run, p->run_bytes) == hipSuccess;
+  p->params_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)max_sources;
+  bool ok = hipMalloc((void**)&p->d_params, p->params_bytes) == hipSuccess;
   ok = ok && hipMalloc((void**)&p->d_err, 64) == hipSuccess;
-  ok = ok && hipMalloc((void**)&p->d_counter, 64) == hipSuccess;
-  ok = ok && hipHostMalloc(&p->h_run, p->run_bytes, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipMalloc((void**)&p->d_counters, 64) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&p->h_params, p->params_bytes, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&p->staged_free, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&p->handoff, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&p->graph_stream, hipStreamNonBlocking) == hipSuccess;
-  for (int i = 0; ok && i < kEventRing; ++i) {
-    ok = hipEventCreate(&p->ev_start[i]) == hipSuccess && hipEventCreate(&p->ev_stop[i]) == hipSuccess;
-  }
+  for (int i = 0; ok && i < kEventRing; ++i)
+    for (int j = 0; ok && j < 3; ++j) ok = hipEventCreate(&p->ev[i][j]) == hipSuccess;
   if (!ok) {
     tdi_plan_destroy(p);
     return TDI_ENOMEM;
   }
-  hipMemset(p->d_err, 0, 64);
-  hipMemset(p->d_counter, 0, 64);
-  hipDeviceSynchronize();
+  if (hipMemset(p->d_err, 0, 64) != hipSuccess || hipMemset(p->d_counters, 0, 64) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    tdi_plan_destroy(p);
+    return TDI_EDEVICE;
+  }
+  memset(p->h_params, 0, p->params_bytes);
 
-  // constant kernel parameters
-  tdi::KParams& kp = p->kp;
-  memset(&kp, 0, sizeof(kp));
-  kp.rd = reinterpret_cast<const tdi::RunDesc*>(p->d_run);
-  kp.src = reinterpret_cast<const tdi::SrcDev*>(reinterpret_cast<const tdi::RunDesc*>(p->d_run) + 1);
-  kp.err_flag = p->d_err;
-  kp.counter = p->d_counter;
+  // constant part of the parameter block
+  tdi::KParams& kp = *p->h_params;
+  kp.err = p->d_err;
+  kp.counters = p->d_counters;
   tdi::OrbitDev& od = kp.orb;
   od.kind = orb->kind;
   od.L = orb->L_m;
@@ -265,7 +425,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   od.t_freeze = orb->t_freeze;
   od.e = orb->L_m / (2.0 * sqrt(3.0) * orb->R_m);
   for (int i = 0; i < 3; ++i) {
-    double b = 2.0 * M_PI * (double)i / 3.0 + orb->lambda0;
+    const double b = 2.0 * M_PI * (double)i / 3.0 + orb->lambda0;
     od.cb[i] = cos(b);
     od.sb[i] = sin(b);
   }
@@ -274,33 +434,19 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   kp.mode = cfg->mode;
   kp.equal_arms = cfg->lfa_equal_arms;
   kp.stencil_m = cfg->tdi_gen == 20 ? 3 : 2;
+  kp.stencil_p = cfg->stencil_order;
   kp.T_s = cfg->hyb_T_samples;
   kp.sigma_s = cfg->hyb_sigma_samples;
-  const int N = cfg->interp_taps;
-  for (int a = 0; a < N; ++a) {          // 1 / prod_{m != j} (j - m), nodes j = a - N/2 + 1
-    int j = a - N / 2 + 1;
-    double prod = 1.0;
-    for (int b = 0; b < N; ++b) {
-      int m = b - N / 2 + 1;
-      if (m != j) prod *= (double)(j - m);
-    }
-    kp.lag_c[a] = 1.0 / prod;
-  }
-  // central stencils of derivative order m (2 for TDI 1.5, 3 for TDI 2.0) and accuracy p
-  static const double s22[] = {1, -2, 1}, s24[] = {-1, 16, -30, 16, -1};
-  static const double s32[] = {-1, 2, 0, -2, 1}, s34[] = {1, -8, 13, 0, -13, 8, -1};
-  const double* num;
-  if (kp.stencil_m == 2) {
-    if (cfg->stencil_order == 2) { num = s22; kp.st_hw = 1; kp.st_den = 1.0; }
-    else { num = s24; kp.st_hw = 2; kp.st_den = 12.0; }
-  } else {
-    if (cfg->stencil_order == 2) { num = s32; kp.st_hw = 2; kp.st_den = 2.0; }
-    else { num = s34; kp.st_hw = 3; kp.st_den = 8.0; }
-  }
-  for (int s = 0; s < 2 * kp.st_hw + 1; ++s) kp.st_num[s] = num[s];
-  p->cand.tile = 256;
-  p->cand.grid = 0;
+  kp.D2_bound = stage2_bound(*cfg, *orb);
+
+  p->launch = {0, 0};
   p->tuned = cfg->autotune ? false : true;
+  if (!cfg->autotune && cfg->use_graph) {
+    // graph replay needs persistent launches: one full occupancy of the chip
+    const Caps caps = window_caps(*cfg, *orb, 1.0);
+    p->launch.grid_lfa = tdi::occupancy_lfa(cfg->interp_taps, cfg->precision, caps.lds_lfa) * p->n_cu;
+    p->launch.grid_full = tdi::occupancy_full(cfg->interp_taps, cfg->precision, caps.lds_full) * p->n_cu;
+  }
   *out = p;
   return TDI_OK;
 }
@@ -308,121 +454,20 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
 tdi_status tdi_plan_destroy(tdi_plan* p) {
   if (!p) return TDI_EINVAL;
   if (p->graph_stream) hipStreamSynchronize(p->graph_stream);
-  if (p->user_stream || true) hipStreamSynchronize(p->user_stream);
+  hipStreamSynchronize(p->user_stream);
   destroy_graph(p);
-  for (int i = 0; i < kEventRing; ++i) {
-    if (p->ev_start[i]) hipEventDestroy(p->ev_start[i]);
-    if (p->ev_stop[i]) hipEventDestroy(p->ev_stop[i]);
-  }
+  for (int i = 0; i < kEventRing; ++i)
+    for (int j = 0; j < 3; ++j)
+      if (p->ev[i][j]) hipEventDestroy(p->ev[i][j]);
   if (p->staged_free) hipEventDestroy(p->staged_free);
+  if (p->handoff) hipEventDestroy(p->handoff);
   if (p->graph_stream) hipStreamDestroy(p->graph_stream);
-  if (p->d_run) hipFree(p->d_run);
+  if (p->d_params) hipFree(p->d_params);
   if (p->d_err) hipFree(p->d_err);
-  if (p->d_counter) hipFree(p->d_counter);
-  if (p->h_run) hipHostFree(p->h_run);
+  if (p->d_counters) hipFree(p->d_counters);
+  if (p->h_params) hipHostFree(p->h_params);
   free(p);
   return TDI_OK;
-}
-
-static tdi_status run_with(tdi_plan* p, const Candidate& cd, int64_t n_sources,
-                           const tdi_source* src, const int64_t* offsets, const double* hp,
-                           const double* hc, void* X, void* Y, void* Z, bool record) {
-  double dt_min = INFINITY;
-  for (int64_t i = 0; i < n_sources; ++i)
-    if (offsets[i + 1] > offsets[i]) dt_min = std::min(dt_min, src[i].dt);
-  int caps[3] = {0, 0, 0};
-  if (isfinite(dt_min)) window_caps(p->cfg, p->orb, cd.tile, dt_min, caps[0], caps[1], caps[2]);
-  size_t lds = tdi::lds_bytes_for(cd.tile, caps[0], caps[1], caps[2], p->cfg.precision);
-  if (lds > (size_t)tdi::max_lds_bytes()) return TDI_ERANGE;
-
-  // the previous upload must have left the pinned buffer before it is rewritten
-  if (p->staged_pending) {
-    if (hipEventSynchronize(p->staged_free) != hipSuccess) return TDI_EDEVICE;
-    p->staged_pending = false;
-  }
-  int64_t tiles = stage_batch(p, cd.tile, n_sources, src, offsets, hp, hc, X, Y, Z, caps);
-  if (tiles == 0) return TDI_OK;
-  const size_t copy_bytes = sizeof(tdi::RunDesc) + sizeof(tdi::SrcDev) * (size_t)n_sources;
-
-  if (p->cfg.use_graph && cd.grid > 0) {
-    // replay a graph of (upload max table, reset, persistent kernel) on the
-    // private stream, ordered after the caller's stream and back
-    if (!p->graph_exec || p->graph_lds != lds || p->graph_grid != cd.grid || p->graph_tile != cd.tile) {
-      destroy_graph(p);
-      if (hipStreamBeginCapture(p->graph_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return TDI_EDEVICE;
-      hipError_t e = upload_and_launch(p, p->graph_stream, p->run_bytes, lds, cd, false);
-      hipGraph_t g = nullptr;
-      hipError_t e2 = hipStreamEndCapture(p->graph_stream, &g);
-      if (e != hipSuccess || e2 != hipSuccess || !g) {
-        if (g) hipGraphDestroy(g);
-        return TDI_EDEVICE;
-      }
-      p->graph = g;
-      if (hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
-        destroy_graph(p);
-        return TDI_EDEVICE;
-      }
-      p->graph_lds = lds;
-      p->graph_grid = cd.grid;
-      p->graph_tile = cd.tile;
-    }
-    hipEvent_t ev = p->ev_start[p->ev_head];
-    if (hipEventRecord(ev, p->user_stream) != hipSuccess) return TDI_EDEVICE;
-    if (hipStreamWaitEvent(p->graph_stream, ev, 0) != hipSuccess) return TDI_EDEVICE;
-    if (record) hipEventRecord(p->ev_start[p->ev_head], p->graph_stream);
-    if (hipGraphLaunch(p->graph_exec, p->graph_stream) != hipSuccess) return TDI_EDEVICE;
-    hipEventRecord(p->ev_stop[p->ev_head], p->graph_stream);
-    hipEventRecord(p->staged_free, p->graph_stream);
-    p->staged_pending = true;
-    if (hipStreamWaitEvent(p->user_stream, p->ev_stop[p->ev_head], 0) != hipSuccess) return TDI_EDEVICE;
-    if (record) {
-      p->ev_head = (p->ev_head + 1) % kEventRing;
-      if (p->ev_count < kEventRing) p->ev_count++;
-    }
-    return TDI_OK;
-  }
-  hipError_t e = upload_and_launch(p, p->user_stream, copy_bytes, lds, cd, record);
-  if (e != hipSuccess) return TDI_EDEVICE;
-  hipEventRecord(p->staged_free, p->user_stream);
-  p->staged_pending = true;
-  return TDI_OK;
-}
-
-static void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
-                     const double* hp, const double* hc, void* X, void* Y, void* Z) {
-  std::vector<Candidate> cands;
-  for (int tile : {256, 512}) {
-    cands.push_back({tile, 0});
-    for (int per_cu : {1, 2, 3, 4}) cands.push_back({tile, per_cu * p->n_cu});
-  }
-  hipEvent_t a, b;
-  hipEventCreate(&a);
-  hipEventCreate(&b);
-  float best = INFINITY;
-  Candidate best_c = p->cand;
-  for (const Candidate& cd : cands) {
-    float tsum = 0.0f;
-    bool ok = true;
-    for (int rep = 0; rep < 2 && ok; ++rep) {
-      hipEventRecord(a, p->user_stream);
-      Candidate c0 = cd;
-      bool ug = p->cfg.use_graph;
-      p->cfg.use_graph = 0;
-      tdi_status s = run_with(p, c0, n_sources, src, offsets, hp, hc, X, Y, Z, false);
-      p->cfg.use_graph = ug;
-      hipEventRecord(b, p->user_stream);
-      if (s != TDI_OK || hipEventSynchronize(b) != hipSuccess) { ok = false; break; }
-      float ms = 0.0f;
-      hipEventElapsedTime(&ms, a, b);
-      if (rep == 1) tsum += ms;
-    }
-    if (ok && tsum < best) { best = tsum; best_c = cd; }
-  }
-  hipEventDestroy(a);
-  hipEventDestroy(b);
-  p->cand = best_c;
-  p->tuned = true;
 }
 
 tdi_status tdi_run(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
@@ -432,16 +477,13 @@ tdi_status tdi_run(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   if (st != TDI_OK) return st;
   if (n_sources > p->max_sources || offsets[n_sources] > p->max_total) return TDI_ESTATE;
   const int64_t total = offsets[n_sources];
-  if (total > 0) {
-    if (!hp || !hc || !X || !Y || !Z) return TDI_EINVAL;
-    const uintptr_t al = p->cfg.precision == TDI_FP64 ? 8 : 4;
-    if (((uintptr_t)hp | (uintptr_t)hc) & 7) return TDI_EINVAL;
-    if ((((uintptr_t)X) | ((uintptr_t)Y) | ((uintptr_t)Z)) & (al - 1)) return TDI_EINVAL;
-  } else {
-    return TDI_OK;
-  }
+  if (total == 0) return TDI_OK;
+  if (!hp || !hc || !X || !Y || !Z) return TDI_EINVAL;
+  const uintptr_t al = p->cfg.precision == TDI_FP64 ? 8 : 4;
+  if (((uintptr_t)hp | (uintptr_t)hc) & 7) return TDI_EINVAL;
+  if ((((uintptr_t)X) | ((uintptr_t)Y) | ((uintptr_t)Z)) & (al - 1)) return TDI_EINVAL;
   if (!p->tuned) autotune(p, n_sources, src, offsets, hp, hc, X, Y, Z);
-  return run_with(p, p->cand, n_sources, src, offsets, hp, hc, X, Y, Z, true);
+  return run_with(p, p->launch, n_sources, src, offsets, hp, hc, X, Y, Z, true, true);
 }
 
 tdi_status tdi_plan_sync(tdi_plan* p) {
@@ -466,16 +508,19 @@ tdi_status tdi_plan_kernel_times(tdi_plan* p, float* ms, int32_t cap, int32_t* c
   *count = 0;
   if (hipStreamSynchronize(p->user_stream) != hipSuccess) return TDI_EDEVICE;
   if (hipStreamSynchronize(p->graph_stream) != hipSuccess) return TDI_EDEVICE;
-  int n = std::min<int>(p->ev_count, cap);
+  // two values per run: LFA kernel (graph replays: the whole graph), full kernel
+  const int runs = std::min<int>(p->ev_count, cap / 2);
   int first = (p->ev_head - p->ev_count + kEventRing) % kEventRing;
-  first = (first + (p->ev_count - n)) % kEventRing;
-  for (int i = 0; i < n; ++i) {
-    int slot = (first + i) % kEventRing;
-    float v = 0.0f;
-    if (hipEventElapsedTime(&v, p->ev_start[slot], p->ev_stop[slot]) != hipSuccess) return TDI_EDEVICE;
-    ms[i] = v;
+  first = (first + (p->ev_count - runs)) % kEventRing;
+  for (int i = 0; i < runs; ++i) {
+    const int slot = (first + i) % kEventRing;
+    float a = 0.0f, b = 0.0f;
+    if (hipEventElapsedTime(&a, p->ev[slot][0], p->ev[slot][1]) != hipSuccess) return TDI_EDEVICE;
+    if (hipEventElapsedTime(&b, p->ev[slot][1], p->ev[slot][2]) != hipSuccess) return TDI_EDEVICE;
+    ms[2 * i] = a;
+    ms[2 * i + 1] = b;
   }
-  *count = n;
+  *count = 2 * runs;
   p->ev_count = 0;
   return TDI_OK;
 }
@@ -483,9 +528,11 @@ tdi_status tdi_plan_kernel_times(tdi_plan* p, float* ms, int32_t cap, int32_t* c
 tdi_status tdi_plan_describe(const tdi_plan* p, char* buf, int32_t buflen) {
   if (!p || !buf || buflen < 1) return TDI_EINVAL;
   snprintf(buf, (size_t)buflen,
-           "{\"tile\": %d, \"grid\": %d, \"persistent\": %d, \"graph\": %d, \"cu\": %d, \"tuned\": %d}",
-           p->cand.tile, p->cand.grid, p->cand.grid > 0 ? 1 : 0,
-           (p->cfg.use_graph && p->cand.grid > 0) ? 1 : 0, p->n_cu, p->tuned ? 1 : 0);
+           "{\"tile_lfa\": %d, \"tile_full\": %d, \"grid_lfa\": %d, \"grid_full\": %d, "
+           "\"graph\": %d, \"cu\": %d, \"tuned\": %d}",
+           tdi::kTileLfa, tdi::kTileFull, p->launch.grid_lfa, p->launch.grid_full,
+           (p->cfg.use_graph && p->launch.grid_lfa > 0 && p->launch.grid_full > 0) ? 1 : 0, p->n_cu,
+           p->tuned ? 1 : 0);
   return TDI_OK;
 }
 

@@ -2,9 +2,17 @@
 // device kernels (tdi_kernels.hip).  Not part of the public ABI.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace tdi {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 waves of 64)
+constexpr int kNodes = 7;         // Chebyshev nodes of the per-tile geometry fit (degree 6)
+constexpr int kNQ = 27;           // fitted geometry quantities per tile
+constexpr int kTileLfa = 1024;    // outputs per LFA tile (4 waves x 256)
+constexpr int kTileFull = 256;    // outputs per full-response tile
+constexpr int kWaveOut = 256;     // LFA FP32: outputs per wave (4 per lane, stride 64)
 
 // Orbit constants prepared once per plan.
 struct OrbitDev {
@@ -16,52 +24,54 @@ struct OrbitDev {
   double L_over_c;
 };
 
-// Per-source record on the device.
+// Per-source record on the device, with the sample ranges and first global
+// tile of each kernel (LFA and full response).
 struct SrcDev {
   double beta, lam, psi, t0, dt, t_hyb;
   int64_t off;           // first sample in the flat arrays
   int64_t n;             // number of samples
-  int64_t tile0;         // first global tile of this source
-  int64_t pad;
+  int64_t lfa_t0, lfa_kb, lfa_ke;     // LFA tiles cover samples [kb, ke)
+  int64_t full_t0, full_kb, full_ke;  // full-response tiles cover samples [kb, ke)
 };
 
-constexpr int kMaxTaps = 32;
-constexpr int kBlock = 256;
-
-// Per-run values, uploaded with the source table in one copy so that a
-// captured graph can be replayed for new batches.  The SrcDev array follows.
-struct RunDesc {
+// Kernel parameters, resident in device memory (one upload per run), followed
+// by the SrcDev array.
+struct KParams {
+  // per run
   int64_t n_src;
-  int64_t n_tiles;
+  int64_t n_tiles_lfa, n_tiles_full;
   const double* hp;
   const double* hc;
   void* X;
   void* Y;
   void* Z;
-  int32_t cap_g, cap_h, cap_y;   // LDS capacities (samples) of the staged windows
-  int32_t pad;
+  int32_t cap_g, cap_hl;               // LFA window capacities (samples): derivative, strain
+  int32_t cap_hf, cap_y;               // full-response capacities: strain, link series
+  int32_t lfa_goff;                    // byte offset of the LFA derivative window in LDS
+  int32_t pad0;
+  // per plan
+  int32_t* err;          // window-check report (8 ints)
+  uint32_t* counters;    // persistent work counters: [0] LFA, [1] full
+  OrbitDev orb;
+  int32_t gen, mode, equal_arms, stencil_m, stencil_p, persistent;
+  double T_s, sigma_s;
+  double D2_bound;       // upper bound of a stage-2 delay (s)
 };
 
-struct KParams {
-  const RunDesc* rd;
-  const SrcDev* src;             // = (const SrcDev*)(rd + 1)
-  int32_t* err_flag;       // set to 1 when a retarded window check fails
-  uint32_t* counter;       // persistent work counter (reset before each run)
-  OrbitDev orb;
-  int32_t gen, mode, equal_arms, stencil_m;
-  double T_s, sigma_s;
-  double lag_c[kMaxTaps];  // Lagrange normalisation 1 / prod_{m != j} (j - m)
-  double st_num[7];        // LFA stencil numerators over offsets -hw..hw
-  double st_den;           // stencil denominator (times dt^m at run time)
-  int32_t st_hw;
-  int32_t tile;            // output samples per tile
-  int32_t persistent;      // 1: loop over tiles with the work counter
-};
+__host__ __device__ inline const SrcDev* sources_of(const KParams* p) {
+  return reinterpret_cast<const SrcDev*>(p + 1);
+}
 
 // Launch entry points (defined in tdi_kernels.hip).
-int launch_reset(uint32_t* counter, int32_t* err_flag, int reset_err, void* stream);
-int launch_main(const KParams& p, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
-size_t lds_bytes_for(int tile, int cap_g, int cap_h, int cap_y, int fp32);
-int max_lds_bytes();
+int set_constants();
+int launch_reset(uint32_t* counters, void* stream);
+int launch_lfa(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
+int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
+// LFA dynamic LDS: h window (FP64), reused for the FP32 wave tables, then the
+// derivative window; goff receives the byte offset of the latter.
+size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int* goff);
+size_t full_lds_bytes(int cap_h, int cap_y, int fp32);
+int occupancy_lfa(int taps, int fp32, size_t lds);
+int occupancy_full(int taps, int fp32, size_t lds);
 
 }  // namespace tdi

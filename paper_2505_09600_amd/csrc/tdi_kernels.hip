@@ -1,19 +1,28 @@
 // Device kernels of the hybrid time-domain LISA response for gfx950.
 //
-// One launch processes a batch of sources split into tiles of output samples.
-// A tile is handled by one 256-thread workgroup and, depending on the mode and
-// on where the tile sits relative to the hybrid window, runs
-//   * the LFA phase  : FP64 central stencil of the strain staged in LDS, then
-//                      six two-component fractional-delay reads per output
-//                      (App. B, Eqs. X15_nonequal_timedelays / X20_nonequal_timedelays
-//                      with the single-link LFA of Eq. yslr_strain_derivatives);
-//   * the full phase : stage 1 builds the six link series y_l on an LDS window
-//                      (Eq. yslr with Eq. H), stage 2 forms X, Y, Z from the
-//                      TDI term lists with arm delays evaluated at the output
-//                      time (Eqs. X1.5, X2.0);
-//   * the blend      : sigmoid weights of Eqs. (sigmoid, hybridized_xs).
-// Orbit geometry, retarded-time arguments and stencils are FP64; the compute
-// type TC of the interpolation and TDI arithmetic is double or float.
+// A batch of sources is cut into tiles of output samples; two persistent
+// kernels walk their tile lists with an atomic work counter:
+//
+//   k_lfa  : low-frequency approximation (Sec. III and App. B).  The strain is
+//            staged in LDS, an FP64 central stencil gives its 2nd (TDI 1.5) or
+//            3rd (TDI 2.0) derivative, and each output reads that series at six
+//            retarded times (two links per Michelson channel), Eqs.
+//            (X15_nonequal_timedelays, X20_nonequal_timedelays) with the
+//            single-link LFA of Eq. (yslr_strain_derivatives).
+//   k_full : full response.  Stage 1 builds the six link series y_l on an LDS
+//            window (Eqs. H, yslr, delta_s, delta_r); stage 2 forms X, Y, Z
+//            from the TDI term lists with every arm delay evaluated at the
+//            output time (Eqs. X1.5, X2.0).
+//
+// In the hybrid mode the LFA kernel writes w+ X^LFA inside the LFA window and
+// the full kernel, which runs after it, adds w- X^Full inside the full window
+// (Eqs. sigmoid, hybridized_xs).
+//
+// Geometry (orbits, light times, antenna patterns, delays) is evaluated
+// exactly in FP64 at seven Chebyshev nodes per tile and fitted by a degree-6
+// polynomial; over a tile (at most a few hours of orbit) the fit error is far
+// below FP64 rounding of the delays.  Retarded-time splits and stencils are
+// FP64.  The compute type TC of interpolation and TDI sums is double or float.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -25,160 +34,58 @@ namespace {
 
 constexpr double kC = 299792458.0;
 
-// Link slots +1,+2,+3,-1,-2,-3 -> sender / receiver spacecraft (0-based).
-// Link l joins the two spacecraft other than |l| with sgn(l) = eps_{s|l|r}.
-__constant__ int c_snd[6] = {2, 0, 1, 1, 2, 0};
-__constant__ int c_rcv[6] = {1, 2, 0, 2, 0, 1};
+__constant__ double c_vinv[kNodes][kNodes];   // monomial coefficients from node values
+__constant__ double c_snode[kNodes];          // Chebyshev nodes on [-1, 1]
 
-// TDI Michelson X terms: sign, link slot of y, number of delays, delay slots
-// (in the order written in Eqs. X1.5 and X2.0).  Y and Z: cyclic relabelling.
-struct Term { int sign, link, nd, d[7]; };
-__constant__ Term c_terms[16] = {
-    {+1, 5, 3, {4, 1, 2}},                  // y_{1-32}(t - L-2 - L2 - L3)
-    {-1, 5, 1, {2}},                        // y_{1-32}(t - L3)
-    {+1, 2, 2, {1, 4}},                     // y_{231}(t - L2 - L-2)
-    {-1, 2, 0, {0}},                        // y_{231}(t)
-    {+1, 1, 1, {4}},                        // y_{123}(t - L-2)
-    {-1, 1, 3, {4, 5, 2}},                  // y_{123}(t - L-2 - L-3 - L3)
-    {+1, 4, 0, {0}},                        // y_{3-21}(t)
-    {-1, 4, 2, {5, 2}},                     // y_{3-21}(t - L-3 - L3)
-    {+1, 5, 5, {4, 1, 2, 2, 5}},            // y_{1-32}(t - L-2 - L2 - 2L3 - L-3)
-    {-1, 5, 7, {2, 2, 5, 4, 4, 1, 1}},      // y_{1-32}(t - 2L3 - L-3 - 2L-2 - 2L2)
-    {+1, 2, 4, {4, 1, 2, 5}},               // y_{231}(t - L-2 - L2 - L3 - L-3)
-    {-1, 2, 6, {2, 5, 4, 4, 1, 1}},         // y_{231}(t - L3 - L-3 - 2L-2 - 2L2)
-    {+1, 1, 7, {4, 4, 1, 2, 2, 5, 5}},      // y_{123}(t - 2L-2 - L2 - 2L3 - 2L-3)
-    {-1, 1, 5, {2, 5, 4, 4, 1}},            // y_{123}(t - L3 - L-3 - 2L-2 - L2)
-    {+1, 4, 6, {4, 1, 2, 2, 5, 5}},         // y_{3-21}(t - L-2 - L2 - 2L3 - 2L-3)
-    {-1, 4, 4, {2, 5, 4, 1}},               // y_{3-21}(t - L3 - L-3 - L-2 - L2)
+// Link slots +1,+2,+3,-1,-2,-3: link l joins the two spacecraft other than |l|,
+// with sgn(l) = eps_{s|l|r} (Sec. II.B).  Spacecraft are 0-based here.
+__host__ __device__ constexpr int snd_of(int a) {
+  return a == 0 ? 2 : a == 1 ? 0 : a == 2 ? 1 : a == 3 ? 1 : a == 4 ? 2 : 0;
+}
+__host__ __device__ constexpr int rcv_of(int a) {
+  return a == 0 ? 1 : a == 1 ? 2 : a == 2 ? 0 : a == 3 ? 2 : a == 4 ? 0 : 1;
+}
+
+// Fitted quantity index: T_a (a = 0..5), xi+_a, xi_x_a, D_a = 2(1 - k.n_a), k.R_i/c.
+__host__ __device__ constexpr int qT(int a) { return a; }
+__host__ __device__ constexpr int qXp(int a) { return 6 + a; }
+__host__ __device__ constexpr int qXc(int a) { return 12 + a; }
+__host__ __device__ constexpr int qD(int a) { return 18 + a; }
+__host__ __device__ constexpr int qKR(int i) { return 24 + i; }
+
+// TDI Michelson X terms of Eqs. (X1.5) and (X2.0): sign, link slot of y and
+// the multiplicity of each light time (slot order) in the delay.  Y and Z
+// follow by cyclic relabelling of the spacecraft.
+__constant__ int c_tsign[16] = {+1, -1, +1, -1, +1, -1, +1, -1, +1, -1, +1, -1, +1, -1, +1, -1};
+__constant__ int c_tlink[16] = {5, 5, 2, 2, 1, 1, 4, 4, 5, 5, 2, 2, 1, 1, 4, 4};
+__constant__ int c_tcoef[16][6] = {
+    {0, 1, 1, 0, 1, 0},   // y_{1-32}(t - L-2 - L2 - L3)
+    {0, 0, 1, 0, 0, 0},   // y_{1-32}(t - L3)
+    {0, 1, 0, 0, 1, 0},   // y_{231}(t - L2 - L-2)
+    {0, 0, 0, 0, 0, 0},   // y_{231}(t)
+    {0, 0, 0, 0, 1, 0},   // y_{123}(t - L-2)
+    {0, 0, 1, 0, 1, 1},   // y_{123}(t - L-2 - L-3 - L3)
+    {0, 0, 0, 0, 0, 0},   // y_{3-21}(t)
+    {0, 0, 1, 0, 0, 1},   // y_{3-21}(t - L-3 - L3)
+    {0, 1, 2, 0, 1, 1},   // y_{1-32}(t - L-2 - L2 - 2L3 - L-3)
+    {0, 2, 2, 0, 2, 1},   // y_{1-32}(t - 2L3 - L-3 - 2L-2 - 2L2)
+    {0, 1, 1, 0, 1, 1},   // y_{231}(t - L-2 - L2 - L3 - L-3)
+    {0, 2, 1, 0, 2, 1},   // y_{231}(t - L3 - L-3 - 2L-2 - 2L2)
+    {0, 1, 2, 0, 2, 2},   // y_{123}(t - 2L-2 - L2 - 2L3 - 2L-3)
+    {0, 1, 1, 0, 2, 1},   // y_{123}(t - L3 - L-3 - 2L-2 - L2)
+    {0, 1, 2, 0, 1, 2},   // y_{3-21}(t - L-2 - L2 - 2L3 - 2L-3)
+    {0, 1, 1, 0, 1, 1},   // y_{3-21}(t - L3 - L-3 - L-2 - L2)
 };
 
-__device__ __forceinline__ int rot_slot(int slot, int c) {
-  return (slot % 3 + c) % 3 + (slot >= 3 ? 3 : 0);
-}
+// slot of link l relabelled c times (1->2->3->1), and its inverse
+__host__ __device__ constexpr int rot_slot(int slot, int c) { return (slot % 3 + c) % 3 + (slot >= 3 ? 3 : 0); }
+__host__ __device__ constexpr int unrot_slot(int slot, int c) { return (slot % 3 + 3 - c) % 3 + (slot >= 3 ? 3 : 0); }
 
-struct Triad { double k[3], u[3], v[3]; };
-
-__device__ __forceinline__ void triad_of(double beta, double lam, Triad& T) {
-  double sb, cb, sl, cl;
-  sincos(beta, &sb, &cb);
-  sincos(lam, &sl, &cl);
-  T.k[0] = -cb * cl; T.k[1] = -cb * sl; T.k[2] = -sb;
-  T.u[0] = sl;       T.u[1] = -cl;      T.u[2] = 0.0;
-  T.v[0] = -sb * cl; T.v[1] = -sb * sl; T.v[2] = cb;
-}
-
-__device__ __forceinline__ double dot3(const double* a, const double* b) {
-  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-}
-
-// Spacecraft i position given cos / sin of the orbital phase alpha.
-__device__ __forceinline__ void sc_pos(const OrbitDev& o, double ca, double sa, int i, double P[3]) {
-  double c2a = ca * ca - sa * sa, s2a = 2.0 * sa * ca;
-  double cb = o.cb[i], sb = o.sb[i];
-  double c2ab = c2a * cb + s2a * sb;      // cos(2 alpha - beta_i)
-  double s2ab = s2a * cb - c2a * sb;      // sin(2 alpha - beta_i)
-  double cab = ca * cb + sa * sb;         // cos(alpha - beta_i)
-  double eR = o.e * o.R;
-  P[0] = o.R * ca + 0.5 * eR * (c2ab - 3.0 * cb);
-  P[1] = o.R * sa + 0.5 * eR * (s2ab - 3.0 * sb);
-  P[2] = -1.7320508075688772 * eR * cab;
-}
-
-// Geometry of one link at a time whose orbital phase has cos/sin (ca, sa) and
-// spacecraft positions R: light time (sender at emission), photon direction,
-// antenna patterns, k.n and k.R of both ends.
-struct LinkGeo { double T, xp, xc, kn, kRs, kRr; };
-
-__device__ void link_geo(const OrbitDev& o, const Triad& tr, double ca, double sa,
-                         const double R[3][3], int slot, LinkGeo& g) {
-  const int s = c_snd[slot], r = c_rcv[slot];
-  double T = o.L_over_c;
-  double E[3] = {R[s][0], R[s][1], R[s][2]};
-  if (o.kind != 0) {
-    for (int it = 0; it < 12; ++it) {
-      double w = o.omega * T, w2 = w * w;
-      double sw = w * (1.0 - w2 * (1.0 / 6.0));
-      double cw = 1.0 - 0.5 * w2 + w2 * w2 * (1.0 / 24.0);
-      sc_pos(o, ca * cw + sa * sw, sa * cw - ca * sw, s, E);   // alpha - omega T
-      double d0 = R[r][0] - E[0], d1 = R[r][1] - E[1], d2 = R[r][2] - E[2];
-      double Tn = sqrt(d0 * d0 + d1 * d1 + d2 * d2) / kC;
-      double dT = Tn - T;
-      T = Tn;
-      if (fabs(dT) <= 4e-15) break;
-    }
-    double w = o.omega * T, w2 = w * w;
-    double sw = w * (1.0 - w2 * (1.0 / 6.0));
-    double cw = 1.0 - 0.5 * w2 + w2 * w2 * (1.0 / 24.0);
-    sc_pos(o, ca * cw + sa * sw, sa * cw - ca * sw, s, E);
-  }
-  double n[3];
-  double inv = 1.0 / (kC * T);
-  n[0] = (R[r][0] - E[0]) * inv;
-  n[1] = (R[r][1] - E[1]) * inv;
-  n[2] = (R[r][2] - E[2]) * inv;
-  double un = dot3(tr.u, n), vn = dot3(tr.v, n);
-  g.T = T;
-  g.xp = un * un - vn * vn;
-  g.xc = 2.0 * un * vn;
-  g.kn = dot3(tr.k, n);
-  g.kRs = dot3(tr.k, R[s]) / kC;
-  g.kRr = dot3(tr.k, R[r]) / kC;
-}
-
-__device__ __forceinline__ void orbit_phase(const OrbitDev& o, double t, double& ca, double& sa,
-                                            double R[3][3]) {
-  double a = o.omega * (o.kind == 0 ? o.t_freeze : t) + o.kappa0;
-  sincos(a, &sa, &ca);
-  for (int i = 0; i < 3; ++i) sc_pos(o, ca, sa, i, R[i]);
-}
-
-// Split of delay d (s) at sample k: read position k - d/dt = i0 + x, x in [0,1).
-__device__ __forceinline__ void split(int64_t k, double d, double dt, int64_t& i0, double& x) {
-  double q = d / dt;
-  double m = ceil(q);
-  i0 = k - (int64_t)m;
-  x = m - q;
-}
-
-// Lagrange weights on nodes j = -N/2+1 .. N/2 via prefix / suffix products.
-template <int N>
-__device__ __forceinline__ void lag_weights(double x, const double* __restrict__ cj, double w[N]) {
-  double pre[N];
-  pre[0] = 1.0;
-#pragma unroll
-  for (int j = 1; j < N; ++j) pre[j] = pre[j - 1] * (x - (double)(j - N / 2));
-  double suf = 1.0;
-#pragma unroll
-  for (int j = N - 1; j >= 0; --j) {
-    w[j] = cj[j] * pre[j] * suf;
-    suf *= (x - (double)(j + 1 - N / 2));
-  }
-}
-
-template <int N, typename TC>
-__device__ __forceinline__ TC dotw(const double w[N], const TC* __restrict__ b) {
-  TC acc = (TC)0;
-#pragma unroll
-  for (int j = 0; j < N; ++j) acc += (TC)w[j] * b[j];
-  return acc;
-}
+__host__ __device__ constexpr size_t align16(size_t v) { return (v + 15) & ~(size_t)15; }
 
 // ---------------------------------------------------------------------------
-// LDS layout
+// Small helpers
 // ---------------------------------------------------------------------------
-struct TileHdr {
-  int64_t w0;        // first sample index of the staged h window
-  int64_t g0;        // first index of the g (LFA) or y (full) window
-  int32_t nh, ng;    // window lengths
-  int32_t bad;       // window does not fit
-  int32_t pad;
-  int64_t src;       // source index of the tile
-};
-
-__host__ __device__ __forceinline__ size_t align_up(size_t v) { return (v + 15) & ~size_t(15); }
-
-// Record a failed window check: err[0] |= code; the first failure also stores
-// (code, sample index, offset, window length) in err[2..5].
 __device__ __forceinline__ void report(int32_t* err, int code, int64_t k, int64_t b, int64_t len) {
   atomicOr(err, code);
   if (atomicCAS(err + 1, 0, 1) == 0) {
@@ -189,470 +96,1012 @@ __device__ __forceinline__ void report(int32_t* err, int code, int64_t k, int64_
   }
 }
 
-// ---------------------------------------------------------------------------
-// LFA phase: outputs k0 .. k0+cnt-1.  acc == nullptr: write results; else add
-// w+ X^LFA into acc (double[3][tile]) for samples inside the LFA window.
-// ---------------------------------------------------------------------------
-template <int N, typename TC>
-__device__ void lfa_phase(const KParams& P, const RunDesc& RD, const SrcDev& S, const Triad& tr, int64_t k0, int cnt,
-                          char* region, TileHdr* hdr, double* acc, double kH) {
-  const int tid = threadIdx.x;
-  const double dt = S.dt;
-  const double Lc = P.orb.L_over_c;
-  const int hw = P.st_hw;
-  double* hwin_p = reinterpret_cast<double*>(region);
-  double* hwin_c = hwin_p + RD.cap_h;
-  TC* gwin_p = reinterpret_cast<TC*>(region + align_up(2 * sizeof(double) * (size_t)RD.cap_h));
-  TC* gwin_c = gwin_p + RD.cap_g;
+// Make LDS writes of the wave visible to all its lanes.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-  // Window of the derivative series from the delays at both ends of the tile.
-  __shared__ double s_qext[2][2];
-  if (tid < 2) {
-    int64_t k = tid == 0 ? k0 : k0 + cnt - 1;
-    double ca, sa, R[3][3];
-    orbit_phase(P.orb, S.t0 + (double)k * dt, ca, sa, R);
-    LinkGeo g[3];
-    for (int a = 0; a < 3; ++a) link_geo(P.orb, tr, ca, sa, R, a, g[a]);
-    double qmin = 1e300, qmax = -1e300;
-    for (int c = 0; c < 3; ++c) {
-      int la = (c + 1) % 3, lb = (c + 2) % 3;
-      double Ta = P.equal_arms ? Lc : g[la].T, Tb = P.equal_arms ? Lc : g[lb].T;
-      double D = (P.gen == 20) ? 2.0 * (Ta + Tb) : (Ta + Tb);
-      double da = D + 0.5 * (g[la].kRs + g[la].kRr), db = D + 0.5 * (g[lb].kRs + g[lb].kRr);
-      qmin = fmin(qmin, fmin(da, db) / dt);
-      qmax = fmax(qmax, fmax(da, db) / dt);
-    }
-    s_qext[tid][0] = qmin;
-    s_qext[tid][1] = qmax;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double qmin = fmin(s_qext[0][0], s_qext[1][0]), qmax = fmax(s_qext[0][1], s_qext[1][1]);
-    int margin = 2 + (int)ceil(4e-4 * (double)cnt);
-    int64_t g0 = k0 - (int64_t)ceil(qmax) - N / 2 + 1 - margin;
-    int64_t g1 = k0 + cnt - 1 - (int64_t)floor(qmin) + N / 2 + margin;
-    int64_t ng = g1 - g0 + 1, nh = ng + 2 * hw;
-    hdr->g0 = g0;
-    hdr->w0 = g0 - hw;
-    hdr->ng = (int32_t)ng;
-    hdr->nh = (int32_t)nh;
-    hdr->bad = (ng > RD.cap_g || nh > RD.cap_h) ? 1 : 0;
-  }
-  __syncthreads();
-  const int64_t w0 = hdr->w0, g0 = hdr->g0;
-  const int nh = hdr->nh, ng = hdr->ng;
-  const bool bad = hdr->bad != 0;
-  if (!bad) {
-    // stage raw h (zero outside the series)
-    for (int i = tid; i < nh; i += kBlock) {
-      int64_t j = w0 + i;
-      bool in = (j >= 0 && j < S.n);
-      hwin_p[i] = in ? RD.hp[S.off + j] : 0.0;
-      hwin_c[i] = in ? RD.hc[S.off + j] : 0.0;
-    }
-    __syncthreads();
-    // FP64 central stencil, divided by den * dt^m; zero outside the series
-    double scale = P.st_den;
-    for (int q = 0; q < P.stencil_m; ++q) scale *= dt;
-    for (int i = tid; i < ng; i += kBlock) {
-      int64_t j = g0 + i;
-      double ap = 0.0, ac = 0.0;
-      if (j >= 0 && j < S.n) {
-        for (int s = 0; s < 2 * hw + 1; ++s) {
-          ap += P.st_num[s] * hwin_p[i + s];
-          ac += P.st_num[s] * hwin_c[i + s];
-        }
-        ap /= scale;
-        ac /= scale;
-      }
-      gwin_p[i] = (TC)ap;
-      gwin_c[i] = (TC)ac;
-    }
-  }
-  __syncthreads();
+// Lagrange normalisation 1 / prod_{m != j} (j - m) for nodes j = a - N/2 + 1.
+template <int N>
+__host__ __device__ constexpr double lag_norm(int a) {
+  double p = 1.0;
+  for (int b = 0; b < N; ++b)
+    if (b != a) p *= (double)(a - b);
+  return 1.0 / p;
+}
 
-  double c2, s2;
-  sincos(2.0 * S.psi, &s2, &c2);
-  const TC tc2 = (TC)c2, ts2 = (TC)s2;
-  for (int i = tid; i < cnt; i += kBlock) {
-    const int64_t k = k0 + i;
-    double outv[3];
-    const double rel = (double)k - kH;
-    const bool in_lfa = acc == nullptr || rel <= 0.5 * P.T_s;
-    if (!in_lfa) continue;
-    if (bad) {
-      outv[0] = outv[1] = outv[2] = __builtin_nan("");
-    } else {
-      double ca, sa, R[3][3];
-      orbit_phase(P.orb, S.t0 + (double)k * dt, ca, sa, R);
-      LinkGeo g[3];
-      for (int a = 0; a < 3; ++a) link_geo(P.orb, tr, ca, sa, R, a, g[a]);
-      for (int c = 0; c < 3; ++c) {
-        int lab[2] = {(c + 1) % 3, (c + 2) % 3};
-        double Ta = P.equal_arms ? Lc : g[lab[0]].T, Tb = P.equal_arms ? Lc : g[lab[1]].T;
-        double pref, D;
-        if (P.gen == 20) { pref = -4.0 * Ta * Tb * (Ta + Tb); D = 2.0 * (Ta + Tb); }
-        else { pref = -2.0 * Ta * Tb; D = Ta + Tb; }
-        TC xi[2];
-        bool ok = true;
-        for (int q = 0; q < 2; ++q) {
-          const LinkGeo& L = g[lab[q]];
-          int64_t i0; double x;
-          split(k, D + 0.5 * (L.kRs + L.kRr), dt, i0, x);
-          int64_t b = i0 - N / 2 + 1 - g0;
-          if (b < 0 || b + N > ng) { ok = false; report(P.err_flag, 2, k, b, ng); break; }
-          TC vp, vc;
-          if (x == 0.0) {
-            vp = gwin_p[b + N / 2 - 1];
-            vc = gwin_c[b + N / 2 - 1];
-          } else {
-            double w[N];
-            lag_weights<N>(x, P.lag_c, w);
-            vp = dotw<N, TC>(w, gwin_p + b);
-            vc = dotw<N, TC>(w, gwin_c + b);
-          }
-          TC sp = tc2 * vp - ts2 * vc;     // rotation by the polarisation angle
-          TC sc = ts2 * vp + tc2 * vc;
-          xi[q] = (TC)L.xp * sp + (TC)L.xc * sc;
-        }
-        outv[c] = ok ? (double)((TC)pref * (xi[0] - xi[1])) : __builtin_nan("");
-      }
-    }
-    if (acc == nullptr) {
-      const int64_t o = S.off + k;
-      if constexpr (sizeof(TC) == 8) {
-        ((double*)RD.X)[o] = outv[0]; ((double*)RD.Y)[o] = outv[1]; ((double*)RD.Z)[o] = outv[2];
-      } else {
-        ((float*)RD.X)[o] = (float)outv[0]; ((float*)RD.Y)[o] = (float)outv[1]; ((float*)RD.Z)[o] = (float)outv[2];
-      }
-    } else {
-      const double z = rel / P.sigma_s;
-      if constexpr (sizeof(TC) == 8) {
-        const double wp = 1.0 / (1.0 + exp(z));
-        for (int c = 0; c < 3; ++c) acc[c * P.tile + i] += wp * outv[c];
-      } else {
-        const float wp = 1.0f / (1.0f + expf((float)z));
-        for (int c = 0; c < 3; ++c) acc[c * P.tile + i] += (double)(wp * (float)outv[c]);
-      }
-    }
+// Lagrange weights on nodes j = -N/2+1 .. N/2 via prefix / suffix products.
+template <int N>
+__device__ __forceinline__ void lag_weights(double x, double w[N]) {
+  double pre[N];
+  pre[0] = 1.0;
+#pragma unroll
+  for (int j = 1; j < N; ++j) pre[j] = pre[j - 1] * (x - (double)(j - N / 2));
+  double suf = 1.0;
+#pragma unroll
+  for (int j = N - 1; j >= 0; --j) {
+    w[j] = lag_norm<N>(j) * pre[j] * suf;
+    suf *= (x - (double)(j + 1 - N / 2));
   }
-  if (bad && tid == 0) report(P.err_flag, 1, k0, ng, nh);
+}
+
+// Lagrange interpolation of NC interleaved series (element j*NC + c) at offset
+// x from the node block starting at b: prefix products forward, suffix products
+// and accumulation backward, so only the N prefix values are live.
+template <int N, int NC, typename TC>
+__device__ __forceinline__ void lag_interp(double x, const TC* __restrict__ b, TC out[NC]) {
+  double pre[N];
+  pre[0] = 1.0;
+#pragma unroll
+  for (int j = 1; j < N; ++j) pre[j] = pre[j - 1] * (x - (double)(j - N / 2));
+  double suf = 1.0;
+  TC acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = (TC)0;
+#pragma unroll
+  for (int j = N - 1; j >= 0; --j) {
+    const TC w = (TC)(lag_norm<N>(j) * pre[j] * suf);
+    suf *= (x - (double)(j + 1 - N / 2));
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += w * b[j * NC + c];
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[c] = acc[c];
+}
+
+__device__ __forceinline__ double sel3(double a0, double a1, double a2, int i) {
+  return i == 0 ? a0 : (i == 1 ? a1 : a2);
+}
+
+// Split of delay d (s) at sample k: read position k - d/dt = i0 + x, x in [0, 1).
+__device__ __forceinline__ void split(int64_t k, double d, double dt, int64_t& i0, double& x) {
+  const double q = d / dt;
+  const double m = ceil(q);
+  i0 = k - (int64_t)m;
+  x = m - q;
+}
+
+// Central stencil numerators (offsets -hw..hw, zero padded to 7), half widths
+// and denominators, indexed by 2 * (m == 3) + (p == 4).
+__constant__ double c_stnum[4][7] = {
+    {1, -2, 1, 0, 0, 0, 0},           // m = 2, p = 2
+    {-1, 16, -30, 16, -1, 0, 0},      // m = 2, p = 4
+    {-1, 2, 0, -2, 1, 0, 0},          // m = 3, p = 2
+    {1, -8, 13, 0, -13, 8, -1},       // m = 3, p = 4
+};
+__constant__ int c_sthw[4] = {1, 2, 2, 3};
+__constant__ double c_stden[4] = {1.0, 12.0, 2.0, 8.0};
+
+// Central stencil numerators (offsets -hw..hw) and denominators.
+__host__ __device__ __forceinline__ void stencil_coeffs(int m, int p, double c[7], int& hw, double& den) {
+  for (int s = 0; s < 7; ++s) c[s] = 0.0;
+  if (m == 2 && p == 2) { hw = 1; den = 1.0; c[0] = 1; c[1] = -2; c[2] = 1; }
+  else if (m == 2) { hw = 2; den = 12.0; c[0] = -1; c[1] = 16; c[2] = -30; c[3] = 16; c[4] = -1; }
+  else if (p == 2) { hw = 2; den = 2.0; c[0] = -1; c[1] = 2; c[2] = 0; c[3] = -2; c[4] = 1; }
+  else { hw = 3; den = 8.0; c[0] = 1; c[1] = -8; c[2] = 13; c[3] = 0; c[4] = -13; c[5] = 8; c[6] = -1; }
 }
 
 // ---------------------------------------------------------------------------
-// Full phase: stage 1 (link series on an LDS window) then stage 2 (TDI).
+// Orbit geometry (exact, FP64)
 // ---------------------------------------------------------------------------
-template <int N, typename TC>
-__device__ void full_phase(const KParams& P, const RunDesc& RD, const SrcDev& S, const Triad& tr, int64_t k0, int cnt,
-                           char* region, TileHdr* hdr, double* acc, double kH) {
-  const int tid = threadIdx.x;
-  const double dt = S.dt;
-  const int ny6 = RD.cap_y;
-  TC* hwin_p = reinterpret_cast<TC*>(region);
-  TC* hwin_c = hwin_p + RD.cap_h;
-  TC* ywin = reinterpret_cast<TC*>(region + align_up(2 * sizeof(TC) * (size_t)RD.cap_h));
-  double* Tcache = reinterpret_cast<double*>(
-      region + align_up(2 * sizeof(TC) * (size_t)RD.cap_h) + align_up(6 * sizeof(TC) * (size_t)ny6));
-
-  // y window from the longest stage-2 delay; h window from the stage-1 delays
-  // at both ends of the y window.
-  __shared__ double s_ext[4];
-  __shared__ int64_t s_y[2];
-  if (tid < 2) {
-    int64_t k = tid == 0 ? k0 : k0 + cnt - 1;
-    double ca, sa, R[3][3];
-    orbit_phase(P.orb, S.t0 + (double)k * dt, ca, sa, R);
-    double Tmax = 0.0;
-    for (int a = 0; a < 6; ++a) { LinkGeo g; link_geo(P.orb, tr, ca, sa, R, a, g); Tmax = fmax(Tmax, g.T); }
-    s_ext[tid] = Tmax;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double Tmax = fmax(s_ext[0], s_ext[1]);
-    int margin = 2 + (int)ceil(4e-4 * (double)cnt);
-    double Dmax = (P.gen == 20 ? 7.0 : 3.0) * Tmax;
-    s_y[0] = k0 - (int64_t)ceil(Dmax / dt) - N / 2 + 1 - margin;
-    s_y[1] = k0 + cnt - 1 + N / 2 + margin;
-  }
-  __syncthreads();
-  if (tid < 2) {
-    int64_t i = s_y[tid];
-    double ca, sa, R[3][3];
-    orbit_phase(P.orb, S.t0 + (double)i * dt, ca, sa, R);
-    double dmin = 1e300, dmax = -1e300;
-    for (int a = 0; a < 6; ++a) {
-      LinkGeo g;
-      link_geo(P.orb, tr, ca, sa, R, a, g);
-      dmin = fmin(dmin, fmin(g.T + g.kRs, g.kRr));
-      dmax = fmax(dmax, fmax(g.T + g.kRs, g.kRr));
-    }
-    s_ext[2 * tid] = dmin;
-    s_ext[2 * tid + 1] = dmax;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    double dmin = fmin(s_ext[0], s_ext[2]), dmax = fmax(s_ext[1], s_ext[3]);
-    int64_t y0 = s_y[0], y1 = s_y[1];
-    int margin = 2 + (int)ceil(4e-4 * (double)(y1 - y0 + 1));
-    int64_t w0 = y0 - (int64_t)ceil(dmax / dt) - N / 2 + 1 - margin;
-    int64_t w1 = y1 - (int64_t)floor(dmin / dt) + N / 2 + margin;
-    hdr->g0 = y0;
-    hdr->ng = (int32_t)(y1 - y0 + 1);
-    hdr->w0 = w0;
-    hdr->nh = (int32_t)(w1 - w0 + 1);
-    hdr->bad = (hdr->ng > RD.cap_y || hdr->nh > RD.cap_h) ? 1 : 0;
-  }
-  __syncthreads();
-  const int64_t w0 = hdr->w0, y0 = hdr->g0;
-  const int nh = hdr->nh, ny = hdr->ng;
-  const bool bad = hdr->bad != 0;
-
-  double c2, s2;
-  sincos(2.0 * S.psi, &s2, &c2);
-  if (!bad) {
-    for (int i = tid; i < nh; i += kBlock) {
-      int64_t j = w0 + i;
-      bool in = (j >= 0 && j < S.n);
-      hwin_p[i] = (TC)(in ? RD.hp[S.off + j] : 0.0);
-      hwin_c[i] = (TC)(in ? RD.hc[S.off + j] : 0.0);
-    }
-    __syncthreads();
-    // Stage 1: y_l[i] = [H_l(t_i - ds) - H_l(t_i - dr)] / (2 (1 - k.n)), zero
-    // outside the series.
-    const TC tc2 = (TC)c2, ts2 = (TC)s2;
-    for (int ii = tid; ii < ny; ii += kBlock) {
-      const int64_t i = y0 + ii;
-      TC yv[6] = {0, 0, 0, 0, 0, 0};
-      bool ok = true;
-      if (i >= 0 && i < S.n) {
-        double ca, sa, R[3][3];
-        orbit_phase(P.orb, S.t0 + (double)i * dt, ca, sa, R);
-        for (int a = 0; a < 6; ++a) {
-          LinkGeo g;
-          link_geo(P.orb, tr, ca, sa, R, a, g);
-          if (i >= k0 && i < k0 + cnt) Tcache[a * P.tile + (int)(i - k0)] = g.T;
-          TC H[2];
-          const double dd[2] = {g.T + g.kRs, g.kRr};
-          for (int q = 0; q < 2; ++q) {
-            int64_t i0; double x;
-            split(i, dd[q], dt, i0, x);
-            int64_t b = i0 - N / 2 + 1 - w0;
-            if (b < 0 || b + N > nh) { ok = false; H[q] = 0; report(P.err_flag, 8, i, b, nh); continue; }
-            TC vp, vc;
-            if (x == 0.0) {
-              vp = hwin_p[b + N / 2 - 1];
-              vc = hwin_c[b + N / 2 - 1];
-            } else {
-              double w[N];
-              lag_weights<N>(x, P.lag_c, w);
-              vp = dotw<N, TC>(w, hwin_p + b);
-              vc = dotw<N, TC>(w, hwin_c + b);
-            }
-            TC sp = tc2 * vp - ts2 * vc, sc = ts2 * vp + tc2 * vc;
-            H[q] = (TC)g.xp * sp + (TC)g.xc * sc;
-          }
-          yv[a] = (H[0] - H[1]) / (TC)(2.0 * (1.0 - g.kn));
-        }
-      }
-      if (!ok) {
-        for (int a = 0; a < 6; ++a) yv[a] = (TC)__builtin_nan("");
-      }
-      for (int a = 0; a < 6; ++a) ywin[a * ny6 + ii] = yv[a];
-    }
-    // outputs beyond the series end never enter stage 2; their light times
-    // are still needed when a tile extends past n (it does not: cnt <= n - k0)
-  }
-  __syncthreads();
-
-  // Stage 2: X, Y, Z from the term lists; every delay uses the light times at
-  // the output sample, summed in FP64 before the split.
-  const int nterms = P.gen == 20 ? 16 : 8;
-  for (int i = tid; i < cnt; i += kBlock) {
-    const int64_t k = k0 + i;
-    const double rel = (double)k - kH;
-    if (acc != nullptr && !(rel >= -0.5 * P.T_s)) continue;
-    double outv[3];
-    if (bad) {
-      outv[0] = outv[1] = outv[2] = __builtin_nan("");
-    } else {
-      double T6[6];
-      for (int a = 0; a < 6; ++a) T6[a] = Tcache[a * P.tile + i];
-      for (int a = 0; a < 6; ++a)
-        if (!(T6[a] > 0.0 && T6[a] < 1e3)) report(P.err_flag, 32, k, (int64_t)(a * 100000 + i), (int64_t)(cnt * 1000 + ny));
-      for (int c = 0; c < 3; ++c) {
-        TC sum = (TC)0;
-        for (int t = 0; t < nterms; ++t) {
-          const Term& tm = c_terms[t];
-          const int ls = rot_slot(tm.link, c);
-          const TC* ys = ywin + ls * ny6;
-          TC v;
-          if (tm.nd == 0) {
-            v = ys[k - y0];
-          } else {
-            double d = 0.0;
-            for (int q = 0; q < tm.nd; ++q) d += T6[rot_slot(tm.d[q], c)];
-            int64_t i0; double x;
-            split(k, d, dt, i0, x);
-            int64_t b = i0 - N / 2 + 1 - y0;
-            if (b < 0 || b + N > ny) { v = (TC)__builtin_nan(""); report(P.err_flag, 16, k, b, ny); }
-            else if (x == 0.0) v = ys[b + N / 2 - 1];
-            else {
-              double w[N];
-              lag_weights<N>(x, P.lag_c, w);
-              v = dotw<N, TC>(w, ys + b);
-            }
-          }
-          sum += tm.sign > 0 ? v : -v;
-        }
-        outv[c] = (double)sum;
-      }
-    }
-    if (acc == nullptr) {
-      const int64_t o = S.off + k;
-      if constexpr (sizeof(TC) == 8) {
-        ((double*)RD.X)[o] = outv[0]; ((double*)RD.Y)[o] = outv[1]; ((double*)RD.Z)[o] = outv[2];
-      } else {
-        ((float*)RD.X)[o] = (float)outv[0]; ((float*)RD.Y)[o] = (float)outv[1]; ((float*)RD.Z)[o] = (float)outv[2];
-      }
-    } else {
-      const double z = rel / P.sigma_s;
-      if constexpr (sizeof(TC) == 8) {
-        const double wm = 1.0 / (1.0 + exp(-z));
-        for (int c = 0; c < 3; ++c) acc[c * P.tile + i] += wm * outv[c];
-      } else {
-        const float wm = 1.0f / (1.0f + expf((float)-z));
-        for (int c = 0; c < 3; ++c) acc[c * P.tile + i] += (double)(wm * (float)outv[c]);
-      }
-    }
-  }
-  if (bad && tid == 0) report(P.err_flag, 4, k0, ny, nh);
+__device__ __forceinline__ void sc_pos(const OrbitDev& o, double ca, double sa, int i, double P[3]) {
+  const double c2a = ca * ca - sa * sa, s2a = 2.0 * sa * ca;
+  const double cb = o.cb[i], sb = o.sb[i];
+  const double c2ab = c2a * cb + s2a * sb;   // cos(2 alpha - beta_i)
+  const double s2ab = s2a * cb - c2a * sb;   // sin(2 alpha - beta_i)
+  const double cab = ca * cb + sa * sb;      // cos(alpha - beta_i)
+  const double eR = o.e * o.R;
+  P[0] = o.R * ca + 0.5 * eR * (c2ab - 3.0 * cb);
+  P[1] = o.R * sa + 0.5 * eR * (s2ab - 3.0 * sb);
+  P[2] = -1.7320508075688772 * eR * cab;
 }
 
-// ---------------------------------------------------------------------------
-// Tile driver
-// ---------------------------------------------------------------------------
-template <int N, typename TC>
-__device__ void do_tile(const KParams& P, const RunDesc& RD, int64_t tile, char* smem) {
-  TileHdr* hdr = reinterpret_cast<TileHdr*>(smem);
-  double* acc = reinterpret_cast<double*>(smem + align_up(sizeof(TileHdr)));
-  char* region = smem + align_up(sizeof(TileHdr)) + align_up(3 * sizeof(double) * (size_t)P.tile);
-  const int tid = threadIdx.x;
-  if (tid == 0) {
-    // last source whose first tile is <= tile (sources without samples own no tiles)
-    int64_t lo = 0, hi = RD.n_src - 1;
-    while (lo < hi) {
-      int64_t mid = (lo + hi + 1) >> 1;
-      if (P.src[mid].tile0 <= tile) lo = mid; else hi = mid - 1;
+// Geometry of link slot a at time t: T, xi+, xi_x, D = 2(1 - k.n) and k.R/c of
+// spacecraft a (meaningful for a < 3).  Light time: receiver at t, sender at
+// the emission time t - T (fixed point from L/c); n is the photon direction.
+__device__ void node_geometry(const OrbitDev& o, double beta, double lam, double t, int a,
+                                          double out[5]) {
+  double sb, cb, sl, cl;
+  sincos(beta, &sb, &cb);
+  sincos(lam, &sl, &cl);
+  const double k[3] = {-cb * cl, -cb * sl, -sb};
+  const double u[3] = {sl, -cl, 0.0};
+  const double v[3] = {-sb * cl, -sb * sl, cb};
+  double sa, ca;
+  sincos(o.omega * (o.kind == 0 ? o.t_freeze : t) + o.kappa0, &sa, &ca);
+  const int s = snd_of(a), r = rcv_of(a);
+  double Rr[3], E[3];
+  sc_pos(o, ca, sa, r, Rr);
+  sc_pos(o, ca, sa, s, E);
+  double T = o.L_over_c;
+  if (o.kind != 0) {
+    for (int it = 0; it < 12; ++it) {
+      const double w = o.omega * T, w2 = w * w;
+      const double sw = w * (1.0 - w2 * (1.0 / 6.0));
+      const double cw = 1.0 - 0.5 * w2 + w2 * w2 * (1.0 / 24.0);
+      sc_pos(o, ca * cw + sa * sw, sa * cw - ca * sw, s, E);   // phase alpha - omega T
+      const double d0 = Rr[0] - E[0], d1 = Rr[1] - E[1], d2 = Rr[2] - E[2];
+      const double Tn = sqrt(d0 * d0 + d1 * d1 + d2 * d2) / kC;
+      const double dT = Tn - T;
+      T = Tn;
+      if (fabs(dT) <= 4e-15) break;
     }
-    hdr->src = lo;
+    const double w = o.omega * T, w2 = w * w;
+    const double sw = w * (1.0 - w2 * (1.0 / 6.0));
+    const double cw = 1.0 - 0.5 * w2 + w2 * w2 * (1.0 / 24.0);
+    sc_pos(o, ca * cw + sa * sw, sa * cw - ca * sw, s, E);
+  }
+  const double inv = 1.0 / (kC * T);
+  const double n0 = (Rr[0] - E[0]) * inv, n1 = (Rr[1] - E[1]) * inv, n2 = (Rr[2] - E[2]) * inv;
+  const double un = u[0] * n0 + u[1] * n1 + u[2] * n2;
+  const double vn = v[0] * n0 + v[1] * n1 + v[2] * n2;
+  const double kn = k[0] * n0 + k[1] * n1 + k[2] * n2;
+  out[0] = T;
+  out[1] = un * un - vn * vn;
+  out[2] = 2.0 * un * vn;
+  out[3] = 2.0 * (1.0 - kn);
+  double Ra[3];
+  sc_pos(o, ca, sa, a < 3 ? a : 0, Ra);
+  out[4] = (k[0] * Ra[0] + k[1] * Ra[1] + k[2] * Ra[2]) / kC;
+}
+
+// Per-tile fit of the geometry over samples [ka, kb] of one source.
+struct GeoFit {
+  double coef[kNQ][kNodes];    // monomial coefficients in s = (k - kc) / kh
+  double vals[kNodes][kNQ];    // node values (scratch)
+  double kc, ikh;
+};
+
+__device__ __forceinline__ double geo_eval(const GeoFit& F, int q, double s) {
+  double v = F.coef[q][kNodes - 1];
+#pragma unroll
+  for (int m = kNodes - 2; m >= 0; --m) v = fma(v, s, F.coef[q][m]);
+  return v;
+}
+
+// Collective: all threads of the block must call.
+__device__ void fit_geometry(const KParams& P, const SrcDev& S, double ka, double kb, GeoFit& F) {
+  const int tid = threadIdx.x;
+  const double kc = 0.5 * (ka + kb);
+  const double kh = fmax(0.5 * (kb - ka), 0.5);
+  if (tid < kNodes * 6) {
+    const int j = tid / 6, a = tid % 6;
+    const double t = S.t0 + (kc + c_snode[j] * kh) * S.dt;
+    double g[5];
+    node_geometry(P.orb, S.beta, S.lam, t, a, g);
+    F.vals[j][qT(a)] = g[0];
+    F.vals[j][qXp(a)] = g[1];
+    F.vals[j][qXc(a)] = g[2];
+    F.vals[j][qD(a)] = g[3];
+    if (a < 3) F.vals[j][qKR(a)] = g[4];
+  }
+  if (tid == 0) {
+    F.kc = kc;
+    F.ikh = 1.0 / kh;
   }
   __syncthreads();
-  const SrcDev S = P.src[hdr->src];
-  const int64_t k0 = (tile - S.tile0) * (int64_t)P.tile;
-  const int cnt = (int)min((int64_t)P.tile, S.n - k0);
-  Triad tr;
-  triad_of(S.beta, S.lam, tr);
-
-  bool needL, needF;
-  double kH = 0.0;
-  if (P.mode == 0) { needL = false; needF = true; }
-  else if (P.mode == 1) { needL = true; needF = false; }
-  else {
-    kH = (S.t_hyb - S.t0) / S.dt;
-    needL = ((double)k0 - kH <= 0.5 * P.T_s);
-    needF = ((double)(k0 + cnt - 1) - kH >= -0.5 * P.T_s);
-  }
-  if (P.mode != 2) {
-    if (needL) lfa_phase<N, TC>(P, RD, S, tr, k0, cnt, region, hdr, nullptr, 0.0);
-    else full_phase<N, TC>(P, RD, S, tr, k0, cnt, region, hdr, nullptr, 0.0);
-  } else {
-    for (int i = tid; i < 3 * P.tile; i += kBlock) acc[i] = 0.0;
-    __syncthreads();
-    if (needL) lfa_phase<N, TC>(P, RD, S, tr, k0, cnt, region, hdr, acc, kH);
-    __syncthreads();
-    if (needF) full_phase<N, TC>(P, RD, S, tr, k0, cnt, region, hdr, acc, kH);
-    __syncthreads();
-    for (int i = tid; i < cnt; i += kBlock) {
-      const int64_t o = S.off + k0 + i;
-      if constexpr (sizeof(TC) == 8) {
-        ((double*)RD.X)[o] = acc[i]; ((double*)RD.Y)[o] = acc[P.tile + i]; ((double*)RD.Z)[o] = acc[2 * P.tile + i];
-      } else {
-        ((float*)RD.X)[o] = (float)acc[i]; ((float*)RD.Y)[o] = (float)acc[P.tile + i];
-        ((float*)RD.Z)[o] = (float)acc[2 * P.tile + i];
-      }
+  if (tid < kNQ * kNodes) {
+    const int q = tid / kNodes, m = tid % kNodes;
+    double c;
+    if (m == 0) {
+      c = F.vals[kNodes / 2][q];    // the centre node is s = 0
+    } else {
+      c = 0.0;
+      for (int j = 0; j < kNodes; ++j) c = fma(c_vinv[m][j], F.vals[j][q], c);
     }
+    F.coef[q][m] = c;
   }
   __syncthreads();
 }
 
-template <int N, typename TC>
-__global__ __launch_bounds__(kBlock) void k_response(KParams P) {
-  extern __shared__ __align__(16) char smem[];
-  __shared__ int64_t s_next;
-  const RunDesc RD = *P.rd;
+// Source of global tile t: last source whose first tile is <= t.
+__device__ __forceinline__ int64_t find_source(const SrcDev* S, int64_t n_src, int64_t t, bool lfa) {
+  int64_t lo = 0, hi = n_src - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    const int64_t t0 = lfa ? S[mid].lfa_t0 : S[mid].full_t0;
+    if (t0 <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Next tile of a persistent or one-shot launch (collective).
+__device__ __forceinline__ int64_t next_tile(const KParams& P, uint32_t* counter, int64_t n_tiles,
+                                             int64_t& iter, int64_t* s_slot) {
   if (!P.persistent) {
-    if ((int64_t)blockIdx.x < RD.n_tiles) do_tile<N, TC>(P, RD, (int64_t)blockIdx.x, smem);
+    const int64_t t = iter == 0 ? (int64_t)blockIdx.x : n_tiles;
+    ++iter;
+    return t;
+  }
+  if (threadIdx.x == 0) *s_slot = (int64_t)atomicAdd(counter, 1u);
+  __syncthreads();
+  const int64_t t = *s_slot;
+  __syncthreads();
+  return t;
+}
+
+// LFA per-channel structure: channel c uses links a = (c+1)%3 (sign +) and
+// b = (c+2)%3 (sign -); link slot l is used by channel (l+2)%3 as side a and by
+// channel (l+1)%3 as side b.
+__host__ __device__ constexpr int chan_of_use(int l, int side) { return side == 0 ? (l + 2) % 3 : (l + 1) % 3; }
+
+// Delay (s) of use (l, side) and its coefficients on the raw (+, x) derivative
+// series: X_c += sign * pref_c * [ (xi+ c2 + xi_x s2) g+ + (xi_x c2 - xi+ s2) g_x ].
+__device__ __forceinline__ void lfa_use(const KParams& P, const double T3[3], const double xp3[3],
+                                        const double xc3[3], const double mu3[3], int l, int side,
+                                        double c2, double s2, double& d, double& kp, double& kx) {
+  const int c = chan_of_use(l, side);
+  const int a = (c + 1) % 3, b = (c + 2) % 3;
+  const double Ta = P.equal_arms ? P.orb.L_over_c : T3[a];
+  const double Tb = P.equal_arms ? P.orb.L_over_c : T3[b];
+  double pref, D;
+  if (P.gen == 20) { pref = -4.0 * Ta * Tb * (Ta + Tb); D = 2.0 * (Ta + Tb); }
+  else { pref = -2.0 * Ta * Tb; D = Ta + Tb; }
+  d = D + mu3[l];
+  const double sg = side == 0 ? pref : -pref;
+  kp = sg * (xp3[l] * c2 + xc3[l] * s2);
+  kx = sg * (xc3[l] * c2 - xp3[l] * s2);
+}
+
+// Positive-link geometry at sample k from the fit.
+__device__ __forceinline__ void lfa_geo(const GeoFit& F, double s, double T3[3], double xp3[3],
+                                        double xc3[3], double mu3[3]) {
+  double kR[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) kR[i] = geo_eval(F, qKR(i), s);
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    T3[l] = geo_eval(F, qT(l), s);
+    xp3[l] = geo_eval(F, qXp(l), s);
+    xc3[l] = geo_eval(F, qXc(l), s);
+    mu3[l] = 0.5 * (kR[snd_of(l)] + kR[rcv_of(l)]);
+  }
+}
+
+template <typename TC>
+__device__ __forceinline__ void store3(const KParams& P, int64_t o, TC x, TC y, TC z) {
+  static_cast<TC*>(P.X)[o] = x;
+  static_cast<TC*>(P.Y)[o] = y;
+  static_cast<TC*>(P.Z)[o] = z;
+}
+
+// ---------------------------------------------------------------------------
+// LFA kernel
+// ---------------------------------------------------------------------------
+struct LfaShared {
+  GeoFit F;
+  int64_t src, k0, g0;
+  int32_t cnt, ng, bad, nh;
+  double c2, s2, inv_scale, kH;
+  double qext[2][2];
+};
+
+// Per wave, FP32 path: the expansion point of each link and quadratic models
+// (in r = k - centre of the wave) of the per-output offset and coefficients.
+struct WaveParams {
+  int64_t mbar[3];                    // integer part of the link's reference delay (samples)
+  float xbar[3];                      // fractional reference offset
+  float delta[6], a1[6], a2[6];       // eps_u(r) = delta - r (a1 + a2 r)
+  float kp0[6], kp1[6], kp2[6];       // coefficient on g+ : kp0 + r (kp1 + r kp2)
+  float kx0[6], kx1[6], kx2[6];
+  double vals[3][6][3];               // scratch: (point, use, {q, kp, kx})
+};
+
+constexpr size_t kWaveParamsBytes = align16(sizeof(WaveParams));
+
+template <int N>
+constexpr size_t wave_tables_bytes() {
+  return 4 * kWaveParamsBytes + (size_t)4 * 3 * N * 16;
+}
+
+template <int N, typename TC>
+__global__ __launch_bounds__(kBlock, 4) void k_lfa(const KParams* __restrict__ Pp) {
+  const KParams& P = *Pp;
+  const SrcDev* __restrict__ SS = sources_of(Pp);
+  __shared__ LfaShared sh;
+  __shared__ int64_t s_next;
+  extern __shared__ __align__(16) char dyn[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr bool kF32 = sizeof(TC) == 4;
+  double* hwin = reinterpret_cast<double*>(dyn);                 // [nh][2], FP64
+  TC* gwin = reinterpret_cast<TC*>(dyn + P.lfa_goff);           // [ng][2]
+  const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
+  const int hw = c_sthw[st];
+
+  int64_t iter = 0;
+  for (;;) {
+    const int64_t tile = next_tile(P, P.counters + 0, P.n_tiles_lfa, iter, &s_next);
+    if (tile >= P.n_tiles_lfa) break;
+    if (tid == 0) {
+      const int64_t s = find_source(SS, P.n_src, tile, true);
+      const SrcDev& S = SS[s];
+      sh.src = s;
+      sh.k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfa;
+      sh.cnt = (int32_t)min((int64_t)kTileLfa, S.lfa_ke - sh.k0);
+      double sn, cs;
+      sincos(2.0 * S.psi, &sn, &cs);
+      sh.c2 = cs;
+      sh.s2 = sn;
+      double sc = c_stden[st];
+      for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
+      sh.inv_scale = 1.0 / sc;
+      sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+    }
+    __syncthreads();
+    const SrcDev& S = SS[sh.src];
+    const int64_t k0 = sh.k0;
+    const int cnt = sh.cnt;
+    fit_geometry(P, S, (double)k0, (double)(k0 + cnt - 1), sh.F);
+
+    // window of the derivative series from the six delays at both tile ends
+    if (tid < 2) {
+      const int64_t k = tid == 0 ? k0 : k0 + cnt - 1;
+      const double s = ((double)k - sh.F.kc) * sh.F.ikh;
+      double T3[3], xp3[3], xc3[3], mu3[3];
+      lfa_geo(sh.F, s, T3, xp3, xc3, mu3);
+      double qmin = 1e300, qmax = -1e300;
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          double d, kp, kx;
+          lfa_use(P, T3, xp3, xc3, mu3, l, side, 0.0, 0.0, d, kp, kx);
+          qmin = fmin(qmin, d / S.dt);
+          qmax = fmax(qmax, d / S.dt);
+        }
+      sh.qext[tid][0] = qmin;
+      sh.qext[tid][1] = qmax;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double qmin = fmin(sh.qext[0][0], sh.qext[1][0]);
+      const double qmax = fmax(sh.qext[0][1], sh.qext[1][1]);
+      const int margin = 2 + (int)ceil(4e-4 * (double)cnt);
+      const int64_t g0 = k0 - (int64_t)ceil(qmax) - N / 2 + 1 - margin;
+      const int64_t g1 = k0 + cnt - 1 - (int64_t)floor(qmin) + N / 2 + margin;
+      sh.g0 = g0;
+      sh.ng = (int32_t)(g1 - g0 + 1);
+      sh.nh = sh.ng + 2 * hw;
+      sh.bad = (sh.ng > P.cap_g || sh.nh > P.cap_hl) ? 1 : 0;
+      if (sh.bad) report(P.err, 1, k0, sh.ng, sh.nh);
+    }
+    __syncthreads();
+    const int64_t g0 = sh.g0;
+    const int ng = sh.ng, nh = sh.nh;
+    const bool bad = sh.bad != 0;
+    const double kH = sh.kH;
+
+    if (!bad) {
+      const int64_t h0 = g0 - hw;
+      for (int i = tid; i < nh; i += kBlock) {
+        const int64_t j = h0 + i;
+        const bool in = j >= 0 && j < S.n;
+        hwin[2 * i] = in ? P.hp[S.off + j] : 0.0;
+        hwin[2 * i + 1] = in ? P.hc[S.off + j] : 0.0;
+      }
+      __syncthreads();
+      // unscaled central stencil sum; 1/(den dt^m) is folded into the coefficients
+      for (int i = tid; i < ng; i += kBlock) {
+        const int64_t j = g0 + i;
+        double ap = 0.0, ac = 0.0;
+        if (j >= 0 && j < S.n) {
+#pragma unroll
+          for (int s = 0; s < 7; ++s) {
+            if (s <= 2 * hw) {
+              ap = fma(c_stnum[st][s], hwin[2 * (i + s)], ap);
+              ac = fma(c_stnum[st][s], hwin[2 * (i + s) + 1], ac);
+            }
+          }
+        }
+        gwin[2 * i] = (TC)ap;
+        gwin[2 * i + 1] = (TC)ac;
+      }
+    }
+    __syncthreads();
+
+    if constexpr (kF32) {
+      // ------------------------------------------------------------------
+      // FP32 bulk: per wave of 256 consecutive outputs (4 per lane, stride
+      // 64) and per link, Lagrange weights at the wave's reference offset and
+      // a second-order expansion in the per-output offset (|eps| < 0.02).
+      // The wave tables reuse the (now free) h window.
+      // ------------------------------------------------------------------
+      WaveParams* wp = reinterpret_cast<WaveParams*>(dyn + wave * kWaveParamsBytes);
+      float4* wts = reinterpret_cast<float4*>(dyn + 4 * kWaveParamsBytes) + wave * 3 * N;
+      const int64_t kw0 = k0 + (int64_t)wave * kWaveOut;
+      const int wcnt = (int)max((int64_t)0, min((int64_t)kWaveOut, k0 + cnt - kw0));
+      // model points: first, middle and last output of the wave (inside the fit)
+      const double hr = 0.5 * (double)(wcnt - 1);
+      const double kw = (double)kw0 + hr;
+      if (!bad && wcnt > 0) {
+        if (lane < 3) {
+          const double r = (double)(lane - 1) * hr;
+          const double s = (kw + r - sh.F.kc) * sh.F.ikh;
+          double T3[3], xp3[3], xc3[3], mu3[3];
+          lfa_geo(sh.F, s, T3, xp3, xc3, mu3);
+#pragma unroll
+          for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+              double d, kp, kx;
+              lfa_use(P, T3, xp3, xc3, mu3, l, side, sh.c2, sh.s2, d, kp, kx);
+              const int u = 2 * l + side;
+              wp->vals[lane][u][0] = d / S.dt;
+              wp->vals[lane][u][1] = kp * sh.inv_scale;
+              wp->vals[lane][u][2] = kx * sh.inv_scale;
+            }
+        }
+        wave_sync();
+        if (lane < 18) {
+          const int u = lane / 3, qi = lane % 3;
+          const double v0 = wp->vals[0][u][qi], v1 = wp->vals[1][u][qi], v2 = wp->vals[2][u][qi];
+          const double c1 = hr > 0.0 ? (v2 - v0) / (2.0 * hr) : 0.0;
+          const double c2q = hr > 0.0 ? (v2 - 2.0 * v1 + v0) / (2.0 * hr * hr) : 0.0;
+          if (qi == 0) {
+            const int l = u / 2;
+            const double qbar = 0.5 * (wp->vals[1][2 * l][0] + wp->vals[1][2 * l + 1][0]);
+            const double mb = ceil(qbar);
+            wp->delta[u] = (float)(qbar - v1);
+            wp->a1[u] = (float)c1;
+            wp->a2[u] = (float)c2q;
+            if ((u & 1) == 0) {
+              wp->mbar[l] = (int64_t)mb;
+              wp->xbar[l] = (float)(mb - qbar);
+            }
+          } else if (qi == 1) {
+            wp->kp0[u] = (float)v1;
+            wp->kp1[u] = (float)c1;
+            wp->kp2[u] = (float)c2q;
+          } else {
+            wp->kx0[u] = (float)v1;
+            wp->kx1[u] = (float)c1;
+            wp->kx2[u] = (float)c2q;
+          }
+        }
+        wave_sync();
+        // weights l_j, l'_j, l''_j at xbar of each link; lanes cover (link, tap)
+        for (int e = lane; e < 3 * N; e += 64) {
+          const int l = e / N, a = e % N;
+          const double x = (double)wp->xbar[l];
+          double p = lag_norm<N>(a), p1 = 0.0, p2 = 0.0;
+          for (int b = 0; b < N; ++b) {
+            if (b == a) continue;
+            const double f = x - (double)(b - N / 2 + 1);
+            p2 = p2 * f + 2.0 * p1;
+            p1 = p1 * f + p;
+            p = p * f;
+          }
+          wts[l * N + a] = make_float4((float)p, (float)p1, (float)p2, 0.0f);
+        }
+        wave_sync();
+
+        float X0[4], X1[4], X2[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) X0[s4] = X1[s4] = X2[s4] = 0.0f;
+        const float2* g2 = reinterpret_cast<const float2*>(gwin);
+        bool okall = true;
+#pragma unroll 1
+        for (int l = 0; l < 3; ++l) {
+          const int64_t mb = wp->mbar[l];
+          int base[4];
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            const int64_t k = kw0 + lane + 64 * s4;
+            const int64_t b = k - mb - N / 2 + 1 - g0;
+            const bool live = (lane + 64 * s4) < wcnt;
+            const bool inwin = b >= 0 && b + N <= ng;
+            if (live && !inwin) { okall = false; report(P.err, 2, k, b, ng); }
+            base[s4] = inwin ? (int)b : 0;
+          }
+          float A[4][2], B[4][2], Cc[4][2];
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            A[s4][0] = A[s4][1] = B[s4][0] = B[s4][1] = Cc[s4][0] = Cc[s4][1] = 0.0f;
+          }
+          const float4* wl = wts + l * N;
+#pragma unroll 2
+          for (int j = 0; j < N; ++j) {
+            const float4 w = wl[j];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const float2 g = g2[base[s4] + j];
+              A[s4][0] = fmaf(w.x, g.x, A[s4][0]);
+              A[s4][1] = fmaf(w.x, g.y, A[s4][1]);
+              B[s4][0] = fmaf(w.y, g.x, B[s4][0]);
+              B[s4][1] = fmaf(w.y, g.y, B[s4][1]);
+              Cc[s4][0] = fmaf(w.z, g.x, Cc[s4][0]);
+              Cc[s4][1] = fmaf(w.z, g.y, Cc[s4][1]);
+            }
+          }
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int u = 2 * l + side;
+            const int c = side == 0 ? (l + 2) % 3 : (l + 1) % 3;
+            const float dl = wp->delta[u], a1 = wp->a1[u], a2 = wp->a2[u];
+            const float p0 = wp->kp0[u], p1 = wp->kp1[u], p2 = wp->kp2[u];
+            const float x0 = wp->kx0[u], x1 = wp->kx1[u], x2 = wp->kx2[u];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+              const float r = (float)(lane + 64 * s4) - (float)hr;
+              const float eps = dl - r * fmaf(a2, r, a1);
+              const float hh = 0.5f * eps;
+              const float Ip = fmaf(eps, fmaf(hh, Cc[s4][0], B[s4][0]), A[s4][0]);
+              const float Ix = fmaf(eps, fmaf(hh, Cc[s4][1], B[s4][1]), A[s4][1]);
+              const float kp = fmaf(r, fmaf(r, p2, p1), p0);
+              const float kx = fmaf(r, fmaf(r, x2, x1), x0);
+              const float v = fmaf(kp, Ip, kx * Ix);
+              if (c == 0) X0[s4] += v;
+              else if (c == 1) X1[s4] += v;
+              else X2[s4] += v;
+            }
+          }
+        }
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          const int i = lane + 64 * s4;
+          if (i >= wcnt) continue;
+          const int64_t k = kw0 + i;
+          float x = X0[s4], y = X1[s4], z = X2[s4];
+          if (!okall) x = y = z = __builtin_nanf("");
+          if (P.mode == 2) {
+            const double rel = (double)k - kH;
+            if (rel <= 0.5 * P.T_s) {
+              const double zz = rel / P.sigma_s;
+              if (zz > -17.0) {       // below, 1/(1+e^z) rounds to 1 in FP32
+                const float w = 1.0f / (1.0f + expf((float)zz));
+                x *= w; y *= w; z *= w;
+              }
+            } else {
+              x = y = z = 0.0f;
+            }
+          }
+          store3<float>(P, S.off + k, x, y, z);
+        }
+      }
+      if (bad) {
+        for (int i = tid; i < cnt; i += kBlock)
+          store3<float>(P, S.off + k0 + i, __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+      }
+    } else {
+      // ------------------------------------------------------------------
+      // FP64: exact per-output Lagrange weights for each of the six reads.
+      // ------------------------------------------------------------------
+      for (int i = tid; i < cnt; i += kBlock) {
+        const int64_t k = k0 + i;
+        double out[3] = {0.0, 0.0, 0.0};
+        if (bad) {
+          out[0] = out[1] = out[2] = __builtin_nan("");
+        } else {
+          const double s = ((double)k - sh.F.kc) * sh.F.ikh;
+          double T3[3], xp3[3], xc3[3], mu3[3];
+          lfa_geo(sh.F, s, T3, xp3, xc3, mu3);
+          double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+#pragma unroll 1
+          for (int u = 0; u < 6; ++u) {
+            const int l = u >> 1, side = u & 1;
+            const int c = side == 0 ? (l + 2) % 3 : (l + 1) % 3;
+            const int a = (c + 1) % 3, bb = (c + 2) % 3;
+            const double Ta = P.equal_arms ? P.orb.L_over_c : sel3(T3[0], T3[1], T3[2], a);
+            const double Tb = P.equal_arms ? P.orb.L_over_c : sel3(T3[0], T3[1], T3[2], bb);
+            double pref, D;
+            if (P.gen == 20) { pref = -4.0 * Ta * Tb * (Ta + Tb); D = 2.0 * (Ta + Tb); }
+            else { pref = -2.0 * Ta * Tb; D = Ta + Tb; }
+            int64_t i0;
+            double x;
+            split(k, D + sel3(mu3[0], mu3[1], mu3[2], l), S.dt, i0, x);
+            const int64_t b = i0 - N / 2 + 1 - g0;
+            double v[2];
+            if (b < 0 || b + N > ng) {
+              report(P.err, 2, k, b, ng);
+              v[0] = v[1] = __builtin_nan("");
+            } else if (x == 0.0) {
+              v[0] = (double)gwin[2 * (b + N / 2 - 1)];
+              v[1] = (double)gwin[2 * (b + N / 2 - 1) + 1];
+            } else {
+              lag_interp<N, 2, TC>(x, gwin + 2 * b, v);
+            }
+            const double gp = (v[0] * sh.c2 - v[1] * sh.s2) * sh.inv_scale;   // rotation to the SSB frame
+            const double gc = (v[0] * sh.s2 + v[1] * sh.c2) * sh.inv_scale;
+            const double xi = sel3(xp3[0], xp3[1], xp3[2], l) * gp + sel3(xc3[0], xc3[1], xc3[2], l) * gc;
+            const double term = side == 0 ? pref * xi : -(pref * xi);
+            if (c == 0) acc0 += term; else if (c == 1) acc1 += term; else acc2 += term;
+          }
+          out[0] = acc0;
+          out[1] = acc1;
+          out[2] = acc2;
+        }
+        if (P.mode == 2) {
+          const double rel = (double)k - kH;
+          if (rel <= 0.5 * P.T_s) {
+            const double w = 1.0 / (1.0 + exp(rel / P.sigma_s));
+            out[0] *= w;
+            out[1] *= w;
+            out[2] *= w;
+          } else {
+            out[0] = out[1] = out[2] = 0.0;
+          }
+        }
+        store3<double>(P, S.off + k, out[0], out[1], out[2]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Full-response kernel
+// ---------------------------------------------------------------------------
+struct FullShared {
+  GeoFit F;
+  int64_t src, k0, y0, w0;
+  int32_t cnt, ny, nh, bad;
+  double c2, s2, kH;
+  double dext[4];
+};
+
+template <int N, typename TC>
+__device__ __forceinline__ void interp2(const TC* win, int64_t b, double x, TC& vp, TC& vc) {
+  if (x == 0.0) {
+    vp = win[2 * (b + N / 2 - 1)];
+    vc = win[2 * (b + N / 2 - 1) + 1];
     return;
   }
-  for (;;) {
-    if (threadIdx.x == 0) s_next = (int64_t)atomicAdd(P.counter, 1u);
-    __syncthreads();
-    const int64_t t = s_next;
-    __syncthreads();
-    if (t >= RD.n_tiles) break;
-    do_tile<N, TC>(P, RD, t, smem);
-  }
-}
-
-__global__ void k_reset(uint32_t* counter, int32_t* err, int reset_err) {
-  if (threadIdx.x < 8) {
-    if (threadIdx.x == 0) *counter = 0u;
-    if (reset_err) err[threadIdx.x] = 0;
-  }
+  TC v[2];
+  lag_interp<N, 2, TC>(x, win + 2 * b, v);
+  vp = v[0];
+  vc = v[1];
 }
 
 template <int N, typename TC>
-int launch_t(const KParams& p, int grid, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((k_response<N, TC>), dim3(grid), dim3(kBlock), lds, st, p);
+__global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ Pp) {
+  const KParams& P = *Pp;
+  const SrcDev* __restrict__ SS = sources_of(Pp);
+  __shared__ FullShared sh;
+  __shared__ int64_t s_next;
+  extern __shared__ __align__(16) char dyn[];
+  const int tid = threadIdx.x;
+  const int cap_y = P.cap_y;
+  TC* hwin = reinterpret_cast<TC*>(dyn);                                        // [cap_hf][2]
+  TC* ywin = reinterpret_cast<TC*>(dyn + align16((size_t)P.cap_hf * 2 * sizeof(TC)));  // [6][cap_y]
+  double* Tc = reinterpret_cast<double*>(dyn + align16((size_t)P.cap_hf * 2 * sizeof(TC)) +
+                                         align16((size_t)cap_y * 6 * sizeof(TC)));       // [6][tile]
+
+  int64_t iter = 0;
+  for (;;) {
+    const int64_t tile = next_tile(P, P.counters + 1, P.n_tiles_full, iter, &s_next);
+    if (tile >= P.n_tiles_full) break;
+    if (tid == 0) {
+      const int64_t s = find_source(SS, P.n_src, tile, false);
+      const SrcDev& S = SS[s];
+      sh.src = s;
+      sh.k0 = S.full_kb + (tile - S.full_t0) * kTileFull;
+      sh.cnt = (int32_t)min((int64_t)kTileFull, S.full_ke - sh.k0);
+      const int margin = 2 + (int)ceil(4e-4 * (double)sh.cnt);
+      sh.y0 = sh.k0 - (int64_t)ceil(P.D2_bound / S.dt) - N / 2 + 1 - margin;
+      sh.ny = (int32_t)(sh.k0 + sh.cnt - 1 + N / 2 + margin - sh.y0 + 1);
+      double sn, cs;
+      sincos(2.0 * S.psi, &sn, &cs);
+      sh.c2 = cs;
+      sh.s2 = sn;
+      sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+    }
+    __syncthreads();
+    const SrcDev& S = SS[sh.src];
+    const int64_t k0 = sh.k0, y0 = sh.y0;
+    const int cnt = sh.cnt, ny = sh.ny;
+    fit_geometry(P, S, (double)y0, (double)(y0 + ny - 1), sh.F);
+
+    // h window from the stage-1 delays at both ends of the y window
+    if (tid < 2) {
+      const int64_t i = tid == 0 ? y0 : y0 + ny - 1;
+      const double s = ((double)i - sh.F.kc) * sh.F.ikh;
+      double kR[3];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) kR[q] = geo_eval(sh.F, qKR(q), s);
+      double dmin = 1e300, dmax = -1e300;
+#pragma unroll
+      for (int a = 0; a < 6; ++a) {
+        const double T = geo_eval(sh.F, qT(a), s);
+        const double ds = T + kR[snd_of(a)], dr = kR[rcv_of(a)];
+        dmin = fmin(dmin, fmin(ds, dr));
+        dmax = fmax(dmax, fmax(ds, dr));
+      }
+      sh.dext[2 * tid] = dmin;
+      sh.dext[2 * tid + 1] = dmax;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double dmin = fmin(sh.dext[0], sh.dext[2]), dmax = fmax(sh.dext[1], sh.dext[3]);
+      const int margin = 2 + (int)ceil(4e-4 * (double)ny);
+      const int64_t w0 = y0 - (int64_t)ceil(dmax / S.dt) - N / 2 + 1 - margin;
+      const int64_t w1 = y0 + ny - 1 - (int64_t)floor(dmin / S.dt) + N / 2 + margin;
+      sh.w0 = w0;
+      sh.nh = (int32_t)(w1 - w0 + 1);
+      sh.bad = (sh.nh > P.cap_hf || ny > cap_y) ? 1 : 0;
+      if (sh.bad) report(P.err, 4, k0, ny, sh.nh);
+    }
+    __syncthreads();
+    const int64_t w0 = sh.w0;
+    const int nh = sh.nh;
+    const bool bad = sh.bad != 0;
+    const double dt = S.dt;
+
+    if (!bad) {
+      for (int i = tid; i < nh; i += kBlock) {
+        const int64_t j = w0 + i;
+        const bool in = j >= 0 && j < S.n;
+        hwin[2 * i] = (TC)(in ? P.hp[S.off + j] : 0.0);
+        hwin[2 * i + 1] = (TC)(in ? P.hc[S.off + j] : 0.0);
+      }
+      __syncthreads();
+      // Stage 1: y_l[i] = [H_l(t_i - ds) - H_l(t_i - dr)] / (2 (1 - k.n)), zero
+      // outside the series; antenna patterns at the reception time t_i.
+      const double c2 = sh.c2, s2 = sh.s2;
+      for (int ii = tid; ii < ny; ii += kBlock) {
+        const int64_t i = y0 + ii;
+        if (!(i >= 0 && i < S.n)) {
+#pragma unroll
+          for (int a = 0; a < 6; ++a) ywin[a * cap_y + ii] = (TC)0;
+          continue;
+        }
+        const double s = ((double)i - sh.F.kc) * sh.F.ikh;
+        const double kR0 = geo_eval(sh.F, qKR(0), s), kR1 = geo_eval(sh.F, qKR(1), s),
+                     kR2 = geo_eval(sh.F, qKR(2), s);
+        // the receiver read is shared by the two links into each spacecraft
+        TC hr[6];
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          int64_t i0;
+          double x;
+          split(i, sel3(kR0, kR1, kR2, q), dt, i0, x);
+          const int64_t b = i0 - N / 2 + 1 - w0;
+          if (b < 0 || b + N > nh) {
+            report(P.err, 8, i, b, nh);
+            hr[2 * q] = hr[2 * q + 1] = (TC)__builtin_nan("");
+          } else {
+            interp2<N, TC>(hwin, b, x, hr[2 * q], hr[2 * q + 1]);
+          }
+        }
+#pragma unroll 1
+        for (int a = 0; a < 6; ++a) {
+          const double T = geo_eval(sh.F, qT(a), s);
+          if (i >= k0 && i < k0 + cnt) Tc[a * kTileFull + (int)(i - k0)] = T;
+          int64_t i0;
+          double x;
+          split(i, T + sel3(kR0, kR1, kR2, snd_of(a)), dt, i0, x);
+          const int64_t b = i0 - N / 2 + 1 - w0;
+          TC vp, vc;
+          if (b < 0 || b + N > nh) {
+            report(P.err, 8, i, b, nh);
+            vp = vc = (TC)__builtin_nan("");
+          } else {
+            interp2<N, TC>(hwin, b, x, vp, vc);
+          }
+          const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
+          const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
+          const int r = rcv_of(a);
+          const TC hrp = r == 0 ? hr[0] : (r == 1 ? hr[2] : hr[4]);
+          const TC hrc = r == 0 ? hr[1] : (r == 1 ? hr[3] : hr[5]);
+          const TC Hs = A * vp + B * vc;
+          const TC Hr = A * hrp + B * hrc;
+          ywin[a * cap_y + ii] = (Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s);
+        }
+      }
+    }
+    __syncthreads();
+
+    // Stage 2: sum of +-y_l at the term delays, light times at the output time.
+    const int nterms = P.gen == 20 ? 16 : 8;
+    const double kH = sh.kH;
+    for (int i = tid; i < cnt; i += kBlock) {
+      const int64_t k = k0 + i;
+      const double rel = (double)k - kH;
+      if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
+      double out[3];
+      if (bad) {
+        out[0] = out[1] = out[2] = __builtin_nan("");
+      } else {
+        double T6[6];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) T6[a] = Tc[a * kTileFull + i];
+#pragma unroll 1
+        for (int c = 0; c < 3; ++c) {
+          TC sum = (TC)0;
+#pragma unroll 1
+          for (int t = 0; t < nterms; ++t) {
+            double d = 0.0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) d += (double)c_tcoef[t][unrot_slot(a, c)] * T6[a];
+            const TC* ys = ywin + rot_slot(c_tlink[t], c) * cap_y;
+            TC v;
+            if (d == 0.0) {
+              v = ys[k - y0];
+            } else {
+              int64_t i0;
+              double x;
+              split(k, d, dt, i0, x);
+              const int64_t b = i0 - N / 2 + 1 - y0;
+              if (b < 0 || b + N > ny) {
+                report(P.err, 16, k, b, ny);
+                v = (TC)__builtin_nan("");
+              } else if (x == 0.0) {
+                v = ys[b + N / 2 - 1];
+              } else {
+                TC vv[1];
+                lag_interp<N, 1, TC>(x, ys + b, vv);
+                v = vv[0];
+              }
+            }
+            sum += c_tsign[t] > 0 ? v : -v;
+          }
+          if (c == 0) out[0] = (double)sum; else if (c == 1) out[1] = (double)sum; else out[2] = (double)sum;
+        }
+      }
+      const int64_t o = S.off + k;
+      if (P.mode == 2) {
+        // add w- X^Full to the LFA part written by k_lfa inside the LFA window
+        const double w = 1.0 / (1.0 + exp(-rel / P.sigma_s));
+        const bool has_lfa = rel <= 0.5 * P.T_s;
+        TC* Xo = static_cast<TC*>(P.X);
+        TC* Yo = static_cast<TC*>(P.Y);
+        TC* Zo = static_cast<TC*>(P.Z);
+        if constexpr (sizeof(TC) == 8) {
+          const double xa = has_lfa ? Xo[o] : 0.0, ya = has_lfa ? Yo[o] : 0.0, za = has_lfa ? Zo[o] : 0.0;
+          Xo[o] = xa + w * out[0];
+          Yo[o] = ya + w * out[1];
+          Zo[o] = za + w * out[2];
+        } else {
+          const float wf = (float)w;
+          const float xa = has_lfa ? Xo[o] : 0.0f, ya = has_lfa ? Yo[o] : 0.0f, za = has_lfa ? Zo[o] : 0.0f;
+          Xo[o] = xa + wf * (float)out[0];
+          Yo[o] = ya + wf * (float)out[1];
+          Zo[o] = za + wf * (float)out[2];
+        }
+      } else {
+        store3<TC>(P, o, (TC)out[0], (TC)out[1], (TC)out[2]);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_reset(uint32_t* counters) {
+  if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
+}
+
+template <int N, typename TC>
+int launch_lfa_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k_lfa<N, TC>), dim3(grid), dim3(kBlock), lds, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, typename TC>
+int launch_full_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k_full<N, TC>), dim3(grid), dim3(kBlock), lds, st, dp);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, typename TC>
+int occ_lfa_t(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_lfa<N, TC>), kBlock, lds) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
+template <int N, typename TC>
+int occ_full_t(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_full<N, TC>), kBlock, lds) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
+template <int N, typename TC>
+size_t wave_bytes_t() {
+  return sizeof(TC) == 4 ? wave_tables_bytes<N>() : 0;
+}
+
+#define TDI_DISPATCH(taps, fp32, FN, ...)          \
+  do {                                             \
+    if (fp32) {                                    \
+      switch (taps) {                              \
+        case 4: return FN<4, float>(__VA_ARGS__);  \
+        case 8: return FN<8, float>(__VA_ARGS__);  \
+        case 16: return FN<16, float>(__VA_ARGS__); \
+        case 32: return FN<32, float>(__VA_ARGS__); \
+      }                                            \
+    } else {                                       \
+      switch (taps) {                              \
+        case 4: return FN<4, double>(__VA_ARGS__); \
+        case 8: return FN<8, double>(__VA_ARGS__); \
+        case 16: return FN<16, double>(__VA_ARGS__); \
+        case 32: return FN<32, double>(__VA_ARGS__); \
+      }                                            \
+    }                                              \
+  } while (0)
+
+size_t wave_bytes(int taps, int fp32) {
+  TDI_DISPATCH(taps, fp32, wave_bytes_t);
+  return 0;
 }
 
 }  // namespace
 
-size_t lds_bytes_for(int tile, int cap_g, int cap_h, int cap_y, int fp32) {
-  size_t tcs = fp32 ? sizeof(float) : sizeof(double);
-  size_t lfa = align_up(2 * sizeof(double) * (size_t)cap_h) + align_up(2 * tcs * (size_t)cap_g);
-  size_t full = align_up(2 * tcs * (size_t)cap_h) + align_up(6 * tcs * (size_t)cap_y) +
-                align_up(6 * sizeof(double) * (size_t)tile);
-  size_t region = lfa > full ? lfa : full;
-  return align_up(sizeof(TileHdr)) + align_up(3 * sizeof(double) * (size_t)tile) + region;
+int set_constants() {
+  // Chebyshev nodes of the first kind (the middle one is exactly 0) and the
+  // inverse of the Vandermonde matrix V[j][m] = s_j^m.
+  double s[kNodes], V[kNodes][2 * kNodes];
+  for (int j = 0; j < kNodes; ++j) {
+    s[j] = cos(M_PI * (2.0 * j + 1.0) / (2.0 * kNodes));
+    if (j == kNodes / 2) s[j] = 0.0;
+  }
+  for (int j = 0; j < kNodes; ++j)
+    for (int m = 0; m < 2 * kNodes; ++m)
+      V[j][m] = m < kNodes ? pow(s[j], (double)m) : (m - kNodes == j ? 1.0 : 0.0);
+  for (int c = 0; c < kNodes; ++c) {          // Gauss-Jordan with partial pivoting
+    int piv = c;
+    for (int r = c + 1; r < kNodes; ++r)
+      if (fabs(V[r][c]) > fabs(V[piv][c])) piv = r;
+    for (int m = 0; m < 2 * kNodes; ++m) {
+      const double t = V[c][m];
+      V[c][m] = V[piv][m];
+      V[piv][m] = t;
+    }
+    const double d = V[c][c];
+    for (int m = 0; m < 2 * kNodes; ++m) V[c][m] /= d;
+    for (int r = 0; r < kNodes; ++r) {
+      if (r == c) continue;
+      const double f = V[r][c];
+      for (int m = 0; m < 2 * kNodes; ++m) V[r][m] -= f * V[c][m];
+    }
+  }
+  double inv[kNodes][kNodes];                 // coefficient m = sum_j inv[m][j] value_j
+  for (int m = 0; m < kNodes; ++m)
+    for (int j = 0; j < kNodes; ++j) inv[m][j] = V[m][kNodes + j];
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_vinv), inv, sizeof(inv)) != hipSuccess) return -1;
+  if (hipMemcpyToSymbol(HIP_SYMBOL(c_snode), s, sizeof(s)) != hipSuccess) return -1;
+  return 0;
 }
 
-int max_lds_bytes() { return 64 * 1024; }
+size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int* goff) {
+  const size_t tcs = fp32 ? sizeof(float) : sizeof(double);
+  size_t hb = align16((size_t)cap_h * 2 * sizeof(double));
+  const size_t wb = align16(wave_bytes(taps, fp32));
+  if (wb > hb) hb = wb;
+  if (goff) *goff = (int)hb;
+  return hb + align16((size_t)cap_g * 2 * tcs);
+}
 
-int launch_reset(uint32_t* counter, int32_t* err_flag, int reset_err, void* stream) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, counter, err_flag, reset_err);
+size_t full_lds_bytes(int cap_h, int cap_y, int fp32) {
+  const size_t tcs = fp32 ? sizeof(float) : sizeof(double);
+  return align16((size_t)cap_h * 2 * tcs) + align16((size_t)cap_y * 6 * tcs) +
+         (size_t)6 * kTileFull * sizeof(double);
+}
+
+int launch_reset(uint32_t* counters, void* stream) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, counters);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_main(const KParams& p, int taps, int fp32, int grid, size_t lds, void* stream) {
-  hipStream_t st = (hipStream_t)stream;
-  if (fp32) {
-    switch (taps) {
-      case 4: return launch_t<4, float>(p, grid, lds, st);
-      case 8: return launch_t<8, float>(p, grid, lds, st);
-      case 16: return launch_t<16, float>(p, grid, lds, st);
-      case 32: return launch_t<32, float>(p, grid, lds, st);
-    }
-  } else {
-    switch (taps) {
-      case 4: return launch_t<4, double>(p, grid, lds, st);
-      case 8: return launch_t<8, double>(p, grid, lds, st);
-      case 16: return launch_t<16, double>(p, grid, lds, st);
-      case 32: return launch_t<32, double>(p, grid, lds, st);
-    }
-  }
+int launch_lfa(const KParams* dp, int taps, int fp32, int grid, size_t lds, void* stream) {
+  TDI_DISPATCH(taps, fp32, launch_lfa_t, dp, grid, lds, (hipStream_t)stream);
   return -2;
+}
+
+int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds, void* stream) {
+  TDI_DISPATCH(taps, fp32, launch_full_t, dp, grid, lds, (hipStream_t)stream);
+  return -2;
+}
+
+int occupancy_lfa(int taps, int fp32, size_t lds) {
+  TDI_DISPATCH(taps, fp32, occ_lfa_t, lds);
+  return 1;
+}
+
+int occupancy_full(int taps, int fp32, size_t lds) {
+  TDI_DISPATCH(taps, fp32, occ_full_t, lds);
+  return 1;
 }
 
 }  // namespace tdi

@@ -1,0 +1,150 @@
+"""Host-side checks of the C ABI (no GPU needed): symbols, validation codes."""
+import ctypes as C
+import math
+
+import numpy as np
+import pytest
+
+from paper_2505_09600_amd import tdi as T
+from paper_2505_09600_amd import workload as W
+
+
+@pytest.fixture(scope="module")
+def L():
+    return T.lib()
+
+
+def _cfg(**kw):
+    d = W.default_config(tdi_gen=20, mode=2, taps=32, stencil_order=4, precision=1)
+    d.update(kw)
+    return T.make_config(d)
+
+
+def _orb(**kw):
+    d = W.default_orbit()
+    d.update(kw)
+    return T.make_orbit(d)
+
+
+def test_library_exports_every_declared_symbol(L):
+    declared = T.header_symbols()
+    assert set(declared) == set(T.EXPORTED)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_header_documents_each_entry_point():
+    import os
+    import re
+    txt = open(os.path.join(os.path.dirname(T.__file__), "..", "include", "tdi.h")).read()
+    for name in T.header_symbols():
+        m = re.search(r"(/\*(?:(?!\*/).)*\*/)\s*\n\s*(?:tdi_status|const char\*)\s+" + name + r"\s*\(",
+                      txt, re.S)
+        assert m, f"{name} has no comment right above its declaration"
+
+
+def test_status_strings(L):
+    for s in (0, -1, -2, -3, -4, -5, -6):
+        assert T.tdi_status_str(s) and T.tdi_status_str(s) != "unknown status"
+    assert T.tdi_status_str(42) == "unknown status"
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("tdi_gen", 30, T.TDI_EUNSUPPORTED),
+    ("mode", 3, T.TDI_EUNSUPPORTED),
+    ("precision", 2, T.TDI_EUNSUPPORTED),
+    ("interp_taps", 12, T.TDI_ERANGE),
+    ("interp_taps", 64, T.TDI_ERANGE),
+    ("stencil_order", 6, T.TDI_ERANGE),
+    ("lfa_equal_arms", 2, T.TDI_ERANGE),
+    ("hyb_T_samples", 0.0, T.TDI_ERANGE),
+    ("hyb_sigma_samples", -1.0, T.TDI_ERANGE),
+    ("hyb_sigma_samples", math.nan, T.TDI_ERANGE),
+    ("autotune", 5, T.TDI_ERANGE),
+])
+def test_config_validation(L, field, value, code):
+    c = _cfg()
+    assert T.tdi_check_config(c, _orb()) == T.TDI_OK
+    setattr(c, field, value)
+    assert T.tdi_check_config(c, _orb()) == code
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("kind", 7, T.TDI_EUNSUPPORTED),
+    ("reserved", 1, T.TDI_EINVAL),
+    ("L_m", -1.0, T.TDI_ERANGE),
+    ("R_m", 1.0e9, T.TDI_ERANGE),
+    ("omega", math.inf, T.TDI_ERANGE),
+    ("omega", 1.0, T.TDI_ERANGE),
+    ("kappa0", math.nan, T.TDI_ERANGE),
+])
+def test_orbit_validation(L, field, value, code):
+    o = _orb()
+    setattr(o, field, value)
+    assert T.tdi_check_config(_cfg(), o) == code
+
+
+def test_null_arguments(L):
+    assert L.tdi_check_config(None, None) == T.TDI_EINVAL
+    assert L.tdi_check_batch(None, 0, None, None) == T.TDI_EINVAL
+    assert L.tdi_run(None, 0, None, None, None, None, None, None, None) == T.TDI_ESTATE
+    assert L.tdi_plan_sync(None) == T.TDI_ESTATE
+    assert L.tdi_plan_destroy(None) == T.TDI_EINVAL
+    n = C.c_int32()
+    assert L.tdi_plan_kernel_times(None, None, 0, C.byref(n)) == T.TDI_EINVAL
+
+
+def _recs(n=3, **kw):
+    out = []
+    for i in range(n):
+        r = dict(beta=0.3, lam=1.0 + i, psi=0.2, t0=0.0, dt=10.0, t_hyb=math.inf)
+        r.update(kw)
+        out.append(r)
+    return out
+
+
+@pytest.mark.parametrize("kw,code", [
+    ({}, T.TDI_OK),
+    (dict(dt=0.0), T.TDI_ERANGE),
+    (dict(dt=-1.0), T.TDI_ERANGE),
+    (dict(beta=2.0), T.TDI_ERANGE),
+    (dict(lam=math.nan), T.TDI_ERANGE),
+    (dict(t_hyb=math.nan), T.TDI_ERANGE),
+    (dict(t_hyb=-math.inf), T.TDI_OK),
+    (dict(t0=math.inf), T.TDI_ERANGE),
+])
+def test_batch_validation(L, kw, code):
+    src = T.make_sources(_recs(**kw))
+    assert T.tdi_check_batch(_cfg(), 3, src, [0, 10, 10, 25]) == code
+
+
+def test_offsets_validation(L):
+    src = T.make_sources(_recs())
+    assert T.tdi_check_batch(_cfg(), 3, src, [1, 10, 20, 30]) == T.TDI_EINVAL
+    assert T.tdi_check_batch(_cfg(), 3, src, [0, 10, 5, 30]) == T.TDI_EINVAL
+    assert T.tdi_check_batch(_cfg(), -1, src, [0]) == T.TDI_EINVAL
+    assert T.tdi_check_batch(_cfg(), 0, None, [0]) == T.TDI_OK
+    assert T.tdi_check_batch(_cfg(), 3, src, [0, 0, 0, 0]) == T.TDI_OK
+
+
+def test_plan_create_without_device_reports_edevice(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a HIP device is present")
+    st, h = T.tdi_plan_create(_cfg(), _orb(), 4, 1000)
+    assert st == T.TDI_EDEVICE
+    assert not h.value
+
+
+def test_plan_refuses_bad_config_before_device(L):
+    c = _cfg(tdi_gen=7)
+    st, h = T.tdi_plan_create(c, _orb(), 4, 1000)
+    assert st == T.TDI_EUNSUPPORTED
+
+
+def test_python_plan_fails_loudly_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a HIP device is present")
+    with pytest.raises(RuntimeError):
+        T.Plan(W.default_config(), W.default_orbit(), 1, 10)
