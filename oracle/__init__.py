@@ -90,6 +90,8 @@ def lib():
                                          C.POINTER(Source), _I64, _D, _D, _D, _D, _D]
         L.orc_response_batch_at.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.c_int64,
                                             C.POINTER(Source), _I64, _D, _D, _I64, _I64, _D, _D, _D]
+        L.orc_response_abs_at.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.POINTER(Source),
+                                          C.c_int64, _D, _D, C.c_int64, _I64, _D, _D, _D]
         L.orc_full_terms_absmax.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.POINTER(Source),
                                             C.c_int64, _D, _D, _D]
         L.orc_num_threads.restype = C.c_int
@@ -211,6 +213,26 @@ def response_at(cfg: dict, orbit: dict, rec, hp, hc, ks):
     lib().orc_response_at(C.byref(c), C.byref(o), C.byref(s), len(hp), _dp(hp), _dp(hc),
                           len(ks), ks.ctypes.data_as(_I64), _dp(X), _dp(Y), _dp(Z))
     return np.stack([X, Y, Z])
+
+
+def response_abs_at(cfg: dict, orbit: dict, rec, hp, hc, ks):
+    """Rounding-error scale A_c(k) at sample indices ks (3, len(ks))."""
+    hp, hc = _f64(hp), _f64(hc)
+    ks = np.ascontiguousarray(np.asarray(ks, dtype=np.int64))
+    X, Y, Z = np.zeros(len(ks)), np.zeros(len(ks)), np.zeros(len(ks))
+    c, o, s = make_config(cfg), make_orbit(orbit), make_source(rec)
+    lib().orc_response_abs_at(C.byref(c), C.byref(o), C.byref(s), len(hp), _dp(hp), _dp(hc),
+                              len(ks), ks.ctypes.data_as(_I64), _dp(X), _dp(Y), _dp(Z))
+    return np.stack([X, Y, Z])
+
+
+def fp64_tolerance(cfg, orbit, rec, hp, hc, ks, ref_at_ks, k_ops: float = 64.0, floor: float = 1e-12):
+    """Per-channel FP64 parity bar: max(floor, k_ops * 2^-53 * kappa_c) with
+    kappa_c = max A_c / max |X_c| over the sampled indices (conditioning)."""
+    A = response_abs_at(cfg, orbit, rec, hp, hc, ks)
+    peak = np.max(np.abs(ref_at_ks), axis=1)
+    kappa = np.where(peak > 0, np.max(A, axis=1) / np.where(peak > 0, peak, 1.0), 0.0)
+    return np.maximum(floor, k_ops * 2.0 ** -53 * kappa), kappa
 
 
 def response_batch(cfg: dict, orbit: dict, batch):

@@ -597,3 +597,161 @@ void orc_response_batch_at(const orc_config* c, const orc_orbit* o, int64_t n_so
     orc_response_at(c, o, &src[i], b - a, hp + a, hc + a, kb - ka, ks + ka, X + ka, Y + ka, Z + ka);
   }
 }
+
+/* ===========================================================================
+ * Rounding-error scale for FP64 comparisons (not part of the method).
+ *
+ * A_c(k) is the response evaluated with every input sample, interpolation
+ * weight, stencil coefficient, antenna pattern and prefactor replaced by its
+ * absolute value and every difference by a sum.  Any evaluation order of the
+ * response in FP64 differs from the exact value by at most a modest multiple
+ * of 2^-53 A_c(k) (the number of operations on the longest path), so
+ * kappa_c = max_k A_c(k) / max_k |X_c(k)| is the conditioning of channel c.
+ * ========================================================================= */
+typedef struct {
+  orc_ctx base;        /* geometry / configuration; its h_SSB holds |h_SSB| bounds */
+} orc_abs;
+
+static double lagrange_abs(const double* s, int64_t n, int64_t i0, double x, int N) {
+  double w[64];
+  orc_lagrange_weights(x, N, w);
+  int jlo = -N / 2 + 1;
+  double acc = 0.0;
+  for (int a = 0; a < N; ++a) {
+    int64_t i = i0 + jlo + a;
+    if (i >= 0 && i < n) acc += fabs(w[a]) * fabs(s[i]);
+  }
+  return acc;
+}
+
+static void abs_init(orc_ctx* x, const orc_config* c, const orc_orbit* o, const orc_source* s,
+                     int64_t n, const double* hp, const double* hc) {
+  ctx_init(x, c, o, s, n, hp, hc);
+  double c2 = fabs(cos(2.0 * s->psi)), s2 = fabs(sin(2.0 * s->psi));
+  for (int64_t i = 0; i < n; ++i) {
+    x->hp_ssb[i] = fabs(hp[i]) * c2 + fabs(hc[i]) * s2;
+    x->hc_ssb[i] = fabs(hp[i]) * s2 + fabs(hc[i]) * c2;
+  }
+}
+
+static void abs_stage1_at(orc_ctx* x, int64_t i, double y6[6]) {
+  orc_geom g;
+  orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, i), &g);
+  int N = x->c->taps;
+  double dt = x->s->dt;
+  for (int a = 0; a < 6; ++a) {
+    int64_t i0; double fx;
+    double acc = 0.0;
+    double d2[2] = {g.ds[a], g.dr[a]};
+    for (int q = 0; q < 2; ++q) {
+      orc_split(i, d2[q], dt, &i0, &fx);
+      acc += fabs(g.xi_p[a]) * lagrange_abs(x->hp_ssb, x->n, i0, fx, N) +
+             fabs(g.xi_c[a]) * lagrange_abs(x->hc_ssb, x->n, i0, fx, N);
+    }
+    y6[a] = acc / fabs(2.0 * (1.0 - g.kn[a]));
+  }
+}
+
+static void abs_ensure_y(orc_ctx* x, int64_t lo, int64_t hi) {
+  ensure_y_alloc(x);
+  if (lo < 0) lo = 0;
+  if (hi > x->n) hi = x->n;
+  for (int64_t i = lo; i < hi; ++i) {
+    if (x->y_ok[i]) continue;
+    double y6[6];
+    abs_stage1_at(x, i, y6);
+    for (int a = 0; a < 6; ++a) x->y[(size_t)a * x->n + i] = y6[a];
+    x->y_ok[i] = 1;
+  }
+}
+
+static void abs_full_at(orc_ctx* x, int64_t k, double out[3]) {
+  orc_geom g;
+  orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, k), &g);
+  int N = x->c->taps;
+  for (int c = 0; c < 3; ++c) {
+    double acc = 0.0;
+    for (int t = 0; t < n_terms(x->c->tdi_gen); ++t) {
+      const orc_term* tm = term_at(t);
+      double d = 0.0;
+      for (int q = 0; q < tm->nd; ++q) d += g.T[link_slot(rotate_link(tm->d[q], c))];
+      int64_t i0; double fx;
+      orc_split(k, d, x->s->dt, &i0, &fx);
+      abs_ensure_y(x, i0 - N / 2 + 1, i0 + N / 2 + 1);
+      acc += lagrange_abs(x->y + (size_t)link_slot(rotate_link(tm->link, c)) * x->n, x->n, i0, fx, N);
+    }
+    out[c] = acc;
+  }
+}
+
+static void abs_ensure_g(orc_ctx* x, int64_t lo, int64_t hi) {
+  ensure_g_alloc(x);
+  if (lo < 0) lo = 0;
+  if (hi > x->n) hi = x->n;
+  double num[7], den;
+  int hw = stencil_coeffs(x->m, x->c->stencil_order, num, &den);
+  double anum[7];
+  for (int q = 0; q < 2 * hw + 1; ++q) anum[q] = fabs(num[q]);
+  double scale = den * pow(x->s->dt, (double)x->m);
+  for (int64_t i = lo; i < hi; ++i) {
+    if (x->g_ok[i]) continue;
+    x->gp[i] = stencil_at(x->hp_ssb, x->n, i, anum, hw, scale);
+    x->gc[i] = stencil_at(x->hc_ssb, x->n, i, anum, hw, scale);
+    x->g_ok[i] = 1;
+  }
+}
+
+static void abs_lfa_at(orc_ctx* x, int64_t k, double out[3]) {
+  orc_geom g;
+  orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, k), &g);
+  int N = x->c->taps;
+  for (int c = 0; c < 3; ++c) {
+    int la = (c + 1) % 3 + 1, lb = (c + 2) % 3 + 1;
+    double Ta = x->c->equal_arms ? x->o->L / ORC_C : g.T[la - 1];
+    double Tb = x->c->equal_arms ? x->o->L / ORC_C : g.T[lb - 1];
+    double pref, d;
+    if (x->c->tdi_gen == 20) { pref = 4.0 * Ta * Tb * (Ta + Tb); d = 2.0 * (Ta + Tb); }
+    else { pref = 2.0 * Ta * Tb; d = Ta + Tb; }
+    double acc = 0.0;
+    int ls[2] = {la, lb};
+    for (int q = 0; q < 2; ++q) {
+      int64_t i0; double fx;
+      orc_split(k, d + g.mu[ls[q] - 1], x->s->dt, &i0, &fx);
+      abs_ensure_g(x, i0 - N / 2 + 1, i0 + N / 2 + 1);
+      int a = link_slot(ls[q]);
+      acc += fabs(g.xi_p[a]) * lagrange_abs(x->gp, x->n, i0, fx, N) +
+             fabs(g.xi_c[a]) * lagrange_abs(x->gc, x->n, i0, fx, N);
+    }
+    out[c] = pref * acc;
+  }
+}
+
+void orc_response_abs_at(const orc_config* c, const orc_orbit* o, const orc_source* s,
+                         int64_t n, const double* hp, const double* hc,
+                         int64_t nk, const int64_t* ks, double* X, double* Y, double* Z) {
+  orc_ctx x;
+  abs_init(&x, c, o, s, n, hp, hc);
+  for (int64_t q = 0; q < nk; ++q) {
+    int64_t k = ks[q];
+    double r[3] = {0.0, 0.0, 0.0}, a[3];
+    if (c->mode == ORC_FULL) {
+      abs_full_at(&x, k, r);
+    } else if (c->mode == ORC_LFA) {
+      abs_lfa_at(&x, k, r);
+    } else {
+      double kH = (s->t_hyb - s->t0) / s->dt;
+      double rel = (double)k - kH, z = rel / c->sigma_samples;
+      double wp = 1.0 / (1.0 + exp(z)), wm = 1.0 / (1.0 + exp(-z));
+      if (rel <= 0.5 * c->T_samples) {
+        abs_lfa_at(&x, k, a);
+        for (int i = 0; i < 3; ++i) r[i] += wp * a[i];
+      }
+      if (rel >= -0.5 * c->T_samples) {
+        abs_full_at(&x, k, a);
+        for (int i = 0; i < 3; ++i) r[i] += wm * a[i];
+      }
+    }
+    X[q] = r[0]; Y[q] = r[1]; Z[q] = r[2];
+  }
+  ctx_free(&x);
+}

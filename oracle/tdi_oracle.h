@@ -113,6 +113,13 @@ void orc_response_batch_at(const orc_config* c, const orc_orbit* o, int64_t n_so
                            const double* hc, const int64_t* k_offsets, const int64_t* ks,
                            double* X, double* Y, double* Z);
 
+/* Rounding-error scale A(k) at selected samples: the response evaluated with
+ * absolute values of every quantity and sums in place of differences (not part
+ * of the method; used to bound FP64 evaluation-order differences). */
+void orc_response_abs_at(const orc_config* c, const orc_orbit* o, const orc_source* s,
+                         int64_t n, const double* hp, const double* hc,
+                         int64_t nk, const int64_t* ks, double* X, double* Y, double* Z);
+
 /* Per-channel condition number: max_k sum_terms |term_k| / max_k |X_k|. */
 void orc_full_terms_absmax(const orc_config* c, const orc_orbit* o, const orc_source* s,
                            int64_t n, const double* hp, const double* hc,

@@ -1,0 +1,184 @@
+"""GPU parity at the benchmark configurations' full sizes, on sampled outputs.
+
+The oracle evaluates the response at selected sample indices (uniform random
+plus a dense window around the peak of each channel and the hybrid switch);
+the HIP library computes every sample.  Per-channel error = max |diff| / max
+|X_oracle| over the sampled indices.  FP64 bar: max(1e-12, 64 u kappa) with the
+conditioning kappa measured by the oracle's absolute-value evaluation; FP32-bulk
+bar: 1e-5 for the LFA and hybrid (the plain FP32 full response is reported
+against max(1e-5, 64 u32 kappa), its own conditioning floor).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2505_09600_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def tdi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2505_09600_amd import tdi as T
+    T.lib()
+    return T
+
+
+def _sample_indices(n, X_gpu, rng, k_hyb=None, n_uniform=150, half=60):
+    ks = set(rng.integers(0, n, n_uniform).tolist())
+    for c in range(3):
+        j = int(np.argmax(np.abs(X_gpu[c])))
+        ks.update(range(max(0, j - half), min(n, j + half), 3))
+    ks.update(range(max(0, n - 200), n, 5))
+    ks.update([0, 1, n - 1])
+    if k_hyb is not None and math.isfinite(k_hyb):
+        kh = int(k_hyb)
+        ks.update(range(max(0, kh - 450), min(n, kh + 450), 15))
+    return np.array(sorted(k for k in ks if 0 <= k < n), dtype=np.int64)
+
+
+def _check_source(orc, name, cfg, orb, rec, hp, hc, X_gpu, fp32, rng, kappa_bar=False):
+    n = len(hp)
+    kH = (rec["t_hyb"] - rec["t0"]) / rec["dt"] if cfg["mode"] == 2 else None
+    ks = _sample_indices(n, X_gpu, rng, kH)
+    ref = orc.response_at(dict(cfg, precision=0), orb, rec, hp, hc, ks)
+    got = X_gpu[:, ks]
+    peak = np.max(np.abs(ref), axis=1)
+    err = np.max(np.abs(got - ref), axis=1) / np.where(peak > 0, peak, 1.0)
+    if fp32 and not kappa_bar:
+        tol = np.full(3, 1e-5)
+        kap = None
+    elif fp32:
+        t64, kap = orc.fp64_tolerance(dict(cfg, precision=0), orb, rec, hp, hc, ks, ref)
+        tol = np.maximum(1e-5, 64 * U32 * kap)
+    else:
+        tol, kap = orc.fp64_tolerance(dict(cfg, precision=0), orb, rec, hp, hc, ks, ref)
+    ks_txt = "" if kap is None else f" kappa {kap[0]:.1e} {kap[1]:.1e} {kap[2]:.1e}"
+    print(f"[parity] {name}: err X,Y,Z = {err[0]:.3e} {err[1]:.3e} {err[2]:.3e}  tol {tol.max():.1e}{ks_txt}"
+          f"  ({len(ks)} samples of {n})", flush=True)
+    assert np.all(np.isfinite(got))
+    assert np.all(err <= tol), (err, tol)
+    return err
+
+
+def _gpu_single(T, cfg, orb, batch, **kw):
+    return T.response(batch, cfg, orb, **kw)
+
+
+@pytest.fixture(scope="module")
+def c2_batch():
+    return W.config_c2()[0]
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_c2_full_response_one_year(tdi, orc, c2_batch, prec):
+    """One year at dt = 10 s, analytic orbit, 32 taps, TDI 2.0, plain full response."""
+    cfg = W.default_config(tdi_gen=20, mode=0, taps=32, precision=prec)
+    orb = W.default_orbit()
+    X = _gpu_single(tdi, cfg, orb, c2_batch)
+    rec, hp, hc = c2_batch.source(0)
+    _check_source(orc, f"c2 full prec{prec}", cfg, orb, rec, hp, hc, X, prec == 1,
+                  np.random.default_rng(21), kappa_bar=True)
+
+
+@pytest.mark.parametrize("gen,p,prec", [(15, 2, 0), (15, 4, 1), (20, 2, 1), (20, 4, 0), (20, 4, 1)])
+def test_c3_lfa_one_year(tdi, orc, c2_batch, gen, p, prec):
+    cfg = W.default_config(tdi_gen=gen, mode=1, taps=32, stencil_order=p, precision=prec)
+    orb = W.default_orbit()
+    X = _gpu_single(tdi, cfg, orb, c2_batch)
+    rec, hp, hc = c2_batch.source(0)
+    _check_source(orc, f"c3 lfa tdi{gen} p{p} prec{prec}", cfg, orb, rec, hp, hc, X, prec == 1,
+                  np.random.default_rng(22))
+
+
+@pytest.fixture(scope="module")
+def c3_hybrid_batch():
+    """The c3 recipe with a chirp mass that reaches the switch (f L / c = 0.05)."""
+    n = 3155760
+    mc, beta, lam, psi, iota, _, _ = W.draw_sources(1003, 1, n, n)
+    part = W.make_source(2.0e5, iota[0], beta[0], lam[0], psi[0], n, 10.0, 0.0)
+    assert math.isfinite(part[0]["t_hyb"])
+    return W._assemble([part], np)
+
+
+@pytest.mark.parametrize("gen,prec", [(15, 0), (15, 1), (20, 0), (20, 1)])
+def test_c3_hybrid_one_year(tdi, orc, c3_hybrid_batch, gen, prec):
+    cfg = W.default_config(tdi_gen=gen, mode=2, taps=32, stencil_order=4, precision=prec)
+    orb = W.default_orbit()
+    X = _gpu_single(tdi, cfg, orb, c3_hybrid_batch)
+    rec, hp, hc = c3_hybrid_batch.source(0)
+    _check_source(orc, f"c3 hybrid tdi{gen} prec{prec}", cfg, orb, rec, hp, hc, X, prec == 1,
+                  np.random.default_rng(23))
+
+
+def test_c4_batch_bench_launch(tdi, orc):
+    """512 sources (7.3e8 samples), FP32-bulk hybrid TDI 2.0 with the benchmark's
+    launch configuration (autotuned persistent kernels replayed from a graph);
+    sampled parity on a seeded subset of sources including every source whose
+    full-response region is non-empty among the first 64."""
+    import torch
+    dev = torch.device("cuda:0")
+    batch, cfg, orb = W.config_c4(xp=torch, device=dev)
+    cfg = dict(cfg, precision=1)
+    hp, hc = batch.hp.contiguous(), batch.hc.contiguous()
+    X = torch.empty(batch.total, dtype=torch.float32, device=dev)
+    Y, Z = torch.empty_like(X), torch.empty_like(X)
+    with tdi.Plan(cfg, orb, batch.n_sources, batch.total, autotune=True, use_graph=True) as plan:
+        for _ in range(2):                    # the second run replays the captured graph
+            plan.run(tdi.make_sources(batch.sources), batch.offsets, hp, hc, X, Y, Z)
+        assert plan.sync() == tdi.TDI_OK
+        desc = plan.describe()
+    assert desc["graph"] == 1 and desc["grid_lfa"] > 0
+    rng = np.random.default_rng(24)
+    hybrid_srcs = [i for i in range(64) if math.isfinite(batch.sources[i]["t_hyb"])]
+    chosen = sorted(set(rng.choice(batch.n_sources, 10, replace=False).tolist() + hybrid_srcs[:6]))
+    for i in chosen:
+        a, b = int(batch.offsets[i]), int(batch.offsets[i + 1])
+        rec = batch.sources[i]
+        out = np.stack([X[a:b].double().cpu().numpy(), Y[a:b].double().cpu().numpy(),
+                        Z[a:b].double().cpu().numpy()])
+        _check_source(orc, f"c4 src{i} n={b - a}", dict(cfg, mode=2), orb, rec, hp[a:b].cpu().numpy(),
+                      hc[a:b].cpu().numpy(), out, True, rng)
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_c5_eccentric_subset(tdi, orc, prec):
+    """4096 x 3e6 samples does not fit one GPU (344 GB); a seeded subset of its
+    sources at full length (dt = 5 s, eccentric modulation) is checked."""
+    batch, cfg, orb = W.config_c5(only=[0, 1, 2, 3])
+    cfg = dict(cfg, precision=prec)
+    X = _gpu_single(tdi, cfg, orb, batch)
+    rng = np.random.default_rng(25)
+    for i in range(batch.n_sources):
+        a, b = int(batch.offsets[i]), int(batch.offsets[i + 1])
+        rec, hp, hc = batch.source(i)
+        _check_source(orc, f"c5 src{i} prec{prec}", cfg, orb, rec, hp, hc, X[:, a:b], prec == 1, rng)
+
+
+def test_near_singular_link_direction(tdi, orc):
+    """Propagation along a link at t0 (1 - k.n ~ 1e-7): the 0/0 of Eq. (yslr) is
+    removable; both sides stay finite and agree."""
+    orb = W.default_orbit(W.ORBIT_FROZEN, t_freeze=0.0)
+    import oracle as O
+    R = O.positions(orb, 0.0)
+    s, r = O.link_ends(1)
+    nvec = (R[r - 1] - R[s - 1]) / np.linalg.norm(R[r - 1] - R[s - 1])
+    nvec = nvec + 3e-4 * np.array([0.0, 0.0, 1.0])
+    nvec /= np.linalg.norm(nvec)
+    beta = math.asin(-nvec[2])
+    lam = math.atan2(-nvec[1], -nvec[0])
+    n, dt = 20000, 5.0
+    t = np.arange(n) * dt
+    hp = np.cos(2 * math.pi * 3e-3 * t)
+    hc = np.sin(2 * math.pi * 3e-3 * t)
+    batch = W.single_source_batch(hp, hc, beta, lam, 0.3, dt=dt)
+    cfg = W.default_config(tdi_gen=20, mode=0, taps=32)
+    X = _gpu_single(tdi, cfg, orb, batch)
+    rec, hp_, hc_ = batch.source(0)
+    _check_source(orc, "near-singular link", cfg, orb, rec, hp_, hc_, X, False, np.random.default_rng(26))
