@@ -101,6 +101,9 @@ def main():
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
     ap.add_argument("--steps-only", action="store_true", help="only the timed hybrid steps (profiling)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the steps, copy a float32 buffer of this size three times (a plain "
+                         "copy kernel of known traffic for scaling PMC byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: only --gpus 1 is supported; the response has no multi-GPU path "
@@ -153,8 +156,18 @@ def main():
     value = total * args.steps / el
     ms_step = 1e3 * el / args.steps
     lfa_ms = float(np.mean([ktimes[2 * i] for i in range(len(ktimes) // 2)])) if ktimes else float("nan")
+    if args.calib_copy_mib > 0:
+        nel = args.calib_copy_mib * (1 << 20) // 4
+        a = torch.ones(nel, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {nel * 4} bytes read and written per launch",
+              file=sys.stderr, flush=True)
+        del a, b
     if args.steps_only:
-        print(json.dumps({"ms_per_step": ms_step, "kernel_ms": lfa_ms}), flush=True)
+        print(json.dumps({"ms_per_step": ms_step, "kernel_ms": lfa_ms, "samples": total}), flush=True)
         return
     plan.close()
 
