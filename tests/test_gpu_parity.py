@@ -107,7 +107,13 @@ def test_ragged_batch_fp32_and_fp64(tdi, orc, mode):
     parts = []
     for i, n in enumerate(lens):
         mc = 10 ** rng.uniform(5, 5.4)
-        rec, hp, hc, meta = W.make_source(mc, 0.7, math.asin(rng.uniform(-1, 1)), rng.uniform(0, 6.28),
+        beta = math.asin(rng.uniform(-1, 1))
+        if n < 64:
+            # near the ecliptic pole |k.R|/c is a few seconds, so a few-sample source
+            # still sees its own strain (elsewhere the SSB delay of up to 500 s moves
+            # every read outside the data and both sides are exactly zero)
+            beta = math.copysign(math.pi / 2 - 0.02, beta)
+        rec, hp, hc, meta = W.make_source(mc, 0.7, beta, rng.uniform(0, 6.28),
                                           rng.uniform(0, 3.14), max(n, 1), 10.0, t0=1e6 * i)
         if n and mode == 2:
             rec["t_hyb"] = rec["t0"] + 0.6 * n * 10.0
@@ -120,8 +126,11 @@ def test_ragged_batch_fp32_and_fp64(tdi, orc, mode):
         got = _run_gpu(tdi, batch, dict(cfg, precision=prec), orb)
         for i in range(batch.n_sources):
             a, b = batch.offsets[i], batch.offsets[i + 1]
-            if b - a < 2:
+            if b == a:
                 continue
+            # (a one-sample LFA output is exactly zero: odd-order central stencils
+            # skip the centre and the neighbours are zero-extended)
+            assert b - a < 7 or np.abs(ref[:, a:b]).max() > 0, "parity case without signal"
             err = _err(orc, got[:, a:b], ref[:, a:b])
             _report(f"ragged mode{mode} prec{prec} src{i} n={b - a}", err, tol)
             assert np.all(err <= tol)
