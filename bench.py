@@ -68,27 +68,42 @@ def load_traffic(kernel_hash: str):
 def cpu_baseline(host_sub, cfg, orb, budget_s: float):
     """The FP64 oracle on a bounded seeded sample of the same workload: seeded
     random output indices of a seeded subset of the sources, evaluated with the
-    oracle's sampled-output entry point (OpenMP across sources)."""
+    oracle's sampled-output entry point (OpenMP across sources).  The sample is
+    grown until one timed evaluation takes about a third of the budget or more;
+    a single-source evaluation (one thread) gives the one-core rate."""
     import oracle
     oracle.build(force=False)
     threads = oracle.num_threads()
-    rng = np.random.default_rng(11)
     lens = [int(host_sub.offsets[i + 1] - host_sub.offsets[i]) for i in range(host_sub.n_sources)]
-    # probe: per-output cost on one source
+    # one core: a single source runs on one OpenMP thread
+    rng = np.random.default_rng(11)
     probe = host_sub.subset([0])
-    ks = [np.sort(rng.integers(0, lens[0], 256))]
-    t = time.perf_counter()
-    oracle.response_batch_at(cfg, orb, probe, ks)
-    per_out = (time.perf_counter() - t) / 256.0
-    m = int(max(64, budget_s * min(threads, host_sub.n_sources) / (host_sub.n_sources * per_out)))
-    ks = [np.sort(rng.integers(0, n, min(m, n))) for n in lens]
-    nout = int(sum(len(k) for k in ks))
-    t = time.perf_counter()
-    oracle.response_batch_at(cfg, orb, host_sub, ks)
-    el = time.perf_counter() - t
+    m1 = 512
+    while True:
+        ks = [np.sort(rng.integers(0, lens[0], m1))]
+        t = time.perf_counter()
+        oracle.response_batch_at(cfg, orb, probe, ks)
+        el1 = time.perf_counter() - t
+        if el1 >= 1.0 or m1 >= lens[0]:
+            break
+        m1 = min(lens[0], int(m1 * max(2.0, 1.5 / max(el1, 1e-3))))
+    one_core = m1 / el1
+    # all cores: grow the per-source sample until the run is long enough
+    m = int(max(64, one_core * 0.5 / host_sub.n_sources * min(threads, host_sub.n_sources)))
+    while True:
+        ks = [np.sort(rng.integers(0, n, min(m, n))) for n in lens]
+        nout = int(sum(len(k) for k in ks))
+        t = time.perf_counter()
+        oracle.response_batch_at(cfg, orb, host_sub, ks)
+        el = time.perf_counter() - t
+        if el >= budget_s / 3.0 or m >= max(lens):
+            break
+        m = int(m * min(8.0, max(1.5, 0.5 * budget_s / max(el, 1e-3))))
     return {"value": nout / el, "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "value_1core": one_core,
             "sample": f"{nout} seeded-random output samples of {host_sub.n_sources} seeded-random sources "
-                      f"of the batch (FP64 hybrid TDI 2.0 oracle, sampled-output entry point), {el:.1f} s wall"}
+                      f"of the batch (FP64 hybrid TDI 2.0 oracle, sampled-output entry point, OpenMP "
+                      f"across sources), {el:.1f} s wall; one core: {m1} samples of one source in {el1:.1f} s"}
 
 
 def main():
@@ -99,7 +114,7 @@ def main():
     ap.add_argument("--n-sources", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work")
+    ap.add_argument("--cpu-budget", type=float, default=30.0, help="upper bound of the timed oracle run (s)")
     ap.add_argument("--steps-only", action="store_true", help="only the timed hybrid steps (profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy a float32 buffer of this size three times (a plain "
@@ -156,6 +171,7 @@ def main():
     value = total * args.steps / el
     ms_step = 1e3 * el / args.steps
     lfa_ms = float(np.mean([ktimes[2 * i] for i in range(len(ktimes) // 2)])) if ktimes else float("nan")
+    full_ms = float(np.mean([ktimes[2 * i + 1] for i in range(len(ktimes) // 2)])) if ktimes else float("nan")
     if args.calib_copy_mib > 0:
         nel = args.calib_copy_mib * (1 << 20) // 4
         a = torch.ones(nel, dtype=torch.float32, device=dev)
@@ -167,11 +183,13 @@ def main():
               file=sys.stderr, flush=True)
         del a, b
     if args.steps_only:
-        print(json.dumps({"ms_per_step": ms_step, "kernel_ms": lfa_ms, "samples": total}), flush=True)
+        print(json.dumps({"ms_per_step": ms_step, "kernel_ms": lfa_ms, "full_kernel_ms": full_ms,
+                          "samples": total, "launch": launch}), flush=True)
         return
     plan.close()
 
-    print(f"[bench] hybrid FP32-bulk: {ms_step:.2f} ms/step, kernel {lfa_ms:.2f} ms, launch {launch}",
+    print(f"[bench] hybrid FP32-bulk: {ms_step:.2f} ms/step, LFA kernel {lfa_ms:.3f} ms, "
+          f"full kernel {full_ms:.3f} ms, launch {launch}",
           file=sys.stderr, flush=True)
     # FP64 plain full response on the same batch (the reference this path must beat)
     ref = None
@@ -206,8 +224,9 @@ def main():
     roof = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved_tflops / FP32_PEAK_TFLOPS,
             "traffic": (traffic["bytes_per_launch"] if traffic else None),
-            "kernel": "k_lfa<32,float> (+ k_full in the same graph replay)",
-            "kernel_ms": lfa_ms,
+            "kernel": (("k_lfa_fast<32>" if launch.get("lfa_fast") else "k_lfa<32,float>") +
+                       ("" if launch.get("graph_kernel_events") else " (+ k_full: whole graph replay)")),
+            "kernel_ms": lfa_ms, "full_kernel_ms": full_ms,
             "flops_per_sample": lfa_flops_per_sample(TAPS),
             "hbm_achieved_gbs": achieved_gbs, "hbm_peak_gbs": HBM_PEAK_GBS,
             "hbm_frac": achieved_gbs / HBM_PEAK_GBS,

@@ -132,8 +132,10 @@ tdi_status tdi_run(tdi_plan* plan, int64_t n_sources, const tdi_source* src,
 tdi_status tdi_plan_sync(tdi_plan* plan);
 
 /* Kernel durations (ms) of the most recent runs, oldest first, two values per
- * run: the LFA kernel and the full-response kernel (a graph replay reports the
- * whole replay as the first value and 0 as the second).  At most 'cap' values
+ * run: the LFA kernel and the full-response kernel.  Graph replays are timed by
+ * event nodes inside the graph; where the runtime cannot retarget those nodes a
+ * replay reports its whole duration as the first value and 0 as the second
+ * (tdi_plan_describe tells which: "graph_kernel_events").  At most 'cap' values
  * (up to 256 runs remembered); *count receives the number written.  Waits for
  * the plan's work; the record is cleared afterwards. */
 tdi_status tdi_plan_kernel_times(tdi_plan* plan, float* ms, int32_t cap, int32_t* count);

@@ -32,6 +32,8 @@ struct Caps {
   int g, hl, hf, y;
   size_t lds_lfa, lds_full;
   int goff;
+  int fast;          // FP32 bulk LFA kernel
+  int tile_lfa;      // outputs per LFA tile
 };
 
 }  // namespace
@@ -41,6 +43,8 @@ struct tdi_plan {
   tdi_orbit orb;
   int64_t max_sources, max_total;
   int device, n_cu;
+  size_t max_lds;                // LDS bytes available to one workgroup
+  int last_fast, last_tile_lfa;  // LFA kernel choice of the latest run
   hipStream_t user_stream;
   hipStream_t graph_stream;      // private stream used for capture and replay
   // device memory
@@ -61,6 +65,9 @@ struct tdi_plan {
   hipGraphExec_t graph_exec;
   Launch graph_launch;
   size_t graph_lds_lfa, graph_lds_full;
+  int graph_fast;
+  hipGraphNode_t graph_ev_node[3];   // event records around the kernels inside the graph
+  bool graph_timed;                  // those nodes are retargeted to the timing ring per replay
   // timing: per recorded run, events before the LFA kernel, between the two
   // kernels and after the full kernel (graph replays: before and after the graph)
   hipEvent_t ev[kEventRing][3];
@@ -143,10 +150,20 @@ double stage2_bound(const tdi_config& c, const tdi_orbit& o) {
   return (c.tdi_gen == 20 ? 7.0 : 3.0) * light_time_bound(o);
 }
 
+// The FP32 bulk LFA kernel applies to steps up to kFastDtMax and to orbits whose
+// delays drift by at most kFastRateMax per unit time.
+bool fast_lfa(const tdi_config& c, const tdi_orbit& o, double dt_max) {
+  return c.precision == TDI_FP32_BULK && c.mode != TDI_MODE_FULL && dt_max <= tdi::kFastDtMax &&
+         move_rate(o) <= tdi::kFastRateMax;
+}
+
 // Worst-case staged window lengths (samples) at sampling step dt; the kernels
 // recompute the actual windows per tile and check them against these.
-Caps window_caps(const tdi_config& c, const tdi_orbit& o, double dt) {
+Caps window_caps(const tdi_config& c, const tdi_orbit& o, double dt, bool fast) {
   Caps k;
+  k.fast = fast ? 1 : 0;
+  k.tile_lfa = fast ? tdi::kTileLfaFast : tdi::kTileLfa;
+  const int lfa_span = fast ? tdi::kFastChunk : tdi::kTileLfa;   // outputs sharing one window
   const int N = c.interp_taps;
   const double Lc = o.L_m / kC;
   const double rate = move_rate(o);
@@ -156,8 +173,8 @@ Caps window_caps(const tdi_config& c, const tdi_orbit& o, double dt) {
   auto margin = [](double cnt) { return 2 + (int)ceil(4e-4 * cnt); };
   // LFA: the six delays D_c + mu_l spread over half an arm plus arm differences
   const double mult = c.tdi_gen == 20 ? 2.0 : 1.0;
-  const double spread_l = 0.5 * Lc * 1.02 + 2.0 * mult * (Tmax - Tmin) + 2.0 * rate * tdi::kTileLfa * dt;
-  k.g = tdi::kTileLfa + (int)ceil(spread_l / dt) + N + 2 * margin(tdi::kTileLfa) + 4;
+  const double spread_l = 0.5 * Lc * 1.02 + 2.0 * mult * (Tmax - Tmin) + 2.0 * rate * lfa_span * dt;
+  k.g = lfa_span + (int)ceil(spread_l / dt) + N + 2 * margin(lfa_span) + 4;
   k.hl = k.g + 2 * hw;
   // full: stage-2 delays reach back (7 or 3) light times
   k.y = tdi::kTileFull + (int)ceil(stage2_bound(c, o) / dt) + N + 2 * margin(tdi::kTileFull) + 4;
@@ -165,7 +182,7 @@ Caps window_caps(const tdi_config& c, const tdi_orbit& o, double dt) {
   const double spread_f = Tmax + Lc * 1.02 + 2.0 * rate * k.y * dt;
   k.hf = k.y + (int)ceil(spread_f / dt) + N + 2 * margin(k.y) + 4;
   const int fp32 = c.precision == TDI_FP32_BULK;
-  k.lds_lfa = tdi::lfa_lds_bytes(N, k.g, k.hl, fp32, &k.goff);
+  k.lds_lfa = tdi::lfa_lds_bytes(N, k.g, k.hl, fp32, k.fast, &k.goff);
   k.lds_full = tdi::full_lds_bytes(k.hf, k.y, fp32);
   return k;
 }
@@ -201,7 +218,7 @@ void stage_batch(tdi_plan* p, int64_t n_sources, const tdi_source* src, const in
     }
     d.lfa_kb = lb; d.lfa_ke = le; d.lfa_t0 = tl;
     d.full_kb = fb; d.full_ke = fe; d.full_t0 = tf;
-    if (le > lb) tl += (le - lb + tdi::kTileLfa - 1) / tdi::kTileLfa;
+    if (le > lb) tl += (le - lb + caps.tile_lfa - 1) / caps.tile_lfa;
     if (fe > fb) tf += (fe - fb + tdi::kTileFull - 1) / tdi::kTileFull;
   }
   kp->n_src = n_sources;
@@ -213,21 +230,23 @@ void stage_batch(tdi_plan* p, int64_t n_sources, const tdi_source* src, const in
   kp->persistent = (ln.grid_lfa > 0 ? 1 : 0) | (ln.grid_full > 0 ? 2 : 0);
 }
 
+// Upload, counter reset and both kernels; evs (optional) are recorded before,
+// between and after the kernels.
 hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& caps, const Launch& ln,
-                   int64_t tiles_lfa, int64_t tiles_full, int ev_slot) {
+                   int64_t tiles_lfa, int64_t tiles_full, const hipEvent_t* evs) {
   hipError_t e = hipMemcpyAsync(p->d_params, p->h_params, copy_bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
   if (tdi::launch_reset(p->d_counters, st) != 0) return hipErrorLaunchFailure;
   const int taps = p->cfg.interp_taps, fp32 = p->cfg.precision;
-  if (ev_slot >= 0) hipEventRecord(p->ev[ev_slot][0], st);
+  if (evs && (e = hipEventRecord(evs[0], st)) != hipSuccess) return e;
   const int gl = ln.grid_lfa > 0 ? ln.grid_lfa : (int)std::max<int64_t>(0, tiles_lfa);
-  if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, gl, caps.lds_lfa, st) != 0)
+  if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, caps.fast, gl, caps.lds_lfa, st) != 0)
     return hipErrorLaunchFailure;
-  if (ev_slot >= 0) hipEventRecord(p->ev[ev_slot][1], st);
+  if (evs && (e = hipEventRecord(evs[1], st)) != hipSuccess) return e;
   const int gf = ln.grid_full > 0 ? ln.grid_full : (int)std::max<int64_t>(0, tiles_full);
   if (gf > 0 && tdi::launch_full(p->d_params, taps, fp32, gf, caps.lds_full, st) != 0)
     return hipErrorLaunchFailure;
-  if (ev_slot >= 0) hipEventRecord(p->ev[ev_slot][2], st);
+  if (evs && (e = hipEventRecord(evs[2], st)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -239,11 +258,15 @@ void destroy_graph(tdi_plan* p) {
 }
 
 // Capture (upload of the whole parameter block, counter reset, both
-// persistent kernels) once; replays pick up new batches from the block.
-bool capture_graph(tdi_plan* p, const Caps& caps, const Launch& ln) {
+// persistent kernels) once; replays pick up new batches from the block.  With
+// timed = true, event records are captured around the kernels (using the
+// events of ring slot 0 as placeholders) and their nodes located so that each
+// replay can point them at its own ring slot.
+bool capture_graph_once(tdi_plan* p, const Caps& caps, const Launch& ln, bool timed) {
   destroy_graph(p);
+  p->graph_timed = false;
   if (hipStreamBeginCapture(p->graph_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
-  hipError_t e = enqueue(p, p->graph_stream, p->params_bytes, caps, ln, 0, 0, -1);
+  hipError_t e = enqueue(p, p->graph_stream, p->params_bytes, caps, ln, 0, 0, timed ? p->ev[0] : nullptr);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(p->graph_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -257,10 +280,41 @@ bool capture_graph(tdi_plan* p, const Caps& caps, const Launch& ln) {
     (void)hipGetLastError();
     return false;
   }
+  if (timed) {
+    size_t n = 0;
+    int found = 0;
+    if (hipGraphGetNodes(g, nullptr, &n) == hipSuccess && n > 0) {
+      std::vector<hipGraphNode_t> nodes(n);
+      if (hipGraphGetNodes(g, nodes.data(), &n) == hipSuccess) {
+        for (size_t i = 0; i < n; ++i) {
+          hipGraphNodeType t;
+          hipEvent_t ev = nullptr;
+          if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeEventRecord) continue;
+          if (hipGraphEventRecordNodeGetEvent(nodes[i], &ev) != hipSuccess) continue;
+          for (int j = 0; j < 3; ++j)
+            if (ev == p->ev[0][j]) {
+              p->graph_ev_node[j] = nodes[i];
+              found |= 1 << j;
+            }
+        }
+      }
+    }
+    (void)hipGetLastError();
+    if (found != 7) {
+      destroy_graph(p);
+      return false;
+    }
+    p->graph_timed = true;
+  }
   p->graph_launch = ln;
   p->graph_lds_lfa = caps.lds_lfa;
   p->graph_lds_full = caps.lds_full;
+  p->graph_fast = caps.fast;
   return true;
+}
+
+bool capture_graph(tdi_plan* p, const Caps& caps, const Launch& ln) {
+  return capture_graph_once(p, caps, ln, true) || capture_graph_once(p, caps, ln, false);
 }
 
 void advance_ring(tdi_plan* p) {
@@ -268,15 +322,29 @@ void advance_ring(tdi_plan* p) {
   if (p->ev_count < kEventRing) p->ev_count++;
 }
 
+// Window capacities for a batch (smallest step) and the LFA kernel choice
+// (largest step); false for a batch without samples.
+bool batch_caps(const tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
+                Caps* caps) {
+  double dt_min = INFINITY, dt_max = 0.0;
+  for (int64_t i = 0; i < n_sources; ++i)
+    if (offsets[i + 1] > offsets[i]) {
+      dt_min = std::min(dt_min, src[i].dt);
+      dt_max = std::max(dt_max, src[i].dt);
+    }
+  if (!isfinite(dt_min)) return false;
+  *caps = window_caps(p->cfg, p->orb, dt_min, fast_lfa(p->cfg, p->orb, dt_max));
+  return true;
+}
+
 tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_source* src,
                     const int64_t* offsets, const double* hp, const double* hc, void* X, void* Y,
                     void* Z, bool record, bool allow_graph) {
-  double dt_min = INFINITY;
-  for (int64_t i = 0; i < n_sources; ++i)
-    if (offsets[i + 1] > offsets[i]) dt_min = std::min(dt_min, src[i].dt);
-  if (!isfinite(dt_min)) return TDI_OK;
-  const Caps caps = window_caps(p->cfg, p->orb, dt_min);
-  if (caps.lds_lfa > 65536 || caps.lds_full > 65536) return TDI_ERANGE;
+  Caps caps;
+  if (!batch_caps(p, n_sources, src, offsets, &caps)) return TDI_OK;
+  if (caps.lds_lfa > p->max_lds || caps.lds_full > p->max_lds) return TDI_ERANGE;
+  p->last_fast = caps.fast;
+  p->last_tile_lfa = caps.tile_lfa;
 
   // the previous upload must have left the pinned image before it is rewritten
   if (p->staged_pending) {
@@ -292,17 +360,31 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
   if (graph) {
     if (!p->graph_exec || p->graph_launch.grid_lfa != ln.grid_lfa ||
         p->graph_launch.grid_full != ln.grid_full || p->graph_lds_lfa != caps.lds_lfa ||
-        p->graph_lds_full != caps.lds_full) {
+        p->graph_lds_full != caps.lds_full || p->graph_fast != caps.fast) {
       if (!capture_graph(p, caps, ln)) return TDI_EDEVICE;
     }
     // replay on the private stream, ordered after the caller's stream and back
     if (hipEventRecord(p->handoff, p->user_stream) != hipSuccess) return TDI_EDEVICE;
     if (hipStreamWaitEvent(p->graph_stream, p->handoff, 0) != hipSuccess) return TDI_EDEVICE;
-    if (record) hipEventRecord(p->ev[slot][0], p->graph_stream);
+    // per-kernel times from the captured event nodes, else the whole replay
+    bool inner = false;
+    if (p->graph_timed) {
+      inner = true;
+      for (int j = 0; j < 3 && inner; ++j)
+        inner = hipGraphExecEventRecordNodeSetEvent(p->graph_exec, p->graph_ev_node[j],
+                                                    p->ev[record ? slot : 0][j]) == hipSuccess;
+      if (!inner) {
+        (void)hipGetLastError();
+        p->graph_timed = false;
+      }
+    }
+    if (record && !inner) hipEventRecord(p->ev[slot][0], p->graph_stream);
     if (hipGraphLaunch(p->graph_exec, p->graph_stream) != hipSuccess) return TDI_EDEVICE;
     if (record) {
-      hipEventRecord(p->ev[slot][1], p->graph_stream);
-      hipEventRecord(p->ev[slot][2], p->graph_stream);
+      if (!inner) {
+        hipEventRecord(p->ev[slot][1], p->graph_stream);
+        hipEventRecord(p->ev[slot][2], p->graph_stream);
+      }
       advance_ring(p);
     }
     hipEventRecord(p->staged_free, p->graph_stream);
@@ -310,7 +392,7 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
     if (hipStreamWaitEvent(p->user_stream, p->staged_free, 0) != hipSuccess) return TDI_EDEVICE;
     return TDI_OK;
   }
-  hipError_t e = enqueue(p, p->user_stream, copy_bytes, caps, ln, tl, tf, record ? slot : -1);
+  hipError_t e = enqueue(p, p->user_stream, copy_bytes, caps, ln, tl, tf, record ? p->ev[slot] : nullptr);
   if (e != hipSuccess) return TDI_EDEVICE;
   hipEventRecord(p->staged_free, p->user_stream);
   p->staged_pending = true;
@@ -320,12 +402,9 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
 
 void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
               const double* hp, const double* hc, void* X, void* Y, void* Z) {
-  double dt_min = INFINITY;
-  for (int64_t i = 0; i < n_sources; ++i)
-    if (offsets[i + 1] > offsets[i]) dt_min = std::min(dt_min, src[i].dt);
-  if (!isfinite(dt_min)) return;
-  const Caps caps = window_caps(p->cfg, p->orb, dt_min);
-  const int ol = tdi::occupancy_lfa(p->cfg.interp_taps, p->cfg.precision, caps.lds_lfa);
+  Caps caps;
+  if (!batch_caps(p, n_sources, src, offsets, &caps)) return;
+  const int ol = tdi::occupancy_lfa(p->cfg.interp_taps, p->cfg.precision, caps.fast, caps.lds_lfa);
   const int of = tdi::occupancy_full(p->cfg.interp_taps, p->cfg.precision, caps.lds_full);
   std::vector<Launch> cands;
   cands.push_back({ol * p->n_cu, of * p->n_cu});
@@ -390,6 +469,9 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   p->max_total = max_total_samples;
   p->device = dev;
   p->n_cu = prop.multiProcessorCount;
+  p->max_lds = prop.sharedMemPerBlock;
+  p->last_fast = 0;
+  p->last_tile_lfa = tdi::kTileLfa;
   p->user_stream = (hipStream_t)hip_stream;
   p->params_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)max_sources;
   bool ok = hipMalloc((void**)&p->d_params, p->params_bytes) == hipSuccess;
@@ -443,8 +525,8 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   p->tuned = cfg->autotune ? false : true;
   if (!cfg->autotune && cfg->use_graph) {
     // graph replay needs persistent launches: one full occupancy of the chip
-    const Caps caps = window_caps(*cfg, *orb, 1.0);
-    p->launch.grid_lfa = tdi::occupancy_lfa(cfg->interp_taps, cfg->precision, caps.lds_lfa) * p->n_cu;
+    const Caps caps = window_caps(*cfg, *orb, 1.0, fast_lfa(*cfg, *orb, 1.0));
+    p->launch.grid_lfa = tdi::occupancy_lfa(cfg->interp_taps, cfg->precision, caps.fast, caps.lds_lfa) * p->n_cu;
     p->launch.grid_full = tdi::occupancy_full(cfg->interp_taps, cfg->precision, caps.lds_full) * p->n_cu;
   }
   *out = p;
@@ -529,10 +611,11 @@ tdi_status tdi_plan_describe(const tdi_plan* p, char* buf, int32_t buflen) {
   if (!p || !buf || buflen < 1) return TDI_EINVAL;
   snprintf(buf, (size_t)buflen,
            "{\"tile_lfa\": %d, \"tile_full\": %d, \"grid_lfa\": %d, \"grid_full\": %d, "
-           "\"graph\": %d, \"cu\": %d, \"tuned\": %d}",
-           tdi::kTileLfa, tdi::kTileFull, p->launch.grid_lfa, p->launch.grid_full,
-           (p->cfg.use_graph && p->launch.grid_lfa > 0 && p->launch.grid_full > 0) ? 1 : 0, p->n_cu,
-           p->tuned ? 1 : 0);
+           "\"graph\": %d, \"graph_kernel_events\": %d, \"cu\": %d, \"tuned\": %d, \"lfa_fast\": %d}",
+           p->last_tile_lfa, tdi::kTileFull, p->launch.grid_lfa, p->launch.grid_full,
+           (p->cfg.use_graph && p->launch.grid_lfa > 0 && p->launch.grid_full > 0) ? 1 : 0,
+           p->graph_timed ? 1 : 0, p->n_cu,
+           p->tuned ? 1 : 0, p->last_fast);
   return TDI_OK;
 }
 

@@ -13,6 +13,16 @@ constexpr int kNQ = 27;           // fitted geometry quantities per tile
 constexpr int kTileLfa = 1024;    // outputs per LFA tile (4 waves x 256)
 constexpr int kTileFull = 256;    // outputs per full-response tile
 constexpr int kWaveOut = 256;     // LFA FP32: outputs per wave (4 per lane, stride 64)
+// FP32 bulk LFA path (k_lfa_fast): chunks of 4 waves x 64 lanes x 9 outputs,
+// four chunks per tile (one geometry fit); its stencil pass covers up to
+// kFastStencilSpan elements in one sweep.
+constexpr int kFastChunk = 2304;
+constexpr int kTileLfaFast = 4 * kFastChunk;
+constexpr int kFastStencilSpan = 11 * kBlock;
+constexpr int kFastOutPerLane = 9;
+constexpr int kWGrid = 64;                 // Lagrange Taylor table: rows per unit offset
+constexpr double kFastDtMax = 40.0;        // s: quadratic chunk models stay below 1e-6 relative
+constexpr double kFastRateMax = 2.0e-4;    // bound of |d delay / dt| for the offset expansions
 
 // Orbit constants prepared once per plan.
 struct OrbitDev {
@@ -48,6 +58,7 @@ struct KParams {
   int32_t cap_g, cap_hl;               // LFA window capacities (samples): derivative, strain
   int32_t cap_hf, cap_y;               // full-response capacities: strain, link series
   int32_t lfa_goff;                    // byte offset of the LFA derivative window in LDS
+                                       // (fast path: of the F_l series; 0 = over the strain)
   int32_t pad0;
   // per plan
   int32_t* err;          // window-check report (8 ints)
@@ -65,13 +76,15 @@ __host__ __device__ inline const SrcDev* sources_of(const KParams* p) {
 // Launch entry points (defined in tdi_kernels.hip).
 int set_constants();
 int launch_reset(uint32_t* counters, void* stream);
-int launch_lfa(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
+// fast != 0 selects the FP32 bulk LFA kernel (fp32 must be 1)
+int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t lds_bytes, void* stream);
 int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
 // LFA dynamic LDS: h window (FP64), reused for the FP32 wave tables, then the
-// derivative window; goff receives the byte offset of the latter.
-size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int* goff);
+// derivative window; goff receives the byte offset of the latter.  Fast path:
+// h window and the three F_l series, overlaid when one stencil sweep suffices.
+size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int* goff);
 size_t full_lds_bytes(int cap_h, int cap_y, int fp32);
-int occupancy_lfa(int taps, int fp32, size_t lds);
+int occupancy_lfa(int taps, int fp32, int fast, size_t lds);
 int occupancy_full(int taps, int fp32, size_t lds);
 
 }  // namespace tdi

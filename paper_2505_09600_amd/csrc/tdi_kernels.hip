@@ -151,6 +151,14 @@ __device__ __forceinline__ void lag_interp(double x, const TC* __restrict__ b, T
   for (int c = 0; c < NC; ++c) out[c] = acc[c];
 }
 
+// A wave-uniform double (read from LDS) moved to scalar registers.
+__device__ __forceinline__ double uniform_f64(double v) {
+  const int64_t b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+  return __longlong_as_double(((int64_t)hi << 32) | (int64_t)(uint32_t)lo);
+}
+
 __device__ __forceinline__ double sel3(double a0, double a1, double a2, int i) {
   return i == 0 ? a0 : (i == 1 ? a1 : a2);
 }
@@ -327,11 +335,10 @@ __device__ __forceinline__ int64_t next_tile(const KParams& P, uint32_t* counter
 // channel (l+1)%3 as side b.
 __host__ __device__ constexpr int chan_of_use(int l, int side) { return side == 0 ? (l + 2) % 3 : (l + 1) % 3; }
 
-// Delay (s) of use (l, side) and its coefficients on the raw (+, x) derivative
-// series: X_c += sign * pref_c * [ (xi+ c2 + xi_x s2) g+ + (xi_x c2 - xi+ s2) g_x ].
-__device__ __forceinline__ void lfa_use(const KParams& P, const double T3[3], const double xp3[3],
-                                        const double xc3[3], const double mu3[3], int l, int side,
-                                        double c2, double s2, double& d, double& kp, double& kx) {
+// Delay (s) of use (l, side) and its signed prefactor (Eqs. X15/X20 with
+// non-equal time delays): X_c += spref * [ (xi+ c2 + xi_x s2) g+ + (xi_x c2 - xi+ s2) g_x ].
+__device__ __forceinline__ void lfa_delay(const KParams& P, const double T3[3], const double mu3[3],
+                                          int l, int side, double& d, double& spref) {
   const int c = chan_of_use(l, side);
   const int a = (c + 1) % 3, b = (c + 2) % 3;
   const double Ta = P.equal_arms ? P.orb.L_over_c : T3[a];
@@ -340,7 +347,15 @@ __device__ __forceinline__ void lfa_use(const KParams& P, const double T3[3], co
   if (P.gen == 20) { pref = -4.0 * Ta * Tb * (Ta + Tb); D = 2.0 * (Ta + Tb); }
   else { pref = -2.0 * Ta * Tb; D = Ta + Tb; }
   d = D + mu3[l];
-  const double sg = side == 0 ? pref : -pref;
+  spref = side == 0 ? pref : -pref;
+}
+
+// Delay and coefficients of use (l, side) on the raw (+, x) derivative series.
+__device__ __forceinline__ void lfa_use(const KParams& P, const double T3[3], const double xp3[3],
+                                        const double xc3[3], const double mu3[3], int l, int side,
+                                        double c2, double s2, double& d, double& kp, double& kx) {
+  double sg;
+  lfa_delay(P, T3, mu3, l, side, d, sg);
   kp = sg * (xp3[l] * c2 + xc3[l] * s2);
   kx = sg * (xc3[l] * c2 - xp3[l] * s2);
 }
@@ -731,6 +746,405 @@ __global__ __launch_bounds__(kBlock, 4) void k_lfa(const KParams* __restrict__ P
 }
 
 // ---------------------------------------------------------------------------
+// LFA kernel, FP32 bulk path for sampling steps up to kFastDtMax
+// ---------------------------------------------------------------------------
+// Per chunk of kFChunk outputs (a tile holds four chunks and one geometry fit):
+//  1. the strain window is staged in LDS in FP64;
+//  2. an FP64 central stencil gives the derivative series g+, g_x of every
+//     element, and the polarisation rotation and antenna patterns of link l,
+//     evaluated at the output time whose retarded time is that element, fold
+//     them into one FP32 series F_l per link, written over the strain window;
+//  3. each lane reads F_l for nine consecutive outputs.  The Lagrange weights
+//     come from a table of their Taylor coefficients (orders 0-3) at a grid
+//     point xbar shared by the wave; each lane re-expands them at its own
+//     offset and accumulates the value A and the x-derivative B of each output,
+//     and each of the two uses of the link then applies its exact offset to
+//     first order: I = A + delta B.
+// F_l = c(t*) g interpolated at t - tau equals c(t) times the interpolated g up
+// to the interpolation error of the smooth product (c varies on the orbital
+// time scale), far below FP32 rounding.  Offsets: |eps_lane| <= 0.04 and
+// |delta| <= 1e-3 samples for orbital drift below 2e-4 (checked on the host).
+constexpr int kFR = 9;                 // outputs per lane (odd: conflict-free LDS stride)
+constexpr int kFWave = 64 * kFR;       // outputs per wave
+constexpr int kFChunk = 4 * kFWave;    // outputs per chunk (one per workgroup pass)
+constexpr int kSR = 11;                // stencil elements per thread (odd: conflict-free 16-byte stride)
+static_assert(kFChunk == kFastChunk && kFR == kFastOutPerLane, "chunk shape");
+static_assert(kSR * kBlock == kFastStencilSpan, "stencil sweep");
+
+// Taylor coefficients (l, l', l''/2, l'''/6) of the N Lagrange basis
+// polynomials at x = g / kWGrid, g = 0..kWGrid (filled by set_constants).
+__constant__ float c_wtab4[kWGrid + 1][4][4];
+__constant__ float c_wtab8[kWGrid + 1][8][4];
+__constant__ float c_wtab16[kWGrid + 1][16][4];
+__constant__ float c_wtab32[kWGrid + 1][32][4];
+
+template <int N>
+__device__ __forceinline__ const float4* wtab_row(int g) {
+  if constexpr (N == 4) return reinterpret_cast<const float4*>(&c_wtab4[g][0][0]);
+  else if constexpr (N == 8) return reinterpret_cast<const float4*>(&c_wtab8[g][0][0]);
+  else if constexpr (N == 16) return reinterpret_cast<const float4*>(&c_wtab16[g][0][0]);
+  else return reinterpret_cast<const float4*>(&c_wtab32[g][0][0]);
+}
+
+struct FastWave {
+  int64_t mbar[3];         // integer base of each link's reads (samples)
+  int32_t gi[3];           // table row of xbar
+  int32_t wcnt;
+  float dl[6], a1[6], a2[6];   // x_u(r) - xbar = dl - r (a1 + a2 r), r = k - wave centre
+  float c0[6], c1[6];          // signed prefactor / stencil scale: c0 + r c1
+  float hr;                    // wave centre relative to its first output
+};
+
+struct FastShared {
+  GeoFit F;
+  int64_t src, k0;
+  int32_t cnt, pad0;
+  double c2, s2, inv_scale, kH;
+  int64_t g0;
+  int32_t ng, ngp, bad, pad1;
+  double qx[2][2];             // chunk ends: min / max delay (samples)
+  double wv[4][3][6][2];       // wave model samples: wave, point, use, {delay, coefficient}
+  double pe[3][3][3];          // precombination samples: link, point, {element, c+, c_x}
+  double pc[3][2][3];          // precombination quadratics: link, {c+, c_x}, coefficient
+  double ec[3];                // their centres (element index)
+  FastWave W[4];
+};
+
+template <int N>
+__global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restrict__ Pp) {
+  const KParams& P = *Pp;
+  const SrcDev* __restrict__ SS = sources_of(Pp);
+  __shared__ FastShared sh;
+  __shared__ int64_t s_next;
+  extern __shared__ __align__(16) char dyn[];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const double2* hwin = reinterpret_cast<const double2*>(dyn);      // [nh] (h+, hx), FP64
+  double2* hwin_w = reinterpret_cast<double2*>(dyn);
+  float* Fw = reinterpret_cast<float*>(dyn + P.lfa_goff);           // [3][ngp], FP32
+  const bool overlay = P.lfa_goff == 0;
+  const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
+  const int hw = c_sthw[st];
+  double stn[7];
+#pragma unroll
+  for (int s = 0; s < 7; ++s) stn[s] = c_stnum[st][s];
+
+  int64_t iter = 0;
+  for (;;) {
+    const int64_t tile = next_tile(P, P.counters + 0, P.n_tiles_lfa, iter, &s_next);
+    if (tile >= P.n_tiles_lfa) break;
+    if (tid == 0) {
+      const int64_t s = find_source(SS, P.n_src, tile, true);
+      const SrcDev& S = SS[s];
+      sh.src = s;
+      sh.k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfaFast;
+      sh.cnt = (int32_t)min((int64_t)kTileLfaFast, S.lfa_ke - sh.k0);
+      double sn, cs;
+      sincos(2.0 * S.psi, &sn, &cs);
+      sh.c2 = cs;
+      sh.s2 = sn;
+      double sc = c_stden[st];
+      for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
+      sh.inv_scale = 1.0 / sc;
+      sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+    }
+    __syncthreads();
+    const SrcDev& S = SS[sh.src];
+    const int64_t k0 = sh.k0;
+    const int cnt = sh.cnt;
+    const double dt = S.dt;
+    // the fit also covers the elements read around the tile (pad of N/2 + 8)
+    fit_geometry(P, S, (double)(k0 - N / 2 - 8), (double)(k0 + cnt - 1 + N / 2 + 8), sh.F);
+
+    for (int64_t kc0 = k0; kc0 < k0 + cnt; kc0 += kFChunk) {
+      const int ccnt = (int)min((int64_t)kFChunk, k0 + cnt - kc0);
+      // ---- A: geometry samples from the fit, one per thread role ----------
+      {
+        int role = -1, w = 0, p = 0;
+        double kq = 0.0;
+        if (tid < 12) {
+          w = tid / 3;
+          p = tid % 3;
+          const int wc = min(max(ccnt - w * kFWave, 0), kFWave);
+          if (wc > 0) {
+            const double hr = 0.5 * (double)(wc - 1);
+            kq = (double)(kc0 + (int64_t)w * kFWave) + hr + (double)(p - 1) * hr;
+            role = 0;
+          }
+        } else if (tid < 14) {
+          kq = tid == 12 ? (double)kc0 : (double)(kc0 + ccnt - 1);
+          role = 1;
+        } else if (tid >= 16 && tid < 25) {
+          w = (tid - 16) / 3;     // link
+          p = (tid - 16) % 3;
+          kq = p == 0 ? (double)(kc0 - N / 2 - 4)
+                      : (p == 1 ? (double)kc0 + 0.5 * (double)(ccnt - 1) : (double)(kc0 + ccnt - 1 + N / 2 + 4));
+          role = 2;
+        }
+        if (role >= 0) {
+          const double s = (kq - sh.F.kc) * sh.F.ikh;
+          double T3[3], xp3[3], xc3[3], mu3[3];
+          lfa_geo(sh.F, s, T3, xp3, xc3, mu3);
+          double qd[6], sp[6];
+#pragma unroll
+          for (int l = 0; l < 3; ++l)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+              double d, g;
+              lfa_delay(P, T3, mu3, l, side, d, g);
+              qd[2 * l + side] = d / dt;
+              sp[2 * l + side] = g * sh.inv_scale;
+            }
+          if (role == 0) {
+#pragma unroll
+            for (int u = 0; u < 6; ++u) {
+              sh.wv[w][p][u][0] = qd[u];
+              sh.wv[w][p][u][1] = sp[u];
+            }
+          } else if (role == 1) {
+            double qmin = qd[0], qmax = qd[0];
+#pragma unroll
+            for (int u = 1; u < 6; ++u) {
+              qmin = fmin(qmin, qd[u]);
+              qmax = fmax(qmax, qd[u]);
+            }
+            sh.qx[tid - 12][0] = qmin;
+            sh.qx[tid - 12][1] = qmax;
+          } else {
+            const int l = w;
+            const double ql = 0.5 * (sel3(qd[0], qd[2], qd[4], l) + sel3(qd[1], qd[3], qd[5], l));
+            const double xp = sel3(xp3[0], xp3[1], xp3[2], l), xc = sel3(xc3[0], xc3[1], xc3[2], l);
+            sh.pe[l][p][0] = kq - ql;
+            sh.pe[l][p][1] = xp * sh.c2 + xc * sh.s2;
+            sh.pe[l][p][2] = xc * sh.c2 - xp * sh.s2;
+          }
+        }
+      }
+      __syncthreads();
+      // ---- B: chunk window, wave models, precombination quadratics -------
+      if (tid == 0) {
+        const double qmin = fmin(sh.qx[0][0], sh.qx[1][0]);
+        const double qmax = fmax(sh.qx[0][1], sh.qx[1][1]);
+        const int margin = 2 + (int)ceil(4e-4 * (double)ccnt);
+        const int64_t g0 = kc0 - (int64_t)ceil(qmax) - N / 2 + 1 - margin;
+        const int64_t g1 = kc0 + ccnt - 1 - (int64_t)floor(qmin) + N / 2 + margin;
+        sh.g0 = g0;
+        sh.ng = (int32_t)(g1 - g0 + 1);
+        sh.ngp = sh.ng + kFR + 1;
+        sh.bad = (sh.ng > P.cap_g) ? 1 : 0;
+        if (sh.bad) report(P.err, 1, kc0, sh.ng, P.cap_g);
+      } else if (tid >= 32 && tid < 44) {
+        const int w = (tid - 32) / 3, l = (tid - 32) % 3;
+        const int wc = min(max(ccnt - w * kFWave, 0), kFWave);
+        FastWave& Wv = sh.W[w];
+        if (l == 0) {
+          Wv.wcnt = wc;
+          Wv.hr = 0.5f * (float)(wc - 1);
+        }
+        if (wc > 0) {
+          const double hr = 0.5 * (double)(wc - 1);
+          const double qbar = 0.5 * (sh.wv[w][1][2 * l][0] + sh.wv[w][1][2 * l + 1][0]);
+          const double mb = ceil(qbar);
+          const int gi = min(max((int)rint((mb - qbar) * (double)kWGrid), 0), kWGrid);
+          const double xbar = (double)gi / (double)kWGrid;
+          Wv.mbar[l] = (int64_t)mb;
+          Wv.gi[l] = gi;
+          for (int side = 0; side < 2; ++side) {
+            const int u = 2 * l + side;
+            const double v0 = sh.wv[w][0][u][0], v1 = sh.wv[w][1][u][0], v2 = sh.wv[w][2][u][0];
+            const double e0 = sh.wv[w][0][u][1], e1 = sh.wv[w][1][u][1], e2 = sh.wv[w][2][u][1];
+            Wv.dl[u] = (float)((mb - v1) - xbar);
+            Wv.a1[u] = hr > 0.0 ? (float)((v2 - v0) / (2.0 * hr)) : 0.0f;
+            Wv.a2[u] = hr > 0.0 ? (float)((v2 - 2.0 * v1 + v0) / (2.0 * hr * hr)) : 0.0f;
+            Wv.c0[u] = (float)e1;
+            Wv.c1[u] = hr > 0.0 ? (float)((e2 - e0) / (2.0 * hr)) : 0.0f;
+          }
+        }
+      } else if (tid >= 48 && tid < 51) {
+        const int l = tid - 48;
+        const double x0 = sh.pe[l][0][0], x1 = sh.pe[l][1][0], x2 = sh.pe[l][2][0];
+        sh.ec[l] = x1;
+        for (int q = 0; q < 2; ++q) {
+          const double f0 = sh.pe[l][0][q + 1], f1 = sh.pe[l][1][q + 1], f2 = sh.pe[l][2][q + 1];
+          // quadratic through the three samples, in u = e - x1
+          const double d01 = (x1 > x0) ? (f1 - f0) / (x1 - x0) : 0.0;
+          const double d12 = (x2 > x1) ? (f2 - f1) / (x2 - x1) : 0.0;
+          const double d012 = (x2 > x0) ? (d12 - d01) / (x2 - x0) : 0.0;
+          sh.pc[l][q][0] = f1;
+          sh.pc[l][q][1] = d01 + (x1 - x0) * d012;
+          sh.pc[l][q][2] = d012;
+        }
+      }
+      __syncthreads();
+      const int64_t g0 = sh.g0;
+      const int ng = sh.ng, ngp = sh.ngp, nh = ng + 2 * hw;
+      const bool bad = sh.bad != 0;
+
+      if (!bad) {
+        // ---- C: stage the strain (zero outside the series) --------------
+        const int64_t h0 = g0 - hw;
+        for (int i = tid; i < nh; i += kBlock) {
+          const int64_t j = h0 + i;
+          const bool in = j >= 0 && j < S.n;
+          hwin_w[i] = make_double2(in ? P.hp[S.off + j] : 0.0, in ? P.hc[S.off + j] : 0.0);
+        }
+        __syncthreads();
+        // ---- D: stencil and precombination, kSR consecutive elements per thread
+        double pcv[3][2][3], ecv[3];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+          ecv[l] = uniform_f64(sh.ec[l] - (double)g0);   // relative to the window start
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int m = 0; m < 3; ++m) pcv[l][q][m] = uniform_f64(sh.pc[l][q][m]);
+        }
+        for (int base = 0; base < ng; base += kSR * kBlock) {
+          const int i0 = base + kSR * tid;
+          const bool act = i0 < ng;
+          float fv[3][kSR];
+          if (act) {
+            double hp_[kSR + 6], hc_[kSR + 6];
+#pragma unroll
+            for (int m = 0; m < kSR + 6; ++m) {
+              const double2 v = hwin[min(i0 + m, nh - 1)];
+              hp_[m] = v.x;
+              hc_[m] = v.y;
+            }
+#pragma unroll
+            for (int e = 0; e < kSR; ++e) {
+              const int64_t j = g0 + i0 + e;
+              double ap = 0.0, ac = 0.0;
+#pragma unroll
+              for (int s = 0; s < 7; ++s) {
+                if (s <= 2 * hw) {
+                  ap = fma(stn[s], hp_[e + s], ap);
+                  ac = fma(stn[s], hc_[e + s], ac);
+                }
+              }
+              if (!(j >= 0 && j < S.n)) ap = ac = 0.0;
+#pragma unroll
+              for (int l = 0; l < 3; ++l) {
+                const double u = (double)(i0 + e) - ecv[l];
+                const double cp = fma(u, fma(u, pcv[l][0][2], pcv[l][0][1]), pcv[l][0][0]);
+                const double cx = fma(u, fma(u, pcv[l][1][2], pcv[l][1][1]), pcv[l][1][0]);
+                fv[l][e] = (float)fma(cp, ap, cx * ac);
+              }
+            }
+          }
+          if (overlay) __syncthreads();     // F_l overwrites the strain window
+          if (act) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+#pragma unroll
+              for (int e = 0; e < kSR; ++e)
+                if (i0 + e < ng) Fw[l * ngp + i0 + e] = fv[l][e];
+          }
+        }
+        __syncthreads();
+
+        // ---- E: interpolation, TDI combination, hybrid weight -------------
+        const FastWave& Wv = sh.W[wave];
+        const int wcnt = Wv.wcnt;
+        const int64_t kw0 = kc0 + (int64_t)wave * kFWave;
+        if (wcnt > 0) {
+          const int nl = min(max(wcnt - kFR * lane, 0), kFR);
+          const float rL = (float)(kFR * lane + kFR / 2) - Wv.hr;
+          float Xa[kFR], Xb[kFR], Xc[kFR];
+#pragma unroll
+          for (int q = 0; q < kFR; ++q) Xa[q] = Xb[q] = Xc[q] = 0.0f;
+          bool ok = true;
+#pragma unroll 1
+          for (int l = 0; l < 3; ++l) {
+            const int64_t b64 = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1 - g0;
+            if (nl > 0 && (b64 < 0 || b64 + nl + N - 2 >= ng)) {
+              ok = false;
+              report(P.err, 2, kw0 + kFR * lane, b64, ng);
+            }
+            const int b = (int)min(max(b64, (int64_t)0), (int64_t)(ngp - (kFR + N - 1)));
+            const float* Fl = Fw + l * ngp + b;
+            float win[kFR + N - 1];
+#pragma unroll
+            for (int t = 0; t < kFR + N - 1; ++t) win[t] = Fl[t];
+            const int u0 = 2 * l, u1 = 2 * l + 1;
+            const float e0 = Wv.dl[u0] - rL * fmaf(Wv.a2[u0], rL, Wv.a1[u0]);
+            const float e1 = Wv.dl[u1] - rL * fmaf(Wv.a2[u1], rL, Wv.a1[u1]);
+            const float eL = 0.5f * (e0 + e1);
+            const float4* row = wtab_row<N>(__builtin_amdgcn_readfirstlane(Wv.gi[l]));
+            float A[kFR], B[kFR];
+#pragma unroll
+            for (int q = 0; q < kFR; ++q) A[q] = B[q] = 0.0f;
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+              const float4 c = row[j];
+              // p(e) = c.x + c.y e + c.z e^2 + c.w e^3 and p'(e) by synthetic division
+              const float b2 = fmaf(eL, c.w, c.z);
+              const float b1 = fmaf(eL, b2, c.y);
+              const float w = fmaf(eL, b1, c.x);
+              const float wd = fmaf(eL, fmaf(eL, c.w, b2), b1);
+#pragma unroll
+              for (int q = 0; q < kFR; ++q) {
+                A[q] = fmaf(w, win[j + q], A[q]);
+                B[q] = fmaf(wd, win[j + q], B[q]);
+              }
+            }
+            // side 0 feeds channel (l+2)%3 (Xa), side 1 channel (l+1)%3 (Xb)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+              const int u = 2 * l + side;
+              const float dl = Wv.dl[u] - eL, a1 = Wv.a1[u], a2 = Wv.a2[u];
+              const float c0 = Wv.c0[u], c1 = Wv.c1[u];
+#pragma unroll
+              for (int q = 0; q < kFR; ++q) {
+                const float r = rL + (float)(q - kFR / 2);
+                const float d = dl - r * fmaf(a2, r, a1);
+                const float I = fmaf(d, B[q], A[q]);
+                const float cf = fmaf(r, c1, c0);
+                if (side == 0) Xa[q] = fmaf(cf, I, Xa[q]);
+                else Xb[q] = fmaf(cf, I, Xb[q]);
+              }
+            }
+            // the next link's (side 0, side 1) channels are this link's (Xc, Xa)
+#pragma unroll
+            for (int q = 0; q < kFR; ++q) {
+              const float t = Xc[q];
+              Xc[q] = Xb[q];
+              Xb[q] = Xa[q];
+              Xa[q] = t;
+            }
+          }
+          // after three links: X = Xc, Y = Xb, Z = Xa
+          const double kH = sh.kH;
+#pragma unroll
+          for (int q = 0; q < kFR; ++q) {
+            if (q >= nl) continue;
+            const int64_t k = kw0 + kFR * lane + q;
+            float x = Xc[q], y = Xb[q], z = Xa[q];
+            if (!ok) x = y = z = __builtin_nanf("");
+            if (P.mode == 2) {
+              const double rel = (double)k - kH;
+              if (rel <= 0.5 * P.T_s) {
+                const double zz = rel / P.sigma_s;
+                if (zz > -17.0) {       // below, 1/(1+e^z) rounds to 1 in FP32
+                  const float wgt = 1.0f / (1.0f + expf((float)zz));
+                  x *= wgt; y *= wgt; z *= wgt;
+                }
+              } else {
+                x = y = z = 0.0f;
+              }
+            }
+            store3<float>(P, S.off + k, x, y, z);
+          }
+        }
+      } else {
+        for (int i = tid; i < ccnt; i += kBlock)
+          store3<float>(P, S.off + kc0 + i, __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Full-response kernel
 // ---------------------------------------------------------------------------
 struct FullShared {
@@ -983,6 +1397,19 @@ int launch_full_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+template <int N>
+int launch_lfa_fast_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k_lfa_fast<N>), dim3(grid), dim3(kBlock), lds, st, dp);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N>
+int occ_lfa_fast_t(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_lfa_fast<N>), kBlock, lds) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
 template <int N, typename TC>
 int occ_lfa_t(size_t lds) {
   int n = 0;
@@ -1026,6 +1453,44 @@ size_t wave_bytes(int taps, int fp32) {
   return 0;
 }
 
+#define TDI_DISPATCH_FAST(taps, FN, ...)           \
+  do {                                             \
+    switch (taps) {                                \
+      case 4: return FN<4>(__VA_ARGS__);           \
+      case 8: return FN<8>(__VA_ARGS__);           \
+      case 16: return FN<16>(__VA_ARGS__);         \
+      case 32: return FN<32>(__VA_ARGS__);         \
+    }                                              \
+  } while (0)
+
+// Taylor coefficients of the Lagrange basis on nodes j - N/2 + 1 at x = g / kWGrid:
+// l_j(x + y) = norm_j prod_{i != j} (x - x_i + y), expanded to y^3.
+template <int N>
+void lagrange_taylor_table(float out[kWGrid + 1][N][4]) {
+  for (int g = 0; g <= kWGrid; ++g) {
+    const long double x = (long double)g / (long double)kWGrid;
+    for (int j = 0; j < N; ++j) {
+      long double c[4] = {1.0L, 0.0L, 0.0L, 0.0L};
+      long double den = 1.0L;
+      for (int i = 0; i < N; ++i) {
+        if (i == j) continue;
+        const long double a = x - (long double)(i - N / 2 + 1);
+        for (int d = 3; d >= 1; --d) c[d] = c[d] * a + c[d - 1];
+        c[0] *= a;
+        den *= (long double)(j - i);
+      }
+      for (int d = 0; d < 4; ++d) out[g][j][d] = (float)(c[d] / den);
+    }
+  }
+}
+
+template <int N>
+int upload_taylor_table(const void* symbol) {
+  static float tab[kWGrid + 1][N][4];
+  lagrange_taylor_table<N>(tab);
+  return hipMemcpyToSymbol(symbol, tab, sizeof(tab)) == hipSuccess ? 0 : -1;
+}
+
 }  // namespace
 
 int set_constants() {
@@ -1061,10 +1526,24 @@ int set_constants() {
     for (int j = 0; j < kNodes; ++j) inv[m][j] = V[m][kNodes + j];
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_vinv), inv, sizeof(inv)) != hipSuccess) return -1;
   if (hipMemcpyToSymbol(HIP_SYMBOL(c_snode), s, sizeof(s)) != hipSuccess) return -1;
+  if (upload_taylor_table<4>(HIP_SYMBOL(c_wtab4)) != 0) return -1;
+  if (upload_taylor_table<8>(HIP_SYMBOL(c_wtab8)) != 0) return -1;
+  if (upload_taylor_table<16>(HIP_SYMBOL(c_wtab16)) != 0) return -1;
+  if (upload_taylor_table<32>(HIP_SYMBOL(c_wtab32)) != 0) return -1;
   return 0;
 }
 
-size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int* goff) {
+size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int* goff) {
+  if (fast) {
+    const size_t hb = align16((size_t)(cap_g + 6) * 2 * sizeof(double));
+    const size_t fb = align16((size_t)3 * (cap_g + kFR + 1) * sizeof(float));
+    if (cap_g <= kFastStencilSpan) {        // one stencil sweep: F_l over the strain
+      if (goff) *goff = 0;
+      return hb > fb ? hb : fb;
+    }
+    if (goff) *goff = (int)hb;
+    return hb + fb;
+  }
   const size_t tcs = fp32 ? sizeof(float) : sizeof(double);
   size_t hb = align16((size_t)cap_h * 2 * sizeof(double));
   const size_t wb = align16(wave_bytes(taps, fp32));
@@ -1084,7 +1563,12 @@ int launch_reset(uint32_t* counters, void* stream) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_lfa(const KParams* dp, int taps, int fp32, int grid, size_t lds, void* stream) {
+int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t lds, void* stream) {
+  if (fast) {
+    if (!fp32) return -2;
+    TDI_DISPATCH_FAST(taps, launch_lfa_fast_t, dp, grid, lds, (hipStream_t)stream);
+    return -2;
+  }
   TDI_DISPATCH(taps, fp32, launch_lfa_t, dp, grid, lds, (hipStream_t)stream);
   return -2;
 }
@@ -1094,7 +1578,11 @@ int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds, voi
   return -2;
 }
 
-int occupancy_lfa(int taps, int fp32, size_t lds) {
+int occupancy_lfa(int taps, int fp32, int fast, size_t lds) {
+  if (fast) {
+    TDI_DISPATCH_FAST(taps, occ_lfa_fast_t, lds);
+    return 1;
+  }
   TDI_DISPATCH(taps, fp32, occ_lfa_t, lds);
   return 1;
 }

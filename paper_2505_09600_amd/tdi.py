@@ -229,8 +229,10 @@ class Plan:
         self.close()
 
 
-def response(batch, cfg: dict, orbit: dict, device="cuda:0", autotune=False, use_graph=False):
-    """One-shot helper: host Batch -> (X, Y, Z) numpy arrays computed on the GPU."""
+def response(batch, cfg: dict, orbit: dict, device="cuda:0", autotune=False, use_graph=False,
+             info: dict | None = None):
+    """One-shot helper: host Batch -> (X, Y, Z) numpy arrays computed on the GPU.
+    If info is a dict it receives the plan's launch description."""
     import torch
     hp = torch.as_tensor(np.asarray(batch.hp), dtype=torch.float64, device=device)
     hc = torch.as_tensor(np.asarray(batch.hc), dtype=torch.float64, device=device)
@@ -239,6 +241,8 @@ def response(batch, cfg: dict, orbit: dict, device="cuda:0", autotune=False, use
         st = p.sync()
         if st != TDI_OK:
             raise TdiError(st, "tdi_plan_sync")
+        if info is not None:
+            info.update(p.describe())
         return np.stack([X.double().cpu().numpy(), Y.double().cpu().numpy(), Z.double().cpu().numpy()])
 
 

@@ -99,6 +99,23 @@ def test_hybrid_fp64_and_fp32(tdi, orc, gen):
     assert np.all(err32 <= 1e-5)
 
 
+@pytest.mark.parametrize("dt,mc,n,fast", [(10.0, 3e5, 40000, 1), (5.0, 6e5, 30000, 1), (60.0, 1e6, 8000, 0)])
+def test_lfa_fp32_kernels(tdi, orc, dt, mc, n, fast):
+    """FP32-bulk LFA: the Taylor-table kernel (steps up to 40 s) and the
+    per-output kernel used above it, both against the FP64 oracle."""
+    batch = _small_analytic(mc=mc, n=n, dt=dt, hybrid=False)
+    orb = W.default_orbit()
+    for gen, p in ((20, 4), (15, 2)):
+        cfg = W.default_config(tdi_gen=gen, mode=1, taps=32, stencil_order=p, precision=1)
+        info = {}
+        got = tdi.response(batch, cfg, orb, info=info)
+        assert info["lfa_fast"] == fast
+        ref = _run_orc(orc, batch, dict(cfg, precision=0), orb)
+        err = _err(orc, got, ref)
+        _report(f"lfa fp32 dt{dt:g} tdi{gen} p{p} fast{fast}", err, 1e-5)
+        assert np.all(err <= 1e-5)
+
+
 @pytest.mark.parametrize("mode", [0, 1, 2])
 def test_ragged_batch_fp32_and_fp64(tdi, orc, mode):
     """Empty, single-sample, shorter-than-taps and multi-tile sources in one batch."""
