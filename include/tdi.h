@@ -131,10 +131,11 @@ tdi_status tdi_run(tdi_plan* plan, int64_t n_sources, const tdi_source* src,
  * call (such samples were written as NaN), else TDI_OK. */
 tdi_status tdi_plan_sync(tdi_plan* plan);
 
-/* Kernel durations (ms) of the most recent runs, oldest first, two values per
- * run: the LFA kernel and the full-response kernel.  Graph replays are timed by
+/* Kernel durations (ms) of the most recent runs, oldest first, three values
+ * per run: the geometry-fit pre-pass of the FP32 LFA path (0 when not used),
+ * the LFA kernel and the full-response kernel.  Graph replays are timed by
  * event nodes inside the graph; where the runtime cannot retarget those nodes a
- * replay reports its whole duration as the first value and 0 as the second
+ * replay reports its whole duration as the LFA value and 0 for the others
  * (tdi_plan_describe tells which: "graph_kernel_events").  At most 'cap' values
  * (up to 256 runs remembered); *count receives the number written.  Waits for
  * the plan's work; the record is cleared afterwards. */

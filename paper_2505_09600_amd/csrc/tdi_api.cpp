@@ -22,6 +22,7 @@ namespace {
 
 constexpr double kC = 299792458.0;
 constexpr int kEventRing = 256;
+constexpr int kEvPerRun = 4;     // before the fit pre-pass, before / after the LFA kernel, after the full kernel
 
 struct Launch {
   int grid_lfa;      // 0 = one workgroup per tile
@@ -49,6 +50,8 @@ struct tdi_plan {
   hipStream_t graph_stream;      // private stream used for capture and replay
   // device memory
   tdi::KParams* d_params;        // KParams followed by SrcDev[max_sources]
+  double* d_fits;                // fast LFA path: per-tile geometry fits
+  int64_t fit_tiles;             // their capacity (tiles)
   size_t params_bytes;
   int32_t* d_err;
   uint32_t* d_counters;
@@ -66,11 +69,11 @@ struct tdi_plan {
   Launch graph_launch;
   size_t graph_lds_lfa, graph_lds_full;
   int graph_fast;
-  hipGraphNode_t graph_ev_node[3];   // event records around the kernels inside the graph
+  hipGraphNode_t graph_ev_node[kEvPerRun];   // event records around the kernels inside the graph
   bool graph_timed;                  // those nodes are retargeted to the timing ring per replay
-  // timing: per recorded run, events before the LFA kernel, between the two
-  // kernels and after the full kernel (graph replays: before and after the graph)
-  hipEvent_t ev[kEventRing][3];
+  // timing: per recorded run, events before the fit pre-pass, before and after
+  // the LFA kernel and after the full kernel
+  hipEvent_t ev[kEventRing][kEvPerRun];
   int ev_count, ev_head;
 };
 
@@ -199,6 +202,8 @@ void stage_batch(tdi_plan* p, int64_t n_sources, const tdi_source* src, const in
     const tdi_source& s = src[i];
     tdi::SrcDev& d = sd[i];
     d.beta = s.beta; d.lam = s.lambda; d.psi = s.psi; d.t0 = s.t0; d.dt = s.dt; d.t_hyb = s.t_hyb;
+    d.c2psi = cos(2.0 * s.psi);
+    d.s2psi = sin(2.0 * s.psi);
     d.off = offsets[i];
     d.n = offsets[i + 1] - offsets[i];
     // sample ranges of the two kernels; the kernels apply the exact window
@@ -230,8 +235,8 @@ void stage_batch(tdi_plan* p, int64_t n_sources, const tdi_source* src, const in
   kp->persistent = (ln.grid_lfa > 0 ? 1 : 0) | (ln.grid_full > 0 ? 2 : 0);
 }
 
-// Upload, counter reset and both kernels; evs (optional) are recorded before,
-// between and after the kernels.
+// Upload, counter reset, the fit pre-pass (fast LFA path) and both kernels;
+// evs (optional, kEvPerRun) are recorded between the steps.
 hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& caps, const Launch& ln,
                    int64_t tiles_lfa, int64_t tiles_full, const hipEvent_t* evs) {
   hipError_t e = hipMemcpyAsync(p->d_params, p->h_params, copy_bytes, hipMemcpyHostToDevice, st);
@@ -240,13 +245,16 @@ hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& c
   const int taps = p->cfg.interp_taps, fp32 = p->cfg.precision;
   if (evs && (e = hipEventRecord(evs[0], st)) != hipSuccess) return e;
   const int gl = ln.grid_lfa > 0 ? ln.grid_lfa : (int)std::max<int64_t>(0, tiles_lfa);
-  if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, caps.fast, gl, caps.lds_lfa, st) != 0)
+  if (gl > 0 && caps.fast && tdi::launch_lfa_fit(p->d_params, taps, 4 * p->n_cu, st) != 0)
     return hipErrorLaunchFailure;
   if (evs && (e = hipEventRecord(evs[1], st)) != hipSuccess) return e;
+  if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, caps.fast, gl, caps.lds_lfa, st) != 0)
+    return hipErrorLaunchFailure;
+  if (evs && (e = hipEventRecord(evs[2], st)) != hipSuccess) return e;
   const int gf = ln.grid_full > 0 ? ln.grid_full : (int)std::max<int64_t>(0, tiles_full);
   if (gf > 0 && tdi::launch_full(p->d_params, taps, fp32, gf, caps.lds_full, st) != 0)
     return hipErrorLaunchFailure;
-  if (evs && (e = hipEventRecord(evs[2], st)) != hipSuccess) return e;
+  if (evs && (e = hipEventRecord(evs[3], st)) != hipSuccess) return e;
   return hipSuccess;
 }
 
@@ -291,7 +299,7 @@ bool capture_graph_once(tdi_plan* p, const Caps& caps, const Launch& ln, bool ti
           hipEvent_t ev = nullptr;
           if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeEventRecord) continue;
           if (hipGraphEventRecordNodeGetEvent(nodes[i], &ev) != hipSuccess) continue;
-          for (int j = 0; j < 3; ++j)
+          for (int j = 0; j < kEvPerRun; ++j)
             if (ev == p->ev[0][j]) {
               p->graph_ev_node[j] = nodes[i];
               found |= 1 << j;
@@ -300,7 +308,7 @@ bool capture_graph_once(tdi_plan* p, const Caps& caps, const Launch& ln, bool ti
       }
     }
     (void)hipGetLastError();
-    if (found != 7) {
+    if (found != (1 << kEvPerRun) - 1) {
       destroy_graph(p);
       return false;
     }
@@ -370,7 +378,7 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
     bool inner = false;
     if (p->graph_timed) {
       inner = true;
-      for (int j = 0; j < 3 && inner; ++j)
+      for (int j = 0; j < kEvPerRun && inner; ++j)
         inner = hipGraphExecEventRecordNodeSetEvent(p->graph_exec, p->graph_ev_node[j],
                                                     p->ev[record ? slot : 0][j]) == hipSuccess;
       if (!inner) {
@@ -378,12 +386,16 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
         p->graph_timed = false;
       }
     }
-    if (record && !inner) hipEventRecord(p->ev[slot][0], p->graph_stream);
+    // without inner events the whole replay is reported as the LFA time
+    if (record && !inner) {
+      hipEventRecord(p->ev[slot][0], p->graph_stream);
+      hipEventRecord(p->ev[slot][1], p->graph_stream);
+    }
     if (hipGraphLaunch(p->graph_exec, p->graph_stream) != hipSuccess) return TDI_EDEVICE;
     if (record) {
       if (!inner) {
-        hipEventRecord(p->ev[slot][1], p->graph_stream);
         hipEventRecord(p->ev[slot][2], p->graph_stream);
+        hipEventRecord(p->ev[slot][3], p->graph_stream);
       }
       advance_ring(p);
     }
@@ -477,12 +489,17 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   bool ok = hipMalloc((void**)&p->d_params, p->params_bytes) == hipSuccess;
   ok = ok && hipMalloc((void**)&p->d_err, 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&p->d_counters, 64) == hipSuccess;
+  if (ok && cfg->precision == TDI_FP32_BULK && cfg->mode != TDI_MODE_FULL) {
+    // fits of the fast LFA path: at most one partial tile per source beyond the full ones
+    p->fit_tiles = max_total_samples / tdi::kTileLfaFast + max_sources + 1;
+    ok = hipMalloc((void**)&p->d_fits, (size_t)p->fit_tiles * tdi::kFitLen * sizeof(double)) == hipSuccess;
+  }
   ok = ok && hipHostMalloc((void**)&p->h_params, p->params_bytes, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&p->staged_free, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&p->handoff, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&p->graph_stream, hipStreamNonBlocking) == hipSuccess;
   for (int i = 0; ok && i < kEventRing; ++i)
-    for (int j = 0; ok && j < 3; ++j) ok = hipEventCreate(&p->ev[i][j]) == hipSuccess;
+    for (int j = 0; ok && j < kEvPerRun; ++j) ok = hipEventCreate(&p->ev[i][j]) == hipSuccess;
   if (!ok) {
     tdi_plan_destroy(p);
     return TDI_ENOMEM;
@@ -497,6 +514,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   // constant part of the parameter block
   tdi::KParams& kp = *p->h_params;
   kp.err = p->d_err;
+  kp.lfa_fits = p->d_fits;
   kp.counters = p->d_counters;
   tdi::OrbitDev& od = kp.orb;
   od.kind = orb->kind;
@@ -539,7 +557,7 @@ tdi_status tdi_plan_destroy(tdi_plan* p) {
   hipStreamSynchronize(p->user_stream);
   destroy_graph(p);
   for (int i = 0; i < kEventRing; ++i)
-    for (int j = 0; j < 3; ++j)
+    for (int j = 0; j < kEvPerRun; ++j)
       if (p->ev[i][j]) hipEventDestroy(p->ev[i][j]);
   if (p->staged_free) hipEventDestroy(p->staged_free);
   if (p->handoff) hipEventDestroy(p->handoff);
@@ -547,6 +565,7 @@ tdi_status tdi_plan_destroy(tdi_plan* p) {
   if (p->d_params) hipFree(p->d_params);
   if (p->d_err) hipFree(p->d_err);
   if (p->d_counters) hipFree(p->d_counters);
+  if (p->d_fits) hipFree(p->d_fits);
   if (p->h_params) hipHostFree(p->h_params);
   free(p);
   return TDI_OK;
@@ -590,19 +609,19 @@ tdi_status tdi_plan_kernel_times(tdi_plan* p, float* ms, int32_t cap, int32_t* c
   *count = 0;
   if (hipStreamSynchronize(p->user_stream) != hipSuccess) return TDI_EDEVICE;
   if (hipStreamSynchronize(p->graph_stream) != hipSuccess) return TDI_EDEVICE;
-  // two values per run: LFA kernel (graph replays: the whole graph), full kernel
-  const int runs = std::min<int>(p->ev_count, cap / 2);
+  // three values per run: fit pre-pass, LFA kernel, full kernel
+  const int runs = std::min<int>(p->ev_count, cap / 3);
   int first = (p->ev_head - p->ev_count + kEventRing) % kEventRing;
   first = (first + (p->ev_count - runs)) % kEventRing;
   for (int i = 0; i < runs; ++i) {
     const int slot = (first + i) % kEventRing;
-    float a = 0.0f, b = 0.0f;
-    if (hipEventElapsedTime(&a, p->ev[slot][0], p->ev[slot][1]) != hipSuccess) return TDI_EDEVICE;
-    if (hipEventElapsedTime(&b, p->ev[slot][1], p->ev[slot][2]) != hipSuccess) return TDI_EDEVICE;
-    ms[2 * i] = a;
-    ms[2 * i + 1] = b;
+    for (int j = 0; j < 3; ++j) {
+      float v = 0.0f;
+      if (hipEventElapsedTime(&v, p->ev[slot][j], p->ev[slot][j + 1]) != hipSuccess) return TDI_EDEVICE;
+      ms[3 * i + j] = v;
+    }
   }
-  *count = 2 * runs;
+  *count = 3 * runs;
   p->ev_count = 0;
   return TDI_OK;
 }

@@ -10,6 +10,7 @@ namespace tdi {
 constexpr int kBlock = 256;       // threads per workgroup (4 waves of 64)
 constexpr int kNodes = 7;         // Chebyshev nodes of the per-tile geometry fit (degree 6)
 constexpr int kNQ = 27;           // fitted geometry quantities per tile
+constexpr int kFitLen = kNQ * kNodes;   // doubles per stored tile fit
 constexpr int kTileLfa = 1024;    // outputs per LFA tile (4 waves x 256)
 constexpr int kTileFull = 256;    // outputs per full-response tile
 constexpr int kWaveOut = 256;     // LFA FP32: outputs per wave (4 per lane, stride 64)
@@ -38,6 +39,7 @@ struct OrbitDev {
 // tile of each kernel (LFA and full response).
 struct SrcDev {
   double beta, lam, psi, t0, dt, t_hyb;
+  double c2psi, s2psi;   // cos 2 psi, sin 2 psi
   int64_t off;           // first sample in the flat arrays
   int64_t n;             // number of samples
   int64_t lfa_t0, lfa_kb, lfa_ke;     // LFA tiles cover samples [kb, ke)
@@ -62,6 +64,7 @@ struct KParams {
   int32_t pad0;
   // per plan
   int32_t* err;          // window-check report (8 ints)
+  double* lfa_fits;      // fast LFA path: kFitLen coefficients per LFA tile (pre-pass output)
   uint32_t* counters;    // persistent work counters: [0] LFA, [1] full
   OrbitDev orb;
   int32_t gen, mode, equal_arms, stencil_m, stencil_p, persistent;
@@ -79,6 +82,8 @@ int launch_reset(uint32_t* counters, void* stream);
 // fast != 0 selects the FP32 bulk LFA kernel (fp32 must be 1)
 int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t lds_bytes, void* stream);
 int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
+// geometry fits of all LFA tiles for the fast path (grid-stride over tiles)
+int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream);
 // LFA dynamic LDS: h window (FP64), reused for the FP32 wave tables, then the
 // derivative window; goff receives the byte offset of the latter.  Fast path:
 // h window and the three F_l series, overlaid when one stencil sweep suffices.

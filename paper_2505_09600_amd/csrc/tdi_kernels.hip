@@ -269,38 +269,47 @@ __device__ __forceinline__ double geo_eval(const GeoFit& F, int q, double s) {
   return v;
 }
 
+// Fit interval [ka, kb] (sample indices) -> centre and half width.
+__device__ __forceinline__ void fit_span(double ka, double kb, double& kc, double& kh) {
+  kc = 0.5 * (ka + kb);
+  kh = fmax(0.5 * (kb - ka), 0.5);
+}
+
+// Node values r = j * 6 + a (node j, link slot a) of the fit over [kc - kh, kc + kh].
+__device__ __forceinline__ void fit_node(const KParams& P, const SrcDev& S, double kc, double kh, int r,
+                                         double vals[kNodes][kNQ]) {
+  const int j = r / 6, a = r % 6;
+  const double t = S.t0 + (kc + c_snode[j] * kh) * S.dt;
+  double g[5];
+  node_geometry(P.orb, S.beta, S.lam, t, a, g);
+  vals[j][qT(a)] = g[0];
+  vals[j][qXp(a)] = g[1];
+  vals[j][qXc(a)] = g[2];
+  vals[j][qD(a)] = g[3];
+  if (a < 3) vals[j][qKR(a)] = g[4];
+}
+
+// Monomial coefficient e = q * kNodes + m from the node values.
+__device__ __forceinline__ double fit_coef(const double vals[kNodes][kNQ], int e) {
+  const int q = e / kNodes, m = e % kNodes;
+  if (m == 0) return vals[kNodes / 2][q];    // the centre node is s = 0
+  double c = 0.0;
+  for (int j = 0; j < kNodes; ++j) c = fma(c_vinv[m][j], vals[j][q], c);
+  return c;
+}
+
 // Collective: all threads of the block must call.
 __device__ void fit_geometry(const KParams& P, const SrcDev& S, double ka, double kb, GeoFit& F) {
   const int tid = threadIdx.x;
-  const double kc = 0.5 * (ka + kb);
-  const double kh = fmax(0.5 * (kb - ka), 0.5);
-  if (tid < kNodes * 6) {
-    const int j = tid / 6, a = tid % 6;
-    const double t = S.t0 + (kc + c_snode[j] * kh) * S.dt;
-    double g[5];
-    node_geometry(P.orb, S.beta, S.lam, t, a, g);
-    F.vals[j][qT(a)] = g[0];
-    F.vals[j][qXp(a)] = g[1];
-    F.vals[j][qXc(a)] = g[2];
-    F.vals[j][qD(a)] = g[3];
-    if (a < 3) F.vals[j][qKR(a)] = g[4];
-  }
+  double kc, kh;
+  fit_span(ka, kb, kc, kh);
+  if (tid < kNodes * 6) fit_node(P, S, kc, kh, tid, F.vals);
   if (tid == 0) {
     F.kc = kc;
     F.ikh = 1.0 / kh;
   }
   __syncthreads();
-  if (tid < kNQ * kNodes) {
-    const int q = tid / kNodes, m = tid % kNodes;
-    double c;
-    if (m == 0) {
-      c = F.vals[kNodes / 2][q];    // the centre node is s = 0
-    } else {
-      c = 0.0;
-      for (int j = 0; j < kNodes; ++j) c = fma(c_vinv[m][j], F.vals[j][q], c);
-    }
-    F.coef[q][m] = c;
-  }
+  if (tid < kNQ * kNodes) F.coef[tid / kNodes][tid % kNodes] = fit_coef(F.vals, tid);
   __syncthreads();
 }
 
@@ -795,8 +804,40 @@ struct FastWave {
   float hr;                    // wave centre relative to its first output
 };
 
+// Geometry sample points of a chunk: 0-11 the first, middle and last output
+// of each wave, 12-13 the chunk ends, 14-22 three points per link bracketing
+// the chunk's element window (precombination models).
+constexpr int kFPts = 23;
+constexpr int kFQ = 12;        // per point: k.R_i/c, T_l, xi+_l, xi_x_l of the positive links
+
+__device__ __forceinline__ double fast_point(int pt, int64_t kc0, int ccnt, int N, bool& live) {
+  live = true;
+  if (pt < 12) {
+    const int w = pt / 3, p = pt % 3;
+    const int wc = min(max(ccnt - w * kFWave, 0), kFWave);
+    if (wc <= 0) {
+      live = false;
+      return 0.0;
+    }
+    const double hr = 0.5 * (double)(wc - 1);
+    return (double)(kc0 + (int64_t)w * kFWave) + hr + (double)(p - 1) * hr;
+  }
+  if (pt < 14) return pt == 12 ? (double)kc0 : (double)(kc0 + ccnt - 1);
+  const int p = (pt - 14) % 3;
+  return p == 0 ? (double)(kc0 - N / 2 - 4)
+                : (p == 1 ? (double)kc0 + 0.5 * (double)(ccnt - 1) : (double)(kc0 + ccnt - 1 + N / 2 + 4));
+}
+
+__device__ __forceinline__ int fast_qindex(int qi) {
+  const int kind = qi / 3, i = qi % 3;
+  return kind == 0 ? qKR(i) : (kind == 1 ? qT(i) : (kind == 2 ? qXp(i) : qXc(i)));
+}
+
+constexpr int kEdgeMax = 64;   // >= N + kFR + 2 hw + 8 for every supported N
+
 struct FastShared {
   GeoFit F;
+  double gv[kFPts][kFQ];       // geometry at the sample points
   int64_t src, k0;
   int32_t cnt, pad0;
   double c2, s2, inv_scale, kH;
@@ -808,7 +849,93 @@ struct FastShared {
   double pc[3][2][3];          // precombination quadratics: link, {c+, c_x}, coefficient
   double ec[3];                // their centres (element index)
   FastWave W[4];
+  // raw derivative pairs (g+, g_x) of the elements next to the two ends of the
+  // series, [0] for elements 0.., [1] for elements ..n-1 (exact edge reads)
+  float2 gedge[2][kEdgeMax];
 };
+
+// Exact read near an end of the series: the oracle's split, Lagrange weights
+// w_j = norm_j P(x) / (x - x_j) with P(x) = prod_i (x - x_i) (x = 0 reads the
+// node), on the raw pairs, and the polarisation coefficients at the output
+// time.  j0 is the absolute element of tap 0, ne the number of stored pairs.
+template <int N>
+__device__ __forceinline__ bool edge_pair(const FastShared& sh, int64_t j, int64_t n, int ne, float2& g) {
+  if (j < 0 || j >= n) { g = make_float2(0.0f, 0.0f); return true; }
+  if (j < ne) { g = sh.gedge[0][j]; return true; }
+  if (j >= n - ne) { g = sh.gedge[1][j - (n - ne)]; return true; }
+  return false;
+}
+
+template <int N>
+__device__ __forceinline__ bool edge_read(const FastShared& sh, int64_t j0, int64_t n, int ne, double x,
+                                          double& sp, double& sx) {
+  sp = sx = 0.0;
+  float2 g;
+  if (x == 0.0) {
+    if (!edge_pair<N>(sh, j0 + N / 2 - 1, n, ne, g)) return false;
+    sp = g.x;
+    sx = g.y;
+    return true;
+  }
+  double Pn = 1.0;
+#pragma unroll 1
+  for (int i = 0; i < N; ++i) Pn *= x - (double)(i - N / 2 + 1);
+  // unit-spaced nodes: norm_j = (-1)^(N-1-j) / (j! (N-1-j)!), so
+  // norm_{j+1} = -norm_j (N-1-j) / (j+1), starting from norm_0 = lag_norm<N>(0)
+  double nj = lag_norm<N>(0);
+  bool ok = true;
+#pragma unroll 1
+  for (int j = 0; j < N; ++j) {
+    ok = edge_pair<N>(sh, j0 + j, n, ne, g) && ok;
+    const double w = nj * Pn / (x - (double)(j - N / 2 + 1));
+    sp = fma(w, (double)g.x, sp);
+    sx = fma(w, (double)g.y, sx);
+    nj = -nj * (double)(N - 1 - j) / (double)(j + 1);
+  }
+  return ok;
+}
+
+template <int N>
+__host__ __device__ constexpr int kFitPad() { return N / 2 + 8; }
+
+// Pre-pass of the fast LFA kernel: the geometry fit of every LFA tile, six
+// tiles (6 x 42 node evaluations) per workgroup pass, written to P.lfa_fits.
+constexpr int kFitTilesPerPass = kBlock / (kNodes * 6);
+
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_lfa_fit(const KParams* __restrict__ Pp) {
+  const KParams& P = *Pp;
+  const SrcDev* __restrict__ SS = sources_of(Pp);
+  __shared__ double vals[kFitTilesPerPass][kNodes][kNQ];
+  __shared__ double span[kFitTilesPerPass][2];
+  __shared__ int64_t srcs[kFitTilesPerPass];
+  const int tid = threadIdx.x;
+  const int lt = tid / (kNodes * 6), r = tid % (kNodes * 6);
+  for (int64_t tb = (int64_t)blockIdx.x * kFitTilesPerPass; tb < P.n_tiles_lfa;
+       tb += (int64_t)gridDim.x * kFitTilesPerPass) {
+    const int64_t tile = tb + lt;
+    const bool mine = lt < kFitTilesPerPass && tile < P.n_tiles_lfa;
+    if (mine && r == 0) {
+      const int64_t s = find_source(SS, P.n_src, tile, true);
+      const SrcDev& S = SS[s];
+      const int64_t k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfaFast;
+      const int64_t cnt = min((int64_t)kTileLfaFast, S.lfa_ke - k0);
+      double kc, kh;
+      fit_span((double)(k0 - kFitPad<N>()), (double)(k0 + cnt - 1 + kFitPad<N>()), kc, kh);
+      span[lt][0] = kc;
+      span[lt][1] = kh;
+      srcs[lt] = s;
+    }
+    __syncthreads();
+    if (mine) fit_node(P, SS[srcs[lt]], span[lt][0], span[lt][1], r, vals[lt]);
+    __syncthreads();
+    for (int e = tid; e < kFitTilesPerPass * kFitLen; e += kBlock) {
+      const int t = e / kFitLen, c = e % kFitLen;
+      if (tb + t < P.n_tiles_lfa) P.lfa_fits[(tb + t) * (int64_t)kFitLen + c] = fit_coef(vals[t], c);
+    }
+    __syncthreads();
+  }
+}
 
 template <int N>
 __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restrict__ Pp) {
@@ -838,10 +965,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
       sh.src = s;
       sh.k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfaFast;
       sh.cnt = (int32_t)min((int64_t)kTileLfaFast, S.lfa_ke - sh.k0);
-      double sn, cs;
-      sincos(2.0 * S.psi, &sn, &cs);
-      sh.c2 = cs;
-      sh.s2 = sn;
+      sh.c2 = S.c2psi;
+      sh.s2 = S.s2psi;
       double sc = c_stden[st];
       for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
       sh.inv_scale = 1.0 / sc;
@@ -852,38 +977,46 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
     const int64_t k0 = sh.k0;
     const int cnt = sh.cnt;
     const double dt = S.dt;
-    // the fit also covers the elements read around the tile (pad of N/2 + 8)
-    fit_geometry(P, S, (double)(k0 - N / 2 - 8), (double)(k0 + cnt - 1 + N / 2 + 8), sh.F);
+    // geometry fit of the tile from the pre-pass (it covers the elements read
+    // around the tile: pad of N/2 + 8)
+    {
+      const double* fit = P.lfa_fits + tile * (int64_t)kFitLen;
+      for (int e = tid; e < kFitLen; e += kBlock) sh.F.coef[e / kNodes][e % kNodes] = fit[e];
+      if (tid == 0) {
+        double kc, kh;
+        fit_span((double)(k0 - kFitPad<N>()), (double)(k0 + cnt - 1 + kFitPad<N>()), kc, kh);
+        sh.F.kc = kc;
+        sh.F.ikh = 1.0 / kh;
+      }
+      __syncthreads();
+    }
 
     for (int64_t kc0 = k0; kc0 < k0 + cnt; kc0 += kFChunk) {
       const int ccnt = (int)min((int64_t)kFChunk, k0 + cnt - kc0);
-      // ---- A: geometry samples from the fit, one per thread role ----------
-      {
-        int role = -1, w = 0, p = 0;
-        double kq = 0.0;
-        if (tid < 12) {
-          w = tid / 3;
-          p = tid % 3;
-          const int wc = min(max(ccnt - w * kFWave, 0), kFWave);
-          if (wc > 0) {
-            const double hr = 0.5 * (double)(wc - 1);
-            kq = (double)(kc0 + (int64_t)w * kFWave) + hr + (double)(p - 1) * hr;
-            role = 0;
-          }
-        } else if (tid < 14) {
-          kq = tid == 12 ? (double)kc0 : (double)(kc0 + ccnt - 1);
-          role = 1;
-        } else if (tid >= 16 && tid < 25) {
-          w = (tid - 16) / 3;     // link
-          p = (tid - 16) % 3;
-          kq = p == 0 ? (double)(kc0 - N / 2 - 4)
-                      : (p == 1 ? (double)kc0 + 0.5 * (double)(ccnt - 1) : (double)(kc0 + ccnt - 1 + N / 2 + 4));
-          role = 2;
-        }
+      // ---- A: geometry at the sample points (one fitted quantity per thread),
+      //      then the per-point delays and prefactors (one thread per point)
+      for (int e = tid; e < kFPts * kFQ; e += kBlock) {
+        const int pt = e / kFQ, qi = e % kFQ;
+        bool live;
+        const double kq = fast_point(pt, kc0, ccnt, N, live);
+        if (live) sh.gv[pt][qi] = geo_eval(sh.F, fast_qindex(qi), (kq - sh.F.kc) * sh.F.ikh);
+      }
+      __syncthreads();
+      if (tid < kFPts) {
+        const int pt = tid;
+        bool live;
+        const double kq = fast_point(pt, kc0, ccnt, N, live);
+        const int role = !live ? -1 : (pt < 12 ? 0 : (pt < 14 ? 1 : 2));
+        const int w = pt < 12 ? pt / 3 : (pt - 14) / 3, p = pt < 12 ? pt % 3 : (pt - 14) % 3;
         if (role >= 0) {
-          const double s = (kq - sh.F.kc) * sh.F.ikh;
           double T3[3], xp3[3], xc3[3], mu3[3];
-          lfa_geo(sh.F, s, T3, xp3, xc3, mu3);
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            T3[l] = sh.gv[pt][3 + l];
+            xp3[l] = sh.gv[pt][6 + l];
+            xc3[l] = sh.gv[pt][9 + l];
+            mu3[l] = 0.5 * (sh.gv[pt][snd_of(l)] + sh.gv[pt][rcv_of(l)]);
+          }
           double qd[6], sp[6];
 #pragma unroll
           for (int l = 0; l < 3; ++l)
@@ -907,8 +1040,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
               qmin = fmin(qmin, qd[u]);
               qmax = fmax(qmax, qd[u]);
             }
-            sh.qx[tid - 12][0] = qmin;
-            sh.qx[tid - 12][1] = qmax;
+            sh.qx[pt - 12][0] = qmin;
+            sh.qx[pt - 12][1] = qmax;
           } else {
             const int l = w;
             const double ql = 0.5 * (sel3(qd[0], qd[2], qd[4], l) + sel3(qd[1], qd[3], qd[5], l));
@@ -989,14 +1122,17 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
         }
         __syncthreads();
         // ---- D: stencil and precombination, kSR consecutive elements per thread
-        double pcv[3][2][3], ecv[3];
+        const int ne = N + kFR + 2 * hw + 8;     // raw pairs kept at each end
+        // the coefficients vary on the orbital time scale: FP32 models suffice
+        // (F_l is stored in FP32); the stencil sums stay FP64
+        float pcv[3][2][3], ecv[3];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
-          ecv[l] = uniform_f64(sh.ec[l] - (double)g0);   // relative to the window start
+          ecv[l] = (float)(sh.ec[l] - (double)g0);   // relative to the window start
 #pragma unroll
           for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int m = 0; m < 3; ++m) pcv[l][q][m] = uniform_f64(sh.pc[l][q][m]);
+            for (int m = 0; m < 3; ++m) pcv[l][q][m] = (float)sh.pc[l][q][m];
         }
         for (int base = 0; base < ng; base += kSR * kBlock) {
           const int i0 = base + kSR * tid;
@@ -1022,12 +1158,17 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
                 }
               }
               if (!(j >= 0 && j < S.n)) ap = ac = 0.0;
+              const float gp = (float)ap, gx = (float)ac;
+              if (j >= 0 && j < S.n) {
+                if (j < ne) sh.gedge[0][j] = make_float2(gp, gx);
+                if (j >= S.n - ne) sh.gedge[1][j - (S.n - ne)] = make_float2(gp, gx);
+              }
 #pragma unroll
               for (int l = 0; l < 3; ++l) {
-                const double u = (double)(i0 + e) - ecv[l];
-                const double cp = fma(u, fma(u, pcv[l][0][2], pcv[l][0][1]), pcv[l][0][0]);
-                const double cx = fma(u, fma(u, pcv[l][1][2], pcv[l][1][1]), pcv[l][1][0]);
-                fv[l][e] = (float)fma(cp, ap, cx * ac);
+                const float u = (float)(i0 + e) - ecv[l];
+                const float cp = fmaf(u, fmaf(u, pcv[l][0][2], pcv[l][0][1]), pcv[l][0][0]);
+                const float cx = fmaf(u, fmaf(u, pcv[l][1][2], pcv[l][1][1]), pcv[l][1][0]);
+                fv[l][e] = fmaf(cp, gp, cx * gx);
               }
             }
           }
@@ -1087,20 +1228,72 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
                 B[q] = fmaf(wd, win[j + q], B[q]);
               }
             }
-            // side 0 feeds channel (l+2)%3 (Xa), side 1 channel (l+1)%3 (Xb)
+            float Iv[2][kFR];
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
               const int u = 2 * l + side;
               const float dl = Wv.dl[u] - eL, a1 = Wv.a1[u], a2 = Wv.a2[u];
+#pragma unroll
+              for (int q = 0; q < kFR; ++q) {
+                const float r = rL + (float)(q - kFR / 2);
+                Iv[side][q] = fmaf(dl - r * fmaf(a2, r, a1), B[q], A[q]);
+              }
+            }
+            // Near the ends of the series the zero extension makes F_l jump: the
+            // expansion in the offset does not hold for such broadband data, so a
+            // lane whose reads touch an end takes the exact split and weights.
+            const int64_t e_lo = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1;
+            const int64_t e_hi = e_lo + kFR + N - 2;
+            const bool edge = nl > 0 && ((e_lo <= hw + 1 && e_hi >= -hw - 2) ||
+                                         (e_lo <= S.n + hw + 1 && e_hi >= S.n - hw - 2));
+            if (edge) {
+              // raw pairs with the coefficients at the output time: the
+              // precombined F_l is exact only for band-limited data
+              const double mq = (double)Wv.mbar[l] - (double)Wv.gi[l] / (double)kWGrid;
+              const int ne = N + kFR + 2 * hw + 8;
+#pragma unroll 1
+              for (int side = 0; side < 2; ++side) {
+                const int u = 2 * l + side;
+                const float dl = Wv.dl[u], a1 = Wv.a1[u], a2 = Wv.a2[u];
+#pragma unroll 1
+                for (int q = 0; q < nl; ++q) {
+                  const float r = rL + (float)(q - kFR / 2);
+                  const int64_t k = kw0 + kFR * lane + q;
+                  const double qf = mq - (double)(dl - r * fmaf(a2, r, a1));   // delay in samples
+                  const double mc = ceil(qf);
+                  const int64_t j0 = k - (int64_t)mc - N / 2 + 1;
+                  double sp, sx;
+                  float v = __builtin_nanf("");
+                  if (!edge_read<N>(sh, j0, S.n, ne, mc - qf, sp, sx)) {
+                    ok = false;
+                    report(P.err, 2, k, j0, S.n);
+                  } else {
+                    const double uu = ((double)k - qf) - sh.ec[l];
+                    const double cp = fma(uu, fma(uu, sh.pc[l][0][2], sh.pc[l][0][1]), sh.pc[l][0][0]);
+                    const double cx = fma(uu, fma(uu, sh.pc[l][1][2], sh.pc[l][1][1]), sh.pc[l][1][0]);
+                    v = (float)fma(cp, sp, cx * sx);
+                  }
+                  // constant indices into Iv keep it in registers
+#pragma unroll
+                  for (int qq = 0; qq < kFR; ++qq)
+                    if (qq == q) {
+                      if (side == 0) Iv[0][qq] = v;
+                      else Iv[1][qq] = v;
+                    }
+                }
+              }
+            }
+            // side 0 feeds channel (l+2)%3 (Xa), side 1 channel (l+1)%3 (Xb)
+#pragma unroll
+            for (int side = 0; side < 2; ++side) {
+              const int u = 2 * l + side;
               const float c0 = Wv.c0[u], c1 = Wv.c1[u];
 #pragma unroll
               for (int q = 0; q < kFR; ++q) {
                 const float r = rL + (float)(q - kFR / 2);
-                const float d = dl - r * fmaf(a2, r, a1);
-                const float I = fmaf(d, B[q], A[q]);
                 const float cf = fmaf(r, c1, c0);
-                if (side == 0) Xa[q] = fmaf(cf, I, Xa[q]);
-                else Xb[q] = fmaf(cf, I, Xb[q]);
+                if (side == 0) Xa[q] = fmaf(cf, Iv[0][q], Xa[q]);
+                else Xb[q] = fmaf(cf, Iv[1][q], Xb[q]);
               }
             }
             // the next link's (side 0, side 1) channels are this link's (Xc, Xa)
@@ -1404,6 +1597,12 @@ int launch_lfa_fast_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
 }
 
 template <int N>
+int launch_lfa_fit_t(const KParams* dp, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_lfa_fit<N>), dim3(grid), dim3(kBlock), 0, st, dp);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N>
 int occ_lfa_fast_t(size_t lds) {
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_lfa_fast<N>), kBlock, lds) != hipSuccess) return 1;
@@ -1570,6 +1769,11 @@ int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t
     return -2;
   }
   TDI_DISPATCH(taps, fp32, launch_lfa_t, dp, grid, lds, (hipStream_t)stream);
+  return -2;
+}
+
+int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream) {
+  TDI_DISPATCH_FAST(taps, launch_lfa_fit_t, dp, grid, (hipStream_t)stream);
   return -2;
 }
 

@@ -60,6 +60,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with paper_2505_09600_amd/build_lib.py")
+        # torch ships its own HIP runtime: load it first so that the library binds
+        # to the same runtime as the tensors and streams it is given
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.tdi_check_config.argtypes = [C.POINTER(tdi_config), C.POINTER(tdi_orbit)]

@@ -31,12 +31,15 @@ def tdi():
 
 
 def _sample_indices(n, X_gpu, rng, k_hyb=None, n_uniform=150, half=60):
+    """Uniform samples, every sample within `half` of each channel's peak (so the
+    peak itself, which normalises the error, is sampled), and every sample of the
+    first and last 120, where the zero extension of the series starts and ends."""
     ks = set(rng.integers(0, n, n_uniform).tolist())
     for c in range(3):
         j = int(np.argmax(np.abs(X_gpu[c])))
-        ks.update(range(max(0, j - half), min(n, j + half), 3))
-    ks.update(range(max(0, n - 200), n, 5))
-    ks.update([0, 1, n - 1])
+        ks.update(range(max(0, j - half), min(n, j + half)))
+    ks.update(range(0, min(n, 120)))
+    ks.update(range(max(0, n - 120), n))
     if k_hyb is not None and math.isfinite(k_hyb):
         kh = int(k_hyb)
         ks.update(range(max(0, kh - 450), min(n, kh + 450), 15))
