@@ -265,16 +265,63 @@ void destroy_graph(tdi_plan* p) {
   p->graph = nullptr;
 }
 
-// Capture (upload of the whole parameter block, counter reset, both
-// persistent kernels) once; replays pick up new batches from the block.  With
-// timed = true, event records are captured around the kernels (using the
-// events of ring slot 0 as placeholders) and their nodes located so that each
+// Event-record nodes spliced into the captured chain (stream capture does not
+// record events): before the fit pre-pass, before and after the LFA kernel and
+// after the full kernel.  The chain is upload -> reset -> [fit] -> LFA -> full.
+bool add_graph_events(tdi_plan* p, hipGraph_t g, bool fast) {
+  size_t n = 0, ne = 0;
+  if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess || hipGraphGetEdges(g, nullptr, nullptr, &ne) != hipSuccess)
+    return false;
+  const size_t want = fast ? 5 : 4;
+  if (n != want || ne != want - 1) return false;
+  std::vector<hipGraphNode_t> nodes(n), from(ne), to(ne);
+  if (hipGraphGetNodes(g, nodes.data(), &n) != hipSuccess) return false;
+  if (hipGraphGetEdges(g, from.data(), to.data(), &ne) != hipSuccess) return false;
+  // order the chain from its root
+  std::vector<hipGraphNode_t> chain;
+  for (size_t i = 0; i < n; ++i)
+    if (std::find(to.begin(), to.end(), nodes[i]) == to.end()) chain.push_back(nodes[i]);
+  if (chain.size() != 1) return false;
+  while (chain.size() < n) {
+    const auto it = std::find(from.begin(), from.end(), chain.back());
+    if (it == from.end()) return false;
+    chain.push_back(to[it - from.begin()]);
+  }
+  // the event before step `at` of the chain (at == n: after the last node)
+  auto splice = [&](size_t at, hipEvent_t ev, hipGraphNode_t* out) -> bool {
+    hipGraphNode_t a = chain[at - 1];
+    if (at < chain.size()) {
+      hipGraphNode_t b = chain[at];
+      if (hipGraphRemoveDependencies(g, &a, &b, 1) != hipSuccess) return false;
+      if (hipGraphAddEventRecordNode(out, g, &a, 1, ev) != hipSuccess) return false;
+      if (hipGraphAddDependencies(g, out, &b, 1) != hipSuccess) return false;
+    } else if (hipGraphAddEventRecordNode(out, g, &a, 1, ev) != hipSuccess) {
+      return false;
+    }
+    chain.insert(chain.begin() + at, *out);
+    return true;
+  };
+  // chain indices: 0 upload, 1 reset, then [fit], LFA, full
+  size_t at = 2;
+  if (!splice(at, p->ev[0][0], &p->graph_ev_node[0])) return false;
+  at += 1 + (fast ? 1 : 0);
+  if (!splice(at, p->ev[0][1], &p->graph_ev_node[1])) return false;
+  at += 2;
+  if (!splice(at, p->ev[0][2], &p->graph_ev_node[2])) return false;
+  at += 2;
+  return splice(at, p->ev[0][3], &p->graph_ev_node[3]);
+}
+
+// Capture (upload of the whole parameter block, counter reset, the fit
+// pre-pass and both persistent kernels) once; replays pick up new batches from
+// the block.  With timed = true, event-record nodes are added around the
+// kernels (using the events of ring slot 0 as placeholders) so that each
 // replay can point them at its own ring slot.
 bool capture_graph_once(tdi_plan* p, const Caps& caps, const Launch& ln, bool timed) {
   destroy_graph(p);
   p->graph_timed = false;
   if (hipStreamBeginCapture(p->graph_stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return false;
-  hipError_t e = enqueue(p, p->graph_stream, p->params_bytes, caps, ln, 0, 0, timed ? p->ev[0] : nullptr);
+  hipError_t e = enqueue(p, p->graph_stream, p->params_bytes, caps, ln, 0, 0, nullptr);
   hipGraph_t g = nullptr;
   hipError_t e2 = hipStreamEndCapture(p->graph_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess || !g) {
@@ -283,37 +330,21 @@ bool capture_graph_once(tdi_plan* p, const Caps& caps, const Launch& ln, bool ti
     return false;
   }
   p->graph = g;
+  if (timed) {
+    const bool added = add_graph_events(p, g, caps.fast != 0);
+    (void)hipGetLastError();
+    if (getenv("TDI_DEBUG")) fprintf(stderr, "tdi: graph event nodes %s\n", added ? "added" : "not added");
+    if (!added) {
+      destroy_graph(p);
+      return false;
+    }
+  }
   if (hipGraphInstantiate(&p->graph_exec, g, nullptr, nullptr, 0) != hipSuccess) {
     destroy_graph(p);
     (void)hipGetLastError();
     return false;
   }
-  if (timed) {
-    size_t n = 0;
-    int found = 0;
-    if (hipGraphGetNodes(g, nullptr, &n) == hipSuccess && n > 0) {
-      std::vector<hipGraphNode_t> nodes(n);
-      if (hipGraphGetNodes(g, nodes.data(), &n) == hipSuccess) {
-        for (size_t i = 0; i < n; ++i) {
-          hipGraphNodeType t;
-          hipEvent_t ev = nullptr;
-          if (hipGraphNodeGetType(nodes[i], &t) != hipSuccess || t != hipGraphNodeTypeEventRecord) continue;
-          if (hipGraphEventRecordNodeGetEvent(nodes[i], &ev) != hipSuccess) continue;
-          for (int j = 0; j < kEvPerRun; ++j)
-            if (ev == p->ev[0][j]) {
-              p->graph_ev_node[j] = nodes[i];
-              found |= 1 << j;
-            }
-        }
-      }
-    }
-    (void)hipGetLastError();
-    if (found != (1 << kEvPerRun) - 1) {
-      destroy_graph(p);
-      return false;
-    }
-    p->graph_timed = true;
-  }
+  p->graph_timed = timed;
   p->graph_launch = ln;
   p->graph_lds_lfa = caps.lds_lfa;
   p->graph_lds_full = caps.lds_full;
@@ -378,9 +409,13 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
     bool inner = false;
     if (p->graph_timed) {
       inner = true;
-      for (int j = 0; j < kEvPerRun && inner; ++j)
-        inner = hipGraphExecEventRecordNodeSetEvent(p->graph_exec, p->graph_ev_node[j],
-                                                    p->ev[record ? slot : 0][j]) == hipSuccess;
+      for (int j = 0; j < kEvPerRun && inner; ++j) {
+        const hipError_t es = hipGraphExecEventRecordNodeSetEvent(p->graph_exec, p->graph_ev_node[j],
+                                                                  p->ev[record ? slot : 0][j]);
+        inner = es == hipSuccess;
+        if (!inner && getenv("TDI_DEBUG"))
+          fprintf(stderr, "tdi: retargeting graph event node %d failed: %d\n", j, (int)es);
+      }
       if (!inner) {
         (void)hipGetLastError();
         p->graph_timed = false;

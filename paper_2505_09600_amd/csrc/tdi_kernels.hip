@@ -840,7 +840,7 @@ struct FastShared {
   double gv[kFPts][kFQ];       // geometry at the sample points
   int64_t src, k0;
   int32_t cnt, pad0;
-  double c2, s2, inv_scale, kH;
+  double c2, s2, inv_scale, kH, idt;
   int64_t g0;
   int32_t ng, ngp, bad, pad1;
   double qx[2][2];             // chunk ends: min / max delay (samples)
@@ -967,6 +967,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
       sh.cnt = (int32_t)min((int64_t)kTileLfaFast, S.lfa_ke - sh.k0);
       sh.c2 = S.c2psi;
       sh.s2 = S.s2psi;
+      sh.idt = 1.0 / S.dt;
       double sc = c_stden[st];
       for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
       sh.inv_scale = 1.0 / sc;
@@ -1002,8 +1003,9 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
         if (live) sh.gv[pt][qi] = geo_eval(sh.F, fast_qindex(qi), (kq - sh.F.kc) * sh.F.ikh);
       }
       __syncthreads();
-      if (tid < kFPts) {
-        const int pt = tid;
+      const int pt_mine = lane * 4 + wave;     // set-up work spread over the four waves
+      if (pt_mine < kFPts) {
+        const int pt = pt_mine;
         bool live;
         const double kq = fast_point(pt, kc0, ccnt, N, live);
         const int role = !live ? -1 : (pt < 12 ? 0 : (pt < 14 ? 1 : 2));
@@ -1024,7 +1026,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             for (int side = 0; side < 2; ++side) {
               double d, g;
               lfa_delay(P, T3, mu3, l, side, d, g);
-              qd[2 * l + side] = d / dt;
+              qd[2 * l + side] = d * sh.idt;
               sp[2 * l + side] = g * sh.inv_scale;
             }
           if (role == 0) {
@@ -1065,8 +1067,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
         sh.ngp = sh.ng + kFR + 1;
         sh.bad = (sh.ng > P.cap_g) ? 1 : 0;
         if (sh.bad) report(P.err, 1, kc0, sh.ng, P.cap_g);
-      } else if (tid >= 32 && tid < 44) {
-        const int w = (tid - 32) / 3, l = (tid - 32) % 3;
+      } else if (tid >= 64 && tid < 76) {
+        const int w = (tid - 64) / 3, l = (tid - 64) % 3;
         const int wc = min(max(ccnt - w * kFWave, 0), kFWave);
         FastWave& Wv = sh.W[w];
         if (l == 0) {
@@ -1081,19 +1083,21 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
           const double xbar = (double)gi / (double)kWGrid;
           Wv.mbar[l] = (int64_t)mb;
           Wv.gi[l] = gi;
+          // differences in FP64, scaling in FP32 (the models are stored in FP32)
+          const float ih = hr > 0.0 ? 0.5f / (float)hr : 0.0f;
           for (int side = 0; side < 2; ++side) {
             const int u = 2 * l + side;
             const double v0 = sh.wv[w][0][u][0], v1 = sh.wv[w][1][u][0], v2 = sh.wv[w][2][u][0];
             const double e0 = sh.wv[w][0][u][1], e1 = sh.wv[w][1][u][1], e2 = sh.wv[w][2][u][1];
             Wv.dl[u] = (float)((mb - v1) - xbar);
-            Wv.a1[u] = hr > 0.0 ? (float)((v2 - v0) / (2.0 * hr)) : 0.0f;
-            Wv.a2[u] = hr > 0.0 ? (float)((v2 - 2.0 * v1 + v0) / (2.0 * hr * hr)) : 0.0f;
+            Wv.a1[u] = (float)(v2 - v0) * ih;
+            Wv.a2[u] = (float)(v2 - 2.0 * v1 + v0) * (2.0f * ih * ih);
             Wv.c0[u] = (float)e1;
-            Wv.c1[u] = hr > 0.0 ? (float)((e2 - e0) / (2.0 * hr)) : 0.0f;
+            Wv.c1[u] = (float)(e2 - e0) * ih;
           }
         }
-      } else if (tid >= 48 && tid < 51) {
-        const int l = tid - 48;
+      } else if (tid >= 128 && tid < 131) {
+        const int l = tid - 128;
         const double x0 = sh.pe[l][0][0], x1 = sh.pe[l][1][0], x2 = sh.pe[l][2][0];
         sh.ec[l] = x1;
         for (int q = 0; q < 2; ++q) {
@@ -1139,6 +1143,15 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
           const bool act = i0 < ng;
           float fv[3][kSR];
           if (act) {
+            // this thread's elements e (absolute j0 + e) inside the series: [elo, ehi);
+            // raw pairs kept for e < es0 (first ne elements) and e >= es1 (last ne)
+            const int64_t j0 = g0 + i0;
+            const int elo = (int)min(max(-j0, (int64_t)0), (int64_t)kSR);
+            const int ehi = (int)min(max(S.n - j0, (int64_t)0), (int64_t)kSR);
+            const int es0 = (int)min(max((int64_t)ne - j0, (int64_t)0), (int64_t)kSR);
+            const int es1 = (int)min(max(S.n - ne - j0, (int64_t)0), (int64_t)kSR);
+            const bool near_end = es0 > 0 || es1 < kSR;
+            const float uf0 = (float)i0;
             double hp_[kSR + 6], hc_[kSR + 6];
 #pragma unroll
             for (int m = 0; m < kSR + 6; ++m) {
@@ -1148,24 +1161,23 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             }
 #pragma unroll
             for (int e = 0; e < kSR; ++e) {
-              const int64_t j = g0 + i0 + e;
+              // all seven taps: the coefficient rows are zero beyond 2 hw
               double ap = 0.0, ac = 0.0;
 #pragma unroll
               for (int s = 0; s < 7; ++s) {
-                if (s <= 2 * hw) {
-                  ap = fma(stn[s], hp_[e + s], ap);
-                  ac = fma(stn[s], hc_[e + s], ac);
-                }
+                ap = fma(stn[s], hp_[e + s], ap);
+                ac = fma(stn[s], hc_[e + s], ac);
               }
-              if (!(j >= 0 && j < S.n)) ap = ac = 0.0;
+              const bool in = e >= elo && e < ehi;
+              if (!in) ap = ac = 0.0;
               const float gp = (float)ap, gx = (float)ac;
-              if (j >= 0 && j < S.n) {
-                if (j < ne) sh.gedge[0][j] = make_float2(gp, gx);
-                if (j >= S.n - ne) sh.gedge[1][j - (S.n - ne)] = make_float2(gp, gx);
+              if (near_end && in) {
+                if (e < es0) sh.gedge[0][(int)(j0 + e)] = make_float2(gp, gx);
+                if (e >= es1) sh.gedge[1][(int)(j0 + e - (S.n - ne))] = make_float2(gp, gx);
               }
 #pragma unroll
               for (int l = 0; l < 3; ++l) {
-                const float u = (float)(i0 + e) - ecv[l];
+                const float u = (uf0 + (float)e) - ecv[l];
                 const float cp = fmaf(u, fmaf(u, pcv[l][0][2], pcv[l][0][1]), pcv[l][0][0]);
                 const float cx = fmaf(u, fmaf(u, pcv[l][1][2], pcv[l][1][1]), pcv[l][1][0]);
                 fv[l][e] = fmaf(cp, gp, cx * gx);
@@ -1305,27 +1317,31 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
               Xa[q] = t;
             }
           }
-          // after three links: X = Xc, Y = Xb, Z = Xa
-          const double kH = sh.kH;
+          // after three links: X = Xc, Y = Xb, Z = Xa.  Hybrid: w+ = 1/(1+e^z),
+          // z = (k - kH)/sigma, zero beyond k - kH = T/2; a wave whose outputs all
+          // have z <= -17 (w+ rounds to 1 in FP32) skips the weight.
+          const double relL = (double)(kw0 + kFR * lane) - sh.kH;   // k - kH of the lane's first output
+          const double isg = 1.0 / P.sigma_s;
+          const bool weigh = P.mode == 2 && ((double)(kw0 + wcnt - 1) - sh.kH) * isg > -17.0;
+          const int64_t o0 = S.off + kw0 + kFR * lane;
 #pragma unroll
           for (int q = 0; q < kFR; ++q) {
             if (q >= nl) continue;
-            const int64_t k = kw0 + kFR * lane + q;
             float x = Xc[q], y = Xb[q], z = Xa[q];
             if (!ok) x = y = z = __builtin_nanf("");
-            if (P.mode == 2) {
-              const double rel = (double)k - kH;
+            if (weigh) {
+              const double rel = relL + (double)q;
               if (rel <= 0.5 * P.T_s) {
-                const double zz = rel / P.sigma_s;
-                if (zz > -17.0) {       // below, 1/(1+e^z) rounds to 1 in FP32
-                  const float wgt = 1.0f / (1.0f + expf((float)zz));
+                const float zz = (float)(rel * isg);
+                if (zz > -17.0f) {
+                  const float wgt = 1.0f / (1.0f + expf(zz));
                   x *= wgt; y *= wgt; z *= wgt;
                 }
               } else {
                 x = y = z = 0.0f;
               }
             }
-            store3<float>(P, S.off + k, x, y, z);
+            store3<float>(P, o0 + q, x, y, z);
           }
         }
       } else {
