@@ -50,7 +50,7 @@ struct tdi_plan {
   hipStream_t graph_stream;      // private stream used for capture and replay
   // device memory
   tdi::KParams* d_params;        // KParams followed by SrcDev[max_sources]
-  double* d_fits;                // fast LFA path: per-tile geometry fits
+  void* d_ftiles;                // fast LFA path: per-tile records of the pre-pass
   int64_t fit_tiles;             // their capacity (tiles)
   size_t params_bytes;
   int32_t* d_err;
@@ -525,9 +525,9 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   ok = ok && hipMalloc((void**)&p->d_err, 64) == hipSuccess;
   ok = ok && hipMalloc((void**)&p->d_counters, 64) == hipSuccess;
   if (ok && cfg->precision == TDI_FP32_BULK && cfg->mode != TDI_MODE_FULL) {
-    // fits of the fast LFA path: at most one partial tile per source beyond the full ones
+    // records of the fast LFA path: at most one partial tile per source beyond the full ones
     p->fit_tiles = max_total_samples / tdi::kTileLfaFast + max_sources + 1;
-    ok = hipMalloc((void**)&p->d_fits, (size_t)p->fit_tiles * tdi::kFitLen * sizeof(double)) == hipSuccess;
+    ok = hipMalloc(&p->d_ftiles, (size_t)p->fit_tiles * tdi::fast_tile_bytes()) == hipSuccess;
   }
   ok = ok && hipHostMalloc((void**)&p->h_params, p->params_bytes, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&p->staged_free, hipEventDisableTiming) == hipSuccess;
@@ -549,7 +549,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   // constant part of the parameter block
   tdi::KParams& kp = *p->h_params;
   kp.err = p->d_err;
-  kp.lfa_fits = p->d_fits;
+  kp.lfa_tiles = p->d_ftiles;
   kp.counters = p->d_counters;
   tdi::OrbitDev& od = kp.orb;
   od.kind = orb->kind;
@@ -600,7 +600,7 @@ tdi_status tdi_plan_destroy(tdi_plan* p) {
   if (p->d_params) hipFree(p->d_params);
   if (p->d_err) hipFree(p->d_err);
   if (p->d_counters) hipFree(p->d_counters);
-  if (p->d_fits) hipFree(p->d_fits);
+  if (p->d_ftiles) hipFree(p->d_ftiles);
   if (p->h_params) hipHostFree(p->h_params);
   free(p);
   return TDI_OK;

@@ -10,7 +10,7 @@ namespace tdi {
 constexpr int kBlock = 256;       // threads per workgroup (4 waves of 64)
 constexpr int kNodes = 7;         // Chebyshev nodes of the per-tile geometry fit (degree 6)
 constexpr int kNQ = 27;           // fitted geometry quantities per tile
-constexpr int kFitLen = kNQ * kNodes;   // doubles per stored tile fit
+constexpr int kFitLen = kNQ * kNodes;   // coefficients of one tile fit
 constexpr int kTileLfa = 1024;    // outputs per LFA tile (4 waves x 256)
 constexpr int kTileFull = 256;    // outputs per full-response tile
 constexpr int kWaveOut = 256;     // LFA FP32: outputs per wave (4 per lane, stride 64)
@@ -21,7 +21,7 @@ constexpr int kFastChunk = 2304;
 constexpr int kTileLfaFast = 4 * kFastChunk;
 constexpr int kFastStencilSpan = 11 * kBlock;
 constexpr int kFastOutPerLane = 9;
-constexpr int kWGrid = 64;                 // Lagrange Taylor table: rows per unit offset
+constexpr int kWGrid = 16;                 // Lagrange Taylor table: rows per unit offset
 constexpr double kFastDtMax = 40.0;        // s: quadratic chunk models stay below 1e-6 relative
 constexpr double kFastRateMax = 2.0e-4;    // bound of |d delay / dt| for the offset expansions
 
@@ -64,7 +64,7 @@ struct KParams {
   int32_t pad0;
   // per plan
   int32_t* err;          // window-check report (8 ints)
-  double* lfa_fits;      // fast LFA path: kFitLen coefficients per LFA tile (pre-pass output)
+  void* lfa_tiles;       // fast LFA path: per-tile records written by the pre-pass
   uint32_t* counters;    // persistent work counters: [0] LFA, [1] full
   OrbitDev orb;
   int32_t gen, mode, equal_arms, stencil_m, stencil_p, persistent;
@@ -82,8 +82,10 @@ int launch_reset(uint32_t* counters, void* stream);
 // fast != 0 selects the FP32 bulk LFA kernel (fp32 must be 1)
 int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t lds_bytes, void* stream);
 int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
-// geometry fits of all LFA tiles for the fast path (grid-stride over tiles)
+// pre-pass of the fast LFA path: per-tile records (geometry fits, chunk
+// windows, wave models) for all LFA tiles (grid-stride over tiles)
 int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream);
+size_t fast_tile_bytes();     // bytes of one per-tile record
 // LFA dynamic LDS: h window (FP64), reused for the FP32 wave tables, then the
 // derivative window; goff receives the byte offset of the latter.  Fast path:
 // h window and the three F_l series, overlaid when one stencil sweep suffices.

@@ -802,13 +802,32 @@ struct FastWave {
   float dl[6], a1[6], a2[6];   // x_u(r) - xbar = dl - r (a1 + a2 r), r = k - wave centre
   float c0[6], c1[6];          // signed prefactor / stencil scale: c0 + r c1
   float hr;                    // wave centre relative to its first output
+  int32_t pad;
 };
+
+// Parameters of one chunk, written by the pre-pass and copied to LDS by the
+// main kernel.
+struct FastChunk {
+  int64_t g0;                  // first element (sample index) of the window
+  int32_t ng, bad;             // window length; bad: it exceeds the staged capacity
+  double ec[3];                // centres (element index) of the precombination quadratics
+  double pc[3][2][3];          // link, {c+, c_x}, monomial coefficient in (e - ec)
+  FastWave W[4];
+};
+
+struct FastTile {
+  int64_t off, n, k0;          // source offset and length, first output of the tile
+  double kH;                   // switch sample (hybrid), -inf otherwise
+  int32_t cnt, nch;            // outputs and chunks of the tile
+  FastChunk C[4];
+};
+static_assert(sizeof(FastChunk) % 8 == 0 && sizeof(FastTile) % 8 == 0, "record alignment");
+constexpr int kChunkWords = (int)(sizeof(FastChunk) / 4);
 
 // Geometry sample points of a chunk: 0-11 the first, middle and last output
 // of each wave, 12-13 the chunk ends, 14-22 three points per link bracketing
 // the chunk's element window (precombination models).
 constexpr int kFPts = 23;
-constexpr int kFQ = 12;        // per point: k.R_i/c, T_l, xi+_l, xi_x_l of the positive links
 
 __device__ __forceinline__ double fast_point(int pt, int64_t kc0, int ccnt, int N, bool& live) {
   live = true;
@@ -828,51 +847,244 @@ __device__ __forceinline__ double fast_point(int pt, int64_t kc0, int ccnt, int 
                 : (p == 1 ? (double)kc0 + 0.5 * (double)(ccnt - 1) : (double)(kc0 + ccnt - 1 + N / 2 + 4));
 }
 
-__device__ __forceinline__ int fast_qindex(int qi) {
-  const int kind = qi / 3, i = qi % 3;
-  return kind == 0 ? qKR(i) : (kind == 1 ? qT(i) : (kind == 2 ? qXp(i) : qXc(i)));
+template <int N>
+__host__ __device__ constexpr int kFitPad() { return N / 2 + 8; }
+
+// ---------------------------------------------------------------------------
+// Pre-pass of the fast LFA kernel.  Per tile: the degree-6 geometry fit (in
+// LDS only) over the tile and the elements read around it, and from it every
+// chunk's window, each wave's offset and prefactor models and the per-link
+// precombination quadratics, written to P.lfa_tiles.  Six tiles per pass
+// (6 x 42 node evaluations).
+// ---------------------------------------------------------------------------
+constexpr int kPrepTiles = kBlock / (kNodes * 6);
+
+struct PrepShared {
+  double vals[kPrepTiles][kNodes][kNQ];
+  double coef[kPrepTiles][kNQ][kNodes];
+  double kc[kPrepTiles], ikh[kPrepTiles];
+  double c2[kPrepTiles], s2[kPrepTiles], isc[kPrepTiles], idt[kPrepTiles];
+  int64_t src[kPrepTiles], k0[kPrepTiles];
+  int32_t cnt[kPrepTiles], live[kPrepTiles];
+  double wv[kPrepTiles][4][4][3][6][2];   // tile, chunk, wave, point, use, {delay, coefficient}
+  double qx[kPrepTiles][4][2][2];         // tile, chunk, end, {min, max delay}
+  double pe[kPrepTiles][4][3][3][3];      // tile, chunk, link, point, {element, c+, c_x}
+};
+
+__device__ __forceinline__ double prep_eval(const double c[kNQ][kNodes], int q, double s) {
+  double v = c[q][kNodes - 1];
+#pragma unroll
+  for (int m = kNodes - 2; m >= 0; --m) v = fma(v, s, c[q][m]);
+  return v;
 }
 
-constexpr int kEdgeMax = 64;   // >= N + kFR + 2 hw + 8 for every supported N
+template <int N>
+__global__ __launch_bounds__(kBlock) void k_lfa_prep(const KParams* __restrict__ Pp) {
+  const KParams& P = *Pp;
+  const SrcDev* __restrict__ SS = sources_of(Pp);
+  FastTile* __restrict__ TT = static_cast<FastTile*>(P.lfa_tiles);
+  __shared__ PrepShared sh;
+  const int tid = threadIdx.x;
+  const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
+  for (int64_t tb = (int64_t)blockIdx.x * kPrepTiles; tb < P.n_tiles_lfa;
+       tb += (int64_t)gridDim.x * kPrepTiles) {
+    // tile headers
+    if (tid < kPrepTiles) {
+      const int64_t tile = tb + tid;
+      sh.live[tid] = tile < P.n_tiles_lfa ? 1 : 0;
+      if (tile < P.n_tiles_lfa) {
+        const int64_t s = find_source(SS, P.n_src, tile, true);
+        const SrcDev& S = SS[s];
+        const int64_t k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfaFast;
+        const int32_t cnt = (int32_t)min((int64_t)kTileLfaFast, S.lfa_ke - k0);
+        double kc, kh;
+        fit_span((double)(k0 - kFitPad<N>()), (double)(k0 + cnt - 1 + kFitPad<N>()), kc, kh);
+        sh.kc[tid] = kc;
+        sh.ikh[tid] = 1.0 / kh;
+        sh.src[tid] = s;
+        sh.k0[tid] = k0;
+        sh.cnt[tid] = cnt;
+        sh.c2[tid] = S.c2psi;
+        sh.s2[tid] = S.s2psi;
+        double sc = c_stden[st];
+        for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
+        sh.isc[tid] = 1.0 / sc;
+        sh.idt[tid] = 1.0 / S.dt;
+        FastTile& T = TT[tile];
+        T.off = S.off;
+        T.n = S.n;
+        T.k0 = k0;
+        T.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+        T.cnt = cnt;
+        T.nch = (cnt + kFChunk - 1) / kFChunk;
+      }
+    }
+    __syncthreads();
+    // node values and fit
+    {
+      const int lt = tid / (kNodes * 6), r = tid % (kNodes * 6);
+      if (lt < kPrepTiles && sh.live[lt]) {
+        const double kh = 1.0 / sh.ikh[lt];
+        fit_node(P, SS[sh.src[lt]], sh.kc[lt], kh, r, sh.vals[lt]);
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < kPrepTiles * kFitLen; e += kBlock) {
+      const int t = e / kFitLen, c = e % kFitLen;
+      if (sh.live[t]) sh.coef[t][c / kNodes][c % kNodes] = fit_coef(sh.vals[t], c);
+    }
+    __syncthreads();
+    // geometry, delays and prefactors at the sample points of every chunk
+    for (int e = tid; e < kPrepTiles * 4 * kFPts; e += kBlock) {
+      const int t = e / (4 * kFPts), c = (e / kFPts) % 4, pt = e % kFPts;
+      if (!sh.live[t]) continue;
+      const int ccnt = min(kFChunk, sh.cnt[t] - c * kFChunk);
+      if (ccnt <= 0) continue;
+      const int64_t kc0 = sh.k0[t] + (int64_t)c * kFChunk;
+      bool live;
+      const double kq = fast_point(pt, kc0, ccnt, N, live);
+      if (!live) continue;
+      const double s = (kq - sh.kc[t]) * sh.ikh[t];
+      double kR[3], T3[3], xp3[3], xc3[3], mu3[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) kR[i] = prep_eval(sh.coef[t], qKR(i), s);
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        T3[l] = prep_eval(sh.coef[t], qT(l), s);
+        xp3[l] = prep_eval(sh.coef[t], qXp(l), s);
+        xc3[l] = prep_eval(sh.coef[t], qXc(l), s);
+        mu3[l] = 0.5 * (kR[snd_of(l)] + kR[rcv_of(l)]);
+      }
+      double qd[6], sp[6];
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          double d, g;
+          lfa_delay(P, T3, mu3, l, side, d, g);
+          qd[2 * l + side] = d * sh.idt[t];
+          sp[2 * l + side] = g * sh.isc[t];
+        }
+      if (pt < 12) {
+        const int w = pt / 3, p = pt % 3;
+#pragma unroll
+        for (int u = 0; u < 6; ++u) {
+          sh.wv[t][c][w][p][u][0] = qd[u];
+          sh.wv[t][c][w][p][u][1] = sp[u];
+        }
+      } else if (pt < 14) {
+        double qmin = qd[0], qmax = qd[0];
+#pragma unroll
+        for (int u = 1; u < 6; ++u) {
+          qmin = fmin(qmin, qd[u]);
+          qmax = fmax(qmax, qd[u]);
+        }
+        sh.qx[t][c][pt - 12][0] = qmin;
+        sh.qx[t][c][pt - 12][1] = qmax;
+      } else {
+        const int l = (pt - 14) / 3, p = (pt - 14) % 3;
+        const double ql = 0.5 * (sel3(qd[0], qd[2], qd[4], l) + sel3(qd[1], qd[3], qd[5], l));
+        const double xp = sel3(xp3[0], xp3[1], xp3[2], l), xc = sel3(xc3[0], xc3[1], xc3[2], l);
+        sh.pe[t][c][l][p][0] = kq - ql;
+        sh.pe[t][c][l][p][1] = xp * sh.c2[t] + xc * sh.s2[t];
+        sh.pe[t][c][l][p][2] = xc * sh.c2[t] - xp * sh.s2[t];
+      }
+    }
+    __syncthreads();
+    // chunk records: window (kind 0), wave models (1..12), precombination (13..15)
+    for (int e = tid; e < kPrepTiles * 4 * 16; e += kBlock) {
+      const int t = e / 64, c = (e / 16) % 4, kind = e % 16;
+      if (!sh.live[t]) continue;
+      const int ccnt = min(kFChunk, sh.cnt[t] - c * kFChunk);
+      if (ccnt <= 0) continue;
+      const int64_t kc0 = sh.k0[t] + (int64_t)c * kFChunk;
+      FastChunk& R = TT[tb + t].C[c];
+      if (kind == 0) {
+        const double qmin = fmin(sh.qx[t][c][0][0], sh.qx[t][c][1][0]);
+        const double qmax = fmax(sh.qx[t][c][0][1], sh.qx[t][c][1][1]);
+        const int margin = 2 + (int)ceil(4e-4 * (double)ccnt);
+        const int64_t g0 = kc0 - (int64_t)ceil(qmax) - N / 2 + 1 - margin;
+        const int64_t g1 = kc0 + ccnt - 1 - (int64_t)floor(qmin) + N / 2 + margin;
+        const int64_t ng = g1 - g0 + 1;
+        R.g0 = g0;
+        R.ng = (int32_t)min(ng, (int64_t)INT32_MAX);
+        R.bad = ng > P.cap_g ? 1 : 0;
+        if (R.bad) report(P.err, 1, kc0, ng, P.cap_g);
+      } else if (kind <= 12) {
+        const int w = (kind - 1) / 3, l = (kind - 1) % 3;
+        const int wc = min(max(ccnt - w * kFWave, 0), kFWave);
+        FastWave& Wv = R.W[w];
+        if (l == 0) {
+          Wv.wcnt = wc;
+          Wv.hr = 0.5f * (float)(wc - 1);
+        }
+        if (wc > 0) {
+          const double hr = 0.5 * (double)(wc - 1);
+          const double qbar = 0.5 * (sh.wv[t][c][w][1][2 * l][0] + sh.wv[t][c][w][1][2 * l + 1][0]);
+          const double mb = ceil(qbar);
+          const int gi = min(max((int)rint((mb - qbar) * (double)kWGrid), 0), kWGrid);
+          const double xbar = (double)gi / (double)kWGrid;
+          Wv.mbar[l] = (int64_t)mb;
+          Wv.gi[l] = gi;
+          // differences in FP64, scaling in FP32 (the models are stored in FP32)
+          const float ih = hr > 0.0 ? 0.5f / (float)hr : 0.0f;
+          for (int side = 0; side < 2; ++side) {
+            const int u = 2 * l + side;
+            const double v0 = sh.wv[t][c][w][0][u][0], v1 = sh.wv[t][c][w][1][u][0], v2 = sh.wv[t][c][w][2][u][0];
+            const double e0 = sh.wv[t][c][w][0][u][1], e1 = sh.wv[t][c][w][1][u][1], e2 = sh.wv[t][c][w][2][u][1];
+            Wv.dl[u] = (float)((mb - v1) - xbar);
+            Wv.a1[u] = (float)(v2 - v0) * ih;
+            Wv.a2[u] = (float)(v2 - 2.0 * v1 + v0) * (2.0f * ih * ih);
+            Wv.c0[u] = (float)e1;
+            Wv.c1[u] = (float)(e2 - e0) * ih;
+          }
+        }
+      } else {
+        const int l = kind - 13;
+        const double x0 = sh.pe[t][c][l][0][0], x1 = sh.pe[t][c][l][1][0], x2 = sh.pe[t][c][l][2][0];
+        R.ec[l] = x1;
+        for (int q = 0; q < 2; ++q) {
+          const double f0 = sh.pe[t][c][l][0][q + 1], f1 = sh.pe[t][c][l][1][q + 1], f2 = sh.pe[t][c][l][2][q + 1];
+          // quadratic through the three samples, in u = e - x1
+          const double d01 = (x1 > x0) ? (f1 - f0) / (x1 - x0) : 0.0;
+          const double d12 = (x2 > x1) ? (f2 - f1) / (x2 - x1) : 0.0;
+          const double d012 = (x2 > x0) ? (d12 - d01) / (x2 - x0) : 0.0;
+          R.pc[l][q][0] = f1;
+          R.pc[l][q][1] = d01 + (x1 - x0) * d012;
+          R.pc[l][q][2] = d012;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
 
-struct FastShared {
-  GeoFit F;
-  double gv[kFPts][kFQ];       // geometry at the sample points
-  int64_t src, k0;
-  int32_t cnt, pad0;
-  double c2, s2, inv_scale, kH, idt;
-  int64_t g0;
-  int32_t ng, ngp, bad, pad1;
-  double qx[2][2];             // chunk ends: min / max delay (samples)
-  double wv[4][3][6][2];       // wave model samples: wave, point, use, {delay, coefficient}
-  double pe[3][3][3];          // precombination samples: link, point, {element, c+, c_x}
-  double pc[3][2][3];          // precombination quadratics: link, {c+, c_x}, coefficient
-  double ec[3];                // their centres (element index)
-  FastWave W[4];
-  // raw derivative pairs (g+, g_x) of the elements next to the two ends of the
-  // series, [0] for elements 0.., [1] for elements ..n-1 (exact edge reads)
-  float2 gedge[2][kEdgeMax];
-};
+// ---------------------------------------------------------------------------
+// Main kernel of the fast LFA path: per chunk, the record written by the
+// pre-pass and the strain window are staged, then stencil + precombination
+// and the interpolation described above.
+// ---------------------------------------------------------------------------
+constexpr int kEdgeMax = 64;   // >= N + kFR + 2 hw + 8 for every supported N
 
 // Exact read near an end of the series: the oracle's split, Lagrange weights
 // w_j = norm_j P(x) / (x - x_j) with P(x) = prod_i (x - x_i) (x = 0 reads the
 // node), on the raw pairs, and the polarisation coefficients at the output
-// time.  j0 is the absolute element of tap 0, ne the number of stored pairs.
-template <int N>
-__device__ __forceinline__ bool edge_pair(const FastShared& sh, int64_t j, int64_t n, int ne, float2& g) {
+// time.  j0 is the absolute element of tap 0, ne the number of stored pairs;
+// ge[0] holds the pairs of elements 0..ne-1, ge[1] those of n-ne..n-1.
+__device__ __forceinline__ bool edge_pair(const float2 (*ge)[kEdgeMax], int64_t j, int64_t n, int ne, float2& g) {
   if (j < 0 || j >= n) { g = make_float2(0.0f, 0.0f); return true; }
-  if (j < ne) { g = sh.gedge[0][j]; return true; }
-  if (j >= n - ne) { g = sh.gedge[1][j - (n - ne)]; return true; }
+  if (j < ne) { g = ge[0][j]; return true; }
+  if (j >= n - ne) { g = ge[1][j - (n - ne)]; return true; }
   return false;
 }
 
 template <int N>
-__device__ __forceinline__ bool edge_read(const FastShared& sh, int64_t j0, int64_t n, int ne, double x,
+__device__ __forceinline__ bool edge_read(const float2 (*ge)[kEdgeMax], int64_t j0, int64_t n, int ne, double x,
                                           double& sp, double& sx) {
   sp = sx = 0.0;
   float2 g;
   if (x == 0.0) {
-    if (!edge_pair<N>(sh, j0 + N / 2 - 1, n, ne, g)) return false;
+    if (!edge_pair(ge, j0 + N / 2 - 1, n, ne, g)) return false;
     sp = g.x;
     sx = g.y;
     return true;
@@ -886,7 +1098,7 @@ __device__ __forceinline__ bool edge_read(const FastShared& sh, int64_t j0, int6
   bool ok = true;
 #pragma unroll 1
   for (int j = 0; j < N; ++j) {
-    ok = edge_pair<N>(sh, j0 + j, n, ne, g) && ok;
+    ok = edge_pair(ge, j0 + j, n, ne, g) && ok;
     const double w = nj * Pn / (x - (double)(j - N / 2 + 1));
     sp = fma(w, (double)g.x, sp);
     sx = fma(w, (double)g.y, sx);
@@ -896,268 +1108,79 @@ __device__ __forceinline__ bool edge_read(const FastShared& sh, int64_t j0, int6
 }
 
 template <int N>
-__host__ __device__ constexpr int kFitPad() { return N / 2 + 8; }
-
-// Pre-pass of the fast LFA kernel: the geometry fit of every LFA tile, six
-// tiles (6 x 42 node evaluations) per workgroup pass, written to P.lfa_fits.
-constexpr int kFitTilesPerPass = kBlock / (kNodes * 6);
-
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_lfa_fit(const KParams* __restrict__ Pp) {
-  const KParams& P = *Pp;
-  const SrcDev* __restrict__ SS = sources_of(Pp);
-  __shared__ double vals[kFitTilesPerPass][kNodes][kNQ];
-  __shared__ double span[kFitTilesPerPass][2];
-  __shared__ int64_t srcs[kFitTilesPerPass];
-  const int tid = threadIdx.x;
-  const int lt = tid / (kNodes * 6), r = tid % (kNodes * 6);
-  for (int64_t tb = (int64_t)blockIdx.x * kFitTilesPerPass; tb < P.n_tiles_lfa;
-       tb += (int64_t)gridDim.x * kFitTilesPerPass) {
-    const int64_t tile = tb + lt;
-    const bool mine = lt < kFitTilesPerPass && tile < P.n_tiles_lfa;
-    if (mine && r == 0) {
-      const int64_t s = find_source(SS, P.n_src, tile, true);
-      const SrcDev& S = SS[s];
-      const int64_t k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfaFast;
-      const int64_t cnt = min((int64_t)kTileLfaFast, S.lfa_ke - k0);
-      double kc, kh;
-      fit_span((double)(k0 - kFitPad<N>()), (double)(k0 + cnt - 1 + kFitPad<N>()), kc, kh);
-      span[lt][0] = kc;
-      span[lt][1] = kh;
-      srcs[lt] = s;
-    }
-    __syncthreads();
-    if (mine) fit_node(P, SS[srcs[lt]], span[lt][0], span[lt][1], r, vals[lt]);
-    __syncthreads();
-    for (int e = tid; e < kFitTilesPerPass * kFitLen; e += kBlock) {
-      const int t = e / kFitLen, c = e % kFitLen;
-      if (tb + t < P.n_tiles_lfa) P.lfa_fits[(tb + t) * (int64_t)kFitLen + c] = fit_coef(vals[t], c);
-    }
-    __syncthreads();
-  }
-}
-
-template <int N>
 __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restrict__ Pp) {
   const KParams& P = *Pp;
-  const SrcDev* __restrict__ SS = sources_of(Pp);
-  __shared__ FastShared sh;
+  const FastTile* __restrict__ TT = static_cast<const FastTile*>(P.lfa_tiles);
+  __shared__ FastChunk ch;                      // the current chunk's record
+  __shared__ float2 gedge[2][kEdgeMax];         // raw (g+, g_x) next to the series ends
   __shared__ int64_t s_next;
   extern __shared__ __align__(16) char dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const double2* hwin = reinterpret_cast<const double2*>(dyn);      // [nh] (h+, hx), FP64
-  double2* hwin_w = reinterpret_cast<double2*>(dyn);
-  float* Fw = reinterpret_cast<float*>(dyn + P.lfa_goff);           // [3][ngp], FP32
-  const bool overlay = P.lfa_goff == 0;
+  float* Fw = reinterpret_cast<float*>(dyn);                        // [3][ngp], FP32
   const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
   const int hw = c_sthw[st];
   double stn[7];
 #pragma unroll
   for (int s = 0; s < 7; ++s) stn[s] = c_stnum[st][s];
+  const int ne = N + kFR + 2 * hw + 8;          // raw pairs kept at each end
 
   int64_t iter = 0;
   for (;;) {
     const int64_t tile = next_tile(P, P.counters + 0, P.n_tiles_lfa, iter, &s_next);
     if (tile >= P.n_tiles_lfa) break;
-    if (tid == 0) {
-      const int64_t s = find_source(SS, P.n_src, tile, true);
-      const SrcDev& S = SS[s];
-      sh.src = s;
-      sh.k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfaFast;
-      sh.cnt = (int32_t)min((int64_t)kTileLfaFast, S.lfa_ke - sh.k0);
-      sh.c2 = S.c2psi;
-      sh.s2 = S.s2psi;
-      sh.idt = 1.0 / S.dt;
-      double sc = c_stden[st];
-      for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
-      sh.inv_scale = 1.0 / sc;
-      sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
-    }
-    __syncthreads();
-    const SrcDev& S = SS[sh.src];
-    const int64_t k0 = sh.k0;
-    const int cnt = sh.cnt;
-    const double dt = S.dt;
-    // geometry fit of the tile from the pre-pass (it covers the elements read
-    // around the tile: pad of N/2 + 8)
-    {
-      const double* fit = P.lfa_fits + tile * (int64_t)kFitLen;
-      for (int e = tid; e < kFitLen; e += kBlock) sh.F.coef[e / kNodes][e % kNodes] = fit[e];
-      if (tid == 0) {
-        double kc, kh;
-        fit_span((double)(k0 - kFitPad<N>()), (double)(k0 + cnt - 1 + kFitPad<N>()), kc, kh);
-        sh.F.kc = kc;
-        sh.F.ikh = 1.0 / kh;
-      }
-      __syncthreads();
-    }
+    const FastTile& T = TT[tile];
+    const int64_t off = T.off, n = T.n, k0 = T.k0;
+    const double kH = T.kH;
+    const int cnt = T.cnt, nch = T.nch;
 
-    for (int64_t kc0 = k0; kc0 < k0 + cnt; kc0 += kFChunk) {
-      const int ccnt = (int)min((int64_t)kFChunk, k0 + cnt - kc0);
-      // ---- A: geometry at the sample points (one fitted quantity per thread),
-      //      then the per-point delays and prefactors (one thread per point)
-      for (int e = tid; e < kFPts * kFQ; e += kBlock) {
-        const int pt = e / kFQ, qi = e % kFQ;
-        bool live;
-        const double kq = fast_point(pt, kc0, ccnt, N, live);
-        if (live) sh.gv[pt][qi] = geo_eval(sh.F, fast_qindex(qi), (kq - sh.F.kc) * sh.F.ikh);
-      }
-      __syncthreads();
-      const int pt_mine = lane * 4 + wave;     // set-up work spread over the four waves
-      if (pt_mine < kFPts) {
-        const int pt = pt_mine;
-        bool live;
-        const double kq = fast_point(pt, kc0, ccnt, N, live);
-        const int role = !live ? -1 : (pt < 12 ? 0 : (pt < 14 ? 1 : 2));
-        const int w = pt < 12 ? pt / 3 : (pt - 14) / 3, p = pt < 12 ? pt % 3 : (pt - 14) % 3;
-        if (role >= 0) {
-          double T3[3], xp3[3], xc3[3], mu3[3];
-#pragma unroll
-          for (int l = 0; l < 3; ++l) {
-            T3[l] = sh.gv[pt][3 + l];
-            xp3[l] = sh.gv[pt][6 + l];
-            xc3[l] = sh.gv[pt][9 + l];
-            mu3[l] = 0.5 * (sh.gv[pt][snd_of(l)] + sh.gv[pt][rcv_of(l)]);
-          }
-          double qd[6], sp[6];
-#pragma unroll
-          for (int l = 0; l < 3; ++l)
-#pragma unroll
-            for (int side = 0; side < 2; ++side) {
-              double d, g;
-              lfa_delay(P, T3, mu3, l, side, d, g);
-              qd[2 * l + side] = d * sh.idt;
-              sp[2 * l + side] = g * sh.inv_scale;
-            }
-          if (role == 0) {
-#pragma unroll
-            for (int u = 0; u < 6; ++u) {
-              sh.wv[w][p][u][0] = qd[u];
-              sh.wv[w][p][u][1] = sp[u];
-            }
-          } else if (role == 1) {
-            double qmin = qd[0], qmax = qd[0];
-#pragma unroll
-            for (int u = 1; u < 6; ++u) {
-              qmin = fmin(qmin, qd[u]);
-              qmax = fmax(qmax, qd[u]);
-            }
-            sh.qx[pt - 12][0] = qmin;
-            sh.qx[pt - 12][1] = qmax;
-          } else {
-            const int l = w;
-            const double ql = 0.5 * (sel3(qd[0], qd[2], qd[4], l) + sel3(qd[1], qd[3], qd[5], l));
-            const double xp = sel3(xp3[0], xp3[1], xp3[2], l), xc = sel3(xc3[0], xc3[1], xc3[2], l);
-            sh.pe[l][p][0] = kq - ql;
-            sh.pe[l][p][1] = xp * sh.c2 + xc * sh.s2;
-            sh.pe[l][p][2] = xc * sh.c2 - xp * sh.s2;
-          }
-        }
-      }
-      __syncthreads();
-      // ---- B: chunk window, wave models, precombination quadratics -------
-      if (tid == 0) {
-        const double qmin = fmin(sh.qx[0][0], sh.qx[1][0]);
-        const double qmax = fmax(sh.qx[0][1], sh.qx[1][1]);
-        const int margin = 2 + (int)ceil(4e-4 * (double)ccnt);
-        const int64_t g0 = kc0 - (int64_t)ceil(qmax) - N / 2 + 1 - margin;
-        const int64_t g1 = kc0 + ccnt - 1 - (int64_t)floor(qmin) + N / 2 + margin;
-        sh.g0 = g0;
-        sh.ng = (int32_t)(g1 - g0 + 1);
-        sh.ngp = sh.ng + kFR + 1;
-        sh.bad = (sh.ng > P.cap_g) ? 1 : 0;
-        if (sh.bad) report(P.err, 1, kc0, sh.ng, P.cap_g);
-      } else if (tid >= 64 && tid < 76) {
-        const int w = (tid - 64) / 3, l = (tid - 64) % 3;
-        const int wc = min(max(ccnt - w * kFWave, 0), kFWave);
-        FastWave& Wv = sh.W[w];
-        if (l == 0) {
-          Wv.wcnt = wc;
-          Wv.hr = 0.5f * (float)(wc - 1);
-        }
-        if (wc > 0) {
-          const double hr = 0.5 * (double)(wc - 1);
-          const double qbar = 0.5 * (sh.wv[w][1][2 * l][0] + sh.wv[w][1][2 * l + 1][0]);
-          const double mb = ceil(qbar);
-          const int gi = min(max((int)rint((mb - qbar) * (double)kWGrid), 0), kWGrid);
-          const double xbar = (double)gi / (double)kWGrid;
-          Wv.mbar[l] = (int64_t)mb;
-          Wv.gi[l] = gi;
-          // differences in FP64, scaling in FP32 (the models are stored in FP32)
-          const float ih = hr > 0.0 ? 0.5f / (float)hr : 0.0f;
-          for (int side = 0; side < 2; ++side) {
-            const int u = 2 * l + side;
-            const double v0 = sh.wv[w][0][u][0], v1 = sh.wv[w][1][u][0], v2 = sh.wv[w][2][u][0];
-            const double e0 = sh.wv[w][0][u][1], e1 = sh.wv[w][1][u][1], e2 = sh.wv[w][2][u][1];
-            Wv.dl[u] = (float)((mb - v1) - xbar);
-            Wv.a1[u] = (float)(v2 - v0) * ih;
-            Wv.a2[u] = (float)(v2 - 2.0 * v1 + v0) * (2.0f * ih * ih);
-            Wv.c0[u] = (float)e1;
-            Wv.c1[u] = (float)(e2 - e0) * ih;
-          }
-        }
-      } else if (tid >= 128 && tid < 131) {
-        const int l = tid - 128;
-        const double x0 = sh.pe[l][0][0], x1 = sh.pe[l][1][0], x2 = sh.pe[l][2][0];
-        sh.ec[l] = x1;
-        for (int q = 0; q < 2; ++q) {
-          const double f0 = sh.pe[l][0][q + 1], f1 = sh.pe[l][1][q + 1], f2 = sh.pe[l][2][q + 1];
-          // quadratic through the three samples, in u = e - x1
-          const double d01 = (x1 > x0) ? (f1 - f0) / (x1 - x0) : 0.0;
-          const double d12 = (x2 > x1) ? (f2 - f1) / (x2 - x1) : 0.0;
-          const double d012 = (x2 > x0) ? (d12 - d01) / (x2 - x0) : 0.0;
-          sh.pc[l][q][0] = f1;
-          sh.pc[l][q][1] = d01 + (x1 - x0) * d012;
-          sh.pc[l][q][2] = d012;
-        }
-      }
-      __syncthreads();
-      const int64_t g0 = sh.g0;
-      const int ng = sh.ng, ngp = sh.ngp, nh = ng + 2 * hw;
-      const bool bad = sh.bad != 0;
+    for (int c = 0; c < nch; ++c) {
+      const int64_t kc0 = k0 + (int64_t)c * kFChunk;
+      const int ccnt = min(kFChunk, cnt - c * kFChunk);
+      const FastChunk& R = T.C[c];
+      const int64_t g0 = R.g0;
+      const int ng = R.ng, ngp = ng + kFR + 1;
+      const bool bad = R.bad != 0;
+      // the chunk record goes to LDS (read after the barrier below)
+      if (tid < kChunkWords) reinterpret_cast<int32_t*>(&ch)[tid] = reinterpret_cast<const int32_t*>(&R)[tid];
 
       if (!bad) {
-        // ---- C: stage the strain (zero outside the series) --------------
-        const int64_t h0 = g0 - hw;
-        for (int i = tid; i < nh; i += kBlock) {
-          const int64_t j = h0 + i;
-          const bool in = j >= 0 && j < S.n;
-          hwin_w[i] = make_double2(in ? P.hp[S.off + j] : 0.0, in ? P.hc[S.off + j] : 0.0);
-        }
-        __syncthreads();
-        // ---- D: stencil and precombination, kSR consecutive elements per thread
-        const int ne = N + kFR + 2 * hw + 8;     // raw pairs kept at each end
+        // ---- stencil and precombination, kSR consecutive elements per thread,
+        // the strain read straight from global memory (neighbouring threads
+        // overlap by 2 hw samples; the cache absorbs the re-reads)
         // the coefficients vary on the orbital time scale: FP32 models suffice
         // (F_l is stored in FP32); the stencil sums stay FP64
         float pcv[3][2][3], ecv[3];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
-          ecv[l] = (float)(sh.ec[l] - (double)g0);   // relative to the window start
+          ecv[l] = (float)(R.ec[l] - (double)g0);   // relative to the window start
 #pragma unroll
           for (int q = 0; q < 2; ++q)
 #pragma unroll
-            for (int m = 0; m < 3; ++m) pcv[l][q][m] = (float)sh.pc[l][q][m];
+            for (int m = 0; m < 3; ++m) pcv[l][q][m] = (float)R.pc[l][q][m];
         }
         for (int base = 0; base < ng; base += kSR * kBlock) {
           const int i0 = base + kSR * tid;
-          const bool act = i0 < ng;
-          float fv[3][kSR];
-          if (act) {
+          if (i0 < ng) {
             // this thread's elements e (absolute j0 + e) inside the series: [elo, ehi);
             // raw pairs kept for e < es0 (first ne elements) and e >= es1 (last ne)
             const int64_t j0 = g0 + i0;
             const int elo = (int)min(max(-j0, (int64_t)0), (int64_t)kSR);
-            const int ehi = (int)min(max(S.n - j0, (int64_t)0), (int64_t)kSR);
+            const int ehi = (int)min(max(n - j0, (int64_t)0), (int64_t)kSR);
             const int es0 = (int)min(max((int64_t)ne - j0, (int64_t)0), (int64_t)kSR);
-            const int es1 = (int)min(max(S.n - ne - j0, (int64_t)0), (int64_t)kSR);
+            const int es1 = (int)min(max(n - ne - j0, (int64_t)0), (int64_t)kSR);
             const bool near_end = es0 > 0 || es1 < kSR;
             const float uf0 = (float)i0;
+            // samples j0 - hw + m, m < kSR + 6, inside the series for m in [mlo, mhi)
+            const int mlo = (int)min(max((int64_t)hw - j0, (int64_t)0), (int64_t)(kSR + 6));
+            const int mhi = (int)min(max(n - j0 + hw, (int64_t)0), (int64_t)(kSR + 6));
+            const double* __restrict__ hpb = P.hp + off + (j0 - hw);
+            const double* __restrict__ hcb = P.hc + off + (j0 - hw);
             double hp_[kSR + 6], hc_[kSR + 6];
 #pragma unroll
             for (int m = 0; m < kSR + 6; ++m) {
-              const double2 v = hwin[min(i0 + m, nh - 1)];
-              hp_[m] = v.x;
-              hc_[m] = v.y;
+              const bool in = m >= mlo && m < mhi;
+              hp_[m] = in ? hpb[m] : 0.0;
+              hc_[m] = in ? hcb[m] : 0.0;
             }
 #pragma unroll
             for (int e = 0; e < kSR; ++e) {
@@ -1172,31 +1195,26 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
               if (!in) ap = ac = 0.0;
               const float gp = (float)ap, gx = (float)ac;
               if (near_end && in) {
-                if (e < es0) sh.gedge[0][(int)(j0 + e)] = make_float2(gp, gx);
-                if (e >= es1) sh.gedge[1][(int)(j0 + e - (S.n - ne))] = make_float2(gp, gx);
+                if (e < es0) gedge[0][(int)(j0 + e)] = make_float2(gp, gx);
+                if (e >= es1) gedge[1][(int)(j0 + e - (n - ne))] = make_float2(gp, gx);
               }
 #pragma unroll
               for (int l = 0; l < 3; ++l) {
                 const float u = (uf0 + (float)e) - ecv[l];
                 const float cp = fmaf(u, fmaf(u, pcv[l][0][2], pcv[l][0][1]), pcv[l][0][0]);
                 const float cx = fmaf(u, fmaf(u, pcv[l][1][2], pcv[l][1][1]), pcv[l][1][0]);
-                fv[l][e] = fmaf(cp, gp, cx * gx);
+                if (i0 + e < ng) Fw[l * ngp + i0 + e] = fmaf(cp, gp, cx * gx);
               }
             }
           }
-          if (overlay) __syncthreads();     // F_l overwrites the strain window
-          if (act) {
-#pragma unroll
-            for (int l = 0; l < 3; ++l)
-#pragma unroll
-              for (int e = 0; e < kSR; ++e)
-                if (i0 + e < ng) Fw[l * ngp + i0 + e] = fv[l][e];
-          }
         }
-        __syncthreads();
+      }
+      __syncthreads();
+
+      if (!bad) {
 
         // ---- E: interpolation, TDI combination, hybrid weight -------------
-        const FastWave& Wv = sh.W[wave];
+        const FastWave& Wv = ch.W[wave];
         const int wcnt = Wv.wcnt;
         const int64_t kw0 = kc0 + (int64_t)wave * kFWave;
         if (wcnt > 0) {
@@ -1222,6 +1240,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             const float e0 = Wv.dl[u0] - rL * fmaf(Wv.a2[u0], rL, Wv.a1[u0]);
             const float e1 = Wv.dl[u1] - rL * fmaf(Wv.a2[u1], rL, Wv.a1[u1]);
             const float eL = 0.5f * (e0 + e1);
+            // the wave's table row, read by scalar loads (SGPR operands)
             const float4* row = wtab_row<N>(__builtin_amdgcn_readfirstlane(Wv.gi[l]));
             float A[kFR], B[kFR];
 #pragma unroll
@@ -1229,11 +1248,14 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
 #pragma unroll
             for (int j = 0; j < N; ++j) {
               const float4 c = row[j];
-              // p(e) = c.x + c.y e + c.z e^2 + c.w e^3 and p'(e) by synthetic division
+              // w = p(e) = c.x + c.y e + c.z e^2 + c.w e^3 by Horner; its slope
+              // p'(e) = c.y + 2 c.z e + 3 c.w e^2 is taken as b1 + e b2 = c.y + 2 c.z e
+              // + 2 c.w e^2: it only multiplies the per-use offset delta (<= 1e-3),
+              // so the dropped c.w e^2 delta is of fifth order in the offsets
               const float b2 = fmaf(eL, c.w, c.z);
               const float b1 = fmaf(eL, b2, c.y);
               const float w = fmaf(eL, b1, c.x);
-              const float wd = fmaf(eL, fmaf(eL, c.w, b2), b1);
+              const float wd = fmaf(eL, b2, b1);
 #pragma unroll
               for (int q = 0; q < kFR; ++q) {
                 A[q] = fmaf(w, win[j + q], A[q]);
@@ -1257,12 +1279,11 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             const int64_t e_lo = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1;
             const int64_t e_hi = e_lo + kFR + N - 2;
             const bool edge = nl > 0 && ((e_lo <= hw + 1 && e_hi >= -hw - 2) ||
-                                         (e_lo <= S.n + hw + 1 && e_hi >= S.n - hw - 2));
+                                         (e_lo <= n + hw + 1 && e_hi >= n - hw - 2));
             if (edge) {
               // raw pairs with the coefficients at the output time: the
               // precombined F_l is exact only for band-limited data
               const double mq = (double)Wv.mbar[l] - (double)Wv.gi[l] / (double)kWGrid;
-              const int ne = N + kFR + 2 * hw + 8;
 #pragma unroll 1
               for (int side = 0; side < 2; ++side) {
                 const int u = 2 * l + side;
@@ -1276,13 +1297,13 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
                   const int64_t j0 = k - (int64_t)mc - N / 2 + 1;
                   double sp, sx;
                   float v = __builtin_nanf("");
-                  if (!edge_read<N>(sh, j0, S.n, ne, mc - qf, sp, sx)) {
+                  if (!edge_read<N>(gedge, j0, n, ne, mc - qf, sp, sx)) {
                     ok = false;
-                    report(P.err, 2, k, j0, S.n);
+                    report(P.err, 2, k, j0, n);
                   } else {
-                    const double uu = ((double)k - qf) - sh.ec[l];
-                    const double cp = fma(uu, fma(uu, sh.pc[l][0][2], sh.pc[l][0][1]), sh.pc[l][0][0]);
-                    const double cx = fma(uu, fma(uu, sh.pc[l][1][2], sh.pc[l][1][1]), sh.pc[l][1][0]);
+                    const double uu = ((double)k - qf) - ch.ec[l];
+                    const double cp = fma(uu, fma(uu, ch.pc[l][0][2], ch.pc[l][0][1]), ch.pc[l][0][0]);
+                    const double cx = fma(uu, fma(uu, ch.pc[l][1][2], ch.pc[l][1][1]), ch.pc[l][1][0]);
                     v = (float)fma(cp, sp, cx * sx);
                   }
                   // constant indices into Iv keep it in registers
@@ -1320,10 +1341,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
           // after three links: X = Xc, Y = Xb, Z = Xa.  Hybrid: w+ = 1/(1+e^z),
           // z = (k - kH)/sigma, zero beyond k - kH = T/2; a wave whose outputs all
           // have z <= -17 (w+ rounds to 1 in FP32) skips the weight.
-          const double relL = (double)(kw0 + kFR * lane) - sh.kH;   // k - kH of the lane's first output
+          const double relL = (double)(kw0 + kFR * lane) - kH;   // k - kH of the lane's first output
           const double isg = 1.0 / P.sigma_s;
-          const bool weigh = P.mode == 2 && ((double)(kw0 + wcnt - 1) - sh.kH) * isg > -17.0;
-          const int64_t o0 = S.off + kw0 + kFR * lane;
+          const bool weigh = P.mode == 2 && ((double)(kw0 + wcnt - 1) - kH) * isg > -17.0;
+          const int64_t o0 = off + kw0 + kFR * lane;
 #pragma unroll
           for (int q = 0; q < kFR; ++q) {
             if (q >= nl) continue;
@@ -1346,7 +1367,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
         }
       } else {
         for (int i = tid; i < ccnt; i += kBlock)
-          store3<float>(P, S.off + kc0 + i, __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
+          store3<float>(P, off + kc0 + i, __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
       }
       __syncthreads();
     }
@@ -1614,7 +1635,7 @@ int launch_lfa_fast_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
 
 template <int N>
 int launch_lfa_fit_t(const KParams* dp, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_lfa_fit<N>), dim3(grid), dim3(kBlock), 0, st, dp);
+  hipLaunchKernelGGL((k_lfa_prep<N>), dim3(grid), dim3(kBlock), 0, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1748,16 +1769,12 @@ int set_constants() {
   return 0;
 }
 
+size_t fast_tile_bytes() { return sizeof(FastTile); }
+
 size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int* goff) {
-  if (fast) {
-    const size_t hb = align16((size_t)(cap_g + 6) * 2 * sizeof(double));
-    const size_t fb = align16((size_t)3 * (cap_g + kFR + 1) * sizeof(float));
-    if (cap_g <= kFastStencilSpan) {        // one stencil sweep: F_l over the strain
-      if (goff) *goff = 0;
-      return hb > fb ? hb : fb;
-    }
-    if (goff) *goff = (int)hb;
-    return hb + fb;
+  if (fast) {                                // the three F_l series only
+    if (goff) *goff = 0;
+    return align16((size_t)3 * (cap_g + kFR + 1) * sizeof(float));
   }
   const size_t tcs = fp32 ? sizeof(float) : sizeof(double);
   size_t hb = align16((size_t)cap_h * 2 * sizeof(double));
