@@ -106,6 +106,150 @@ def cpu_baseline(host_sub, cfg, orb, budget_s: float):
                       f"across sources), {el:.1f} s wall; one core: {m1} samples of one source in {el1:.1f} s"}
 
 
+def time_plan(tdi, torch, hp, hc, recs, offsets, cfg, orb, steps, warmup, autotune=True):
+    """Time one configuration with the library's autotuned, graph-replayed plan;
+    per-kernel times come from the plan's event records."""
+    dev = hp.device
+    total = int(offsets[-1])
+    dt = torch.float32 if cfg["precision"] == 1 else torch.float64
+    X = torch.empty(total, dtype=dt, device=dev)
+    Y = torch.empty_like(X)
+    Z = torch.empty_like(X)
+    src = tdi.make_sources(recs)
+    with tdi.Plan(cfg, orb, len(recs), total, autotune=autotune, use_graph=True) as plan:
+        for _ in range(warmup):
+            plan.run(src, offsets, hp, hc, X, Y, Z)
+        if plan.sync() != tdi.TDI_OK:
+            raise RuntimeError("window check failed")
+        plan.kernel_times()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.run(src, offsets, hp, hc, X, Y, Z)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kt = plan.kernel_times()
+        if plan.sync() != tdi.TDI_OK:
+            raise RuntimeError("window check failed")
+        launch = plan.describe()
+    del X, Y, Z
+    runs = len(kt) // 3
+    mean = [float(np.mean(kt[j::3][:runs])) if runs else float("nan") for j in range(3)]
+    return {"ms_per_run": 1e3 * el / steps, "samples_per_s": total * steps / el,
+            "prep_ms": mean[0], "lfa_ms": mean[1], "full_ms": mean[2], "launch": launch}
+
+
+def secondary(args):
+    """Single-source configurations (c1-c3) and the sampler-scale batch (c5, two
+    device-resident waves of 2048 sources whose per-wave times are summed)."""
+    import torch
+    from paper_2505_09600_amd import tdi
+    from paper_2505_09600_amd import workload as W
+    tdi.lib()
+    dev = torch.device("cuda:0")
+    out = {"metric": METRIC, "unit": "samples/s", "n_gpus": 1, "data": "synthetic",
+           "higher_is_better": True}
+    if args.config in ("c1", "c2", "c3"):
+        runs = {}
+        if args.config == "c1":
+            batch, cfg, orb = W.config_c1()
+            cases = {"full fp64 tdi1.5 N16": cfg}
+            wl = "one pre-merger chirp, 2^14 samples at dt=5 s, frozen constellation (seed 1001)"
+        else:
+            batch, cfg, orb = W.config_c2()
+            if args.config == "c2":
+                cases = {f"full {p} tdi2.0 N32": dict(cfg, mode=0, precision=i) for i, p in ((0, "fp64"), (1, "fp32"))}
+            else:
+                cases = {}
+                for gen in (15, 20):
+                    for st in (2, 4):
+                        for i, pr in ((0, "fp64"), (1, "fp32")):
+                            cases[f"lfa p{st} {pr} tdi{gen}"] = dict(cfg, mode=1, tdi_gen=gen, stencil_order=st, precision=i)
+            wl = "one year at dt=10 s, 3155760 samples, analytic orbit (seed 1002)"
+        hp = torch.as_tensor(batch.hp, device=dev)
+        hc = torch.as_tensor(batch.hc, device=dev)
+        for name, c in cases.items():
+            runs[name] = time_plan(tdi, torch, hp, hc, batch.sources, batch.offsets, c, orb, args.steps, args.warmup)
+            print(f"[bench] {args.config} {name}: {runs[name]['ms_per_run']:.3f} ms/run", file=sys.stderr, flush=True)
+        if args.config == "c3":
+            # the c3 recipe with a chirp mass that reaches the switch (hybrid)
+            n = 3155760
+            mc, beta, lam, psi, iota, _, _ = W.draw_sources(1003, 1, n, n)
+            part = W.make_source(2.0e5, iota[0], beta[0], lam[0], psi[0], n, 10.0, 0.0)
+            hb = W._assemble([part], np)
+            hhp = torch.as_tensor(hb.hp, device=dev)
+            hhc = torch.as_tensor(hb.hc, device=dev)
+            for gen in (15, 20):
+                for i, pr in ((0, "fp64"), (1, "fp32")):
+                    name = f"hybrid {pr} tdi{gen} (mc 2e5, seed 1003)"
+                    c = dict(cfg, mode=2, tdi_gen=gen, stencil_order=4, precision=i)
+                    runs[name] = time_plan(tdi, torch, hhp, hhc, hb.sources, hb.offsets, c, orb, args.steps, args.warmup)
+                    print(f"[bench] c3 {name}: {runs[name]['ms_per_run']:.3f} ms/run", file=sys.stderr, flush=True)
+        out.update({"config": {"workload": f"{args.config}: {wl}"}, "runs": runs,
+                    "steps": args.steps, "warmup": args.warmup})
+        print(json.dumps(out), flush=True)
+        return
+    # c5: 4096 sources x 3e6 samples at dt = 5 s (eccentric modulation) in two waves
+    n = 3000000
+    mc, beta, lam, psi, iota, ns, e0 = W.draw_sources(1005, 4096, n, n, ecc=True)
+    orb = W.default_orbit()
+    waves = []
+    for w in range(2):
+        idx = range(2048 * w, 2048 * (w + 1))
+        total = 2048 * n
+        hp = torch.empty(total, dtype=torch.float64, device=dev)
+        hc = torch.empty_like(hp)
+        recs = []
+        t_gen = time.perf_counter()
+        for j, i in enumerate(idx):
+            rec, a, b, _ = W.make_source(mc[i], iota[i], beta[i], lam[i], psi[i], n, 5.0, 0.0,
+                                         e0=e0[i], xp=torch, device=dev)
+            hp[j * n:(j + 1) * n] = a
+            hc[j * n:(j + 1) * n] = b
+            recs.append(rec)
+            if (j + 1) % 512 == 0:
+                print(f"[bench] c5 wave {w}: {j + 1} sources generated", file=sys.stderr, flush=True)
+        recs = np.array(recs, dtype=W.SOURCE_DTYPE)
+        offsets = np.arange(2049, dtype=np.int64) * n
+        torch.cuda.synchronize()
+        print(f"[bench] c5 wave {w}: generated {total} samples in {time.perf_counter() - t_gen:.1f} s",
+              file=sys.stderr, flush=True)
+        cfg = W.default_config(tdi_gen=20, mode=2, taps=32, stencil_order=4, precision=1)
+        r = time_plan(tdi, torch, hp, hc, recs, offsets, cfg, orb, args.steps, args.warmup)
+        print(f"[bench] c5 wave {w} hybrid fp32: {r['ms_per_run']:.2f} ms/run", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        if not args.no_fp64_reference:
+            # FP64 outputs for the whole wave would not fit beside the strain:
+            # the plain FP64 full response is timed on the wave's first 1024 sources
+            c64 = W.default_config(tdi_gen=20, mode=0, taps=32, stencil_order=4, precision=0)
+            r["fp64_full"] = time_plan(tdi, torch, hp, hc, recs[:1024], offsets[:1025], c64, orb,
+                                       1, 1, autotune=False)
+            r["fp64_full"]["sources"] = 1024
+            print(f"[bench] c5 wave {w} full fp64 (1024 sources): "
+                  f"{r['fp64_full']['ms_per_run']:.1f} ms/run", file=sys.stderr, flush=True)
+            torch.cuda.empty_cache()
+        waves.append(r)
+        del hp, hc
+        torch.cuda.empty_cache()
+    ms = sum(r["ms_per_run"] for r in waves)
+    value = 4096 * n / (ms * 1e-3)
+    out.update({"value": value, "ms_per_step": ms, "steps": args.steps, "warmup": args.warmup,
+                "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+                "config": {"workload": "c5: 4096 sources x 3e6 samples at dt=5 s, eccentric modulation "
+                                       "(seed 1005), hybrid TDI 2.0 FP32-bulk, two device-resident waves "
+                                       "of 2048 sources, per-wave times summed",
+                           "total_samples": 4096 * n},
+                "waves": waves})
+    if not args.no_fp64_reference:
+        ms64 = sum(r["fp64_full"]["ms_per_run"] for r in waves)
+        v64 = 2048 * n / (ms64 * 1e-3)
+        out["fp64_full_reference"] = {"value": v64, "unit": "samples/s",
+                                      "config": "plain full response, FP64, TDI 2.0, timed on "
+                                                "1024 sources of each wave"}
+        out["speedup_vs_fp64_full"] = value / v64
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,11 +263,17 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy a float32 buffer of this size three times (a plain "
                          "copy kernel of known traffic for scaling PMC byte counters)")
+    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c4 (default): the headline batched hybrid line; c1-c3: single-source "
+                         "timings of every mode; c5: the 4096-source batch in two waves")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: only --gpus 1 is supported; the response has no multi-GPU path "
               "(a batch would be sharded by source across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
+    if args.config != "c4":
+        secondary(args)
+        return
 
     import torch
     from paper_2505_09600_amd import tdi
