@@ -57,6 +57,7 @@ typedef enum {
 enum { TDI_ORBIT_FROZEN = 0, TDI_ORBIT_ANALYTIC1 = 1 };
 enum { TDI_MODE_FULL = 0, TDI_MODE_LFA = 1, TDI_MODE_HYBRID = 2 };
 enum { TDI_FP64 = 0, TDI_FP32_BULK = 1 };
+enum { TDI_CHANNELS_XYZ = 0, TDI_CHANNELS_AET = 1 };
 
 /* Constellation orbit (Sec. II.B uses an equal-arm analytic orbit).
  * ANALYTIC1: rigid equilateral first-order analytic orbit at radius R_m with
@@ -97,6 +98,11 @@ typedef struct {
   double hyb_sigma_samples; /* sigmoid width sigma in samples (paper default T/40), > 0 */
   int32_t autotune;         /* 1: time the launch candidates on the first run and keep the best */
   int32_t use_graph;        /* 1: capture the run sequence in a hipGraph and replay it */
+  int32_t channels;         /* TDI_CHANNELS_XYZ: write X, Y, Z.  TDI_CHANNELS_AET: write the
+                               noise-orthogonal combinations defined at the end of Sec. II.B instead,
+                               A = (Z - X)/sqrt 2, E = (X - 2Y + Z)/sqrt 6, T = (X + Y + Z)/sqrt 3,
+                               into the same three arrays (fused into the store) */
+  int32_t reserved;         /* must be 0 */
 } tdi_config;
 
 typedef struct tdi_plan tdi_plan;

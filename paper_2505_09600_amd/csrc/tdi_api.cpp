@@ -107,6 +107,8 @@ tdi_status tdi_check_config(const tdi_config* c, const tdi_orbit* o) {
   if (c->lfa_equal_arms != 0 && c->lfa_equal_arms != 1) return TDI_ERANGE;
   if (c->autotune != 0 && c->autotune != 1) return TDI_ERANGE;
   if (c->use_graph != 0 && c->use_graph != 1) return TDI_ERANGE;
+  if (c->channels != TDI_CHANNELS_XYZ && c->channels != TDI_CHANNELS_AET) return TDI_EUNSUPPORTED;
+  if (c->reserved != 0) return TDI_EINVAL;
   if (!(c->hyb_T_samples > 0.0) || !is_fin(c->hyb_T_samples)) return TDI_ERANGE;
   if (!(c->hyb_sigma_samples > 0.0) || !is_fin(c->hyb_sigma_samples)) return TDI_ERANGE;
   if (!(o->L_m > 0.0) || !is_fin(o->L_m)) return TDI_ERANGE;
@@ -567,6 +569,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   od.L_over_c = orb->L_m / kC;
   kp.gen = cfg->tdi_gen;
   kp.mode = cfg->mode;
+  kp.aet = cfg->channels == TDI_CHANNELS_AET ? 1 : 0;
   kp.equal_arms = cfg->lfa_equal_arms;
   kp.stencil_m = cfg->tdi_gen == 20 ? 3 : 2;
   kp.stencil_p = cfg->stencil_order;

@@ -68,6 +68,7 @@ struct KParams {
   uint32_t* counters;    // persistent work counters: [0] LFA, [1] full
   OrbitDev orb;
   int32_t gen, mode, equal_arms, stencil_m, stencil_p, persistent;
+  int32_t aet, pad1;     // aet: store A, E, T instead of X, Y, Z
   double T_s, sigma_s;
   double D2_bound;       // upper bound of a stage-2 delay (s)
 };

@@ -384,8 +384,23 @@ __device__ __forceinline__ void lfa_geo(const GeoFit& F, double s, double T3[3],
   }
 }
 
+// A, E, T from X, Y, Z (end of Sec. II.B): an orthonormal map, applied in the
+// output precision just before the store.
+template <typename TC>
+__device__ __forceinline__ void to_aet(TC& x, TC& y, TC& z) {
+  const TC r2 = (TC)0.70710678118654752440, r6 = (TC)0.40824829046386301637,
+           r3 = (TC)0.57735026918962576451;
+  const TC a = (z - x) * r2;
+  const TC e = (x - (TC)2 * y + z) * r6;
+  const TC t = (x + y + z) * r3;
+  x = a;
+  y = e;
+  z = t;
+}
+
 template <typename TC>
 __device__ __forceinline__ void store3(const KParams& P, int64_t o, TC x, TC y, TC z) {
+  if (P.aet) to_aet<TC>(x, y, z);
   static_cast<TC*>(P.X)[o] = x;
   static_cast<TC*>(P.Y)[o] = y;
   static_cast<TC*>(P.Z)[o] = z;
@@ -1588,6 +1603,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
         // add w- X^Full to the LFA part written by k_lfa inside the LFA window
         const double w = 1.0 / (1.0 + exp(-rel / P.sigma_s));
         const bool has_lfa = rel <= 0.5 * P.T_s;
+        if (P.aet) to_aet<double>(out[0], out[1], out[2]);
         TC* Xo = static_cast<TC*>(P.X);
         TC* Yo = static_cast<TC*>(P.Y);
         TC* Zo = static_cast<TC*>(P.Z);

@@ -21,6 +21,7 @@ TDI_OK, TDI_EINVAL, TDI_ERANGE, TDI_ENOMEM, TDI_EDEVICE, TDI_EUNSUPPORTED, TDI_E
 TDI_ORBIT_FROZEN, TDI_ORBIT_ANALYTIC1 = 0, 1
 TDI_MODE_FULL, TDI_MODE_LFA, TDI_MODE_HYBRID = 0, 1, 2
 TDI_FP64, TDI_FP32_BULK = 0, 1
+TDI_CHANNELS_XYZ, TDI_CHANNELS_AET = 0, 1
 
 EXPORTED = ["tdi_check_config", "tdi_check_batch", "tdi_plan_create", "tdi_run", "tdi_plan_sync",
             "tdi_plan_kernel_times", "tdi_plan_describe", "tdi_plan_destroy", "tdi_status_str"]
@@ -48,7 +49,7 @@ class tdi_config(C.Structure):
                 ("stencil_order", C.c_int32), ("lfa_equal_arms", C.c_int32),
                 ("precision", C.c_int32), ("hyb_T_samples", C.c_double),
                 ("hyb_sigma_samples", C.c_double), ("autotune", C.c_int32),
-                ("use_graph", C.c_int32)]
+                ("use_graph", C.c_int32), ("channels", C.c_int32), ("reserved", C.c_int32)]
 
 
 _lib = None
@@ -148,7 +149,8 @@ def make_orbit(d: dict) -> tdi_orbit:
 def make_config(d: dict, autotune: int = 0, use_graph: int = 0) -> tdi_config:
     return tdi_config(int(d["tdi_gen"]), int(d["mode"]), int(d["taps"]), int(d["stencil_order"]),
                       int(d.get("equal_arms", 0)), int(d.get("precision", 0)),
-                      float(d["T_samples"]), float(d["sigma_samples"]), int(autotune), int(use_graph))
+                      float(d["T_samples"]), float(d["sigma_samples"]), int(autotune), int(use_graph),
+                      int(d.get("channels", 0)), 0)
 
 
 def make_sources(records) -> C.Array:
