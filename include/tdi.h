@@ -158,6 +158,62 @@ tdi_status tdi_plan_destroy(tdi_plan* plan);
 /* Static, human-readable description of a status code. */
 const char* tdi_status_str(tdi_status s);
 
+/* ---------------------------------------------------------------------------
+ * Noise-weighted inner product of A, E, T series (the likelihood's steps after
+ * the response): <x|y> = 4 Re int df conj(x~) y~ / S_n, Eq. (scalar_product)
+ * and App. (scalar product), with the analytic PSDs of Sec. II.C, Eqs. (SnAE),
+ * (SnT), and the galactic foreground of Eq. (sgal).  x~ is the discrete form of
+ * Eq. (defFT): dt times the DFT of the series zero-extended to
+ * N = max(2, next power of two >= n) samples; the integral is the sum over the
+ * bins 0 < f_k = k / (N dt) < 1 / (2 dt) with f_min <= f_k <= f_max, times
+ * df = 1 / (N dt).  ln L = -1/2 sum_c <d - h|d - h> (Eq. derived_likelihood)
+ * follows from the three products per channel that tdi_ip_run returns.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t tdi_gen;        /* 15 or 20: the TDI factor Lambda(f) of Eqs. (SnAE), (SnT) */
+  int32_t galactic;       /* 1: add the galactic foreground, 0: instrument noise only */
+  double T_obs_years;     /* observation time in the foreground's knee relations, years, > 0 */
+  double L_m;             /* arm length in x = 2 pi f L / c, m, > 0 */
+  double f_min, f_max;    /* band, Hz: 0 < f_min < f_max < c/(4L) (TDI 2.0) or c/(2L) (TDI 1.5),
+                             below the first zero of the PSD */
+} tdi_noise;
+
+typedef struct tdi_ip_plan tdi_ip_plan;
+
+/* Host-only validation of a noise description: TDI_OK, TDI_EINVAL (null),
+ * TDI_EUNSUPPORTED (generation) or TDI_ERANGE. */
+tdi_status tdi_check_noise(const tdi_noise* noise);
+
+/* Create an inner-product plan on the current HIP device for batches of at
+ * most max_sources sources, max_total_samples samples in all and
+ * max_source_samples per source, all sampled at dt seconds.  precision:
+ * TDI_FP64 (double inputs, FP64 transforms) or TDI_FP32_BULK (float inputs,
+ * FP32 transforms); the weighted sums accumulate in FP64 either way.  The plan
+ * owns the 1/S_n table and a transform workspace of 6 max_total_samples
+ * complex elements.  Sources longer than 2^24 (FP32) or 2^22 (FP64) samples
+ * return TDI_ERANGE; no gfx950 device returns TDI_EDEVICE. */
+tdi_status tdi_ip_plan_create(tdi_ip_plan** out, const tdi_noise* noise, int32_t precision, double dt,
+                              int64_t max_sources, int64_t max_total_samples,
+                              int64_t max_source_samples, void* hip_stream);
+
+/* Enqueue the inner products of one batch (asynchronous, on the plan's stream).
+ * offsets: host CSR array of n_sources + 1 entries as for tdi_run.  x, y: host
+ * arrays of three device pointers each, the A, E, T series (float or double
+ * by the plan's precision; a response run with channels = TDI_CHANNELS_AET
+ * writes them).  out: device array of 9 n_sources doubles; source i receives,
+ * for channel c = A, E, T, out[9 i + 3 c + 0..2] = <x|x>, <x|y>, <y|y>.
+ * TDI_ESTATE when the batch exceeds the plan's maxima. */
+tdi_status tdi_ip_run(tdi_ip_plan* plan, int64_t n_sources, const int64_t* offsets,
+                      const void* const* x, const void* const* y, double* out);
+
+/* Kernel durations (ms) of the most recent inner-product runs, three per run:
+ * the column pass, the row pass with the weighted sums, the final reduction.
+ * Waits for the plan's work; the record is cleared afterwards. */
+tdi_status tdi_ip_kernel_times(tdi_ip_plan* plan, float* ms, int32_t cap, int32_t* count);
+
+/* Wait for the plan's outstanding work and release it.  NULL: TDI_EINVAL. */
+tdi_status tdi_ip_plan_destroy(tdi_ip_plan* plan);
+
 #ifdef __cplusplus
 }
 #endif

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtdi.so")
-SOURCES = [os.path.join(CSRC, "tdi_kernels.hip"), os.path.join(CSRC, "tdi_api.cpp")]
+SOURCES = [os.path.join(CSRC, n) for n in ("tdi_kernels.hip", "tdi_api.cpp", "tdi_ip_kernels.hip", "tdi_ip.cpp")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -24,7 +24,9 @@ TDI_FP64, TDI_FP32_BULK = 0, 1
 TDI_CHANNELS_XYZ, TDI_CHANNELS_AET = 0, 1
 
 EXPORTED = ["tdi_check_config", "tdi_check_batch", "tdi_plan_create", "tdi_run", "tdi_plan_sync",
-            "tdi_plan_kernel_times", "tdi_plan_describe", "tdi_plan_destroy", "tdi_status_str"]
+            "tdi_plan_kernel_times", "tdi_plan_describe", "tdi_plan_destroy", "tdi_status_str",
+            "tdi_check_noise", "tdi_ip_plan_create", "tdi_ip_run", "tdi_ip_kernel_times",
+            "tdi_ip_plan_destroy"]
 
 
 class TdiError(RuntimeError):
@@ -50,6 +52,11 @@ class tdi_config(C.Structure):
                 ("precision", C.c_int32), ("hyb_T_samples", C.c_double),
                 ("hyb_sigma_samples", C.c_double), ("autotune", C.c_int32),
                 ("use_graph", C.c_int32), ("channels", C.c_int32), ("reserved", C.c_int32)]
+
+
+class tdi_noise(C.Structure):
+    _fields_ = [("tdi_gen", C.c_int32), ("galactic", C.c_int32), ("T_obs_years", C.c_double),
+                ("L_m", C.c_double), ("f_min", C.c_double), ("f_max", C.c_double)]
 
 
 _lib = None
@@ -80,6 +87,12 @@ def lib():
         L.tdi_plan_kernel_times.argtypes = [P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
         L.tdi_plan_describe.argtypes = [P, C.c_char_p, C.c_int32]
         L.tdi_plan_destroy.argtypes = [P]
+        L.tdi_check_noise.argtypes = [C.POINTER(tdi_noise)]
+        L.tdi_ip_plan_create.argtypes = [C.POINTER(P), C.POINTER(tdi_noise), C.c_int32, C.c_double,
+                                         C.c_int64, C.c_int64, C.c_int64, P]
+        L.tdi_ip_run.argtypes = [P, C.c_int64, C.POINTER(C.c_int64), C.POINTER(P), C.POINTER(P), P]
+        L.tdi_ip_kernel_times.argtypes = [P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
+        L.tdi_ip_plan_destroy.argtypes = [P]
         L.tdi_status_str.argtypes = [C.c_int]
         L.tdi_status_str.restype = C.c_char_p
         for name in EXPORTED:
@@ -252,6 +265,102 @@ def response(batch, cfg: dict, orbit: dict, device="cuda:0", autotune=False, use
         if info is not None:
             info.update(p.describe())
         return np.stack([X.double().cpu().numpy(), Y.double().cpu().numpy(), Z.double().cpu().numpy()])
+
+
+# --- noise-weighted inner product ------------------------------------------------
+def make_noise(d: dict) -> tdi_noise:
+    return tdi_noise(int(d["tdi_gen"]), int(d["galactic"]), float(d["T_obs_years"]), float(d["L_m"]),
+                     float(d["f_min"]), float(d["f_max"]))
+
+
+def tdi_check_noise(noise: tdi_noise) -> int:
+    return lib().tdi_check_noise(C.byref(noise))
+
+
+def tdi_ip_plan_create(noise: tdi_noise, precision: int, dt: float, max_sources: int, max_total: int,
+                       max_source: int, stream: int = 0):
+    h = C.c_void_p()
+    st = lib().tdi_ip_plan_create(C.byref(h), C.byref(noise), int(precision), float(dt), int(max_sources),
+                                  int(max_total), int(max_source), C.c_void_p(stream))
+    return st, h
+
+
+def tdi_ip_run(plan, n_sources: int, offsets, x_ptrs, y_ptrs, out_ptr: int) -> int:
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    xa = (C.c_void_p * 3)(*[C.c_void_p(int(v)) for v in x_ptrs])
+    ya = (C.c_void_p * 3)(*[C.c_void_p(int(v)) for v in y_ptrs])
+    return lib().tdi_ip_run(plan, int(n_sources), offs.ctypes.data_as(C.POINTER(C.c_int64)), xa, ya,
+                            C.c_void_p(out_ptr))
+
+
+def tdi_ip_kernel_times(plan, cap: int = 192):
+    buf = (C.c_float * cap)()
+    n = C.c_int32()
+    st = lib().tdi_ip_kernel_times(plan, buf, cap, C.byref(n))
+    return st, [buf[i] for i in range(n.value)]
+
+
+def tdi_ip_plan_destroy(plan) -> int:
+    return lib().tdi_ip_plan_destroy(plan)
+
+
+class IpPlan:
+    """RAII wrapper of a tdi_ip_plan bound to a torch device and stream."""
+
+    def __init__(self, noise: dict, precision: int, dt: float, max_sources: int, max_total: int,
+                 max_source: int, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the TDI library needs a HIP device (no CPU fallback)")
+        self.torch = torch
+        self.fp64 = int(precision) == TDI_FP64
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        st, h = tdi_ip_plan_create(make_noise(noise), precision, dt, max_sources, max_total, max_source,
+                                   self.stream.cuda_stream)
+        if st != TDI_OK:
+            raise TdiError(st, "tdi_ip_plan_create")
+        self.handle = h
+
+    def run(self, offsets, x3, y3, out=None):
+        """x3, y3: three device tensors each (A, E, T) of the plan's dtype.
+        Returns a (n_sources, 3, 3) float64 device tensor of <x|x>, <x|y>, <y|y>."""
+        torch = self.torch
+        dt = torch.float64 if self.fp64 else torch.float32
+        n_src = len(offsets) - 1
+        total = int(offsets[-1])
+        for t in list(x3) + list(y3):
+            if t.dtype != dt or not t.is_cuda or not t.is_contiguous() or t.numel() < total:
+                raise TypeError("inputs must be contiguous device tensors of the plan's dtype")
+        if out is None:
+            out = torch.empty((max(n_src, 1), 3, 3), dtype=torch.float64, device=x3[0].device)
+        st = tdi_ip_run(self.handle, n_src, offsets, [t.data_ptr() for t in x3],
+                        [t.data_ptr() for t in y3], out.data_ptr())
+        if st != TDI_OK:
+            raise TdiError(st, "tdi_ip_run")
+        return out[:n_src]
+
+    def kernel_times(self):
+        st, v = tdi_ip_kernel_times(self.handle)
+        if st != TDI_OK:
+            raise TdiError(st, "tdi_ip_kernel_times")
+        return v
+
+    def close(self):
+        if getattr(self, "handle", None):
+            tdi_ip_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
 
 
 def header_symbols(path: str | None = None):

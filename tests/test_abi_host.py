@@ -150,3 +150,45 @@ def test_python_plan_fails_loudly_without_gpu():
         pytest.skip("a HIP device is present")
     with pytest.raises(RuntimeError):
         T.Plan(W.default_config(), W.default_orbit(), 1, 10)
+
+
+def _noise(**kw):
+    d = dict(tdi_gen=20, galactic=1, T_obs_years=1.0, L_m=2.5e9, f_min=1e-4, f_max=0.029)
+    d.update(kw)
+    return T.make_noise(d)
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("tdi_gen", 10, T.TDI_EUNSUPPORTED),
+    ("galactic", 2, T.TDI_ERANGE),
+    ("T_obs_years", 0.0, T.TDI_ERANGE),
+    ("L_m", math.nan, T.TDI_ERANGE),
+    ("f_min", 0.0, T.TDI_ERANGE),
+    ("f_max", 1e-5, T.TDI_ERANGE),
+    ("f_max", 0.031, T.TDI_ERANGE),     # past the first zero of the TDI 2.0 PSD, c/(4L)
+])
+def test_noise_validation(L, field, value, code):
+    n = _noise()
+    assert T.tdi_check_noise(n) == T.TDI_OK
+    setattr(n, field, value)
+    assert T.tdi_check_noise(n) == code
+
+
+def test_noise_band_limit_depends_on_generation(L):
+    # TDI 1.5 PSDs vanish first at c/(2L) = 0.06 Hz
+    assert T.tdi_check_noise(_noise(tdi_gen=15, f_max=0.05)) == T.TDI_OK
+    assert T.tdi_check_noise(_noise(tdi_gen=20, f_max=0.05)) == T.TDI_ERANGE
+
+
+def test_ip_entry_points_without_device(L):
+    st, h = T.tdi_ip_plan_create(_noise(), T.TDI_FP32_BULK, 10.0, 4, 1000, 500)
+    assert st == T.TDI_EDEVICE and not h.value
+    # argument errors are reported before any device work
+    assert T.tdi_ip_plan_create(_noise(f_min=-1.0), T.TDI_FP32_BULK, 10.0, 4, 1000, 500)[0] == T.TDI_ERANGE
+    assert T.tdi_ip_plan_create(_noise(), 7, 10.0, 4, 1000, 500)[0] == T.TDI_EUNSUPPORTED
+    assert T.tdi_ip_plan_create(_noise(), T.TDI_FP32_BULK, 0.0, 4, 1000, 500)[0] == T.TDI_ERANGE
+    # longest supported source: 2^24 (FP32), 2^22 (FP64)
+    assert T.tdi_ip_plan_create(_noise(), T.TDI_FP64, 10.0, 4, 1 << 23, (1 << 22) + 1)[0] == T.TDI_ERANGE
+    assert T.tdi_ip_run(None, 1, np.array([0, 5]), [0, 0, 0], [0, 0, 0], 0) == T.TDI_EINVAL
+    assert T.lib().tdi_ip_plan_destroy(None) == T.TDI_EINVAL
+    assert T.lib().tdi_ip_kernel_times(None, None, 0, None) == T.TDI_EINVAL
