@@ -250,6 +250,79 @@ def secondary(args):
     print(json.dumps(out), flush=True)
 
 
+def likelihood(args):
+    """The likelihood's steps after the response on the 512-source batch: the
+    FP32-bulk hybrid response written as A, E, T, then the noise-weighted inner
+    products of data and template per source (TDI 2.0 PSDs with the galactic
+    foreground, 1e-4..0.029 Hz).  The data are the responses of the same sources
+    at a polarisation angle 0.01 rad away."""
+    import torch
+    from paper_2505_09600_amd import tdi
+    from paper_2505_09600_amd import workload as W
+    tdi.lib()
+    dev = torch.device("cuda:0")
+    batch, cfg, orb = W.config_c4(n_sources=args.n_sources, xp=torch, device=dev)
+    total = batch.total
+    hp, hc = batch.hp.contiguous(), batch.hc.contiguous()
+    cfg32 = dict(cfg, precision=1, mode=2, tdi_gen=20, taps=TAPS, stencil_order=4, channels=1)
+    src_h = tdi.make_sources(batch.sources)
+    recs_d = batch.sources.copy()
+    recs_d["psi"] = recs_d["psi"] + 0.01
+    src_d = tdi.make_sources(recs_d)
+    H = [torch.empty(total, dtype=torch.float32, device=dev) for _ in range(3)]
+    D = [torch.empty(total, dtype=torch.float32, device=dev) for _ in range(3)]
+    noise = dict(tdi_gen=20, galactic=1, T_obs_years=1.0, L_m=W.ARM_L, f_min=1e-4, f_max=0.029)
+    n_max = int(np.max(np.diff(batch.offsets)))
+    out = torch.empty((batch.n_sources, 3, 3), dtype=torch.float64, device=dev)
+    with tdi.Plan(cfg32, orb, batch.n_sources, total, autotune=True, use_graph=True) as plan, \
+            tdi.IpPlan(noise, tdi.TDI_FP32_BULK, 10.0, batch.n_sources, total, n_max) as ip:
+        plan.run(src_d, batch.offsets, hp, hc, *D)
+        for _ in range(args.warmup):
+            plan.run(src_h, batch.offsets, hp, hc, *H)
+            ip.run(batch.offsets, D, H, out)
+        if plan.sync() != tdi.TDI_OK:
+            raise RuntimeError("window check failed")
+        plan.kernel_times()
+        ip.kernel_times()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ip.run(batch.offsets, D, H, out)
+        torch.cuda.synchronize()
+        t_ip = (time.perf_counter() - t0) / args.steps
+        kt_ip = ip.kernel_times()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plan.run(src_h, batch.offsets, hp, hc, *H)
+            ip.run(batch.offsets, D, H, out)
+        torch.cuda.synchronize()
+        t_all = (time.perf_counter() - t0) / args.steps
+        kt_resp = plan.kernel_times()
+        ip.kernel_times()
+        ipv = out.cpu().numpy()
+    runs = len(kt_ip) // 3
+    p1, p2, rd = (float(np.mean(kt_ip[j::3][:runs])) for j in range(3))
+    runs_r = len(kt_resp) // 3
+    r_fit, r_lfa, r_full = (float(np.mean(kt_resp[j::3][:runs_r])) for j in range(3))
+    lnl = -0.5 * np.sum(ipv[:, :, 0] - 2.0 * ipv[:, :, 1] + ipv[:, :, 2], axis=1)
+    ip_ms = p1 + p2 + rd
+    gbs = 24.0 * total / (ip_ms * 1e-3) / 1e9
+    res = {"metric": "likelihood steps after the response: samples/s (FP32)", "unit": "samples/s",
+           "n_gpus": 1, "data": "synthetic", "higher_is_better": True, "steps": args.steps,
+           "warmup": args.warmup,
+           "config": {"workload": "512 sources of the batched hybrid benchmark (seed 1004), A, E, T "
+                                  "written by the response, inner products against data at psi + 0.01",
+                      "total_samples": total, "band_hz": [1e-4, 0.029], "tdi": "2.0", "galactic": True},
+           "inner_product": {"value": total / t_ip, "ms_per_step": 1e3 * t_ip, "pass1_ms": p1,
+                             "pass2_ms": p2, "reduce_ms": rd,
+                             "hbm_algorithmic_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                             "bytes_per_sample_algorithmic": 24},
+           "response_plus_inner_product": {"value": total / t_all, "ms_per_step": 1e3 * t_all,
+                                           "response_kernels_ms": [r_fit, r_lfa, r_full]},
+           "lnL_finite": bool(np.all(np.isfinite(lnl))), "lnL_first": [float(v) for v in lnl[:3]]}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -263,14 +336,18 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy a float32 buffer of this size three times (a plain "
                          "copy kernel of known traffic for scaling PMC byte counters)")
-    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "lnl"],
                     help="c4 (default): the headline batched hybrid line; c1-c3: single-source "
-                         "timings of every mode; c5: the 4096-source batch in two waves")
+                         "timings of every mode; c5: the 4096-source batch in two waves; lnl: the "
+                         "inner products that follow the response on the c4 batch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: only --gpus 1 is supported; the response has no multi-GPU path "
               "(a batch would be sharded by source across GPUs with no communication)", file=sys.stderr)
         sys.exit(2)
+    if args.config == "lnl":
+        likelihood(args)
+        return
     if args.config != "c4":
         secondary(args)
         return

@@ -61,6 +61,26 @@ struct Psd {
   }
 };
 
+// e^{-2 pi i m / 2^logM} for m in [0, count), stored as (re, im) pairs of T
+template <typename T>
+std::vector<T> roots(int64_t count, int logM, int64_t stride) {
+  std::vector<T> v(2 * (size_t)count);
+  const double M = ldexp(1.0, logM);
+  for (int64_t m = 0; m < count; ++m) {
+    const double a = 2.0 * M_PI * ((double)(m * stride) / M);
+    v[2 * (size_t)m] = (T)cos(a);
+    v[2 * (size_t)m + 1] = (T)(-sin(a));
+  }
+  return v;
+}
+
+template <typename T>
+bool upload_roots(void** dst, int64_t count, int logM, int64_t stride) {
+  const std::vector<T> v = roots<T>(count, logM, stride);
+  if (hipMalloc(dst, sizeof(T) * v.size()) != hipSuccess) return false;
+  return hipMemcpy(*dst, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice) == hipSuccess;
+}
+
 int log2_fft_length(int64_t n) {
   int lg = 1;
   while (((int64_t)1 << lg) < n) ++lg;
@@ -98,9 +118,14 @@ struct tdi_ip_plan {
   double dt;
   int64_t max_sources, max_total, max_source;
   int logNmax;
-  int64_t kmax;
+  int grid;                       // persistent workgroups: two per compute unit, a multiple of 8
   hipStream_t stream;
-  double* d_winv;
+  double* d_wt;                   // weight tables, one per length (see IpParams)
+  int64_t wofs[32];               // offset of the table of length 2^logN
+  void* d_tw;                     // twiddle tables (see IpParams)
+  void* d_th;
+  void* d_tl;
+  int tbits;
   void* d_ws;
   int64_t ws_cap;                 // complex elements
   double* d_part;
@@ -132,7 +157,10 @@ tdi_status tdi_check_noise(const tdi_noise* n) {
 tdi_status tdi_ip_plan_destroy(tdi_ip_plan* p) {
   if (!p) return TDI_EINVAL;
   (void)hipStreamSynchronize(p->stream);
-  if (p->d_winv) hipFree(p->d_winv);
+  if (p->d_wt) hipFree(p->d_wt);
+  if (p->d_tw) hipFree(p->d_tw);
+  if (p->d_th) hipFree(p->d_th);
+  if (p->d_tl) hipFree(p->d_tl);
   if (p->d_ws) hipFree(p->d_ws);
   if (p->d_part) hipFree(p->d_part);
   if (p->d_params) hipFree(p->d_params);
@@ -175,7 +203,7 @@ tdi_status tdi_ip_plan_create(tdi_ip_plan** out, const tdi_noise* noise, int32_t
   p->max_total = max_total_samples;
   p->max_source = max_source_samples;
   p->logNmax = sp.logN;
-  p->kmax = ((int64_t)1 << sp.logN) / 2;
+  p->grid = std::max(8, (2 * prop.multiProcessorCount + 7) & ~7);
   p->stream = (hipStream_t)hip_stream;
   const int64_t row = (int64_t)1 << ((fp64 ? 12 : 13) - 1);
   const size_t vbytes = fp64 ? 16 : 8;
@@ -183,7 +211,13 @@ tdi_status tdi_ip_plan_create(tdi_ip_plan** out, const tdi_noise* noise, int32_t
   p->ws_cap = 6 * std::max<int64_t>(max_total_samples, 1);
   p->part_cap = 3 * (max_total_samples / row + max_sources) + 3;
   p->params_bytes = sizeof(tdi_ip::IpParams) + sizeof(tdi_ip::IpSrc) * (size_t)max_sources;
-  bool ok = hipMalloc((void**)&p->d_winv, sizeof(double) * 2 * (size_t)(p->kmax + 1)) == hipSuccess;
+  // weight tables for every length 2^1 .. N_max: N entries each (two classes of N/2)
+  int64_t wt_total = 0;
+  for (int lg = 1; lg <= sp.logN; ++lg) {
+    p->wofs[lg] = wt_total;
+    wt_total += (int64_t)1 << lg;
+  }
+  bool ok = hipMalloc((void**)&p->d_wt, sizeof(double) * (size_t)wt_total) == hipSuccess;
   ok = ok && hipMalloc(&p->d_ws, vbytes * (size_t)p->ws_cap) == hipSuccess;
   ok = ok && hipMalloc((void**)&p->d_part, sizeof(double) * 3 * (size_t)p->part_cap) == hipSuccess;
   ok = ok && hipMalloc((void**)&p->d_params, p->params_bytes) == hipSuccess;
@@ -195,19 +229,55 @@ tdi_status tdi_ip_plan_create(tdi_ip_plan** out, const tdi_noise* noise, int32_t
     tdi_ip_plan_destroy(p);
     return TDI_ENOMEM;
   }
-  // 1 / S_n on the finest grid f = k / (N_max dt); shorter transforms read every 2^s-th entry
-  std::vector<double> w(2 * (size_t)(p->kmax + 1), 0.0);
+  // 1 / S_n on the finest grid f = k / (N_max dt), k < N_max / 2; a length
+  // N = N_max / 2^s reads entry k 2^s.  Each length's table is reordered to
+  // the second pass's bin order and zeroed outside the band [f_min, f_max].
+  const int64_t half_max = ((int64_t)1 << sp.logN) / 2;
+  std::vector<double> base(2 * (size_t)half_max, 0.0);
   const Psd psd(*noise);
-  const double Ndt = (double)((int64_t)1 << sp.logN) * dt;
-  for (int64_t k = 1; k <= p->kmax; ++k) {
+  const double Ndt_max = (double)((int64_t)1 << sp.logN) * dt;
+  for (int64_t k = 1; k < half_max; ++k) {
     double sae, stt;
-    psd.eval((double)k / Ndt, &sae, &stt);
-    w[(size_t)k] = sae > 0.0 ? 1.0 / sae : 0.0;
-    w[(size_t)(p->kmax + 1 + k)] = stt > 0.0 ? 1.0 / stt : 0.0;
+    psd.eval((double)k / Ndt_max, &sae, &stt);
+    base[2 * (size_t)k] = sae > 0.0 ? 1.0 / sae : 0.0;
+    base[2 * (size_t)k + 1] = stt > 0.0 ? 1.0 / stt : 0.0;
   }
-  if (hipMemcpy(p->d_winv, w.data(), sizeof(double) * w.size(), hipMemcpyHostToDevice) != hipSuccess) {
+  std::vector<double> wt((size_t)wt_total, 0.0);
+  for (int lg = 1; lg <= sp.logN; ++lg) {
+    Split s;
+    split_of((int64_t)1 << lg, fp64, &s);
+    const int64_t N = (int64_t)1 << lg, N1 = (int64_t)1 << s.logN1, hw = ((int64_t)1 << s.logN2) / 2;
+    const double Ndt = (double)N * dt;
+    double* t = wt.data() + p->wofs[lg];
+    for (int64_t k1 = 0; k1 < N1; ++k1) {
+      for (int64_t k2 = 0; k2 < hw; ++k2) {
+        const int64_t k = k1 + N1 * k2;
+        const double f = (double)k / Ndt;
+        if (k < 1 || f < noise->f_min || f > noise->f_max) continue;
+        const size_t kb = (size_t)(k << (sp.logN - lg));
+        t[k1 * hw + k2] = base[2 * kb];
+        t[N / 2 + k1 * hw + k2] = base[2 * kb + 1];
+      }
+    }
+  }
+  if (hipMemcpy(p->d_wt, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice) != hipSuccess) {
     tdi_ip_plan_destroy(p);
     return TDI_EDEVICE;
+  }
+  // twiddles: LDS stages (E = 2^logE roots of unity) and the four-step factor
+  // e^{-2 pi i m / N_max} split as th[m >> tbits] tl[m mod 2^tbits]
+  const int logE = fp64 ? 12 : 13;
+  p->tbits = (sp.logN + 1) / 2;
+  const int64_t nh = (int64_t)1 << (sp.logN - p->tbits), nl = (int64_t)1 << p->tbits;
+  ok = fp64 ? upload_roots<double>(&p->d_tw, (int64_t)1 << logE, logE, 1) &&
+                  upload_roots<double>(&p->d_th, nh, sp.logN, nl) &&
+                  upload_roots<double>(&p->d_tl, nl, sp.logN, 1)
+            : upload_roots<float>(&p->d_tw, (int64_t)1 << logE, logE, 1) &&
+                  upload_roots<float>(&p->d_th, nh, sp.logN, nl) &&
+                  upload_roots<float>(&p->d_tl, nl, sp.logN, 1);
+  if (!ok) {
+    tdi_ip_plan_destroy(p);
+    return TDI_ENOMEM;
   }
   *out = p;
   return TDI_OK;
@@ -259,6 +329,7 @@ tdi_status tdi_ip_run(tdi_ip_plan* p, int64_t n_sources, const int64_t* offsets,
     r.t2 = t2;
     r.part = part;
     r.ws = ws;
+    r.wofs = p->wofs[sp.logN];
     t1 += 3 * (int64_t)sp.n1;
     t2 += 3 * (int64_t)sp.n2;
     part += 3 * (int64_t)sp.n2;
@@ -275,8 +346,11 @@ tdi_status tdi_ip_run(tdi_ip_plan* p, int64_t n_sources, const int64_t* offsets,
   P.ws = p->d_ws;
   P.part = p->d_part;
   P.out = out;
-  P.winv = p->d_winv;
-  P.kmax = p->kmax;
+  P.wt = p->d_wt;
+  P.tw = p->d_tw;
+  P.th = p->d_th;
+  P.tl = p->d_tl;
+  P.tbits = p->tbits;
   P.logNmax = p->logNmax;
   P.dt = p->dt;
   P.f_min = p->noise.f_min;
@@ -289,9 +363,9 @@ tdi_status tdi_ip_run(tdi_ip_plan* p, int64_t n_sources, const int64_t* offsets,
   p->staged_pending = true;
   const int slot = p->ev_head;
   bool ok = hipEventRecord(p->ev[slot][0], s) == hipSuccess;
-  ok = ok && tdi_ip::launch_pass1(p->d_params, fp64, t1, s) == 0;
+  ok = ok && tdi_ip::launch_pass1(p->d_params, fp64, t1, p->grid, s) == 0;
   ok = ok && hipEventRecord(p->ev[slot][1], s) == hipSuccess;
-  ok = ok && tdi_ip::launch_pass2(p->d_params, fp64, t2, s) == 0;
+  ok = ok && tdi_ip::launch_pass2(p->d_params, fp64, t2, p->grid, s) == 0;
   ok = ok && hipEventRecord(p->ev[slot][2], s) == hipSuccess;
   ok = ok && tdi_ip::launch_reduce(p->d_params, n_sources, s) == 0;
   ok = ok && hipEventRecord(p->ev[slot][3], s) == hipSuccess;

@@ -18,8 +18,11 @@
 //
 // The transforms are radix-4 (plus one radix-2 stage for odd log2 length)
 // Stockham passes in LDS with natural-order output, in the precision of the
-// input (float or double); the weighted sums accumulate in double.
+// input (float or double); the weighted sums accumulate in double.  Twiddle
+// factors are read from tables computed on the host in FP64 and rounded once.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "tdi_ip_internal.h"
 
@@ -30,28 +33,12 @@ template <typename T> struct Cplx;
 template <> struct Cplx<float> { using V = float2; };
 template <> struct Cplx<double> { using V = double2; };
 
-__device__ __forceinline__ void sincospi_t(float a, float* s, float* c) { sincospif(a, s, c); }
-__device__ __forceinline__ void sincospi_t(double a, double* s, double* c) { sincospi(a, s, c); }
-__device__ __forceinline__ float ldexp_t(float a, int e) { return ldexpf(a, e); }
-__device__ __forceinline__ double ldexp_t(double a, int e) { return ldexp(a, e); }
 
 template <typename V>
 __device__ __forceinline__ V cmul(V a, V b) {
   V r;
   r.x = a.x * b.x - a.y * b.y;
   r.y = a.x * b.y + a.y * b.x;
-  return r;
-}
-
-// e^{-2 pi i m / M} for 0 <= m < M, M a power of two: 2 m / M is exact in T.
-template <typename T, typename V>
-__device__ __forceinline__ V root(int64_t m, int logM) {
-  const T a = ldexp_t((T)m, 1 - logM);
-  T s, c;
-  sincospi_t(a, &s, &c);
-  V r;
-  r.x = c;
-  r.y = -s;
   return r;
 }
 
@@ -70,6 +57,42 @@ __device__ __forceinline__ void dft4(V* a) {
 }
 
 template <typename V>
+__device__ __forceinline__ void dft4r(V& a0, V& a1, V& a2, V& a3) {
+  V a[4] = {a0, a1, a2, a3};
+  dft4(a);
+  a0 = a[0];
+  a1 = a[1];
+  a2 = a[2];
+  a3 = a[3];
+}
+
+// 16-point DFT in registers as 4 x 4: transforms over n1 of a[4 n1 + n2], the
+// twiddles e^{-2 pi i n2 k1 / 16}, transforms over n2.  X[k1 + 4 k2] ends in
+// a[4 k1 + k2], so output k is read from a[4 (k mod 4) + k / 4].
+template <typename T, typename V>
+__device__ __forceinline__ void dft16(V* a) {
+  const T c1 = (T)0.92387953251128675613, s1 = (T)0.38268343236508977173, h = (T)0.70710678118654752440;
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4r(a[n2], a[4 + n2], a[8 + n2], a[12 + n2]);
+  V w;
+  w.x = c1; w.y = -s1; a[5] = cmul(a[5], w);      // W^1
+  w.x = h; w.y = -h; a[6] = cmul(a[6], w);        // W^2
+  a[9] = cmul(a[9], w);
+  w.x = s1; w.y = -c1; a[7] = cmul(a[7], w);      // W^3
+  a[13] = cmul(a[13], w);
+  {                                               // W^4 = -i
+    const V t = a[10];
+    a[10].x = t.y;
+    a[10].y = -t.x;
+  }
+  w.x = -h; w.y = -h; a[11] = cmul(a[11], w);     // W^6
+  a[14] = cmul(a[14], w);
+  w.x = -c1; w.y = s1; a[15] = cmul(a[15], w);    // W^9
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4r(a[4 * k1], a[4 * k1 + 1], a[4 * k1 + 2], a[4 * k1 + 3]);
+}
+
+template <typename V>
 __device__ __forceinline__ void dft2(V* a) {
   V t;
   t.x = a[0].x - a[1].x; t.y = a[0].y - a[1].y;
@@ -77,18 +100,25 @@ __device__ __forceinline__ void dft2(V* a) {
   a[1] = t;
 }
 
+// LDS layout: logical element i sits at i + i / 32, one pad element per 32, so
+// that the strided accesses of the early stages spread over the banks.
+template <typename T> constexpr int lds_elems() { return elems_of<T>() + elems_of<T>() / 32; }
+__device__ __forceinline__ int lp(int i) { return i + (i >> 5); }
+
 // One Stockham stage of radix R on B sequences of length L = 2^logL held in
-// LDS; element e of sequence b sits at buf[b * bs + e * es].  Ns is the length
+// LDS; element e of sequence b sits at logical index (b << lbs) + (e << les).  Ns is the length
 // of the sub-transforms already formed.  Butterfly q maps to sequence
 // b = q mod B (B = 2^logB) and index j = q / B, so that neighbouring lanes touch
 // neighbouring sequences (interleaved layout) or neighbouring elements.
+// Twiddles e^{-2 pi i k r / (Ns R)} come from the table tw of e^{-2 pi i m / E}.
 template <typename T, int R>
-__device__ void fft_stage(typename Cplx<T>::V* buf, int logL, int logNs, int logB, int bs, int es) {
+__device__ __forceinline__ void fft_stage(typename Cplx<T>::V* buf, const typename Cplx<T>::V* __restrict__ tw,
+                                          int logL, int logNs, int logB, int lbs, int les) {
   using V = typename Cplx<T>::V;
-  constexpr int kMaxQ = elems_of<T>() / (R * kIpBlock);
-  constexpr int kLogR = R == 4 ? 2 : 1;
-  const int nb = 1 << (logL - kLogR);          // butterflies per sequence
-  const int total = nb << logB;
+  constexpr int kMaxQ = elems_of<T>() / (R * kIpBlock) > 0 ? elems_of<T>() / (R * kIpBlock) : 1;
+  constexpr int kLogR = R == 16 ? 4 : (R == 4 ? 2 : 1);
+  const int lnb = logL - kLogR;                // log2 butterflies per sequence
+  const int total = 1 << (lnb + logB);
   const int Ns = 1 << logNs;
   V v[kMaxQ][R];
 #pragma unroll
@@ -96,9 +126,9 @@ __device__ void fft_stage(typename Cplx<T>::V* buf, int logL, int logNs, int log
     const int q = threadIdx.x + i * kIpBlock;
     if (q < total) {
       const int b = q & ((1 << logB) - 1), j = q >> logB;
-      const V* src = buf + b * bs + j * es;
+      const int base = (b << lbs) + (j << les);
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[i][r] = src[r * nb * es];
+      for (int r = 0; r < R; ++r) v[i][r] = buf[lp(base + (r << (lnb + les)))];
     }
   }
   __syncthreads();
@@ -109,35 +139,66 @@ __device__ void fft_stage(typename Cplx<T>::V* buf, int logL, int logNs, int log
       const int b = q & ((1 << logB) - 1), j = q >> logB;
       const int k = j & (Ns - 1);
       if (logNs > 0) {
-        const V w1 = root<T, V>(k, logNs + kLogR);
-        V w = w1;
+        const int step = k << (log_elems_of<T>() - logNs - kLogR);
 #pragma unroll
-        for (int r = 1; r < R; ++r) {
-          v[i][r] = cmul(v[i][r], w);
-          if (r + 1 < R) w = cmul(w, w1);
-        }
+        for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[r * step]);
       }
-      if constexpr (R == 4) dft4(v[i]); else dft2(v[i]);
-      V* dst = buf + b * bs + ((j - k) * R + k) * es;
+      const int base = (b << lbs) + ((((j - k) << kLogR) + k) << les);
+      if constexpr (R == 16) {
+        dft16<T, V>(v[i]);
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns * es] = v[i][r];
+        for (int r = 0; r < 16; ++r) buf[lp(base + (r << (logNs + les)))] = v[i][4 * (r & 3) + (r >> 2)];
+      } else {
+        if constexpr (R == 4) dft4(v[i]); else dft2(v[i]);
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[lp(base + (r << (logNs + les)))] = v[i][r];
+      }
     }
   }
   __syncthreads();
 }
 
 // Forward DFT (e^{-2 pi i j k / L}) of B sequences in place, natural order out.
+// FP32: one radix-2 and one radix-4 stage as log2 L mod 4 requires, then radix
+// 16 in registers.  FP64 (twice the registers per element): radix 4 after an
+// optional radix-2 stage.
 template <typename T>
-__device__ void lds_fft(typename Cplx<T>::V* buf, int logL, int logB, int bs, int es) {
+__device__ __forceinline__ void lds_fft(typename Cplx<T>::V* buf, const typename Cplx<T>::V* __restrict__ tw,
+                                        int logL, int logB, int lbs, int les) {
   int logNs = 0;
   if (logL & 1) {
-    fft_stage<T, 2>(buf, logL, 0, logB, bs, es);
+    fft_stage<T, 2>(buf, tw, logL, 0, logB, lbs, les);
     logNs = 1;
   }
-  while (logNs < logL) {
-    fft_stage<T, 4>(buf, logL, logNs, logB, bs, es);
-    logNs += 2;
+  if constexpr (sizeof(T) == 4) {
+    if (logL & 2) {
+      fft_stage<T, 4>(buf, tw, logL, logNs, logB, lbs, les);
+      logNs += 2;
+    }
+    while (logNs < logL) {
+      fft_stage<T, 16>(buf, tw, logL, logNs, logB, lbs, les);
+      logNs += 4;
+    }
+  } else {
+    while (logNs < logL) {
+      fft_stage<T, 4>(buf, tw, logL, logNs, logB, lbs, les);
+      logNs += 2;
+    }
   }
+}
+
+// Persistent workgroups: workgroups are dealt to the eight XCDs in turn, so
+// XCD x = blockIdx mod 8 owns the x-th eighth of the tasks, and its workgroups
+// walk that range together with a stride of their count.  Neighbouring column
+// blocks (which share cache lines) are then in flight at the same time in the
+// same L2, and a workgroup's owning source only moves forward.  The grid is a
+// multiple of 8.
+__device__ __forceinline__ void task_span(int64_t nt, int64_t* b, int64_t* e, int64_t* stride) {
+  const int64_t px = (nt + 7) >> 3;
+  const int64_t x = blockIdx.x & 7;
+  *b = x * px + (blockIdx.x >> 3);
+  *e = min((x + 1) * px, nt);
+  *stride = gridDim.x >> 3;
 }
 
 // the source that owns a task: last s with first-task(s) <= task
@@ -159,14 +220,9 @@ __device__ __forceinline__ T load_or_zero(const void* p, int64_t off, int64_t j,
 
 // Pass 1: columns j2 in [c0, c0 + cols) of one channel of one source.
 template <typename T>
-__global__ void __launch_bounds__(kIpBlock) k_ip_pass1(const IpParams* __restrict__ P) {
+__device__ __forceinline__ void pass1_task(const IpParams* __restrict__ P, const IpSrc& S, int64_t local,
+                                           typename Cplx<T>::V* buf) {
   using V = typename Cplx<T>::V;
-  __shared__ V buf[elems_of<T>()];
-  const int64_t task = blockIdx.x;
-  if (task >= P->n_t1) return;
-  const IpSrc* SS = ip_sources(P);
-  const IpSrc S = SS[find_task_source<1>(SS, P->n_src, task)];
-  const int64_t local = task - S.t1;
   const int c = (int)(local / S.n1);
   const int blk = (int)(local - (int64_t)c * S.n1);
   const int logC = 31 - __builtin_clz(S.cols);
@@ -175,25 +231,81 @@ __global__ void __launch_bounds__(kIpBlock) k_ip_pass1(const IpParams* __restric
   const int64_t c0 = (int64_t)blk * C;
   const void* xs = P->x[c];
   const void* ys = P->y[c];
-  // element (j1, col) at buf[j1 * C + col]: neighbouring lanes read neighbouring samples
-  for (int e = threadIdx.x; e < C * N1; e += kIpBlock) {
-    const int j1 = e >> logC, col = e & (C - 1);
-    const int64_t j = (int64_t)j1 * N2 + c0 + col;
-    V z;
-    z.x = load_or_zero<T>(xs, S.off, j, S.n);
-    z.y = load_or_zero<T>(ys, S.off, j, S.n);
-    buf[e] = z;
+  // element (j1, col) at buf[j1 * C + col]: neighbouring lanes read neighbouring
+  // samples.  A first-pass task always fills the LDS (C N1 = E): every load of
+  // a thread is issued before the first is consumed.
+  constexpr int kIt = elems_of<T>() / kIpBlock;
+  constexpr int kG = 4;
+#pragma unroll
+  for (int h = 0; h < kIt / kG; ++h) {
+    V z[kG];
+#pragma unroll
+    for (int it = 0; it < kG; ++it) {
+      const int e = threadIdx.x + (h * kG + it) * kIpBlock;
+      const int j1 = e >> logC, col = e & (C - 1);
+      const int64_t j = ((int64_t)j1 << S.logN2) + c0 + col;
+      z[it].x = load_or_zero<T>(xs, S.off, j, S.n);
+      z[it].y = load_or_zero<T>(ys, S.off, j, S.n);
+    }
+#pragma unroll
+    for (int it = 0; it < kG; ++it) buf[lp(threadIdx.x + (h * kG + it) * kIpBlock)] = z[it];
   }
   __syncthreads();
-  lds_fft<T>(buf, S.logN1, logC, 1, C);
+  lds_fft<T>(buf, static_cast<const V*>(P->tw), S.logN1, logC, 0, logC);
   V* W = static_cast<V*>(P->ws) + S.ws + (int64_t)c * ((int64_t)1 << S.logN);
   const int64_t mask = ((int64_t)1 << S.logN) - 1;
-  for (int e = threadIdx.x; e < C * N1; e += kIpBlock) {
-    const int k1 = e >> logC, col = e & (C - 1);
-    const int64_t j2 = c0 + col;
-    V z = buf[e];
-    if (k1 != 0 && j2 != 0) z = cmul(z, root<T, V>((j2 * k1) & mask, S.logN));
-    W[(int64_t)k1 * N2 + j2] = z;
+  const int up = P->logNmax - S.logN, tb = P->tbits;
+  const V* th = static_cast<const V*>(P->th);
+  const V* tl = static_cast<const V*>(P->tl);
+  // twiddle loads in groups of four, each issued together
+#pragma unroll 1
+  for (int h = 0; h < kIt / kG; ++h) {
+    V wh[kG], wl[kG];
+#pragma unroll
+    for (int it = 0; it < kG; ++it) {
+      const int e = threadIdx.x + (h * kG + it) * kIpBlock;
+      const int k1 = e >> logC, col = e & (C - 1);
+      // e^{-2 pi i j2 k1 / N} = e^{-2 pi i m / N_max} with m = (j2 k1 mod N) 2^up;
+      // j2 < N2 and k1 < N1 are below 2^12, so the 24-bit product is exact
+      const int64_t m = ((int64_t)__umul24((unsigned)(c0 + col), (unsigned)k1) & mask) << up;
+      wh[it] = th[m >> tb];
+      wl[it] = tl[m & ((1 << tb) - 1)];
+    }
+#pragma unroll
+    for (int it = 0; it < kG; ++it) {
+      const int e = threadIdx.x + (h * kG + it) * kIpBlock;
+      const int k1 = e >> logC, col = e & (C - 1);
+      W[((int64_t)k1 << S.logN2) + c0 + col] = cmul(buf[lp(e)], cmul(wh[it], wl[it]));
+    }
+  }
+}
+
+// persistent driver of a pass: walk the workgroup's task range, advancing the
+// owning source along it
+template <int Pass>
+__device__ __forceinline__ int64_t first_task(const IpSrc& s) { return Pass == 1 ? s.t1 : s.t2; }
+
+template <typename T>
+__global__ void __launch_bounds__(kIpBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_ip_pass1(const IpParams* __restrict__ P) {
+  using V = typename Cplx<T>::V;
+  __shared__ V buf[lds_elems<T>()];
+  int64_t t, te, dt;
+  task_span(P->n_t1, &t, &te, &dt);
+  if (t >= te) return;
+  const IpSrc* SS = ip_sources(P);
+  const int64_t ns = P->n_src;
+  int64_t s = find_task_source<1>(SS, ns, t);
+  IpSrc S = SS[s];
+  int64_t next = s + 1 < ns ? SS[s + 1].t1 : INT64_MAX;
+  for (; t < te; t += dt) {
+    while (t >= next) {
+      ++s;
+      S = SS[s];
+      next = s + 1 < ns ? SS[s + 1].t1 : INT64_MAX;
+    }
+    pass1_task<T>(P, S, t - S.t1, buf);
+    __syncthreads();
   }
 }
 
@@ -222,68 +334,89 @@ __device__ __forceinline__ void block_sum3(double* v, double* red) {
 // Pass 2: rows k1 and N1 - k1 of one channel (or the whole series when
 // N1 = 1), then the weighted sums over the bins 0 < k < N/2 they hold.
 template <typename T>
-__global__ void __launch_bounds__(kIpBlock) k_ip_pass2(const IpParams* __restrict__ P) {
+__device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const IpSrc& S, int64_t local,
+                                           typename Cplx<T>::V* buf, double* red) {
   using V = typename Cplx<T>::V;
-  __shared__ V buf[elems_of<T>()];
-  __shared__ double red[3 * (kIpBlock / 64)];
-  const int64_t task = blockIdx.x;
-  if (task >= P->n_t2) return;
-  const IpSrc* SS = ip_sources(P);
-  const IpSrc S = SS[find_task_source<2>(SS, P->n_src, task)];
-  const int64_t local = task - S.t2;
   const int c = (int)(local / S.n2);
   const int i = (int)(local - (int64_t)c * S.n2);
   const int N1 = 1 << S.logN1, N2 = 1 << S.logN2;
   const int64_t N = (int64_t)1 << S.logN;
   const int r0 = i, r1 = (N1 - i) & (N1 - 1);
   const int B = r0 == r1 ? 1 : 2;
-  if (N1 == 1) {
-    const void* xs = P->x[c];
-    const void* ys = P->y[c];
-    for (int e = threadIdx.x; e < N2; e += kIpBlock) {
-      V z;
-      z.x = load_or_zero<T>(xs, S.off, e, S.n);
-      z.y = load_or_zero<T>(ys, S.off, e, S.n);
-      buf[e] = z;
+  // every load of a thread is issued before the first is consumed
+  constexpr int kIt = elems_of<T>() / kIpBlock;
+  const int cnt = B << S.logN2;
+  {
+    V z[kIt];
+    if (N1 == 1) {
+      const void* xs = P->x[c];
+      const void* ys = P->y[c];
+#pragma unroll
+      for (int it = 0; it < kIt; ++it) {
+        const int e = threadIdx.x + it * kIpBlock;
+        z[it].x = load_or_zero<T>(xs, S.off, e, S.n);
+        z[it].y = load_or_zero<T>(ys, S.off, e, S.n);
+      }
+    } else {
+      const V* W = static_cast<const V*>(P->ws) + S.ws + (int64_t)c * N;
+#pragma unroll
+      for (int it = 0; it < kIt; ++it) {
+        const int e = threadIdx.x + it * kIpBlock;
+        if (e < cnt) {
+          const int b = e >> S.logN2, k2 = e & (N2 - 1);
+          z[it] = W[((int64_t)(b == 0 ? r0 : r1) << S.logN2) + k2];
+        }
+      }
     }
-  } else {
-    const V* W = static_cast<const V*>(P->ws) + S.ws + (int64_t)c * N;
-    for (int e = threadIdx.x; e < B * N2; e += kIpBlock) {
-      const int b = e >> S.logN2, k2 = e & (N2 - 1);
-      buf[e] = W[(int64_t)(b == 0 ? r0 : r1) * N2 + k2];
+#pragma unroll
+    for (int it = 0; it < kIt; ++it) {
+      const int e = threadIdx.x + it * kIpBlock;
+      if (e < cnt) buf[lp(e)] = z[it];
     }
   }
   __syncthreads();
-  lds_fft<T>(buf, S.logN2, B == 2 ? 1 : 0, N2, 1);
+  lds_fft<T>(buf, static_cast<const V*>(P->tw), S.logN2, B == 2 ? 1 : 0, S.logN2, 0);
   // bins: row b holds k = k1b + N1 k2; the partner N - k lies in the other row
   // at N2 - 1 - k2 (k1b != 0), or in row 0 itself at (N2 - k2) mod N2 (k1b = 0)
-  const double* winv = P->winv + (c < 2 ? 0 : P->kmax + 1);
-  const int shift = P->logNmax - S.logN;
-  const double Ndt = (double)N * P->dt;
+  // weight of bin k = k1b + N1 k2 (k < N/2 means k2 < N2/2): wt[k1b N2/2 + k2]
+  const double* wt = P->wt + S.wofs + (c < 2 ? 0 : N / 2);
   double acc[3] = {0.0, 0.0, 0.0};
-  for (int e = threadIdx.x; e < B * N2; e += kIpBlock) {
-    const int b = e >> S.logN2, k2 = e & (N2 - 1);
-    const int k1b = b == 0 ? r0 : r1;
-    const int64_t k = (int64_t)k1b + (int64_t)N1 * k2;
-    if (k < 1 || 2 * k >= N) continue;
-    const double f = (double)k / Ndt;
-    if (f < P->f_min || f > P->f_max) continue;
-    int pb, pk2;
-    if (k1b == 0) {
-      pb = b;
-      pk2 = (N2 - k2) & (N2 - 1);
-    } else {
-      pb = B == 1 ? b : 1 - b;
-      pk2 = N2 - 1 - k2;
+  // weights in groups of four, each group's loads issued together
+  constexpr int kG = 4;
+#pragma unroll
+  for (int g = 0; g < kIt / kG; ++g) {
+    double wk[kG];
+#pragma unroll
+    for (int it = 0; it < kG; ++it) {
+      const int e = threadIdx.x + (g * kG + it) * kIpBlock;
+      const int b = e >> S.logN2, k2 = e & (N2 - 1);
+      const int k1b = b == 0 ? r0 : r1;
+      const int64_t k = (int64_t)k1b + ((int64_t)k2 << S.logN1);
+      wk[it] = (e < cnt && k >= 1 && 2 * k < N) ? wt[((int64_t)k1b << (S.logN2 - 1)) + k2] : 0.0;
     }
-    const V z = buf[e];
-    const V p = buf[(pb << S.logN2) + pk2];
-    const double w = winv[k << shift];
-    const double ax = (double)z.x + (double)p.x, ay = (double)z.y - (double)p.y;
-    const double bx = (double)z.x - (double)p.x, by = (double)z.y + (double)p.y;
-    acc[0] += w * (ax * ax + ay * ay);
-    acc[1] += w * ((double)z.x * (double)p.y + (double)z.y * (double)p.x);
-    acc[2] += w * (bx * bx + by * by);
+#pragma unroll
+    for (int it = 0; it < kG; ++it) {
+      const int e = threadIdx.x + (g * kG + it) * kIpBlock;
+      const double w = wk[it];
+      if (w == 0.0) continue;          // outside the band, or not a bin 0 < k < N/2 of this task
+      const int b = e >> S.logN2, k2 = e & (N2 - 1);
+      const int k1b = b == 0 ? r0 : r1;
+      int pb, pk2;
+      if (k1b == 0) {
+        pb = b;
+        pk2 = (N2 - k2) & (N2 - 1);
+      } else {
+        pb = B == 1 ? b : 1 - b;
+        pk2 = N2 - 1 - k2;
+      }
+      const V z = buf[lp(e)];
+      const V p = buf[lp((pb << S.logN2) + pk2)];
+      const double ax = (double)z.x + (double)p.x, ay = (double)z.y - (double)p.y;
+      const double bx = (double)z.x - (double)p.x, by = (double)z.y + (double)p.y;
+      acc[0] += w * (ax * ax + ay * ay);
+      acc[1] += w * ((double)z.x * (double)p.y + (double)z.y * (double)p.x);
+      acc[2] += w * (bx * bx + by * by);
+    }
   }
   block_sum3(acc, red);
   if (threadIdx.x == 0) {
@@ -291,6 +424,31 @@ __global__ void __launch_bounds__(kIpBlock) k_ip_pass2(const IpParams* __restric
     o[0] = acc[0];
     o[1] = acc[1];
     o[2] = acc[2];
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kIpBlock) __attribute__((amdgpu_waves_per_eu(4)))
+k_ip_pass2(const IpParams* __restrict__ P) {
+  using V = typename Cplx<T>::V;
+  __shared__ V buf[lds_elems<T>()];
+  __shared__ double red[3 * (kIpBlock / 64)];
+  int64_t t, te, dt;
+  task_span(P->n_t2, &t, &te, &dt);
+  if (t >= te) return;
+  const IpSrc* SS = ip_sources(P);
+  const int64_t ns = P->n_src;
+  int64_t s = find_task_source<2>(SS, ns, t);
+  IpSrc S = SS[s];
+  int64_t next = s + 1 < ns ? SS[s + 1].t2 : INT64_MAX;
+  for (; t < te; t += dt) {
+    while (t >= next) {
+      ++s;
+      S = SS[s];
+      next = s + 1 < ns ? SS[s + 1].t2 : INT64_MAX;
+    }
+    pass2_task<T>(P, S, t - S.t2, buf, red);
+    __syncthreads();
   }
 }
 
@@ -312,17 +470,19 @@ __global__ void __launch_bounds__(kIpBlock) k_ip_reduce(const IpParams* __restri
 
 }  // namespace
 
-int launch_pass1(const IpParams* dp, int fp64, int64_t tasks, void* stream) {
+int launch_pass1(const IpParams* dp, int fp64, int64_t tasks, int grid, void* stream) {
   if (tasks <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
+  tasks = std::min<int64_t>((tasks + 7) & ~(int64_t)7, grid);
   if (fp64) hipLaunchKernelGGL(k_ip_pass1<double>, dim3((unsigned)tasks), dim3(kIpBlock), 0, st, dp);
   else hipLaunchKernelGGL(k_ip_pass1<float>, dim3((unsigned)tasks), dim3(kIpBlock), 0, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_pass2(const IpParams* dp, int fp64, int64_t tasks, void* stream) {
+int launch_pass2(const IpParams* dp, int fp64, int64_t tasks, int grid, void* stream) {
   if (tasks <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
+  tasks = std::min<int64_t>((tasks + 7) & ~(int64_t)7, grid);
   if (fp64) hipLaunchKernelGGL(k_ip_pass2<double>, dim3((unsigned)tasks), dim3(kIpBlock), 0, st, dp);
   else hipLaunchKernelGGL(k_ip_pass2<float>, dim3((unsigned)tasks), dim3(kIpBlock), 0, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
