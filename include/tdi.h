@@ -132,6 +132,26 @@ tdi_status tdi_run(tdi_plan* plan, int64_t n_sources, const tdi_source* src,
                    const int64_t* offsets, const double* hp, const double* hc,
                    void* X, void* Y, void* Z);
 
+/* Enqueue the six single-link outputs of one batch on the plan's stream
+ * (asynchronous), in the plan's mode, precision, taps, stencil order and
+ * hybrid window:
+ *   TDI_MODE_FULL: Eq. (yslr) with Eq. (H), y_l = [H_l(t - delta_s) -
+ *     H_l(t - delta_r)] / (2 (1 - k.n_l)), Eqs. (delta_s), (delta_r);
+ *   TDI_MODE_LFA: Eq. (yslr_strain_derivatives) for every link, y_l =
+ *     -(L_l/2c) [xi+_l h+'(t - L_l/2c - mu_l) + xi_x_l hx'(...)], mu_l =
+ *     k.(R_s + R_r)/(2c), the first derivative by the central stencil of the
+ *     configured accuracy (L_l = L for lfa_equal_arms);
+ *   TDI_MODE_HYBRID: Eq. (hybridized_yslr) with the windows and weights of
+ *     the X, Y, Z hybrid.
+ * y: device array of 6 * offsets[n_sources] doubles (TDI_FP64) or floats
+ * (TDI_FP32_BULK), link-major: link slot a occupies y[a * total .. a * total +
+ * total - 1] with slots ordered +1, +2, +3, -1, -2, -3 (link l joins the two
+ * spacecraft other than |l|, its direction given by the sign convention of
+ * Sec. II.B).  src, offsets, hp, hc as for tdi_run.  Runs outside the plan's
+ * graph; TDI_ERANGE if the read window of a tile would exceed the LDS. */
+tdi_status tdi_run_links(tdi_plan* plan, int64_t n_sources, const tdi_source* src,
+                         const int64_t* offsets, const double* hp, const double* hc, void* y);
+
 /* Wait for the plan's work and report device-side window checks:
  * TDI_ERANGE if any retarded-time window left the staged range since the last
  * call (such samples were written as NaN), else TDI_OK. */

@@ -81,6 +81,8 @@ def lib():
         L.orc_stencil.argtypes = [_D, C.c_int64, C.c_int, C.c_int, C.c_double, _D]
         L.orc_links.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.POINTER(Source),
                                 C.c_int64, _D, _D, _D]
+        L.orc_link_outputs.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.POINTER(Source),
+                                       C.c_int64, _D, _D, _D]
         L.orc_tdi_combine.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_double, _D, _D, _D, _D, _D]
         L.orc_response.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.POINTER(Source),
                                    C.c_int64, _D, _D, _D, _D, _D]
@@ -184,6 +186,15 @@ def links(cfg: dict, orbit: dict, rec, hp, hc):
     y = np.zeros((6, len(hp)))
     c, o, s = make_config(cfg), make_orbit(orbit), make_source(rec)
     lib().orc_links(C.byref(c), C.byref(o), C.byref(s), len(hp), _dp(hp), _dp(hc), _dp(y))
+    return y
+
+
+def link_outputs(cfg: dict, orbit: dict, rec, hp, hc):
+    """The six single-link outputs (6, n) in cfg's mode (full, LFA or hybrid)."""
+    hp, hc = _f64(hp), _f64(hc)
+    y = np.zeros((6, len(hp)))
+    c, o, s = make_config(cfg), make_orbit(orbit), make_source(rec)
+    lib().orc_link_outputs(C.byref(c), C.byref(o), C.byref(s), len(hp), _dp(hp), _dp(hc), _dp(y))
     return y
 
 

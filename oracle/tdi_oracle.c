@@ -497,9 +497,49 @@ static int64_t first_y_needed(const orc_ctx* x) {
   return lo < 0.0 ? 0 : (int64_t)lo;
 }
 
+/* Single-link LFA at output sample k, Eq. (yslr_strain_derivatives) for each
+ * link: y_l(t_k) = -(T_l/2) [xi+_l(t_k) h+'(t_k - T_l/2 - mu_l) +
+ * xi_x_l(t_k) hx'(...)], T_l = L_l(t_k)/c (L/c for equal arms),
+ * mu_l = k.(R_s + R_r)/(2c) (the same for l and -l), h' the first derivative
+ * of h_SSB by the central stencil of accuracy p on the grid (the context's
+ * derivative order must be 1), read at the retarded time by N-tap Lagrange. */
+static void lfa_links_at(orc_ctx* x, int64_t k, double y6[6]) {
+  static const int L6[6] = {1, 2, 3, -1, -2, -3};
+  orc_geom g;
+  orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, k), &g);
+  for (int a = 0; a < 6; ++a) {
+    int l = L6[a];
+    double T = x->c->equal_arms ? x->o->L / ORC_C : g.T[a];
+    double mu = g.mu[(l > 0 ? l : -l) - 1];
+    y6[a] = -0.5 * T * Xi(x, &g, l, k, 0.5 * T + mu);
+  }
+}
+
 /* ---------------------------------------------------------------------------
  * Public entry points.
  * ------------------------------------------------------------------------- */
+void orc_link_outputs(const orc_config* c, const orc_orbit* o, const orc_source* s,
+                      int64_t n, const double* hp, const double* hc, double* y) {
+  orc_ctx x;
+  ctx_init(&x, c, o, s, n, hp, hc);
+  x.m = 1;
+  if (c->mode != ORC_FULL) fill_g_all(&x);      /* read-only below: safe across threads */
+  double kH = (s->t_hyb - s->t0) / s->dt;
+  #pragma omp parallel for schedule(dynamic, 256) if (!in_parallel())
+  for (int64_t k = 0; k < n; ++k) {
+    double r[6] = {0, 0, 0, 0, 0, 0}, a6[6];
+    double rel = (double)k - kH, z = rel / c->sigma_samples;
+    int lfa = c->mode == ORC_LFA || (c->mode == ORC_HYBRID && rel <= 0.5 * c->T_samples);
+    int full = c->mode == ORC_FULL || (c->mode == ORC_HYBRID && rel >= -0.5 * c->T_samples);
+    double wp = c->mode == ORC_HYBRID ? 1.0 / (1.0 + exp(z)) : 1.0;
+    double wm = c->mode == ORC_HYBRID ? 1.0 / (1.0 + exp(-z)) : 1.0;
+    if (lfa) { lfa_links_at(&x, k, a6); for (int a = 0; a < 6; ++a) r[a] += wp * a6[a]; }
+    if (full) { stage1_at(&x, k, a6); for (int a = 0; a < 6; ++a) r[a] += wm * a6[a]; }
+    for (int a = 0; a < 6; ++a) y[(size_t)a * (size_t)n + (size_t)k] = r[a];
+  }
+  ctx_free(&x);
+}
+
 void orc_links(const orc_config* c, const orc_orbit* o, const orc_source* s,
                int64_t n, const double* hp, const double* hc, double* y) {
   orc_ctx x;

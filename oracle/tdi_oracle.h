@@ -85,6 +85,12 @@ void orc_stencil(const double* h, int64_t n, int m, int p, double dt, double* g)
 void orc_links(const orc_config* c, const orc_orbit* o, const orc_source* s,
                int64_t n, const double* hp, const double* hc, double* y /* 6*n */);
 
+/* The six single-link outputs y[a*n + k] in the configuration's mode: full
+ * (stage 1), LFA (Eq. yslr_strain_derivatives per link) or their hybrid
+ * (Eq. hybridized_yslr); link order as above. */
+void orc_link_outputs(const orc_config* c, const orc_orbit* o, const orc_source* s,
+                      int64_t n, const double* hp, const double* hc, double* y /* 6*n */);
+
 /* Stage 2 on arbitrary link series and per-sample light times T[l*n + k]. */
 void orc_tdi_combine(int gen, int N, int64_t n, double dt, const double* y,
                      const double* T, double* X, double* Y, double* Z);

@@ -625,6 +625,65 @@ tdi_status tdi_run(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   return run_with(p, p->launch, n_sources, src, offsets, hp, hc, X, Y, Z, true, true);
 }
 
+tdi_status tdi_run_links(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
+                         const double* hp, const double* hc, void* y) {
+  if (!p) return TDI_ESTATE;
+  tdi_status st = tdi_check_batch(&p->cfg, n_sources, src, offsets);
+  if (st != TDI_OK) return st;
+  if (n_sources > p->max_sources || offsets[n_sources] > p->max_total) return TDI_ESTATE;
+  const int64_t total = offsets[n_sources];
+  if (total == 0) return TDI_OK;
+  if (!hp || !hc || !y) return TDI_EINVAL;
+  const int fp32 = p->cfg.precision == TDI_FP32_BULK ? 1 : 0;
+  if (((uintptr_t)hp | (uintptr_t)hc) & 7) return TDI_EINVAL;
+  if (((uintptr_t)y) & (fp32 ? 3 : 7)) return TDI_EINVAL;
+  // read window of a tile: the tile, the spread of every delay the links use
+  // (|k.R|/c <= (R (1 + e) + L)/c, light times <= 1.01 L/c), the taps, margins
+  const tdi_orbit& o = p->orb;
+  const double spread = 2.0 * (o.R_m + 2.0 * o.L_m) / kC + 1.01 * o.L_m / kC;
+  const int N = p->cfg.interp_taps;
+  const int margin = 2 + (int)ceil(4e-4 * (double)tdi::kTileLinks);
+  int cap = 0;
+  for (int64_t i = 0; i < n_sources; ++i)
+    cap = std::max(cap, tdi::kTileLinks + (int)ceil(spread / src[i].dt) + N + 2 * margin + 8);
+  const size_t lds = tdi::links_lds_bytes(cap, fp32);
+  if (lds > p->max_lds) return TDI_ERANGE;
+  if (p->staged_pending) {
+    if (hipEventSynchronize(p->staged_free) != hipSuccess) return TDI_EDEVICE;
+    p->staged_pending = false;
+  }
+  tdi::KParams* kp = p->h_params;
+  tdi::SrcDev* sd = reinterpret_cast<tdi::SrcDev*>(kp + 1);
+  int64_t tiles = 0;
+  for (int64_t i = 0; i < n_sources; ++i) {
+    const tdi_source& s = src[i];
+    tdi::SrcDev& d = sd[i];
+    d.beta = s.beta; d.lam = s.lambda; d.psi = s.psi; d.t0 = s.t0; d.dt = s.dt; d.t_hyb = s.t_hyb;
+    d.c2psi = cos(2.0 * s.psi);
+    d.s2psi = sin(2.0 * s.psi);
+    d.off = offsets[i];
+    d.n = offsets[i + 1] - offsets[i];
+    d.lfa_kb = 0; d.lfa_ke = d.n; d.lfa_t0 = tiles;
+    d.full_kb = 0; d.full_ke = 0; d.full_t0 = 0;
+    tiles += (d.n + tdi::kTileLinks - 1) / tdi::kTileLinks;
+  }
+  kp->n_src = n_sources;
+  kp->n_tiles_lfa = tiles;
+  kp->n_tiles_full = 0;
+  kp->hp = hp; kp->hc = hc; kp->X = y; kp->Y = nullptr; kp->Z = nullptr;
+  kp->cap_lk = cap;
+  kp->link_stride = total;
+  kp->persistent = 0;
+  const size_t copy_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)n_sources;
+  hipStream_t s = p->user_stream;
+  if (hipMemcpyAsync(p->d_params, p->h_params, copy_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+    return TDI_EDEVICE;
+  if (hipEventRecord(p->staged_free, s) != hipSuccess) return TDI_EDEVICE;
+  p->staged_pending = true;
+  if (tdi::launch_links(p->d_params, N, fp32, tiles, lds, s) != 0) return TDI_EDEVICE;
+  return TDI_OK;
+}
+
 tdi_status tdi_plan_sync(tdi_plan* p) {
   if (!p) return TDI_ESTATE;
   if (hipStreamSynchronize(p->user_stream) != hipSuccess) return TDI_EDEVICE;

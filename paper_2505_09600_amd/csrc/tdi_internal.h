@@ -24,6 +24,7 @@ constexpr int kFastOutPerLane = 9;
 constexpr int kWGrid = 16;                 // Lagrange Taylor table: rows per unit offset
 constexpr double kFastDtMax = 40.0;        // s: quadratic chunk models stay below 1e-6 relative
 constexpr double kFastRateMax = 2.0e-4;    // bound of |d delay / dt| for the offset expansions
+constexpr int kTileLinks = 256;            // link outputs: outputs per tile (one per thread)
 
 // Orbit constants prepared once per plan.
 struct OrbitDev {
@@ -68,7 +69,8 @@ struct KParams {
   uint32_t* counters;    // persistent work counters: [0] LFA, [1] full
   OrbitDev orb;
   int32_t gen, mode, equal_arms, stencil_m, stencil_p, persistent;
-  int32_t aet, pad1;     // aet: store A, E, T instead of X, Y, Z
+  int32_t aet, cap_lk;   // aet: store A, E, T instead of X, Y, Z; cap_lk: link-output window
+  int64_t link_stride;   // link outputs: elements between the six link arrays (X is their base)
   double T_s, sigma_s;
   double D2_bound;       // upper bound of a stage-2 delay (s)
 };
@@ -83,6 +85,9 @@ int launch_reset(uint32_t* counters, void* stream);
 // fast != 0 selects the FP32 bulk LFA kernel (fp32 must be 1)
 int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t lds_bytes, void* stream);
 int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
+// link outputs: one workgroup per tile of kTileLinks samples (tile list in SrcDev::lfa_t0)
+int launch_links(const KParams* dp, int taps, int fp32, int64_t grid, size_t lds, void* stream);
+size_t links_lds_bytes(int cap, int fp32);
 // pre-pass of the fast LFA path: per-tile records (geometry fits, chunk
 // windows, wave models) for all LFA tiles (grid-stride over tiles)
 int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream);

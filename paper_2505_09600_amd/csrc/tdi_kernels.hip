@@ -182,10 +182,13 @@ __constant__ double c_stnum[4][7] = {
 __constant__ int c_sthw[4] = {1, 2, 2, 3};
 __constant__ double c_stden[4] = {1.0, 12.0, 2.0, 8.0};
 
-// Central stencil numerators (offsets -hw..hw) and denominators.
+// Central stencil numerators (offsets -hw..hw) and denominators of derivative
+// order m (1, 2, 3) and accuracy p (2, 4).
 __host__ __device__ __forceinline__ void stencil_coeffs(int m, int p, double c[7], int& hw, double& den) {
   for (int s = 0; s < 7; ++s) c[s] = 0.0;
-  if (m == 2 && p == 2) { hw = 1; den = 1.0; c[0] = 1; c[1] = -2; c[2] = 1; }
+  if (m == 1 && p == 2) { hw = 1; den = 2.0; c[0] = -1; c[1] = 0; c[2] = 1; }
+  else if (m == 1) { hw = 2; den = 12.0; c[0] = 1; c[1] = -8; c[2] = 0; c[3] = 8; c[4] = -1; }
+  else if (m == 2 && p == 2) { hw = 1; den = 1.0; c[0] = 1; c[1] = -2; c[2] = 1; }
   else if (m == 2) { hw = 2; den = 12.0; c[0] = -1; c[1] = 16; c[2] = -30; c[3] = 16; c[4] = -1; }
   else if (p == 2) { hw = 2; den = 2.0; c[0] = -1; c[1] = 2; c[2] = 0; c[3] = -2; c[4] = 1; }
   else { hw = 3; den = 8.0; c[0] = 1; c[1] = -8; c[2] = 13; c[3] = 0; c[4] = -13; c[5] = 8; c[6] = -1; }
@@ -1627,6 +1630,182 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Link outputs: the six single links y_slr on the grid of each source.
+//   full:   Eq. (yslr), y = [H_l(t - delta_s) - H_l(t - delta_r)] / (2 (1 - k.n)),
+//           H_l from Eq. (H) with the antenna patterns at the reception time;
+//   LFA:    Eq. (yslr_strain_derivatives) for every link,
+//           y = -(T_l / 2) [xi+ h+'(t - T_l/2 - mu_l) + xi_x hx'(...)],
+//           mu_l = k.(R_s + R_r)/(2c), h' the first derivative by the central
+//           stencil of accuracy p on the grid (zero outside the series);
+//   hybrid: Eq. (hybridized_yslr) with the windows and weights of the TDI hybrid.
+// One workgroup per tile of kTileLinks outputs, one output per thread.
+// ---------------------------------------------------------------------------
+struct LinkShared {
+  GeoFit F;
+  int64_t src, k0, w0;
+  int32_t cnt, nh, bad, pad;
+  double c2, s2, kH;
+  double dext[4];
+};
+
+template <int N, typename TC>
+__global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp) {
+  const KParams& P = *Pp;
+  const SrcDev* __restrict__ SS = sources_of(Pp);
+  __shared__ LinkShared sh;
+  extern __shared__ __align__(16) char dyn[];
+  const int tid = threadIdx.x;
+  const int cap = P.cap_lk;
+  TC* hwin = reinterpret_cast<TC*>(dyn);                                              // [cap][2]
+  TC* gwin = reinterpret_cast<TC*>(dyn + align16((size_t)cap * 2 * sizeof(TC)));     // [cap][2]
+  const int64_t tile = blockIdx.x;
+  if (tile >= P.n_tiles_lfa) return;
+  const bool want_lfa = P.mode != 0, want_full = P.mode != 1;
+  if (tid == 0) {
+    const int64_t s = find_source(SS, P.n_src, tile, true);
+    const SrcDev& S = SS[s];
+    sh.src = s;
+    sh.k0 = (tile - S.lfa_t0) * kTileLinks;
+    sh.cnt = (int32_t)min((int64_t)kTileLinks, S.n - sh.k0);
+    sh.c2 = S.c2psi;
+    sh.s2 = S.s2psi;
+    sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : 0.0;
+  }
+  __syncthreads();
+  const SrcDev& S = SS[sh.src];
+  const int64_t k0 = sh.k0;
+  const int cnt = sh.cnt;
+  fit_geometry(P, S, (double)k0, (double)(k0 + cnt - 1), sh.F);
+  // read window from every delay at both ends of the tile
+  if (tid < 2) {
+    const int64_t i = tid == 0 ? k0 : k0 + cnt - 1;
+    const double s = ((double)i - sh.F.kc) * sh.F.ikh;
+    double kR[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) kR[q] = geo_eval(sh.F, qKR(q), s);
+    double dmin = 1e300, dmax = -1e300;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      const double T = geo_eval(sh.F, qT(a), s);
+      const double Tl = P.equal_arms ? P.orb.L_over_c : T;
+      const double ds = T + kR[snd_of(a)], dr = kR[rcv_of(a)];
+      const double dl = 0.5 * Tl + 0.5 * (kR[snd_of(a)] + kR[rcv_of(a)]);
+      dmin = fmin(dmin, fmin(fmin(ds, dr), dl));
+      dmax = fmax(dmax, fmax(fmax(ds, dr), dl));
+    }
+    sh.dext[2 * tid] = dmin;
+    sh.dext[2 * tid + 1] = dmax;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double dmin = fmin(sh.dext[0], sh.dext[2]), dmax = fmax(sh.dext[1], sh.dext[3]);
+    const int margin = 2 + (int)ceil(4e-4 * (double)cnt);
+    const int64_t w0 = k0 - (int64_t)ceil(dmax / S.dt) - N / 2 + 1 - margin;
+    const int64_t w1 = k0 + cnt - 1 - (int64_t)floor(dmin / S.dt) + N / 2 + margin;
+    sh.w0 = w0;
+    sh.nh = (int32_t)(w1 - w0 + 1);
+    sh.bad = sh.nh > cap ? 1 : 0;
+    if (sh.bad) report(P.err, 16, k0, 0, sh.nh);
+  }
+  __syncthreads();
+  const int64_t w0 = sh.w0;
+  const int nh = sh.nh;
+  const double dt = S.dt;
+  const int64_t stride = P.link_stride;
+  TC* Yo = static_cast<TC*>(P.X);
+  if (sh.bad) {
+    if (tid < cnt)
+      for (int a = 0; a < 6; ++a) Yo[a * stride + S.off + k0 + tid] = (TC)__builtin_nan("");
+    return;
+  }
+  // strain window (full part) and first-derivative window (LFA part), the
+  // derivative taken in FP64 on the grid from the strain in global memory
+  double st[7];
+  int hw;
+  double den;
+  stencil_coeffs(1, P.stencil_p, st, hw, den);
+  const double gscale = 1.0 / (den * dt);
+  for (int i = tid; i < nh; i += kBlock) {
+    const int64_t j = w0 + i;
+    const bool in = j >= 0 && j < S.n;
+    if (want_full) {
+      hwin[2 * i] = (TC)(in ? P.hp[S.off + j] : 0.0);
+      hwin[2 * i + 1] = (TC)(in ? P.hc[S.off + j] : 0.0);
+    }
+    if (want_lfa) {
+      double gp = 0.0, gc = 0.0;
+      if (in) {
+        for (int q = -hw; q <= hw; ++q) {
+          const int64_t jj = j + q;
+          if (jj >= 0 && jj < S.n) {
+            gp += st[q + hw] * P.hp[S.off + jj];
+            gc += st[q + hw] * P.hc[S.off + jj];
+          }
+        }
+      }
+      gwin[2 * i] = (TC)(gp * gscale);
+      gwin[2 * i + 1] = (TC)(gc * gscale);
+    }
+  }
+  __syncthreads();
+  if (tid >= cnt) return;
+  const int64_t k = k0 + tid;
+  const double s = ((double)k - sh.F.kc) * sh.F.ikh;
+  const double rel = (double)k - sh.kH;
+  const bool lfa = P.mode == 1 || (P.mode == 2 && rel <= 0.5 * P.T_s);
+  const bool full = P.mode == 0 || (P.mode == 2 && rel >= -0.5 * P.T_s);
+  double wp = 1.0, wm = 1.0;
+  if (P.mode == 2) {
+    wp = 1.0 / (1.0 + exp(rel / P.sigma_s));
+    wm = 1.0 / (1.0 + exp(-rel / P.sigma_s));
+  }
+  const double kR[3] = {geo_eval(sh.F, qKR(0), s), geo_eval(sh.F, qKR(1), s), geo_eval(sh.F, qKR(2), s)};
+  const double c2 = sh.c2, s2 = sh.s2;
+#pragma unroll 1
+  for (int a = 0; a < 6; ++a) {
+    const double T = geo_eval(sh.F, qT(a), s);
+    const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
+    const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
+    const int sn = snd_of(a), rc = rcv_of(a);
+    TC y = (TC)0;
+    if (lfa) {
+      const double Tl = P.equal_arms ? P.orb.L_over_c : T;
+      int64_t i0;
+      double x;
+      split(k, 0.5 * Tl + 0.5 * (kR[sn] + kR[rc]), dt, i0, x);
+      const int64_t b = i0 - N / 2 + 1 - w0;
+      TC vp, vc;
+      if (b < 0 || b + N > nh) {
+        report(P.err, 16, k, b, nh);
+        vp = vc = (TC)__builtin_nan("");
+      } else {
+        interp2<N, TC>(gwin, b, x, vp, vc);
+      }
+      y += (TC)(wp * (-0.5 * Tl)) * (A * vp + B * vc);
+    }
+    if (full) {
+      TC v[4];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        int64_t i0;
+        double x;
+        split(k, e == 0 ? T + kR[sn] : kR[rc], dt, i0, x);
+        const int64_t b = i0 - N / 2 + 1 - w0;
+        if (b < 0 || b + N > nh) {
+          report(P.err, 16, k, b, nh);
+          v[2 * e] = v[2 * e + 1] = (TC)__builtin_nan("");
+        } else {
+          interp2<N, TC>(hwin, b, x, v[2 * e], v[2 * e + 1]);
+        }
+      }
+      const TC Hs = A * v[0] + B * v[1], Hr = A * v[2] + B * v[3];
+      y += (TC)wm * ((Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s));
+    }
+    Yo[a * stride + S.off + k] = y;
+  }
+}
+
 __global__ void k_reset(uint32_t* counters) {
   if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
 }
@@ -1640,6 +1819,12 @@ int launch_lfa_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
 template <int N, typename TC>
 int launch_full_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
   hipLaunchKernelGGL((k_full<N, TC>), dim3(grid), dim3(kBlock), lds, st, dp);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, typename TC>
+int launch_links_t(const KParams* dp, int64_t grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k_links<N, TC>), dim3((unsigned)grid), dim3(kBlock), lds, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -1829,6 +2014,17 @@ int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream) {
 int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds, void* stream) {
   TDI_DISPATCH(taps, fp32, launch_full_t, dp, grid, lds, (hipStream_t)stream);
   return -2;
+}
+
+int launch_links(const KParams* dp, int taps, int fp32, int64_t grid, size_t lds, void* stream) {
+  if (grid <= 0) return 0;
+  TDI_DISPATCH(taps, fp32, launch_links_t, dp, grid, lds, (hipStream_t)stream);
+  return -2;
+}
+
+size_t links_lds_bytes(int cap, int fp32) {
+  const size_t e = fp32 ? 4 : 8;
+  return align16((size_t)cap * 2 * e) * 2;
 }
 
 int occupancy_lfa(int taps, int fp32, int fast, size_t lds) {

@@ -23,7 +23,8 @@ TDI_MODE_FULL, TDI_MODE_LFA, TDI_MODE_HYBRID = 0, 1, 2
 TDI_FP64, TDI_FP32_BULK = 0, 1
 TDI_CHANNELS_XYZ, TDI_CHANNELS_AET = 0, 1
 
-EXPORTED = ["tdi_check_config", "tdi_check_batch", "tdi_plan_create", "tdi_run", "tdi_plan_sync",
+EXPORTED = ["tdi_check_config", "tdi_check_batch", "tdi_plan_create", "tdi_run", "tdi_run_links",
+            "tdi_plan_sync",
             "tdi_plan_kernel_times", "tdi_plan_describe", "tdi_plan_destroy", "tdi_status_str",
             "tdi_check_noise", "tdi_ip_plan_create", "tdi_ip_run", "tdi_ip_kernel_times",
             "tdi_ip_plan_destroy"]
@@ -83,6 +84,7 @@ def lib():
                                       C.c_int64, C.c_int64, P]
         L.tdi_run.argtypes = [P, C.c_int64, C.POINTER(tdi_source), C.POINTER(C.c_int64),
                               P, P, P, P, P]
+        L.tdi_run_links.argtypes = [P, C.c_int64, C.POINTER(tdi_source), C.POINTER(C.c_int64), P, P, P]
         L.tdi_plan_sync.argtypes = [P]
         L.tdi_plan_kernel_times.argtypes = [P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
         L.tdi_plan_describe.argtypes = [P, C.c_char_p, C.c_int32]
@@ -130,6 +132,12 @@ def tdi_run(plan, n_sources: int, src, offsets, hp_ptr: int, hc_ptr: int, x_ptr:
     return lib().tdi_run(plan, int(n_sources), src, offs.ctypes.data_as(C.POINTER(C.c_int64)),
                          C.c_void_p(hp_ptr), C.c_void_p(hc_ptr), C.c_void_p(x_ptr),
                          C.c_void_p(y_ptr), C.c_void_p(z_ptr))
+
+
+def tdi_run_links(plan, n_sources: int, src, offsets, hp_ptr: int, hc_ptr: int, y_ptr: int) -> int:
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    return lib().tdi_run_links(plan, int(n_sources), src, offs.ctypes.data_as(C.POINTER(C.c_int64)),
+                               C.c_void_p(hp_ptr), C.c_void_p(hc_ptr), C.c_void_p(y_ptr))
 
 
 def tdi_plan_sync(plan) -> int:
@@ -219,6 +227,26 @@ class Plan:
         if st != TDI_OK:
             raise TdiError(st, "tdi_run")
         return outs[0][:n], outs[1][:n], outs[2][:n]
+
+    def run_links(self, sources, offsets, hp, hc, y=None):
+        """Enqueue the six link outputs of one batch; returns a (6, total) view
+        (slots +1, +2, +3, -1, -2, -3)."""
+        torch = self.torch
+        n = int(offsets[-1])
+        if hp.dtype != torch.float64 or hc.dtype != torch.float64 or not hp.is_cuda or not hc.is_cuda:
+            raise TypeError("hp, hc must be float64 device tensors")
+        if not (hp.is_contiguous() and hc.is_contiguous()) or hp.numel() < n or hc.numel() < n:
+            raise ValueError("hp, hc must be contiguous with at least offsets[-1] samples")
+        if y is None:
+            y = torch.empty(max(6 * n, 1), dtype=self.out_dtype(), device=hp.device)
+        elif y.dtype != self.out_dtype() or not y.is_contiguous() or y.numel() < 6 * n:
+            raise TypeError("y must be contiguous with 6 * offsets[-1] elements of the plan's dtype")
+        src = sources if isinstance(sources, C.Array) else make_sources(sources)
+        st = tdi_run_links(self.handle, len(offsets) - 1, src, offsets, hp.data_ptr(), hc.data_ptr(),
+                           y.data_ptr())
+        if st != TDI_OK:
+            raise TdiError(st, "tdi_run_links")
+        return y[:6 * n].view(6, n)
 
     def sync(self) -> int:
         return tdi_plan_sync(self.handle)
