@@ -323,6 +323,53 @@ def likelihood(args):
     print(json.dumps(res), flush=True)
 
 
+def link_outputs(args):
+    """The six single-link outputs of the 512-source batch (FP32-bulk hybrid:
+    the per-link LFA before the switch, the full links after it, blended per
+    link), timed with HIP events on the plan's stream."""
+    import torch
+    from paper_2505_09600_amd import tdi
+    from paper_2505_09600_amd import workload as W
+    tdi.lib()
+    dev = torch.device("cuda:0")
+    batch, cfg, orb = W.config_c4(n_sources=args.n_sources, xp=torch, device=dev)
+    total = batch.total
+    hp, hc = batch.hp.contiguous(), batch.hc.contiguous()
+    src = tdi.make_sources(batch.sources)
+    res = {"metric": "single-link outputs: samples/s (six links per sample)", "unit": "samples/s",
+           "n_gpus": 1, "data": "synthetic", "higher_is_better": True, "steps": args.steps,
+           "warmup": args.warmup,
+           "config": {"workload": "512 sources of the batched hybrid benchmark (seed 1004), six links "
+                                  "per sample, 32 taps, 4th-order first-derivative stencil",
+                      "total_samples": total}, "runs": {}}
+    for name, prec, mode in (("hybrid fp32", 1, 2), ("lfa fp32", 1, 1), ("full fp32", 1, 0), ("full fp64", 0, 0)):
+        c = dict(cfg, precision=prec, mode=mode, tdi_gen=20, taps=TAPS, stencil_order=4)
+        y = torch.empty(6 * total, dtype=torch.float32 if prec else torch.float64, device=dev)
+        steps = args.steps if prec else max(1, args.steps // 5)
+        with tdi.Plan(c, orb, batch.n_sources, total) as plan:
+            for _ in range(args.warmup):
+                plan.run_links(src, batch.offsets, hp, hc, y)
+            if plan.sync() != tdi.TDI_OK:
+                raise RuntimeError("window check failed")
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(steps):
+                plan.run_links(src, batch.offsets, hp, hc, y)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / steps
+            if plan.sync() != tdi.TDI_OK:
+                raise RuntimeError("window check failed")
+        bps = 16 + 6 * (4 if prec else 8)
+        gbs = bps * total / (ms * 1e-3) / 1e9
+        res["runs"][name] = {"ms_per_run": ms, "samples_per_s": total / (ms * 1e-3),
+                             "hbm_algorithmic_gbs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                             "bytes_per_sample_algorithmic": bps}
+        print(f"[bench] links {name}: {ms:.2f} ms", file=sys.stderr, flush=True)
+        del y
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,10 +383,11 @@ def main():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy a float32 buffer of this size three times (a plain "
                          "copy kernel of known traffic for scaling PMC byte counters)")
-    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "lnl"],
+    ap.add_argument("--config", default="c4", choices=["c1", "c2", "c3", "c4", "c5", "lnl", "links"],
                     help="c4 (default): the headline batched hybrid line; c1-c3: single-source "
                          "timings of every mode; c5: the 4096-source batch in two waves; lnl: the "
-                         "inner products that follow the response on the c4 batch")
+                         "inner products that follow the response on the c4 batch; links: the six "
+                         "single-link outputs of the c4 batch")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: only --gpus 1 is supported; the response has no multi-GPU path "
@@ -347,6 +395,9 @@ def main():
         sys.exit(2)
     if args.config == "lnl":
         likelihood(args)
+        return
+    if args.config == "links":
+        link_outputs(args)
         return
     if args.config != "c4":
         secondary(args)
