@@ -102,7 +102,11 @@ typedef struct {
                                noise-orthogonal combinations defined at the end of Sec. II.B instead,
                                A = (Z - X)/sqrt 2, E = (X - 2Y + Z)/sqrt 6, T = (X + Y + Z)/sqrt 3,
                                into the same three arrays (fused into the store) */
-  int32_t reserved;         /* must be 0 */
+  int32_t lfa_terms;        /* single-link LFA (tdi_run_links): 0 or 1 = the leading term of
+                               Eq. (yslr_with_tau_derivatives); 2 = also its next term,
+                               -(L/2c)(1/6)[L(1 - k.n)/(2c)]^2 times the third derivative of H.
+                               tdi_run supports only the leading term (2 gives
+                               TDI_EUNSUPPORTED in the LFA and hybrid modes) */
 } tdi_config;
 
 typedef struct tdi_plan tdi_plan;

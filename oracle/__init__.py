@@ -41,7 +41,7 @@ class Orbit(C.Structure):
 class Config(C.Structure):
     _fields_ = [("tdi_gen", C.c_int32), ("mode", C.c_int32), ("taps", C.c_int32),
                 ("stencil_order", C.c_int32), ("equal_arms", C.c_int32),
-                ("pad_", C.c_int32), ("T_samples", C.c_double),
+                ("lfa_terms", C.c_int32), ("T_samples", C.c_double),
                 ("sigma_samples", C.c_double)]
 
 
@@ -116,7 +116,8 @@ def make_orbit(d: dict) -> Orbit:
 
 def make_config(d: dict) -> Config:
     return Config(int(d["tdi_gen"]), int(d["mode"]), int(d["taps"]), int(d["stencil_order"]),
-                  int(d.get("equal_arms", 0)), 0, float(d["T_samples"]), float(d["sigma_samples"]))
+                  int(d.get("equal_arms", 0)), int(d.get("lfa_terms", 0)), float(d["T_samples"]),
+                  float(d["sigma_samples"]))
 
 
 def make_source(rec) -> Source:

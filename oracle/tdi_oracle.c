@@ -503,7 +503,7 @@ static int64_t first_y_needed(const orc_ctx* x) {
  * mu_l = k.(R_s + R_r)/(2c) (the same for l and -l), h' the first derivative
  * of h_SSB by the central stencil of accuracy p on the grid (the context's
  * derivative order must be 1), read at the retarded time by N-tap Lagrange. */
-static void lfa_links_at(orc_ctx* x, int64_t k, double y6[6]) {
+static void lfa_links_at(orc_ctx* x, orc_ctx* x3, int64_t k, double y6[6]) {
   static const int L6[6] = {1, 2, 3, -1, -2, -3};
   orc_geom g;
   orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, k), &g);
@@ -511,7 +511,15 @@ static void lfa_links_at(orc_ctx* x, int64_t k, double y6[6]) {
     int l = L6[a];
     double T = x->c->equal_arms ? x->o->L / ORC_C : g.T[a];
     double mu = g.mu[(l > 0 ? l : -l) - 1];
-    y6[a] = -0.5 * T * Xi(x, &g, l, k, 0.5 * T + mu);
+    double v = Xi(x, &g, l, k, 0.5 * T + mu);
+    /* Next term of Eq. (yslr_with_tau_derivatives), m = 1: (1/3!) times
+     * [L (1 - k.n) / (2c)]^2 times the third derivative of H, the
+     * tau-derivatives taken as t-derivatives as in the leading term. */
+    if (x3) {
+      double e = 0.5 * T * (1.0 - g.kn[a]);
+      v += e * e / 6.0 * Xi(x3, &g, l, k, 0.5 * T + mu);
+    }
+    y6[a] = -0.5 * T * v;
   }
 }
 
@@ -520,9 +528,11 @@ static void lfa_links_at(orc_ctx* x, int64_t k, double y6[6]) {
  * ------------------------------------------------------------------------- */
 void orc_link_outputs(const orc_config* c, const orc_orbit* o, const orc_source* s,
                       int64_t n, const double* hp, const double* hc, double* y) {
-  orc_ctx x;
+  orc_ctx x, x3;
   ctx_init(&x, c, o, s, n, hp, hc);
   x.m = 1;
+  int nlo = c->lfa_terms == 2 && c->mode != ORC_FULL;
+  if (nlo) { ctx_init(&x3, c, o, s, n, hp, hc); x3.m = 3; fill_g_all(&x3); }
   if (c->mode != ORC_FULL) fill_g_all(&x);      /* read-only below: safe across threads */
   double kH = (s->t_hyb - s->t0) / s->dt;
   #pragma omp parallel for schedule(dynamic, 256) if (!in_parallel())
@@ -533,10 +543,11 @@ void orc_link_outputs(const orc_config* c, const orc_orbit* o, const orc_source*
     int full = c->mode == ORC_FULL || (c->mode == ORC_HYBRID && rel >= -0.5 * c->T_samples);
     double wp = c->mode == ORC_HYBRID ? 1.0 / (1.0 + exp(z)) : 1.0;
     double wm = c->mode == ORC_HYBRID ? 1.0 / (1.0 + exp(-z)) : 1.0;
-    if (lfa) { lfa_links_at(&x, k, a6); for (int a = 0; a < 6; ++a) r[a] += wp * a6[a]; }
+    if (lfa) { lfa_links_at(&x, nlo ? &x3 : NULL, k, a6); for (int a = 0; a < 6; ++a) r[a] += wp * a6[a]; }
     if (full) { stage1_at(&x, k, a6); for (int a = 0; a < 6; ++a) r[a] += wm * a6[a]; }
     for (int a = 0; a < 6; ++a) y[(size_t)a * (size_t)n + (size_t)k] = r[a];
   }
+  if (nlo) ctx_free(&x3);
   ctx_free(&x);
 }
 

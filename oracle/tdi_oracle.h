@@ -35,7 +35,7 @@ typedef struct {
   int32_t taps;           /* N, even */
   int32_t stencil_order;  /* p in {2, 4} */
   int32_t equal_arms;     /* LFA only: 1 = equal constant delays L/c */
-  int32_t pad_;
+  int32_t lfa_terms;      /* single-link LFA: 2 = keep the next (m = 1) term of the central series */
   double T_samples;       /* hybrid window length, samples */
   double sigma_samples;   /* sigmoid width, samples */
 } orc_config;

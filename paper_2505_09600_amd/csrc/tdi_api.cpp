@@ -108,7 +108,7 @@ tdi_status tdi_check_config(const tdi_config* c, const tdi_orbit* o) {
   if (c->autotune != 0 && c->autotune != 1) return TDI_ERANGE;
   if (c->use_graph != 0 && c->use_graph != 1) return TDI_ERANGE;
   if (c->channels != TDI_CHANNELS_XYZ && c->channels != TDI_CHANNELS_AET) return TDI_EUNSUPPORTED;
-  if (c->reserved != 0) return TDI_EINVAL;
+  if (c->lfa_terms < 0 || c->lfa_terms > 2) return TDI_ERANGE;
   if (!(c->hyb_T_samples > 0.0) || !is_fin(c->hyb_T_samples)) return TDI_ERANGE;
   if (!(c->hyb_sigma_samples > 0.0) || !is_fin(c->hyb_sigma_samples)) return TDI_ERANGE;
   if (!(o->L_m > 0.0) || !is_fin(o->L_m)) return TDI_ERANGE;
@@ -570,6 +570,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   kp.gen = cfg->tdi_gen;
   kp.mode = cfg->mode;
   kp.aet = cfg->channels == TDI_CHANNELS_AET ? 1 : 0;
+  kp.lfa_terms = cfg->lfa_terms == 2 ? 2 : 1;
   kp.equal_arms = cfg->lfa_equal_arms;
   kp.stencil_m = cfg->tdi_gen == 20 ? 3 : 2;
   kp.stencil_p = cfg->stencil_order;
@@ -621,6 +622,7 @@ tdi_status tdi_run(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   const uintptr_t al = p->cfg.precision == TDI_FP64 ? 8 : 4;
   if (((uintptr_t)hp | (uintptr_t)hc) & 7) return TDI_EINVAL;
   if ((((uintptr_t)X) | ((uintptr_t)Y) | ((uintptr_t)Z)) & (al - 1)) return TDI_EINVAL;
+  if (p->cfg.lfa_terms == 2 && p->cfg.mode != TDI_MODE_FULL) return TDI_EUNSUPPORTED;
   if (!p->tuned) autotune(p, n_sources, src, offsets, hp, hc, X, Y, Z);
   return run_with(p, p->launch, n_sources, src, offsets, hp, hc, X, Y, Z, true, true);
 }
@@ -646,7 +648,7 @@ tdi_status tdi_run_links(tdi_plan* p, int64_t n_sources, const tdi_source* src, 
   int cap = 0;
   for (int64_t i = 0; i < n_sources; ++i)
     cap = std::max(cap, tdi::kTileLinks + (int)ceil(spread / src[i].dt) + N + 2 * margin + 8);
-  const size_t lds = tdi::links_lds_bytes(cap, fp32);
+  const size_t lds = tdi::links_lds_bytes(cap, fp32, p->cfg.lfa_terms == 2 ? 3 : 2);
   if (lds > p->max_lds) return TDI_ERANGE;
   if (p->staged_pending) {
     if (hipEventSynchronize(p->staged_free) != hipSuccess) return TDI_EDEVICE;

@@ -62,7 +62,7 @@ struct KParams {
   int32_t cap_hf, cap_y;               // full-response capacities: strain, link series
   int32_t lfa_goff;                    // byte offset of the LFA derivative window in LDS
                                        // (fast path: of the F_l series; 0 = over the strain)
-  int32_t pad0;
+  int32_t lfa_terms;                   // single-link LFA: 1 leading term, 2 with the next term
   // per plan
   int32_t* err;          // window-check report (8 ints)
   void* lfa_tiles;       // fast LFA path: per-tile records written by the pre-pass
@@ -87,7 +87,7 @@ int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t
 int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
 // link outputs: one workgroup per tile of kTileLinks samples (tile list in SrcDev::lfa_t0)
 int launch_links(const KParams* dp, int taps, int fp32, int64_t grid, size_t lds, void* stream);
-size_t links_lds_bytes(int cap, int fp32);
+size_t links_lds_bytes(int cap, int fp32, int windows);
 // pre-pass of the fast LFA path: per-tile records (geometry fits, chunk
 // windows, wave models) for all LFA tiles (grid-stride over tiles)
 int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream);

@@ -1638,6 +1638,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
 //           y = -(T_l / 2) [xi+ h+'(t - T_l/2 - mu_l) + xi_x hx'(...)],
 //           mu_l = k.(R_s + R_r)/(2c), h' the first derivative by the central
 //           stencil of accuracy p on the grid (zero outside the series);
+//           with two terms, the next term of Eq. (yslr_with_tau_derivatives),
+//           (T_l (1 - k.n_l) / 2)^2 / 6 times the third derivative, joins h';
 //   hybrid: Eq. (hybridized_yslr) with the windows and weights of the TDI hybrid.
 // One workgroup per tile of kTileLinks outputs, one output per thread.
 // ---------------------------------------------------------------------------
@@ -1659,6 +1661,7 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
   const int cap = P.cap_lk;
   TC* hwin = reinterpret_cast<TC*>(dyn);                                              // [cap][2]
   TC* gwin = reinterpret_cast<TC*>(dyn + align16((size_t)cap * 2 * sizeof(TC)));     // [cap][2]
+  TC* g3win = reinterpret_cast<TC*>(dyn + 2 * align16((size_t)cap * 2 * sizeof(TC)));  // [cap][2]
   const int64_t tile = blockIdx.x;
   if (tile >= P.n_tiles_lfa) return;
   const bool want_lfa = P.mode != 0, want_full = P.mode != 1;
@@ -1721,11 +1724,13 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
   }
   // strain window (full part) and first-derivative window (LFA part), the
   // derivative taken in FP64 on the grid from the strain in global memory
-  double st[7];
-  int hw;
-  double den;
+  double st[7], st3[7];
+  int hw, hw3;
+  double den, den3;
   stencil_coeffs(1, P.stencil_p, st, hw, den);
-  const double gscale = 1.0 / (den * dt);
+  stencil_coeffs(3, P.stencil_p, st3, hw3, den3);
+  const double gscale = 1.0 / (den * dt), g3scale = 1.0 / (den3 * dt * dt * dt);
+  const bool nlo = want_lfa && P.lfa_terms == 2;
   for (int i = tid; i < nh; i += kBlock) {
     const int64_t j = w0 + i;
     const bool in = j >= 0 && j < S.n;
@@ -1746,6 +1751,20 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
       }
       gwin[2 * i] = (TC)(gp * gscale);
       gwin[2 * i + 1] = (TC)(gc * gscale);
+    }
+    if (nlo) {
+      double gp = 0.0, gc = 0.0;
+      if (in) {
+        for (int q = -hw3; q <= hw3; ++q) {
+          const int64_t jj = j + q;
+          if (jj >= 0 && jj < S.n) {
+            gp += st3[q + hw3] * P.hp[S.off + jj];
+            gc += st3[q + hw3] * P.hc[S.off + jj];
+          }
+        }
+      }
+      g3win[2 * i] = (TC)(gp * g3scale);
+      g3win[2 * i + 1] = (TC)(gc * g3scale);
     }
   }
   __syncthreads();
@@ -1775,14 +1794,21 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
       double x;
       split(k, 0.5 * Tl + 0.5 * (kR[sn] + kR[rc]), dt, i0, x);
       const int64_t b = i0 - N / 2 + 1 - w0;
-      TC vp, vc;
+      TC vp, vc, v3p = (TC)0, v3c = (TC)0;
       if (b < 0 || b + N > nh) {
         report(P.err, 16, k, b, nh);
         vp = vc = (TC)__builtin_nan("");
       } else {
         interp2<N, TC>(gwin, b, x, vp, vc);
+        if (nlo) interp2<N, TC>(g3win, b, x, v3p, v3c);
       }
-      y += (TC)(wp * (-0.5 * Tl)) * (A * vp + B * vc);
+      TC lf = A * vp + B * vc;
+      if (nlo) {
+        // (T (1 - k.n) / 2)^2 / 6 with 1 - k.n = D / 2
+        const double e = 0.25 * Tl * geo_eval(sh.F, qD(a), s);
+        lf += (TC)(e * e / 6.0) * (A * v3p + B * v3c);
+      }
+      y += (TC)(wp * (-0.5 * Tl)) * lf;
     }
     if (full) {
       TC v[4];
@@ -2022,9 +2048,9 @@ int launch_links(const KParams* dp, int taps, int fp32, int64_t grid, size_t lds
   return -2;
 }
 
-size_t links_lds_bytes(int cap, int fp32) {
+size_t links_lds_bytes(int cap, int fp32, int windows) {
   const size_t e = fp32 ? 4 : 8;
-  return align16((size_t)cap * 2 * e) * 2;
+  return align16((size_t)cap * 2 * e) * (size_t)windows;
 }
 
 int occupancy_lfa(int taps, int fp32, int fast, size_t lds) {

@@ -62,7 +62,8 @@ def test_status_strings(L):
     ("hyb_sigma_samples", math.nan, T.TDI_ERANGE),
     ("autotune", 5, T.TDI_ERANGE),
     ("channels", 2, T.TDI_EUNSUPPORTED),
-    ("reserved", 1, T.TDI_EINVAL),
+    ("lfa_terms", 3, T.TDI_ERANGE),
+    ("lfa_terms", -1, T.TDI_ERANGE),
 ])
 def test_config_validation(L, field, value, code):
     c = _cfg()

@@ -94,3 +94,50 @@ def test_links_hybrid_long_source(tdi, orc, prec):
     orb = W.default_orbit()
     got = _gpu_links(tdi, batch, cfg, orb)
     _check(orc, f"links hybrid n=1e6 prec{prec}", batch, cfg, orb, got, TOL[prec])
+
+
+def test_links_between_graph_replays(tdi, orc):
+    """A link-output run between two graph-replayed responses on one plan
+    leaves the response unchanged (both runs share the parameter block)."""
+    import torch
+    batch = _ragged()
+    cfg = W.default_config(tdi_gen=20, mode=2, taps=32, stencil_order=4, precision=1)
+    orb = W.default_orbit()
+    hp = torch.as_tensor(np.asarray(batch.hp), dtype=torch.float64, device="cuda:0")
+    hc = torch.as_tensor(np.asarray(batch.hc), dtype=torch.float64, device="cuda:0")
+    with tdi.Plan(cfg, orb, batch.n_sources, batch.total, autotune=False, use_graph=True) as p:
+        first = [v.clone() for v in p.run(batch.sources, batch.offsets, hp, hc)]
+        y = p.run_links(batch.sources, batch.offsets, hp, hc)
+        second = p.run(batch.sources, batch.offsets, hp, hc)
+        assert p.sync() == tdi.TDI_OK
+        for a, b in zip(first, second):
+            assert torch.equal(a, b)
+        ref = orc.link_outputs(cfg, orb, *batch.source(4))
+        a, b = int(batch.offsets[4]), int(batch.offsets[5])
+        got = y[:, a:b].double().cpu().numpy()
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("mode", [1, 2])
+def test_links_next_term(tdi, orc, mode, prec):
+    """The optional m = 1 term of the single-link LFA (lfa_terms = 2)."""
+    batch = _ragged()
+    cfg = W.default_config(tdi_gen=20, mode=mode, taps=32, stencil_order=4, precision=prec)
+    cfg["lfa_terms"] = 2
+    orb = W.default_orbit()
+    got = _gpu_links(tdi, batch, cfg, orb)
+    _check(orc, f"links lfa two terms mode{mode} prec{prec}", batch, cfg, orb, got, TOL[prec])
+
+
+def test_tdi_run_refuses_the_next_term(tdi):
+    import torch
+    batch = _ragged()
+    cfg = W.default_config(tdi_gen=20, mode=1, taps=32, stencil_order=4, precision=1)
+    cfg["lfa_terms"] = 2
+    hp = torch.as_tensor(np.asarray(batch.hp), dtype=torch.float64, device="cuda:0")
+    hc = torch.as_tensor(np.asarray(batch.hc), dtype=torch.float64, device="cuda:0")
+    with tdi.Plan(cfg, W.default_orbit(), batch.n_sources, batch.total) as p:
+        with pytest.raises(tdi.TdiError) as e:
+            p.run(batch.sources, batch.offsets, hp, hc)
+        assert e.value.status == tdi.TDI_EUNSUPPORTED

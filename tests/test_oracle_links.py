@@ -107,3 +107,25 @@ def test_full_link_outputs_are_stage_one(orc):
     rec, hp, hc, _ = W.make_source(4.0e5, 0.5, -0.2, 2.0, 0.1, 3000, 10.0, 0.0)
     cfg = _cfg(0, tdi_gen=20, taps=32)
     assert np.array_equal(orc.link_outputs(cfg, orb, rec, hp, hc), orc.links(cfg, orb, rec, hp, hc))
+
+
+def test_next_term_raises_the_convergence_to_f_fourth(orc):
+    """With the m = 1 term of Eq. (yslr_with_tau_derivatives) the truncation
+    moves to the term after it: the error falls as f^4 (frozen constellation,
+    where no velocity term sets a floor)."""
+    orb = W.default_orbit(W.ORBIT_FROZEN)
+    rec = _rec()
+    errs, errs1 = [], []
+    for f in (8e-3, 4e-3, 2e-3):
+        hp, hc = _mono(f)
+        full = orc.link_outputs(_cfg(0), orb, rec, hp, hc)
+        two = orc.link_outputs(_cfg(1, lfa_terms=2), orb, rec, hp, hc)
+        one = orc.link_outputs(_cfg(1), orb, rec, hp, hc)
+        sl = slice(600, 3400)
+        peak = np.max(np.abs(full[:, sl]))
+        errs.append(np.max(np.abs(two[:, sl] - full[:, sl])) / peak)
+        errs1.append(np.max(np.abs(one[:, sl] - full[:, sl])) / peak)
+    slopes = [math.log(errs[i] / errs[i + 1]) / math.log(2.0) for i in range(2)]
+    for s in slopes:
+        assert abs(s - 4.0) < 0.3, (errs, slopes)
+    assert errs[-1] < 1e-2 * errs1[-1]
