@@ -54,7 +54,7 @@ typedef enum {
   TDI_ESTATE = -6         /* batch exceeds the plan's declared maxima, or bad plan */
 } tdi_status;
 
-enum { TDI_ORBIT_FROZEN = 0, TDI_ORBIT_ANALYTIC1 = 1 };
+enum { TDI_ORBIT_FROZEN = 0, TDI_ORBIT_ANALYTIC1 = 1, TDI_ORBIT_TABLE = 2 };
 enum { TDI_MODE_FULL = 0, TDI_MODE_LFA = 1, TDI_MODE_HYBRID = 2 };
 enum { TDI_FP64 = 0, TDI_FP32_BULK = 1 };
 enum { TDI_CHANNELS_XYZ = 0, TDI_CHANNELS_AET = 1 };
@@ -64,7 +64,14 @@ enum { TDI_CHANNELS_XYZ = 0, TDI_CHANNELS_AET = 1 };
  *   eccentricity L_m / (2 sqrt(3) R_m), orbital phase alpha = omega t + kappa0,
  *   spacecraft i at beta_i = 2 pi (i-1)/3 + lambda0; light times solve the
  *   light-time equation with the sender at emission time.
- * FROZEN: positions of ANALYTIC1 at t_freeze, all six light times L_m / c. */
+ * FROZEN: positions of ANALYTIC1 at t_freeze, all six light times L_m / c.
+ * TABLE: spacecraft positions sampled on a uniform time grid (for instance
+ *   an orbit file, or eccentric Keplerian orbits whose arms flex), read by
+ *   8-point Lagrange interpolation in time; light times solve the same
+ *   light-time equation.  L_m is the nominal arm (equal-arm LFA); R_m,
+ *   omega, kappa0, lambda0 and t_freeze are ignored.  The table is copied at
+ *   plan creation; a batch whose sources (with their retarded-time margins)
+ *   reach outside the table's span returns TDI_ERANGE. */
 typedef struct {
   int32_t kind;       /* TDI_ORBIT_* */
   int32_t reserved;   /* must be 0 */
@@ -74,6 +81,10 @@ typedef struct {
   double kappa0;      /* rad */
   double lambda0;     /* rad */
   double t_freeze;    /* s (FROZEN only) */
+  const double* table;   /* TABLE: host array [n_table][3][3], sample j, spacecraft 1..3, x y z (m, SSB) */
+  int64_t n_table;       /* TABLE: >= 8 samples */
+  double table_t0;       /* TABLE: time of sample 0, s */
+  double table_dt;       /* TABLE: sample spacing, s, > 0 */
 } tdi_orbit;
 
 /* One source: sky position, polarisation, time grid and switch time.

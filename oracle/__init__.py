@@ -35,7 +35,9 @@ def build(force: bool = True) -> str:
 class Orbit(C.Structure):
     _fields_ = [("kind", C.c_int32), ("pad_", C.c_int32), ("L", C.c_double),
                 ("R", C.c_double), ("omega", C.c_double), ("kappa0", C.c_double),
-                ("lambda0", C.c_double), ("t_freeze", C.c_double)]
+                ("lambda0", C.c_double), ("t_freeze", C.c_double),
+                ("table", C.POINTER(C.c_double)), ("n_table", C.c_int64),
+                ("table_t0", C.c_double), ("table_dt", C.c_double)]
 
 
 class Config(C.Structure):
@@ -110,8 +112,16 @@ def _f64(a):
 
 
 def make_orbit(d: dict) -> Orbit:
-    return Orbit(int(d["kind"]), 0, d["L"], d["R"], d["omega"], d["kappa0"], d["lambda0"],
-                 d.get("t_freeze", 0.0))
+    o = Orbit(int(d["kind"]), 0, d["L"], d["R"], d["omega"], d["kappa0"], d["lambda0"],
+              d.get("t_freeze", 0.0))
+    if d.get("table") is not None:
+        tab = np.ascontiguousarray(d["table"], dtype=np.float64).reshape(-1, 3, 3)
+        o._table = tab                       # kept alive with the struct
+        o.table = tab.ctypes.data_as(C.POINTER(C.c_double))
+        o.n_table = tab.shape[0]
+        o.table_t0 = float(d["table_t0"])
+        o.table_dt = float(d["table_dt"])
+    return o
 
 
 def make_config(d: dict) -> Config:

@@ -90,6 +90,24 @@ void orc_triad(double beta, double lam, double k[3], double u[3], double v[3]) {
  * e = L / (2 sqrt(3) R).  FROZEN takes the positions at t_freeze.
  * ------------------------------------------------------------------------- */
 void orc_positions(const orc_orbit* o, double t, double R[3][3]) {
+  if (o->kind == ORC_ORBIT_TABLE) {
+    /* Sampled orbit: 8-point Lagrange interpolation in time on the samples
+     * around t (the same product-form weights as the fractional delays). */
+    double u = (t - o->table_t0) / o->table_dt;
+    int64_t i0 = (int64_t)floor(u);
+    double x = u - (double)i0, w[8];
+    int64_t j0 = i0 - 3;
+    if (j0 < 0) { x += (double)j0; j0 = 0; }
+    if (j0 > o->n_table - 8) { x += (double)(j0 - (o->n_table - 8)); j0 = o->n_table - 8; }
+    orc_lagrange_weights(x, 8, w);
+    for (int i = 0; i < 3; ++i)
+      for (int c = 0; c < 3; ++c) {
+        double acc = 0.0;
+        for (int m = 0; m < 8; ++m) acc += w[m] * o->table[9 * (j0 + m) + 3 * i + c];
+        R[i][c] = acc;
+      }
+    return;
+  }
   double tt = (o->kind == ORC_ORBIT_FROZEN) ? o->t_freeze : t;
   double e = o->L / (2.0 * sqrt(3.0) * o->R);
   double alpha = o->omega * tt + o->kappa0;

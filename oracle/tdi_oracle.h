@@ -15,7 +15,7 @@
 extern "C" {
 #endif
 
-enum { ORC_ORBIT_FROZEN = 0, ORC_ORBIT_ANALYTIC1 = 1 };
+enum { ORC_ORBIT_FROZEN = 0, ORC_ORBIT_ANALYTIC1 = 1, ORC_ORBIT_TABLE = 2 };
 enum { ORC_FULL = 0, ORC_LFA = 1, ORC_HYBRID = 2 };
 
 typedef struct {
@@ -27,6 +27,9 @@ typedef struct {
   double kappa0;     /* initial orbital phase, rad */
   double lambda0;    /* initial constellation orientation, rad */
   double t_freeze;   /* FROZEN: positions are taken at this time, s */
+  const double* table;   /* TABLE: positions [n_table][3][3] (sample, spacecraft, xyz), m */
+  int64_t n_table;
+  double table_t0, table_dt;
 } orc_orbit;
 
 typedef struct {

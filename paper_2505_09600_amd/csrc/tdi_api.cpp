@@ -29,6 +29,10 @@ struct Launch {
   int grid_full;
 };
 
+struct OrbitBounds {
+  double rate, tmax, tmin, rmax;
+};
+
 struct Caps {
   int g, hl, hf, y;
   size_t lds_lfa, lds_full;
@@ -41,7 +45,9 @@ struct Caps {
 
 struct tdi_plan {
   tdi_config cfg;
-  tdi_orbit orb;
+  tdi_orbit orb;                 // the table pointer of a TABLE orbit is not kept
+  OrbitBounds ob;
+  double* d_orbtab;              // TABLE: device copy of the sampled positions
   int64_t max_sources, max_total;
   int device, n_cu;
   size_t max_lds;                // LDS bytes available to one workgroup
@@ -99,7 +105,8 @@ tdi_status tdi_check_config(const tdi_config* c, const tdi_orbit* o) {
   if (c->tdi_gen != 15 && c->tdi_gen != 20) return TDI_EUNSUPPORTED;
   if (c->mode < TDI_MODE_FULL || c->mode > TDI_MODE_HYBRID) return TDI_EUNSUPPORTED;
   if (c->precision != TDI_FP64 && c->precision != TDI_FP32_BULK) return TDI_EUNSUPPORTED;
-  if (o->kind != TDI_ORBIT_FROZEN && o->kind != TDI_ORBIT_ANALYTIC1) return TDI_EUNSUPPORTED;
+  if (o->kind != TDI_ORBIT_FROZEN && o->kind != TDI_ORBIT_ANALYTIC1 && o->kind != TDI_ORBIT_TABLE)
+    return TDI_EUNSUPPORTED;
   if (o->reserved != 0) return TDI_EINVAL;
   const int N = c->interp_taps;
   if (N != 4 && N != 8 && N != 16 && N != 32) return TDI_ERANGE;
@@ -112,6 +119,14 @@ tdi_status tdi_check_config(const tdi_config* c, const tdi_orbit* o) {
   if (!(c->hyb_T_samples > 0.0) || !is_fin(c->hyb_T_samples)) return TDI_ERANGE;
   if (!(c->hyb_sigma_samples > 0.0) || !is_fin(c->hyb_sigma_samples)) return TDI_ERANGE;
   if (!(o->L_m > 0.0) || !is_fin(o->L_m)) return TDI_ERANGE;
+  if (o->kind == TDI_ORBIT_TABLE) {
+    if (!o->table) return TDI_EINVAL;
+    if (o->n_table < 8) return TDI_ERANGE;
+    if (!(o->table_dt > 0.0) || !is_fin(o->table_dt) || !is_fin(o->table_t0)) return TDI_ERANGE;
+    for (int64_t i = 0; i < 9 * o->n_table; ++i)
+      if (!is_fin(o->table[i])) return TDI_ERANGE;
+    return TDI_OK;
+  }
   if (!(o->R_m > o->L_m) || !is_fin(o->R_m)) return TDI_ERANGE;
   if (!(o->omega >= 0.0) || !is_fin(o->omega)) return TDI_ERANGE;
   if (!is_fin(o->kappa0) || !is_fin(o->lambda0) || !is_fin(o->t_freeze)) return TDI_ERANGE;
@@ -142,38 +157,68 @@ tdi_status tdi_check_batch(const tdi_config* c, int64_t n_sources, const tdi_sou
 
 namespace {
 
-double move_rate(const tdi_orbit& o) {
-  const double e = o.L_m / (2.0 * sqrt(3.0) * o.R_m);
-  return o.R_m * o.omega * (1.0 + 2.0 * e) / kC + 1e-12;   // bound of |k.V| / c
+// Bounds of an orbit used to size windows: rate = bound of |V| / c (delay
+// drift per unit time), light times within [tmin, tmax], |R_i| <= rmax.
+OrbitBounds orbit_bounds(const tdi_orbit& o) {
+  OrbitBounds b;
+  if (o.kind != TDI_ORBIT_TABLE) {
+    const double e = o.L_m / (2.0 * sqrt(3.0) * o.R_m);
+    b.rate = o.R_m * o.omega * (1.0 + 2.0 * e) / kC + 1e-12;
+    b.tmax = o.L_m / kC * (1.0 + 4.0 * b.rate) + 1e-9;
+    b.tmin = o.L_m / kC * (1.0 - 4.0 * b.rate) - 1e-9;
+    b.rmax = o.R_m + 2.0 * o.L_m;
+    return b;
+  }
+  // sampled orbit: speeds from successive samples (10 % allowance for the
+  // curvature between them), arm lengths and distances from the samples
+  double vmax = 0.0, dmax = 0.0, dmin = 1e300, rmax = 0.0;
+  const double* T = o.table;
+  for (int64_t j = 0; j < o.n_table; ++j) {
+    for (int i = 0; i < 3; ++i) {
+      const double* p = T + 9 * j + 3 * i;
+      rmax = std::max(rmax, sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]));
+      if (j + 1 < o.n_table) {
+        const double* q = p + 9;
+        const double d0 = q[0] - p[0], d1 = q[1] - p[1], d2 = q[2] - p[2];
+        vmax = std::max(vmax, sqrt(d0 * d0 + d1 * d1 + d2 * d2) / o.table_dt);
+      }
+      const double* r = T + 9 * j + 3 * ((i + 1) % 3);
+      const double e0 = r[0] - p[0], e1 = r[1] - p[1], e2 = r[2] - p[2];
+      const double d = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+      dmax = std::max(dmax, d);
+      dmin = std::min(dmin, d);
+    }
+  }
+  b.rate = 1.1 * vmax / kC + 1e-12;
+  b.tmax = dmax / kC * (1.0 + 4.0 * b.rate) + 1e-9;
+  b.tmin = dmin / kC * (1.0 - 4.0 * b.rate) - 1e-9;
+  b.rmax = rmax;
+  return b;
 }
 
-double light_time_bound(const tdi_orbit& o) {
-  return o.L_m / kC * (1.0 + 4.0 * move_rate(o)) + 1e-9;
-}
-
-double stage2_bound(const tdi_config& c, const tdi_orbit& o) {
-  return (c.tdi_gen == 20 ? 7.0 : 3.0) * light_time_bound(o);
+double stage2_bound(const tdi_config& c, const OrbitBounds& b) {
+  return (c.tdi_gen == 20 ? 7.0 : 3.0) * b.tmax;
 }
 
 // The FP32 bulk LFA kernel applies to steps up to kFastDtMax and to orbits whose
 // delays drift by at most kFastRateMax per unit time.
-bool fast_lfa(const tdi_config& c, const tdi_orbit& o, double dt_max) {
+bool fast_lfa(const tdi_config& c, const OrbitBounds& b, double dt_max) {
   return c.precision == TDI_FP32_BULK && c.mode != TDI_MODE_FULL && dt_max <= tdi::kFastDtMax &&
-         move_rate(o) <= tdi::kFastRateMax;
+         b.rate <= tdi::kFastRateMax;
 }
 
 // Worst-case staged window lengths (samples) at sampling step dt; the kernels
 // recompute the actual windows per tile and check them against these.
-Caps window_caps(const tdi_config& c, const tdi_orbit& o, double dt, bool fast) {
+Caps window_caps(const tdi_config& c, const OrbitBounds& ob, double dt, bool fast) {
   Caps k;
   k.fast = fast ? 1 : 0;
   k.tile_lfa = fast ? tdi::kTileLfaFast : tdi::kTileLfa;
   const int lfa_span = fast ? tdi::kFastChunk : tdi::kTileLfa;   // outputs sharing one window
   const int N = c.interp_taps;
-  const double Lc = o.L_m / kC;
-  const double rate = move_rate(o);
-  const double Tmax = light_time_bound(o);
-  const double Tmin = Lc * (1.0 - 4.0 * rate) - 1e-9;
+  const double rate = ob.rate;
+  const double Tmax = ob.tmax;
+  const double Tmin = ob.tmin;
+  const double Lc = Tmax;
   const int hw = (c.tdi_gen == 20) ? (c.stencil_order == 4 ? 3 : 2) : (c.stencil_order == 4 ? 2 : 1);
   auto margin = [](double cnt) { return 2 + (int)ceil(4e-4 * cnt); };
   // LFA: the six delays D_c + mu_l spread over half an arm plus arm differences
@@ -182,7 +227,7 @@ Caps window_caps(const tdi_config& c, const tdi_orbit& o, double dt, bool fast) 
   k.g = lfa_span + (int)ceil(spread_l / dt) + N + 2 * margin(lfa_span) + 4;
   k.hl = k.g + 2 * hw;
   // full: stage-2 delays reach back (7 or 3) light times
-  k.y = tdi::kTileFull + (int)ceil(stage2_bound(c, o) / dt) + N + 2 * margin(tdi::kTileFull) + 4;
+  k.y = tdi::kTileFull + (int)ceil(stage2_bound(c, ob) / dt) + N + 2 * margin(tdi::kTileFull) + 4;
   // stage-1 delays: light time plus spacecraft separations along k, plus drift
   const double spread_f = Tmax + Lc * 1.02 + 2.0 * rate * k.y * dt;
   k.hf = k.y + (int)ceil(spread_f / dt) + N + 2 * margin(k.y) + 4;
@@ -190,6 +235,24 @@ Caps window_caps(const tdi_config& c, const tdi_orbit& o, double dt, bool fast) 
   k.lds_lfa = tdi::lfa_lds_bytes(N, k.g, k.hl, fp32, k.fast, &k.goff);
   k.lds_full = tdi::full_lds_bytes(k.hf, k.y, fp32);
   return k;
+}
+
+// A sampled orbit must cover every time the kernels evaluate the geometry at:
+// each source's span, the stage-2 and light-time reach before it and the
+// tap and tile margins, with the 8-point interpolation stencil inside the table.
+bool table_covers(const tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets) {
+  if (p->orb.kind != TDI_ORBIT_TABLE) return true;
+  const double lo = p->orb.table_t0 + 3.0 * p->orb.table_dt;
+  const double hi = p->orb.table_t0 + (double)(p->orb.n_table - 5) * p->orb.table_dt;
+  const double pad = p->cfg.interp_taps / 2 + 32;
+  for (int64_t i = 0; i < n_sources; ++i) {
+    const int64_t n = offsets[i + 1] - offsets[i];
+    if (n == 0) continue;
+    const double a = src[i].t0 - stage2_bound(p->cfg, p->ob) - 2.0 * p->ob.tmax - pad * src[i].dt;
+    const double b = src[i].t0 + (double)(n - 1) * src[i].dt + pad * src[i].dt;
+    if (!(a >= lo && b <= hi)) return false;
+  }
+  return true;
 }
 
 // Fill the pinned parameter image for one batch (work lists of both kernels).
@@ -374,7 +437,7 @@ bool batch_caps(const tdi_plan* p, int64_t n_sources, const tdi_source* src, con
       dt_max = std::max(dt_max, src[i].dt);
     }
   if (!isfinite(dt_min)) return false;
-  *caps = window_caps(p->cfg, p->orb, dt_min, fast_lfa(p->cfg, p->orb, dt_max));
+  *caps = window_caps(p->cfg, p->ob, dt_min, fast_lfa(p->cfg, p->ob, dt_max));
   return true;
 }
 
@@ -514,6 +577,8 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   if (!p) return TDI_ENOMEM;
   p->cfg = *cfg;
   p->orb = *orb;
+  p->orb.table = nullptr;
+  p->ob = orbit_bounds(*orb);
   p->max_sources = max_sources;
   p->max_total = max_total_samples;
   p->device = dev;
@@ -567,6 +632,23 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
     od.sb[i] = sin(b);
   }
   od.L_over_c = orb->L_m / kC;
+  if (orb->kind == TDI_ORBIT_TABLE) {
+    const size_t tb = sizeof(double) * 9 * (size_t)orb->n_table;
+    if (hipMalloc((void**)&p->d_orbtab, tb) != hipSuccess) {
+      tdi_plan_destroy(p);
+      return TDI_ENOMEM;
+    }
+    if (hipMemcpy(p->d_orbtab, orb->table, tb, hipMemcpyHostToDevice) != hipSuccess) {
+      tdi_plan_destroy(p);
+      return TDI_EDEVICE;
+    }
+    od.tab = p->d_orbtab;
+    od.ntab = orb->n_table;
+    od.tab_t0 = orb->table_t0;
+    od.tab_idt = 1.0 / orb->table_dt;
+    od.R = p->ob.rmax;
+    od.e = 0.0;
+  }
   kp.gen = cfg->tdi_gen;
   kp.mode = cfg->mode;
   kp.aet = cfg->channels == TDI_CHANNELS_AET ? 1 : 0;
@@ -576,13 +658,13 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   kp.stencil_p = cfg->stencil_order;
   kp.T_s = cfg->hyb_T_samples;
   kp.sigma_s = cfg->hyb_sigma_samples;
-  kp.D2_bound = stage2_bound(*cfg, *orb);
+  kp.D2_bound = stage2_bound(*cfg, p->ob);
 
   p->launch = {0, 0};
   p->tuned = cfg->autotune ? false : true;
   if (!cfg->autotune && cfg->use_graph) {
     // graph replay needs persistent launches: one full occupancy of the chip
-    const Caps caps = window_caps(*cfg, *orb, 1.0, fast_lfa(*cfg, *orb, 1.0));
+    const Caps caps = window_caps(*cfg, p->ob, 1.0, fast_lfa(*cfg, p->ob, 1.0));
     p->launch.grid_lfa = tdi::occupancy_lfa(cfg->interp_taps, cfg->precision, caps.fast, caps.lds_lfa) * p->n_cu;
     p->launch.grid_full = tdi::occupancy_full(cfg->interp_taps, cfg->precision, caps.lds_full) * p->n_cu;
   }
@@ -605,6 +687,7 @@ tdi_status tdi_plan_destroy(tdi_plan* p) {
   if (p->d_err) hipFree(p->d_err);
   if (p->d_counters) hipFree(p->d_counters);
   if (p->d_ftiles) hipFree(p->d_ftiles);
+  if (p->d_orbtab) hipFree(p->d_orbtab);
   if (p->h_params) hipHostFree(p->h_params);
   free(p);
   return TDI_OK;
@@ -623,6 +706,7 @@ tdi_status tdi_run(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   if (((uintptr_t)hp | (uintptr_t)hc) & 7) return TDI_EINVAL;
   if ((((uintptr_t)X) | ((uintptr_t)Y) | ((uintptr_t)Z)) & (al - 1)) return TDI_EINVAL;
   if (p->cfg.lfa_terms == 2 && p->cfg.mode != TDI_MODE_FULL) return TDI_EUNSUPPORTED;
+  if (!table_covers(p, n_sources, src, offsets)) return TDI_ERANGE;
   if (!p->tuned) autotune(p, n_sources, src, offsets, hp, hc, X, Y, Z);
   return run_with(p, p->launch, n_sources, src, offsets, hp, hc, X, Y, Z, true, true);
 }
@@ -641,8 +725,8 @@ tdi_status tdi_run_links(tdi_plan* p, int64_t n_sources, const tdi_source* src, 
   if (((uintptr_t)y) & (fp32 ? 3 : 7)) return TDI_EINVAL;
   // read window of a tile: the tile, the spread of every delay the links use
   // (|k.R|/c <= (R (1 + e) + L)/c, light times <= 1.01 L/c), the taps, margins
-  const tdi_orbit& o = p->orb;
-  const double spread = 2.0 * (o.R_m + 2.0 * o.L_m) / kC + 1.01 * o.L_m / kC;
+  if (!table_covers(p, n_sources, src, offsets)) return TDI_ERANGE;
+  const double spread = 2.0 * p->ob.rmax / kC + p->ob.tmax;
   const int N = p->cfg.interp_taps;
   const int margin = 2 + (int)ceil(4e-4 * (double)tdi::kTileLinks);
   int cap = 0;

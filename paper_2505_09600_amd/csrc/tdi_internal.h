@@ -28,12 +28,15 @@ constexpr int kTileLinks = 256;            // link outputs: outputs per tile (on
 
 // Orbit constants prepared once per plan.
 struct OrbitDev {
-  int32_t kind;          // 0 frozen, 1 first-order analytic
+  int32_t kind;          // 0 frozen, 1 first-order analytic, 2 sampled table
   int32_t pad;
   double L, R, omega, kappa0, t_freeze;
   double e;              // L / (2 sqrt(3) R)
   double cb[3], sb[3];   // cos / sin of beta_i = 2 pi i / 3 + lambda0
   double L_over_c;
+  const double* tab;     // table: [ntab][3][3] positions (device)
+  int64_t ntab;
+  double tab_t0, tab_idt;  // time of sample 0, 1 / spacing
 };
 
 // Per-source record on the device, with the sample ranges and first global

@@ -209,6 +209,37 @@ __device__ __forceinline__ void sc_pos(const OrbitDev& o, double ca, double sa, 
   P[2] = -1.7320508075688772 * eR * cab;
 }
 
+// Sampled orbit: position of spacecraft i at time t by 8-point Lagrange
+// interpolation in time (nodes j0 .. j0 + 7 around t, clamped to the table;
+// the host checks that every evaluated time lies inside it).
+__device__ void tab_pos(const OrbitDev& o, double t, int i, double P[3]) {
+  const double u = (t - o.tab_t0) * o.tab_idt;
+  int64_t j0 = (int64_t)floor(u) - 3;
+  j0 = j0 < 0 ? 0 : (j0 > o.ntab - 8 ? o.ntab - 8 : j0);
+  const double x = u - (double)(j0 + 3);
+  // weights of the nodes at offsets m = -3 .. 4 from j0 + 3
+  double w[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    double num = 1.0, den = 1.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q == m) continue;
+      num *= x - (double)(q - 3);
+      den *= (double)(m - q);
+    }
+    w[m] = num / den;
+  }
+  P[0] = P[1] = P[2] = 0.0;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const double* r = o.tab + 9 * (j0 + m) + 3 * i;
+    P[0] = fma(w[m], r[0], P[0]);
+    P[1] = fma(w[m], r[1], P[1]);
+    P[2] = fma(w[m], r[2], P[2]);
+  }
+}
+
 // Geometry of link slot a at time t: T, xi+, xi_x, D = 2(1 - k.n) and k.R/c of
 // spacecraft a (meaningful for a < 3).  Light time: receiver at t, sender at
 // the emission time t - T (fixed point from L/c); n is the photon direction.
@@ -220,14 +251,27 @@ __device__ void node_geometry(const OrbitDev& o, double beta, double lam, double
   const double k[3] = {-cb * cl, -cb * sl, -sb};
   const double u[3] = {sl, -cl, 0.0};
   const double v[3] = {-sb * cl, -sb * sl, cb};
-  double sa, ca;
-  sincos(o.omega * (o.kind == 0 ? o.t_freeze : t) + o.kappa0, &sa, &ca);
   const int s = snd_of(a), r = rcv_of(a);
   double Rr[3], E[3];
-  sc_pos(o, ca, sa, r, Rr);
-  sc_pos(o, ca, sa, s, E);
   double T = o.L_over_c;
-  if (o.kind != 0) {
+  double sa = 0.0, ca = 1.0;
+  if (o.kind == 2) {
+    tab_pos(o, t, r, Rr);
+    for (int it = 0; it < 12; ++it) {
+      tab_pos(o, t - T, s, E);
+      const double d0 = Rr[0] - E[0], d1 = Rr[1] - E[1], d2 = Rr[2] - E[2];
+      const double Tn = sqrt(d0 * d0 + d1 * d1 + d2 * d2) / kC;
+      const double dT = Tn - T;
+      T = Tn;
+      if (fabs(dT) <= 4e-15) break;
+    }
+    tab_pos(o, t - T, s, E);
+  } else {
+    sincos(o.omega * (o.kind == 0 ? o.t_freeze : t) + o.kappa0, &sa, &ca);
+    sc_pos(o, ca, sa, r, Rr);
+    sc_pos(o, ca, sa, s, E);
+  }
+  if (o.kind == 1) {
     for (int it = 0; it < 12; ++it) {
       const double w = o.omega * T, w2 = w * w;
       const double sw = w * (1.0 - w2 * (1.0 / 6.0));
@@ -254,7 +298,8 @@ __device__ void node_geometry(const OrbitDev& o, double beta, double lam, double
   out[2] = 2.0 * un * vn;
   out[3] = 2.0 * (1.0 - kn);
   double Ra[3];
-  sc_pos(o, ca, sa, a < 3 ? a : 0, Ra);
+  if (o.kind == 2) tab_pos(o, t, a < 3 ? a : 0, Ra);
+  else sc_pos(o, ca, sa, a < 3 ? a : 0, Ra);
   out[4] = (k[0] * Ra[0] + k[1] * Ra[1] + k[2] * Ra[2]) / kC;
 }
 

@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtdi.so")
 
 TDI_OK, TDI_EINVAL, TDI_ERANGE, TDI_ENOMEM, TDI_EDEVICE, TDI_EUNSUPPORTED, TDI_ESTATE = 0, -1, -2, -3, -4, -5, -6
-TDI_ORBIT_FROZEN, TDI_ORBIT_ANALYTIC1 = 0, 1
+TDI_ORBIT_FROZEN, TDI_ORBIT_ANALYTIC1, TDI_ORBIT_TABLE = 0, 1, 2
 TDI_MODE_FULL, TDI_MODE_LFA, TDI_MODE_HYBRID = 0, 1, 2
 TDI_FP64, TDI_FP32_BULK = 0, 1
 TDI_CHANNELS_XYZ, TDI_CHANNELS_AET = 0, 1
@@ -39,7 +39,9 @@ class TdiError(RuntimeError):
 class tdi_orbit(C.Structure):
     _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("L_m", C.c_double),
                 ("R_m", C.c_double), ("omega", C.c_double), ("kappa0", C.c_double),
-                ("lambda0", C.c_double), ("t_freeze", C.c_double)]
+                ("lambda0", C.c_double), ("t_freeze", C.c_double),
+                ("table", C.POINTER(C.c_double)), ("n_table", C.c_int64),
+                ("table_t0", C.c_double), ("table_dt", C.c_double)]
 
 
 class tdi_source(C.Structure):
@@ -163,8 +165,16 @@ def tdi_plan_destroy(plan) -> int:
 
 # --- conveniences -------------------------------------------------------------
 def make_orbit(d: dict) -> tdi_orbit:
-    return tdi_orbit(int(d["kind"]), 0, float(d["L"]), float(d["R"]), float(d["omega"]),
-                     float(d["kappa0"]), float(d["lambda0"]), float(d.get("t_freeze", 0.0)))
+    o = tdi_orbit(int(d["kind"]), 0, float(d["L"]), float(d["R"]), float(d["omega"]),
+                  float(d["kappa0"]), float(d["lambda0"]), float(d.get("t_freeze", 0.0)))
+    if d.get("table") is not None:
+        tab = np.ascontiguousarray(d["table"], dtype=np.float64).reshape(-1, 3, 3)
+        o._table = tab                       # kept alive with the struct
+        o.table = tab.ctypes.data_as(C.POINTER(C.c_double))
+        o.n_table = tab.shape[0]
+        o.table_t0 = float(d["table_t0"])
+        o.table_dt = float(d["table_dt"])
+    return o
 
 
 def make_config(d: dict, autotune: int = 0, use_graph: int = 0) -> tdi_config:

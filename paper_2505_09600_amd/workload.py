@@ -43,6 +43,7 @@ OMEGA_YR = 2.0 * math.pi / (365.25 * 86400.0)   # rad/s, Julian year
 # Orbit kinds (same integer codes as the C ABI).
 ORBIT_FROZEN = 0
 ORBIT_ANALYTIC1 = 1
+ORBIT_TABLE = 2
 
 # tdi_source record layout shared by the C ABI and the oracle (host memory).
 SOURCE_DTYPE = np.dtype([("beta", "<f8"), ("lam", "<f8"), ("psi", "<f8"),
@@ -54,6 +55,47 @@ def default_orbit(kind: int = ORBIT_ANALYTIC1, t_freeze: float = 0.0,
     """Orbit spec: rigid equilateral first-order analytic orbit at 1 AU."""
     return dict(kind=int(kind), L=ARM_L, R=AU, omega=OMEGA_YR,
                 kappa0=float(kappa0), lambda0=float(lambda0), t_freeze=float(t_freeze))
+
+
+def keplerian_orbit_table(t0: float, dt: float, n: int, L: float = ARM_L, R: float = AU,
+                          omega: float = OMEGA_YR, kappa0: float = 0.0, lambda0: float = 0.0):
+    """Positions (n, 3, 3) of three spacecraft on exact Keplerian ellipses,
+    sampled at t0 + j dt: semi-major axis R, eccentricity e = L/(2 sqrt3 R),
+    inclination sqrt3 e, ascending node at beta_i + pi/2 and perihelion
+    argument -pi/2 (beta_i = 2 pi i/3 + lambda0), mean anomaly
+    omega t + kappa0 - beta_i.  To first order in e these are the rigid
+    analytic orbit; at second order the arms flex (a stand-in for sampled
+    orbit files).  Kepler's equation is solved by Newton iteration."""
+    e = L / (2.0 * math.sqrt(3.0) * R)
+    inc = math.sqrt(3.0) * e
+    t = t0 + np.arange(n, dtype=np.float64) * dt
+    out = np.zeros((n, 3, 3))
+    for i in range(3):
+        beta = 2.0 * math.pi * i / 3.0 + lambda0
+        node, argp = beta + 0.5 * math.pi, -0.5 * math.pi
+        M = omega * t + kappa0 - beta
+        E = M.copy()
+        for _ in range(30):
+            E = E - (E - e * np.sin(E) - M) / (1.0 - e * np.cos(E))
+        xp = R * (np.cos(E) - e)
+        yp = R * math.sqrt(1.0 - e * e) * np.sin(E)
+        # perifocal -> ecliptic: rotate by argp, tilt by inc about the node line, rotate by node
+        ca, sa = math.cos(argp), math.sin(argp)
+        x1, y1 = ca * xp - sa * yp, sa * xp + ca * yp
+        ci, si = math.cos(inc), math.sin(inc)
+        y2, z2 = ci * y1, si * y1
+        cn, sn = math.cos(node), math.sin(node)
+        out[:, i, 0] = cn * x1 - sn * y2
+        out[:, i, 1] = sn * x1 + cn * y2
+        out[:, i, 2] = z2
+    return out
+
+
+def table_orbit(table, t0: float, dt: float, L: float = ARM_L) -> dict:
+    """Orbit spec of a sampled table (TABLE kind); L is the nominal arm."""
+    return dict(kind=ORBIT_TABLE, L=L, R=AU, omega=0.0, kappa0=0.0, lambda0=0.0, t_freeze=0.0,
+                table=np.ascontiguousarray(table, dtype=np.float64), table_t0=float(t0),
+                table_dt=float(dt))
 
 
 def default_config(tdi_gen=20, mode=0, taps=32, stencil_order=4, equal_arms=0,

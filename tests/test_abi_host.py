@@ -193,3 +193,24 @@ def test_ip_entry_points_without_device(L):
     assert T.tdi_ip_run(None, 1, np.array([0, 5]), [0, 0, 0], [0, 0, 0], 0) == T.TDI_EINVAL
     assert T.lib().tdi_ip_plan_destroy(None) == T.TDI_EINVAL
     assert T.lib().tdi_ip_kernel_times(None, None, 0, None) == T.TDI_EINVAL
+
+
+def _table_orb(n=16, dt=3600.0, **kw):
+    tab = W.keplerian_orbit_table(0.0, dt, n)
+    d = W.table_orbit(tab, 0.0, dt)
+    d.update(kw)
+    return d
+
+
+def test_table_orbit_validation(L):
+    c = _cfg()
+    assert T.tdi_check_config(c, T.make_orbit(_table_orb())) == T.TDI_OK
+    assert T.tdi_check_config(c, T.make_orbit(_table_orb(n=7))) == T.TDI_ERANGE
+    assert T.tdi_check_config(c, T.make_orbit(_table_orb(table_dt=0.0))) == T.TDI_ERANGE
+    bad = _table_orb()
+    bad["table"] = bad["table"].copy()
+    bad["table"][3, 1, 2] = math.nan
+    assert T.tdi_check_config(c, T.make_orbit(bad)) == T.TDI_ERANGE
+    o = T.make_orbit(_table_orb())
+    o.table = None
+    assert T.tdi_check_config(c, o) == T.TDI_EINVAL
