@@ -376,6 +376,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-sources", type=int, default=512)
+    ap.add_argument("--orbit", default="analytic", choices=["analytic", "table"],
+                    help="c4: the first-order analytic orbit (default) or flexing Keplerian orbits "
+                         "read from an hourly position table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0, help="upper bound of the timed oracle run (s)")
@@ -412,6 +415,11 @@ def main():
     torch.cuda.set_device(dev)
     t_gen = time.perf_counter()
     batch, cfg, orb = W.config_c4(n_sources=args.n_sources, xp=torch, device=dev)
+    if args.orbit == "table":
+        # eccentric Keplerian orbits sampled hourly, spanning the longest source
+        span = float(np.max(np.diff(batch.offsets))) * 10.0
+        t_lo, step = -2 * 86400.0, 3600.0
+        orb = W.table_orbit(W.keplerian_orbit_table(t_lo, step, int((span + 4 * 86400.0) / step)), t_lo, step)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t_gen
     total = batch.total
@@ -525,7 +533,8 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched hybrid TDI 2.0, 512 sources, lengths log-uniform 2^18..2^22 at "
-                               "dt=10 s (seed 1004), FP32-bulk with FP64 delays and stencils",
+                               "dt=10 s (seed 1004), FP32-bulk with FP64 delays and stencils"
+                               + ("; Keplerian orbits from an hourly table" if args.orbit == "table" else ""),
                    "n_sources": batch.n_sources, "total_samples": total, "taps": TAPS,
                    "stencil_order": 4, "tdi": "2.0", "mode": "hybrid",
                    "sources_with_full_region": n_full_region, "launch": launch,
