@@ -159,6 +159,9 @@ def secondary(args):
             batch, cfg, orb = W.config_c2()
             if args.config == "c2":
                 cases = {f"full {p} tdi2.0 N32": dict(cfg, mode=0, precision=i) for i, p in ((0, "fp64"), (1, "fp32"))}
+                # the same with time-nested delays (light times at each retarded time)
+                cases.update({f"full {p} tdi2.0 N32 nested": dict(cfg, mode=0, precision=i, nested_delays=1)
+                              for i, p in ((0, "fp64"), (1, "fp32"))})
             else:
                 cases = {}
                 for gen in (15, 20):

@@ -118,6 +118,13 @@ typedef struct {
                                -(L/2c)(1/6)[L(1 - k.n)/(2c)]^2 times the third derivative of H.
                                tdi_run supports only the leading term (2 gives
                                TDI_EUNSUPPORTED in the LFA and hybrid modes) */
+  int32_t nested_delays;    /* full response (FULL mode and the full part of HYBRID): 0 = every
+                               delay of Eqs. (X1.5), (X2.0) at the output time, as the paper does
+                               (Sec. II.B); 1 = time-nested delays, each light time taken at the
+                               time its delay is applied, D_a D_b f(t) = f(t - T_a(t) -
+                               T_b(t - T_a(t))).  No effect on the LFA or on tdi_run_links.
+                               Other values give TDI_ERANGE. */
+  int32_t reserved2;        /* must be 0 */
 } tdi_config;
 
 typedef struct tdi_plan tdi_plan;

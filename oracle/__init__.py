@@ -43,7 +43,8 @@ class Orbit(C.Structure):
 class Config(C.Structure):
     _fields_ = [("tdi_gen", C.c_int32), ("mode", C.c_int32), ("taps", C.c_int32),
                 ("stencil_order", C.c_int32), ("equal_arms", C.c_int32),
-                ("lfa_terms", C.c_int32), ("T_samples", C.c_double),
+                ("lfa_terms", C.c_int32), ("nested_delays", C.c_int32), ("pad_", C.c_int32),
+                ("T_samples", C.c_double),
                 ("sigma_samples", C.c_double)]
 
 
@@ -86,6 +87,10 @@ def lib():
         L.orc_link_outputs.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.POINTER(Source),
                                        C.c_int64, _D, _D, _D]
         L.orc_tdi_combine.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_double, _D, _D, _D, _D, _D]
+        L.orc_tdi_combine_nested.argtypes = [C.c_int, C.c_int, C.c_int64, C.c_double,
+                                             _D, _D, _D, _D, _D]
+        L.orc_nested_term.argtypes = [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                      C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_response.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.POINTER(Source),
                                    C.c_int64, _D, _D, _D, _D, _D]
         L.orc_response_at.argtypes = [C.POINTER(Config), C.POINTER(Orbit), C.POINTER(Source),
@@ -126,7 +131,8 @@ def make_orbit(d: dict) -> Orbit:
 
 def make_config(d: dict) -> Config:
     return Config(int(d["tdi_gen"]), int(d["mode"]), int(d["taps"]), int(d["stencil_order"]),
-                  int(d.get("equal_arms", 0)), int(d.get("lfa_terms", 0)), float(d["T_samples"]),
+                  int(d.get("equal_arms", 0)), int(d.get("lfa_terms", 0)),
+                  int(d.get("nested_delays", 0)), 0, float(d["T_samples"]),
                   float(d["sigma_samples"]))
 
 
@@ -209,12 +215,21 @@ def link_outputs(cfg: dict, orbit: dict, rec, hp, hc):
     return y
 
 
-def tdi_combine(gen: int, N: int, dt: float, y, T):
+def tdi_combine(gen: int, N: int, dt: float, y, T, nested: bool = False):
     y, T = _f64(y), _f64(T)
     n = y.shape[1]
     X, Y, Z = np.zeros(n), np.zeros(n), np.zeros(n)
-    lib().orc_tdi_combine(gen, N, n, dt, _dp(y), _dp(T), _dp(X), _dp(Y), _dp(Z))
+    fn = lib().orc_tdi_combine_nested if nested else lib().orc_tdi_combine
+    fn(gen, N, n, dt, _dp(y), _dp(T), _dp(X), _dp(Y), _dp(Z))
     return X, Y, Z
+
+
+def nested_term(t: int):
+    """(sign, link, delays in the order applied) of term t in time-nested form."""
+    sign, link, nd = C.c_int(), C.c_int(), C.c_int()
+    d = (C.c_int * 8)()
+    lib().orc_nested_term(t, C.byref(sign), C.byref(link), C.byref(nd), d)
+    return sign.value, link.value, tuple(d[:nd.value])
 
 
 def response(cfg: dict, orbit: dict, rec, hp, hc):

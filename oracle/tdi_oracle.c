@@ -7,6 +7,7 @@
  *   - antenna patterns and link projection            Sec. II.A, Eqs. (H, xi_plus, xi_cross)
  *   - single-link response and propagation delays     Sec. II.B, Eqs. (yslr, delta_s, delta_r)
  *   - Michelson X 1.5 / 2.0, delays evaluated at t    Sec. II.B, Eqs. (X1.5, X2.0)
+ *     (optionally time-nested delays)
  *   - low-frequency response (central differences)    Sec. III, Eqs. (yslr_strain_derivatives,
  *                                                     X15_with_strain_derivatives,
  *                                                     X20_with_strain_derivatives);
@@ -276,6 +277,48 @@ static int n_terms(int gen) { return gen == 20 ? 16 : 8; }
 static const orc_term* term_at(int t) { return t < 8 ? &X15_TERMS[t] : &X20_EXTRA_TERMS[t - 8]; }
 
 /* ---------------------------------------------------------------------------
+ * The same combinations with time-nested delays (an option: the paper takes
+ * every delay at t, Sec. II.B, text after Eq. X2.0).  A delay operator shifts
+ * by the light time of its link at the time it is applied,
+ *   D_l f(t) = f(t - T_l(t)),   D_a D_b f(t) = f(t - T_a(t) - T_b(t - T_a(t))),
+ * so the leftmost factor is taken at the output time.  With the two round
+ * trips from spacecraft 1,
+ *   A = D_{+3} D_{-3}  (out along 1->2, back along 2->1, which arrives at t),
+ *   B = D_{-2} D_{+2}  (out along 1->3, back along 3->1),
+ * and the two one-arm signals received at spacecraft 1,
+ *   eta2 = y_{231} + D_{+3} y_{1-32},   eta3 = y_{3-21} + D_{-2} y_{123},
+ * Eq. (X1.5) is (B - 1) eta2 - (A - 1) eta3 and Eq. (X2.0) adds
+ * (B A - A B B) eta2 + (B A A - A B) eta3.  Expanded, every product carries the
+ * delays of one printed term above, in a definite order.
+ * ------------------------------------------------------------------------- */
+typedef struct { int sign; const char* word; int eta; } orc_word;
+
+static const orc_word NESTED_WORDS[8] = {
+    {+1, "B", 2}, {-1, "", 2}, {+1, "", 3}, {-1, "A", 3},            /* X1.5 */
+    {+1, "BA", 2}, {-1, "ABB", 2}, {+1, "BAA", 3}, {-1, "AB", 3},     /* added by X2.0 */
+};
+
+void orc_nested_term(int t, int* sign, int* link, int* nd, int d[8]) {
+  const orc_word* w = &NESTED_WORDS[t / 2];
+  int n = 0;
+  for (const char* ch = w->word; *ch; ++ch) {
+    if (*ch == 'A') { d[n++] = +3; d[n++] = -3; }
+    else            { d[n++] = -2; d[n++] = +2; }
+  }
+  /* even t: the link received at spacecraft 1; odd t: the far link, reached
+   * through one more leg into spacecraft 1, applied last */
+  const int near = w->eta == 2 ? +3 : -2, far = w->eta == 2 ? -3 : +2;
+  if (t % 2 == 0) {
+    *link = near;
+  } else {
+    *link = far;
+    d[n++] = near;
+  }
+  *sign = w->sign;
+  *nd = n;
+}
+
+/* ---------------------------------------------------------------------------
  * Evaluation context: h_SSB, lazily filled link series y and LFA derivative
  * series g (each entry computed at most once).
  * ------------------------------------------------------------------------- */
@@ -386,22 +429,44 @@ static double lagrange_y(orc_ctx* x, int slot, int64_t i0, double fx) {
   return orc_lagrange(x->y + (size_t)slot * x->n, x->n, i0, fx, N);
 }
 
-/* Stage 2 at output sample k, Eqs. (X1.5)/(X2.0): all delays L_l -> c T_l(t_k);
- * a term's delays are summed first, then split.  If absterms is non-null the
- * sum of |term| per channel is returned there as well. */
+/* Term t of channel c at output sample k: sign, link of y and total delay.
+ * Delays at t_k (the paper's choice): the light times of the term are summed.
+ * Time-nested: each light time is taken at t_k less the delays applied before
+ * it.  The retarded time is formed in absolute time only as the argument of
+ * the slowly varying light time; the split uses the delay alone. */
+static void term_delay(const orc_ctx* x, const orc_geom* g, int c, int t, int64_t k,
+                       int* sign, int* link, double* d) {
+  double acc = 0.0;
+  if (x->c->nested_delays) {
+    int nd, dl[8];
+    orc_nested_term(t, sign, link, &nd, dl);
+    for (int q = 0; q < nd; ++q) acc += orc_light_time(x->o, rotate_link(dl[q], c), t_of(x, k) - acc);
+  } else {
+    const orc_term* tm = term_at(t);
+    for (int q = 0; q < tm->nd; ++q) acc += g->T[link_slot(rotate_link(tm->d[q], c))];
+    *sign = tm->sign;
+    *link = tm->link;
+  }
+  *link = rotate_link(*link, c);
+  *d = acc;
+}
+
+/* Stage 2 at output sample k, Eqs. (X1.5)/(X2.0): all delays L_l -> c T_l(t_k)
+ * (or time-nested, above); a term's delays are summed first, then split.  If
+ * absterms is non-null the sum of |term| per channel is returned there too. */
 static void full_at(orc_ctx* x, int64_t k, double out[3], double* absterms) {
   orc_geom g;
   orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, k), &g);
   for (int c = 0; c < 3; ++c) {
     double acc = 0.0, aabs = 0.0;
     for (int t = 0; t < n_terms(x->c->tdi_gen); ++t) {
-      const orc_term* tm = term_at(t);
-      double d = 0.0;
-      for (int q = 0; q < tm->nd; ++q) d += g.T[link_slot(rotate_link(tm->d[q], c))];
+      int sign, link;
+      double d;
+      term_delay(x, &g, c, t, k, &sign, &link, &d);
       int64_t i0; double fx;
       orc_split(k, d, x->s->dt, &i0, &fx);
-      double v = lagrange_y(x, link_slot(rotate_link(tm->link, c)), i0, fx);
-      acc += (double)tm->sign * v;
+      double v = lagrange_y(x, link_slot(link), i0, fx);
+      acc += (double)sign * v;
       aabs += fabs(v);
     }
     out[c] = acc;
@@ -599,6 +664,31 @@ void orc_tdi_combine(int gen, int N, int64_t n, double dt, const double* y,
   }
 }
 
+void orc_tdi_combine_nested(int gen, int N, int64_t n, double dt, const double* y,
+                            const double* T, double* X, double* Y, double* Z) {
+  double* outs[3] = {X, Y, Z};
+#pragma omp parallel for schedule(static) if (n > 4096 && !in_parallel())
+  for (int64_t k = 0; k < n; ++k) {
+    for (int c = 0; c < 3; ++c) {
+      double acc = 0.0;
+      for (int t = 0; t < n_terms(gen); ++t) {
+        int sign, link, nd, dl[8];
+        orc_nested_term(t, &sign, &link, &nd, dl);
+        double d = 0.0;
+        for (int q = 0; q < nd; ++q) {
+          int64_t j0; double fj;
+          orc_split(k, d, dt, &j0, &fj);
+          d += orc_lagrange(T + (size_t)link_slot(rotate_link(dl[q], c)) * n, n, j0, fj, N);
+        }
+        int64_t i0; double fx;
+        orc_split(k, d, dt, &i0, &fx);
+        acc += (double)sign * orc_lagrange(y + (size_t)link_slot(rotate_link(link, c)) * n, n, i0, fx, N);
+      }
+      outs[c][k] = acc;
+    }
+  }
+}
+
 void orc_response(const orc_config* c, const orc_orbit* o, const orc_source* s,
                   int64_t n, const double* hp, const double* hc,
                   double* X, double* Y, double* Z) {
@@ -741,13 +831,13 @@ static void abs_full_at(orc_ctx* x, int64_t k, double out[3]) {
   for (int c = 0; c < 3; ++c) {
     double acc = 0.0;
     for (int t = 0; t < n_terms(x->c->tdi_gen); ++t) {
-      const orc_term* tm = term_at(t);
-      double d = 0.0;
-      for (int q = 0; q < tm->nd; ++q) d += g.T[link_slot(rotate_link(tm->d[q], c))];
+      int sign, link;
+      double d;
+      term_delay(x, &g, c, t, k, &sign, &link, &d);
       int64_t i0; double fx;
       orc_split(k, d, x->s->dt, &i0, &fx);
       abs_ensure_y(x, i0 - N / 2 + 1, i0 + N / 2 + 1);
-      acc += lagrange_abs(x->y + (size_t)link_slot(rotate_link(tm->link, c)) * x->n, x->n, i0, fx, N);
+      acc += lagrange_abs(x->y + (size_t)link_slot(link) * x->n, x->n, i0, fx, N);
     }
     out[c] = acc;
   }

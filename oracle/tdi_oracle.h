@@ -39,6 +39,9 @@ typedef struct {
   int32_t stencil_order;  /* p in {2, 4} */
   int32_t equal_arms;     /* LFA only: 1 = equal constant delays L/c */
   int32_t lfa_terms;      /* single-link LFA: 2 = keep the next (m = 1) term of the central series */
+  int32_t nested_delays;  /* full response: 1 = each delay at the time it is applied (time-nested),
+                             0 = every delay at the output time (the paper's choice) */
+  int32_t pad_;
   double T_samples;       /* hybrid window length, samples */
   double sigma_samples;   /* sigmoid width, samples */
 } orc_config;
@@ -97,6 +100,17 @@ void orc_link_outputs(const orc_config* c, const orc_orbit* o, const orc_source*
 /* Stage 2 on arbitrary link series and per-sample light times T[l*n + k]. */
 void orc_tdi_combine(int gen, int N, int64_t n, double dt, const double* y,
                      const double* T, double* X, double* Y, double* Z);
+
+/* Term t of Eq. (X1.5) (t < 8) or of Eq. (X2.0) (t < 16) in time-nested form:
+ * sign, link of y, and its delays in the order they are applied (d[0] is
+ * taken at the output time, d[q] at the output time less the first q). */
+void orc_nested_term(int t, int* sign, int* link, int* nd, int d[8]);
+
+/* Stage 2 with time-nested delays: the light time of each later delay is read
+ * from T at the retarded time by N-tap Lagrange interpolation (zero outside
+ * [0, n), so only samples whose retarded reads stay inside are meaningful). */
+void orc_tdi_combine_nested(int gen, int N, int64_t n, double dt, const double* y,
+                            const double* T, double* X, double* Y, double* Z);
 
 /* Whole response for one source (all samples). */
 void orc_response(const orc_config* c, const orc_orbit* o, const orc_source* s,

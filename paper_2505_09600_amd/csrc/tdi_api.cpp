@@ -116,6 +116,8 @@ tdi_status tdi_check_config(const tdi_config* c, const tdi_orbit* o) {
   if (c->use_graph != 0 && c->use_graph != 1) return TDI_ERANGE;
   if (c->channels != TDI_CHANNELS_XYZ && c->channels != TDI_CHANNELS_AET) return TDI_EUNSUPPORTED;
   if (c->lfa_terms < 0 || c->lfa_terms > 2) return TDI_ERANGE;
+  if (c->nested_delays != 0 && c->nested_delays != 1) return TDI_ERANGE;
+  if (c->reserved2 != 0) return TDI_EINVAL;
   if (!(c->hyb_T_samples > 0.0) || !is_fin(c->hyb_T_samples)) return TDI_ERANGE;
   if (!(c->hyb_sigma_samples > 0.0) || !is_fin(c->hyb_sigma_samples)) return TDI_ERANGE;
   if (!(o->L_m > 0.0) || !is_fin(o->L_m)) return TDI_ERANGE;
@@ -653,6 +655,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   kp.mode = cfg->mode;
   kp.aet = cfg->channels == TDI_CHANNELS_AET ? 1 : 0;
   kp.lfa_terms = cfg->lfa_terms == 2 ? 2 : 1;
+  kp.nested = cfg->nested_delays;
   kp.equal_arms = cfg->lfa_equal_arms;
   kp.stencil_m = cfg->tdi_gen == 20 ? 3 : 2;
   kp.stencil_p = cfg->stencil_order;

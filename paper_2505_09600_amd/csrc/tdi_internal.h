@@ -73,6 +73,7 @@ struct KParams {
   OrbitDev orb;
   int32_t gen, mode, equal_arms, stencil_m, stencil_p, persistent;
   int32_t aet, cap_lk;   // aet: store A, E, T instead of X, Y, Z; cap_lk: link-output window
+  int32_t nested, pad1;  // nested: time-nested stage-2 delays
   int64_t link_stride;   // link outputs: elements between the six link arrays (X is their base)
   double T_s, sigma_s;
   double D2_bound;       // upper bound of a stage-2 delay (s)

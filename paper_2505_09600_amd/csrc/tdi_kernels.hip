@@ -77,6 +77,37 @@ __constant__ int c_tcoef[16][6] = {
     {0, 1, 1, 0, 1, 1},   // y_{3-21}(t - L3 - L-3 - L-2 - L2)
 };
 
+// The same terms with time-nested delays (optional): a delay operator shifts
+// by the light time of its link at the time it is applied, so a product's
+// leftmost factor is taken at the output time and each later one at the
+// output time less the delays before it.  With the round trips from
+// spacecraft 1, A = D+3 D-3 and B = D-2 D+2, and the one-arm signals
+// eta2 = y+3 + D+3 y-3 and eta3 = y-2 + D-2 y+2, Eq. (X1.5) is
+// B eta2 - eta2 + eta3 - A eta3 and Eq. (X2.0) adds
+// B A eta2 - A B B eta2 + B A A eta3 - A B eta3.  Slots in application order
+// (A = {2, 5}, B = {4, 1}); the far link of a one-arm signal takes one more leg.
+__constant__ int c_nsign[16] = {+1, +1, -1, -1, +1, +1, -1, -1, +1, +1, -1, -1, +1, +1, -1, -1};
+__constant__ int c_nlink[16] = {2, 5, 2, 5, 4, 1, 4, 1, 2, 5, 2, 5, 4, 1, 4, 1};
+__constant__ int c_nlen[16] = {2, 3, 0, 1, 0, 1, 2, 3, 4, 5, 6, 7, 6, 7, 4, 5};
+__constant__ int c_nseq[16][7] = {
+    {4, 1},                  // B eta2: y+3
+    {4, 1, 2},               //         y-3
+    {},                      // -eta2
+    {2},
+    {},                      // eta3: y-2
+    {4},                     //       y+2
+    {2, 5},                  // -A eta3
+    {2, 5, 4},
+    {4, 1, 2, 5},            // B A eta2
+    {4, 1, 2, 5, 2},
+    {2, 5, 4, 1, 4, 1},      // -A B B eta2
+    {2, 5, 4, 1, 4, 1, 2},
+    {4, 1, 2, 5, 2, 5},      // B A A eta3
+    {4, 1, 2, 5, 2, 5, 4},
+    {2, 5, 4, 1},            // -A B eta3
+    {2, 5, 4, 1, 4},
+};
+
 // slot of link l relabelled c times (1->2->3->1), and its inverse
 __host__ __device__ constexpr int rot_slot(int slot, int c) { return (slot % 3 + c) % 3 + (slot >= 3 ? 3 : 0); }
 __host__ __device__ constexpr int unrot_slot(int slot, int c) { return (slot % 3 + 3 - c) % 3 + (slot >= 3 ? 3 : 0); }
@@ -1599,7 +1630,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
     }
     __syncthreads();
 
-    // Stage 2: sum of +-y_l at the term delays, light times at the output time.
+    // Stage 2: sum of +-y_l at the term delays, light times at the output time
+    // (or time-nested: each light time from the fit at its retarded sample).
     const int nterms = P.gen == 20 ? 16 : 8;
     const double kH = sh.kH;
     for (int i = tid; i < cnt; i += kBlock) {
@@ -1619,9 +1651,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
 #pragma unroll 1
           for (int t = 0; t < nterms; ++t) {
             double d = 0.0;
+            int slot, sign;
+            if (P.nested) {
+#pragma unroll 1
+              for (int q = 0; q < c_nlen[t]; ++q) {
+                const double sq = ((double)k - d / dt - sh.F.kc) * sh.F.ikh;
+                d += geo_eval(sh.F, qT(rot_slot(c_nseq[t][q], c)), sq);
+              }
+              slot = c_nlink[t];
+              sign = c_nsign[t];
+            } else {
 #pragma unroll
-            for (int a = 0; a < 6; ++a) d += (double)c_tcoef[t][unrot_slot(a, c)] * T6[a];
-            const TC* ys = ywin + rot_slot(c_tlink[t], c) * cap_y;
+              for (int a = 0; a < 6; ++a) d += (double)c_tcoef[t][unrot_slot(a, c)] * T6[a];
+              slot = c_tlink[t];
+              sign = c_tsign[t];
+            }
+            const TC* ys = ywin + rot_slot(slot, c) * cap_y;
             TC v;
             if (d == 0.0) {
               v = ys[k - y0];
@@ -1641,7 +1686,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
                 v = vv[0];
               }
             }
-            sum += c_tsign[t] > 0 ? v : -v;
+            sum += sign > 0 ? v : -v;
           }
           if (c == 0) out[0] = (double)sum; else if (c == 1) out[1] = (double)sum; else out[2] = (double)sum;
         }

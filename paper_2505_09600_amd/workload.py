@@ -99,13 +99,16 @@ def table_orbit(table, t0: float, dt: float, L: float = ARM_L) -> dict:
 
 
 def default_config(tdi_gen=20, mode=0, taps=32, stencil_order=4, equal_arms=0,
-                   precision=0, T_samples=800.0, sigma_samples=20.0, channels=0) -> dict:
+                   precision=0, T_samples=800.0, sigma_samples=20.0, channels=0,
+                   nested_delays=0) -> dict:
     """Response configuration (hybrid defaults T = 800 dt, sigma = T/40;
-    channels 0 = X, Y, Z, 1 = A, E, T)."""
+    channels 0 = X, Y, Z, 1 = A, E, T; nested_delays 1 = time-nested delays
+    in the full response)."""
     return dict(tdi_gen=int(tdi_gen), mode=int(mode), taps=int(taps),
                 stencil_order=int(stencil_order), equal_arms=int(equal_arms),
                 precision=int(precision), T_samples=float(T_samples),
-                sigma_samples=float(sigma_samples), channels=int(channels))
+                sigma_samples=float(sigma_samples), channels=int(channels),
+                nested_delays=int(nested_delays))
 
 
 # ----------------------------------------------------------------------------

@@ -64,6 +64,9 @@ def test_status_strings(L):
     ("channels", 2, T.TDI_EUNSUPPORTED),
     ("lfa_terms", 3, T.TDI_ERANGE),
     ("lfa_terms", -1, T.TDI_ERANGE),
+    ("nested_delays", 2, T.TDI_ERANGE),
+    ("nested_delays", -1, T.TDI_ERANGE),
+    ("reserved2", 1, T.TDI_EINVAL),
 ])
 def test_config_validation(L, field, value, code):
     c = _cfg()
