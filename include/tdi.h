@@ -232,7 +232,7 @@ tdi_status tdi_check_noise(const tdi_noise* noise);
  * TDI_FP64 (double inputs, FP64 transforms) or TDI_FP32_BULK (float inputs,
  * FP32 transforms); the weighted sums accumulate in FP64 either way.  The plan
  * owns the 1/S_n table and a transform workspace of 6 max_total_samples
- * complex elements.  Sources longer than 2^24 (FP32) or 2^22 (FP64) samples
+ * complex elements.  Sources longer than 2^25 (FP32) or 2^23 (FP64) samples
  * return TDI_ERANGE; no gfx950 device returns TDI_EDEVICE. */
 tdi_status tdi_ip_plan_create(tdi_ip_plan** out, const tdi_noise* noise, int32_t precision, double dt,
                               int64_t max_sources, int64_t max_total_samples,

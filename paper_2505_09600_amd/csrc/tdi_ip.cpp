@@ -92,19 +92,24 @@ struct Split {
   int logN, logN1, logN2, cols, n1, n2;
 };
 
+// pass-1 and pass-2 tile elements (log2) of the transform precision
+int log_tile(int fp64, int pass) {
+  return fp64 ? (pass == 1 ? tdi_ip::Tile<double, 1>::kLogE : tdi_ip::Tile<double, 2>::kLogE)
+              : (pass == 1 ? tdi_ip::Tile<float, 1>::kLogE : tdi_ip::Tile<float, 2>::kLogE);
+}
+
 bool split_of(int64_t n, int fp64, Split* s) {
-  const int E = fp64 ? tdi_ip::kElemsD : tdi_ip::kElemsF;
-  const int logE = fp64 ? 12 : 13;
+  const int E1 = 1 << log_tile(fp64, 1), logE2 = log_tile(fp64, 2);
   s->logN = log2_fft_length(n);
-  if (s->logN <= logE) {
+  if (s->logN <= logE2) {
     *s = {s->logN, 0, s->logN, 0, 0, n > 0 ? 1 : 0};
     return true;
   }
-  s->logN2 = logE - 1;                     // two rows of the second pass share the LDS
+  s->logN2 = logE2 - 1;                    // two rows of the second pass share its tile
   s->logN1 = s->logN - s->logN2;
   const int N1 = 1 << s->logN1, N2 = 1 << s->logN2;
-  if (N1 > E / 2) return false;            // at least two columns per first-pass task
-  s->cols = std::min(E / N1, N2);
+  if (N1 > E1 / 2) return false;           // at least two columns per first-pass task
+  s->cols = std::min(E1 / N1, N2);
   s->n1 = N2 / s->cols;
   s->n2 = N1 / 2 + 1;
   return true;
@@ -118,9 +123,10 @@ struct tdi_ip_plan {
   double dt;
   int64_t max_sources, max_total, max_source;
   int logNmax;
-  int grid;                       // persistent workgroups: two per compute unit, a multiple of 8
+  int grid1, grid2;               // persistent workgroups of the passes (resident count, multiple of 8)
   hipStream_t stream;
-  double* d_wt;                   // weight tables, one per length (see IpParams)
+  void* d_wt;                     // weight tables, one per length, transform precision (see IpParams)
+  int32_t wexp;                   // power-of-two scale of the FP32 weight table
   int64_t wofs[32];               // offset of the table of length 2^logN
   void* d_tw;                     // twiddle tables (see IpParams)
   void* d_th;
@@ -203,9 +209,12 @@ tdi_status tdi_ip_plan_create(tdi_ip_plan** out, const tdi_noise* noise, int32_t
   p->max_total = max_total_samples;
   p->max_source = max_source_samples;
   p->logNmax = sp.logN;
-  p->grid = std::max(8, (2 * prop.multiProcessorCount + 7) & ~7);
+  const int per1 = fp64 ? tdi_ip::Tile<double, 1>::kPerCu : tdi_ip::Tile<float, 1>::kPerCu;
+  const int per2 = fp64 ? tdi_ip::Tile<double, 2>::kPerCu : tdi_ip::Tile<float, 2>::kPerCu;
+  p->grid1 = std::max(8, (per1 * prop.multiProcessorCount + 7) & ~7);
+  p->grid2 = std::max(8, (per2 * prop.multiProcessorCount + 7) & ~7);
   p->stream = (hipStream_t)hip_stream;
-  const int64_t row = (int64_t)1 << ((fp64 ? 12 : 13) - 1);
+  const int64_t row = (int64_t)1 << (log_tile(fp64, 2) - 1);
   const size_t vbytes = fp64 ? 16 : 8;
   // every zero-extended length is below twice the source length; three channels
   p->ws_cap = 6 * std::max<int64_t>(max_total_samples, 1);
@@ -217,7 +226,8 @@ tdi_status tdi_ip_plan_create(tdi_ip_plan** out, const tdi_noise* noise, int32_t
     p->wofs[lg] = wt_total;
     wt_total += (int64_t)1 << lg;
   }
-  bool ok = hipMalloc((void**)&p->d_wt, sizeof(double) * (size_t)wt_total) == hipSuccess;
+  const size_t wbytes = fp64 ? sizeof(double) : sizeof(float);
+  bool ok = hipMalloc(&p->d_wt, wbytes * (size_t)wt_total) == hipSuccess;
   ok = ok && hipMalloc(&p->d_ws, vbytes * (size_t)p->ws_cap) == hipSuccess;
   ok = ok && hipMalloc((void**)&p->d_part, sizeof(double) * 3 * (size_t)p->part_cap) == hipSuccess;
   ok = ok && hipMalloc((void**)&p->d_params, p->params_bytes) == hipSuccess;
@@ -260,13 +270,24 @@ tdi_status tdi_ip_plan_create(tdi_ip_plan** out, const tdi_noise* noise, int32_t
       }
     }
   }
-  if (hipMemcpy(p->d_wt, wt.data(), sizeof(double) * wt.size(), hipMemcpyHostToDevice) != hipSuccess) {
+  // FP32 transforms read the weights scaled by 2^-wexp (largest weight in
+  // [0.5, 1)) and rounded once to FP32; the reduction multiplies by 2^wexp
+  p->wexp = 0;
+  std::vector<float> wt32(fp64 ? 0 : wt.size());
+  if (!fp64) {
+    double wmax = 0.0;
+    for (double v : wt) wmax = std::max(wmax, v);
+    if (wmax > 0.0) frexp(wmax, &p->wexp);
+    for (size_t i = 0; i < wt32.size(); ++i) wt32[i] = (float)ldexp(wt[i], -p->wexp);
+  }
+  const void* wsrc = fp64 ? (const void*)wt.data() : (const void*)wt32.data();
+  if (hipMemcpy(p->d_wt, wsrc, wbytes * wt.size(), hipMemcpyHostToDevice) != hipSuccess) {
     tdi_ip_plan_destroy(p);
     return TDI_EDEVICE;
   }
-  // twiddles: LDS stages (E = 2^logE roots of unity) and the four-step factor
+  // twiddles: LDS stages (2^log_tw roots of unity) and the four-step factor
   // e^{-2 pi i m / N_max} split as th[m >> tbits] tl[m mod 2^tbits]
-  const int logE = fp64 ? 12 : 13;
+  const int logE = fp64 ? tdi_ip::log_tw<double>() : tdi_ip::log_tw<float>();
   p->tbits = (sp.logN + 1) / 2;
   const int64_t nh = (int64_t)1 << (sp.logN - p->tbits), nl = (int64_t)1 << p->tbits;
   ok = fp64 ? upload_roots<double>(&p->d_tw, (int64_t)1 << logE, logE, 1) &&
@@ -347,6 +368,7 @@ tdi_status tdi_ip_run(tdi_ip_plan* p, int64_t n_sources, const int64_t* offsets,
   P.part = p->d_part;
   P.out = out;
   P.wt = p->d_wt;
+  P.wexp = p->wexp;
   P.tw = p->d_tw;
   P.th = p->d_th;
   P.tl = p->d_tl;
@@ -363,9 +385,9 @@ tdi_status tdi_ip_run(tdi_ip_plan* p, int64_t n_sources, const int64_t* offsets,
   p->staged_pending = true;
   const int slot = p->ev_head;
   bool ok = hipEventRecord(p->ev[slot][0], s) == hipSuccess;
-  ok = ok && tdi_ip::launch_pass1(p->d_params, fp64, t1, p->grid, s) == 0;
+  ok = ok && tdi_ip::launch_pass1(p->d_params, fp64, t1, p->grid1, s) == 0;
   ok = ok && hipEventRecord(p->ev[slot][1], s) == hipSuccess;
-  ok = ok && tdi_ip::launch_pass2(p->d_params, fp64, t2, p->grid, s) == 0;
+  ok = ok && tdi_ip::launch_pass2(p->d_params, fp64, t2, p->grid2, s) == 0;
   ok = ok && hipEventRecord(p->ev[slot][2], s) == hipSuccess;
   ok = ok && tdi_ip::launch_reduce(p->d_params, n_sources, s) == 0;
   ok = ok && hipEventRecord(p->ev[slot][3], s) == hipSuccess;

@@ -7,15 +7,24 @@
 
 namespace tdi_ip {
 
-constexpr int kIpBlock = 512;            // threads per workgroup
-// complex elements one workgroup holds in LDS (64 KB): FP32 and FP64
-constexpr int kElemsF = 8192;
-constexpr int kElemsD = 4096;
-
-template <typename T> constexpr int elems_of() { return sizeof(T) == 4 ? kElemsF : kElemsD; }
-template <typename T> constexpr int log_elems_of() { return sizeof(T) == 4 ? 13 : 12; }
-// longest row of the second pass (two rows share the LDS)
-template <typename T> constexpr int row_max() { return elems_of<T>() / 2; }
+// Tile shapes of the two passes (T = float or double, complex elements in LDS).
+// Pass 1 reads column blocks of the input (stride N2): a 128 KB tile, one
+// workgroup of 1024 threads per compute unit, makes every row of a block a
+// long contiguous read.  Pass 2 (and the one-pass path) reads whole rows: 64 KB
+// tiles let two workgroups of 512 threads share a compute unit, so that one's
+// transforms overlap the other's loads.
+template <typename T, int Pass> struct Tile {
+  static constexpr int kLogE = (sizeof(T) == 4 ? 13 : 12) + (Pass == 1 ? 1 : 0);
+  static constexpr int kE = 1 << kLogE;
+  static constexpr int kBlock = Pass == 1 ? 1024 : 512;
+  static constexpr int kPerCu = Pass == 1 ? 1 : 2;     // resident workgroups per compute unit
+};
+// workgroup sizes by pass (single-argument names for __launch_bounds__)
+template <typename T> constexpr int kBlock1 = Tile<T, 1>::kBlock;
+template <typename T> constexpr int kBlock2 = Tile<T, 2>::kBlock;
+// the LDS-stage twiddle table holds 2^log_tw roots of unity (the larger tile)
+template <typename T> constexpr int log_tw() { return Tile<T, 1>::kLogE; }
+constexpr int kReduceBlock = 256;
 
 // Per-source record.  The zero-extended length N = 2^logN is split as
 // N = N1 * N2 (N1 = 1: one pass straight from the input).
@@ -36,12 +45,15 @@ struct IpParams {
   void* ws;                // complex workspace of the two-pass transforms
   double* part;            // 3 partial sums per pass-2 task
   double* out;             // 9 per source: per channel <x|x>, <x|y>, <y|y>
-  // weights 1 / S_n(f_k), zero outside the band, one table per length N laid
-  // out in the order of the second pass: [class A/E, T][k1 < N1][k2 < N2/2]
-  // for bin k = k1 + N1 k2
-  const double* wt;
+  // weights 2^-wexp / S_n(f_k) in the transform precision, zero outside the
+  // band, one table per length N laid out in the order of the second pass:
+  // [class A/E, T][k1 < N1][k2 < N2/2] for bin k = k1 + N1 k2.  1/S_n is of
+  // order 1e40, beyond FP32: the power-of-two scale keeps it in range and the
+  // reduction undoes it exactly (wexp = 0 for FP64 tables).
+  const void* wt;
+  int32_t wexp, pad0;
   // twiddle tables in the transform precision (complex pairs):
-  //   tw[m] = e^{-2 pi i m / E} (E = LDS elements), for the LDS stages;
+  //   tw[m] = e^{-2 pi i m / 2^log_tw}, for the LDS stages;
   //   th[h] = e^{-2 pi i h 2^tbits / N_max}, tl[l] = e^{-2 pi i l / N_max}, for the
   //   four-step twiddle e^{-2 pi i m / N_max} = th[m >> tbits] tl[m mod 2^tbits]
   const void* tw;

@@ -102,7 +102,7 @@ __device__ __forceinline__ void dft2(V* a) {
 
 // LDS layout: logical element i sits at i + i / 32, one pad element per 32, so
 // that the strided accesses of the early stages spread over the banks.
-template <typename T> constexpr int lds_elems() { return elems_of<T>() + elems_of<T>() / 32; }
+template <int E> constexpr int lds_elems() { return E + E / 32; }
 __device__ __forceinline__ int lp(int i) { return i + (i >> 5); }
 
 // One Stockham stage of radix R on B sequences of length L = 2^logL held in
@@ -110,12 +110,13 @@ __device__ __forceinline__ int lp(int i) { return i + (i >> 5); }
 // of the sub-transforms already formed.  Butterfly q maps to sequence
 // b = q mod B (B = 2^logB) and index j = q / B, so that neighbouring lanes touch
 // neighbouring sequences (interleaved layout) or neighbouring elements.
-// Twiddles e^{-2 pi i k r / (Ns R)} come from the table tw of e^{-2 pi i m / E}.
-template <typename T, int R>
+// Twiddles e^{-2 pi i k r / (Ns R)} come from the table tw of e^{-2 pi i m / 2^log_tw}.
+// E: complex elements of the tile, BLK: threads of the workgroup.
+template <typename T, int R, int E, int BLK>
 __device__ __forceinline__ void fft_stage(typename Cplx<T>::V* buf, const typename Cplx<T>::V* __restrict__ tw,
                                           int logL, int logNs, int logB, int lbs, int les) {
   using V = typename Cplx<T>::V;
-  constexpr int kMaxQ = elems_of<T>() / (R * kIpBlock) > 0 ? elems_of<T>() / (R * kIpBlock) : 1;
+  constexpr int kMaxQ = E / (R * BLK) > 0 ? E / (R * BLK) : 1;
   constexpr int kLogR = R == 16 ? 4 : (R == 4 ? 2 : 1);
   const int lnb = logL - kLogR;                // log2 butterflies per sequence
   const int total = 1 << (lnb + logB);
@@ -123,7 +124,7 @@ __device__ __forceinline__ void fft_stage(typename Cplx<T>::V* buf, const typena
   V v[kMaxQ][R];
 #pragma unroll
   for (int i = 0; i < kMaxQ; ++i) {
-    const int q = threadIdx.x + i * kIpBlock;
+    const int q = threadIdx.x + i * BLK;
     if (q < total) {
       const int b = q & ((1 << logB) - 1), j = q >> logB;
       const int base = (b << lbs) + (j << les);
@@ -134,12 +135,12 @@ __device__ __forceinline__ void fft_stage(typename Cplx<T>::V* buf, const typena
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < kMaxQ; ++i) {
-    const int q = threadIdx.x + i * kIpBlock;
+    const int q = threadIdx.x + i * BLK;
     if (q < total) {
       const int b = q & ((1 << logB) - 1), j = q >> logB;
       const int k = j & (Ns - 1);
       if (logNs > 0) {
-        const int step = k << (log_elems_of<T>() - logNs - kLogR);
+        const int step = k << (log_tw<T>() - logNs - kLogR);
 #pragma unroll
         for (int r = 1; r < R; ++r) v[i][r] = cmul(v[i][r], tw[r * step]);
       }
@@ -162,26 +163,26 @@ __device__ __forceinline__ void fft_stage(typename Cplx<T>::V* buf, const typena
 // FP32: one radix-2 and one radix-4 stage as log2 L mod 4 requires, then radix
 // 16 in registers.  FP64 (twice the registers per element): radix 4 after an
 // optional radix-2 stage.
-template <typename T>
+template <typename T, int E, int BLK>
 __device__ __forceinline__ void lds_fft(typename Cplx<T>::V* buf, const typename Cplx<T>::V* __restrict__ tw,
                                         int logL, int logB, int lbs, int les) {
   int logNs = 0;
   if (logL & 1) {
-    fft_stage<T, 2>(buf, tw, logL, 0, logB, lbs, les);
+    fft_stage<T, 2, E, BLK>(buf, tw, logL, 0, logB, lbs, les);
     logNs = 1;
   }
   if constexpr (sizeof(T) == 4) {
     if (logL & 2) {
-      fft_stage<T, 4>(buf, tw, logL, logNs, logB, lbs, les);
+      fft_stage<T, 4, E, BLK>(buf, tw, logL, logNs, logB, lbs, les);
       logNs += 2;
     }
     while (logNs < logL) {
-      fft_stage<T, 16>(buf, tw, logL, logNs, logB, lbs, les);
+      fft_stage<T, 16, E, BLK>(buf, tw, logL, logNs, logB, lbs, les);
       logNs += 4;
     }
   } else {
     while (logNs < logL) {
-      fft_stage<T, 4>(buf, tw, logL, logNs, logB, lbs, les);
+      fft_stage<T, 4, E, BLK>(buf, tw, logL, logNs, logB, lbs, les);
       logNs += 2;
     }
   }
@@ -223,6 +224,7 @@ template <typename T>
 __device__ __forceinline__ void pass1_task(const IpParams* __restrict__ P, const IpSrc& S, int64_t local,
                                            typename Cplx<T>::V* buf) {
   using V = typename Cplx<T>::V;
+  using TL = Tile<T, 1>;
   const int c = (int)(local / S.n1);
   const int blk = (int)(local - (int64_t)c * S.n1);
   const int logC = 31 - __builtin_clz(S.cols);
@@ -234,46 +236,47 @@ __device__ __forceinline__ void pass1_task(const IpParams* __restrict__ P, const
   // element (j1, col) at buf[j1 * C + col]: neighbouring lanes read neighbouring
   // samples.  A first-pass task always fills the LDS (C N1 = E): every load of
   // a thread is issued before the first is consumed.
-  constexpr int kIt = elems_of<T>() / kIpBlock;
+  constexpr int kIt = TL::kE / TL::kBlock;
   constexpr int kG = 4;
 #pragma unroll
   for (int h = 0; h < kIt / kG; ++h) {
     V z[kG];
 #pragma unroll
     for (int it = 0; it < kG; ++it) {
-      const int e = threadIdx.x + (h * kG + it) * kIpBlock;
+      const int e = threadIdx.x + (h * kG + it) * TL::kBlock;
       const int j1 = e >> logC, col = e & (C - 1);
       const int64_t j = ((int64_t)j1 << S.logN2) + c0 + col;
       z[it].x = load_or_zero<T>(xs, S.off, j, S.n);
       z[it].y = load_or_zero<T>(ys, S.off, j, S.n);
     }
 #pragma unroll
-    for (int it = 0; it < kG; ++it) buf[lp(threadIdx.x + (h * kG + it) * kIpBlock)] = z[it];
+    for (int it = 0; it < kG; ++it) buf[lp(threadIdx.x + (h * kG + it) * TL::kBlock)] = z[it];
   }
   __syncthreads();
-  lds_fft<T>(buf, static_cast<const V*>(P->tw), S.logN1, logC, 0, logC);
+  lds_fft<T, TL::kE, TL::kBlock>(buf, static_cast<const V*>(P->tw), S.logN1, logC, 0, logC);
   V* W = static_cast<V*>(P->ws) + S.ws + (int64_t)c * ((int64_t)1 << S.logN);
   const int64_t mask = ((int64_t)1 << S.logN) - 1;
   const int up = P->logNmax - S.logN, tb = P->tbits;
   const V* th = static_cast<const V*>(P->th);
   const V* tl = static_cast<const V*>(P->tl);
   // twiddle loads in groups of four, each issued together
+  constexpr int kGT = 4;
 #pragma unroll 1
-  for (int h = 0; h < kIt / kG; ++h) {
-    V wh[kG], wl[kG];
+  for (int h = 0; h < kIt / kGT; ++h) {
+    V wh[kGT], wl[kGT];
 #pragma unroll
-    for (int it = 0; it < kG; ++it) {
-      const int e = threadIdx.x + (h * kG + it) * kIpBlock;
+    for (int it = 0; it < kGT; ++it) {
+      const int e = threadIdx.x + (h * kGT + it) * TL::kBlock;
       const int k1 = e >> logC, col = e & (C - 1);
       // e^{-2 pi i j2 k1 / N} = e^{-2 pi i m / N_max} with m = (j2 k1 mod N) 2^up;
-      // j2 < N2 and k1 < N1 are below 2^12, so the 24-bit product is exact
+      // j2 < N2 and k1 < N1 are below 2^13: 24-bit operands, the product fits 32 bits
       const int64_t m = ((int64_t)__umul24((unsigned)(c0 + col), (unsigned)k1) & mask) << up;
       wh[it] = th[m >> tb];
       wl[it] = tl[m & ((1 << tb) - 1)];
     }
 #pragma unroll
-    for (int it = 0; it < kG; ++it) {
-      const int e = threadIdx.x + (h * kG + it) * kIpBlock;
+    for (int it = 0; it < kGT; ++it) {
+      const int e = threadIdx.x + (h * kGT + it) * TL::kBlock;
       const int k1 = e >> logC, col = e & (C - 1);
       W[((int64_t)k1 << S.logN2) + c0 + col] = cmul(buf[lp(e)], cmul(wh[it], wl[it]));
     }
@@ -286,10 +289,10 @@ template <int Pass>
 __device__ __forceinline__ int64_t first_task(const IpSrc& s) { return Pass == 1 ? s.t1 : s.t2; }
 
 template <typename T>
-__global__ void __launch_bounds__(kIpBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kBlock1<T>) __attribute__((amdgpu_waves_per_eu(4)))
 k_ip_pass1(const IpParams* __restrict__ P) {
   using V = typename Cplx<T>::V;
-  __shared__ V buf[lds_elems<T>()];
+  __shared__ V buf[lds_elems<Tile<T, 1>::kE>()];
   int64_t t, te, dt;
   task_span(P->n_t1, &t, &te, &dt);
   if (t >= te) return;
@@ -309,6 +312,7 @@ k_ip_pass1(const IpParams* __restrict__ P) {
   }
 }
 
+template <int BLK>
 __device__ __forceinline__ void block_sum3(double* v, double* red) {
   for (int o = 32; o > 0; o >>= 1) {
     v[0] += __shfl_down(v[0], o, 64);
@@ -323,7 +327,7 @@ __device__ __forceinline__ void block_sum3(double* v, double* red) {
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 1; i < kIpBlock / 64; ++i) {
+    for (int i = 1; i < BLK / 64; ++i) {
       v[0] += red[3 * i];
       v[1] += red[3 * i + 1];
       v[2] += red[3 * i + 2];
@@ -337,6 +341,7 @@ template <typename T>
 __device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const IpSrc& S, int64_t local,
                                            typename Cplx<T>::V* buf, double* red) {
   using V = typename Cplx<T>::V;
+  using TL = Tile<T, 2>;
   const int c = (int)(local / S.n2);
   const int i = (int)(local - (int64_t)c * S.n2);
   const int N1 = 1 << S.logN1, N2 = 1 << S.logN2;
@@ -344,7 +349,7 @@ __device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const
   const int r0 = i, r1 = (N1 - i) & (N1 - 1);
   const int B = r0 == r1 ? 1 : 2;
   // every load of a thread is issued before the first is consumed
-  constexpr int kIt = elems_of<T>() / kIpBlock;
+  constexpr int kIt = TL::kE / TL::kBlock;
   const int cnt = B << S.logN2;
   {
     V z[kIt];
@@ -353,7 +358,7 @@ __device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const
       const void* ys = P->y[c];
 #pragma unroll
       for (int it = 0; it < kIt; ++it) {
-        const int e = threadIdx.x + it * kIpBlock;
+        const int e = threadIdx.x + it * TL::kBlock;
         z[it].x = load_or_zero<T>(xs, S.off, e, S.n);
         z[it].y = load_or_zero<T>(ys, S.off, e, S.n);
       }
@@ -361,7 +366,7 @@ __device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const
       const V* W = static_cast<const V*>(P->ws) + S.ws + (int64_t)c * N;
 #pragma unroll
       for (int it = 0; it < kIt; ++it) {
-        const int e = threadIdx.x + it * kIpBlock;
+        const int e = threadIdx.x + it * TL::kBlock;
         if (e < cnt) {
           const int b = e >> S.logN2, k2 = e & (N2 - 1);
           z[it] = W[((int64_t)(b == 0 ? r0 : r1) << S.logN2) + k2];
@@ -370,34 +375,34 @@ __device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const
     }
 #pragma unroll
     for (int it = 0; it < kIt; ++it) {
-      const int e = threadIdx.x + it * kIpBlock;
+      const int e = threadIdx.x + it * TL::kBlock;
       if (e < cnt) buf[lp(e)] = z[it];
     }
   }
   __syncthreads();
-  lds_fft<T>(buf, static_cast<const V*>(P->tw), S.logN2, B == 2 ? 1 : 0, S.logN2, 0);
+  lds_fft<T, TL::kE, TL::kBlock>(buf, static_cast<const V*>(P->tw), S.logN2, B == 2 ? 1 : 0, S.logN2, 0);
   // bins: row b holds k = k1b + N1 k2; the partner N - k lies in the other row
   // at N2 - 1 - k2 (k1b != 0), or in row 0 itself at (N2 - k2) mod N2 (k1b = 0)
   // weight of bin k = k1b + N1 k2 (k < N/2 means k2 < N2/2): wt[k1b N2/2 + k2]
-  const double* wt = P->wt + S.wofs + (c < 2 ? 0 : N / 2);
+  const T* wt = static_cast<const T*>(P->wt) + S.wofs + (c < 2 ? 0 : N / 2);
   double acc[3] = {0.0, 0.0, 0.0};
-  // weights in groups of four, each group's loads issued together
-  constexpr int kG = 4;
+  // weights in groups of eight, each group's loads issued together
+  constexpr int kG = 8;
 #pragma unroll
   for (int g = 0; g < kIt / kG; ++g) {
-    double wk[kG];
+    T wk[kG];
 #pragma unroll
     for (int it = 0; it < kG; ++it) {
-      const int e = threadIdx.x + (g * kG + it) * kIpBlock;
+      const int e = threadIdx.x + (g * kG + it) * TL::kBlock;
       const int b = e >> S.logN2, k2 = e & (N2 - 1);
       const int k1b = b == 0 ? r0 : r1;
       const int64_t k = (int64_t)k1b + ((int64_t)k2 << S.logN1);
-      wk[it] = (e < cnt && k >= 1 && 2 * k < N) ? wt[((int64_t)k1b << (S.logN2 - 1)) + k2] : 0.0;
+      wk[it] = (e < cnt && k >= 1 && 2 * k < N) ? wt[((int64_t)k1b << (S.logN2 - 1)) + k2] : (T)0;
     }
 #pragma unroll
     for (int it = 0; it < kG; ++it) {
-      const int e = threadIdx.x + (g * kG + it) * kIpBlock;
-      const double w = wk[it];
+      const int e = threadIdx.x + (g * kG + it) * TL::kBlock;
+      const double w = (double)wk[it];
       if (w == 0.0) continue;          // outside the band, or not a bin 0 < k < N/2 of this task
       const int b = e >> S.logN2, k2 = e & (N2 - 1);
       const int k1b = b == 0 ? r0 : r1;
@@ -418,7 +423,7 @@ __device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const
       acc[2] += w * (bx * bx + by * by);
     }
   }
-  block_sum3(acc, red);
+  block_sum3<TL::kBlock>(acc, red);
   if (threadIdx.x == 0) {
     double* o = P->part + 3 * (S.part + (int64_t)c * S.n2 + i);
     o[0] = acc[0];
@@ -428,11 +433,11 @@ __device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kIpBlock) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ void __launch_bounds__(kBlock2<T>) __attribute__((amdgpu_waves_per_eu(4)))
 k_ip_pass2(const IpParams* __restrict__ P) {
   using V = typename Cplx<T>::V;
-  __shared__ V buf[lds_elems<T>()];
-  __shared__ double red[3 * (kIpBlock / 64)];
+  __shared__ V buf[lds_elems<Tile<T, 2>::kE>()];
+  __shared__ double red[3 * (Tile<T, 2>::kBlock / 64)];
   int64_t t, te, dt;
   task_span(P->n_t2, &t, &te, &dt);
   if (t >= te) return;
@@ -455,8 +460,8 @@ k_ip_pass2(const IpParams* __restrict__ P) {
 // Per source and channel: sum the pass-2 partials in task order and scale,
 // <x|x> = dt/N sum w |Z + conj P|^2, <x|y> = 2 dt/N sum w Im(Z P),
 // <y|y> = dt/N sum w |Z - conj P|^2.
-__global__ void __launch_bounds__(kIpBlock) k_ip_reduce(const IpParams* __restrict__ P) {
-  const int64_t id = (int64_t)blockIdx.x * kIpBlock + threadIdx.x;
+__global__ void __launch_bounds__(kReduceBlock) k_ip_reduce(const IpParams* __restrict__ P) {
+  const int64_t id = (int64_t)blockIdx.x * kReduceBlock + threadIdx.x;
   if (id >= 9 * P->n_src) return;
   const int64_t s = id / 9;
   const int cq = (int)(id - 9 * s), c = cq / 3, q = cq - 3 * c;
@@ -464,7 +469,7 @@ __global__ void __launch_bounds__(kIpBlock) k_ip_reduce(const IpParams* __restri
   double sum = 0.0;
   const double* part = P->part + 3 * (S.part + (int64_t)c * S.n2) + q;
   for (int i = 0; i < S.n2; ++i) sum += part[3 * i];
-  const double scale = (q == 1 ? 2.0 : 1.0) * P->dt / (double)((int64_t)1 << S.logN);
+  const double scale = ldexp((q == 1 ? 2.0 : 1.0) * P->dt / (double)((int64_t)1 << S.logN), P->wexp);
   P->out[id] = S.n2 > 0 ? sum * scale : 0.0;
 }
 
@@ -474,8 +479,8 @@ int launch_pass1(const IpParams* dp, int fp64, int64_t tasks, int grid, void* st
   if (tasks <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   tasks = std::min<int64_t>((tasks + 7) & ~(int64_t)7, grid);
-  if (fp64) hipLaunchKernelGGL(k_ip_pass1<double>, dim3((unsigned)tasks), dim3(kIpBlock), 0, st, dp);
-  else hipLaunchKernelGGL(k_ip_pass1<float>, dim3((unsigned)tasks), dim3(kIpBlock), 0, st, dp);
+  if (fp64) hipLaunchKernelGGL(k_ip_pass1<double>, dim3((unsigned)tasks), dim3(Tile<double, 1>::kBlock), 0, st, dp);
+  else hipLaunchKernelGGL(k_ip_pass1<float>, dim3((unsigned)tasks), dim3(Tile<float, 1>::kBlock), 0, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -483,15 +488,15 @@ int launch_pass2(const IpParams* dp, int fp64, int64_t tasks, int grid, void* st
   if (tasks <= 0) return 0;
   hipStream_t st = (hipStream_t)stream;
   tasks = std::min<int64_t>((tasks + 7) & ~(int64_t)7, grid);
-  if (fp64) hipLaunchKernelGGL(k_ip_pass2<double>, dim3((unsigned)tasks), dim3(kIpBlock), 0, st, dp);
-  else hipLaunchKernelGGL(k_ip_pass2<float>, dim3((unsigned)tasks), dim3(kIpBlock), 0, st, dp);
+  if (fp64) hipLaunchKernelGGL(k_ip_pass2<double>, dim3((unsigned)tasks), dim3(Tile<double, 2>::kBlock), 0, st, dp);
+  else hipLaunchKernelGGL(k_ip_pass2<float>, dim3((unsigned)tasks), dim3(Tile<float, 2>::kBlock), 0, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 int launch_reduce(const IpParams* dp, int64_t n_src, void* stream) {
   if (n_src <= 0) return 0;
-  const int64_t blocks = (9 * n_src + kIpBlock - 1) / kIpBlock;
-  hipLaunchKernelGGL(k_ip_reduce, dim3((unsigned)blocks), dim3(kIpBlock), 0, (hipStream_t)stream, dp);
+  const int64_t blocks = (9 * n_src + kReduceBlock - 1) / kReduceBlock;
+  hipLaunchKernelGGL(k_ip_reduce, dim3((unsigned)blocks), dim3(kReduceBlock), 0, (hipStream_t)stream, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

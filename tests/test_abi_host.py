@@ -191,8 +191,11 @@ def test_ip_entry_points_without_device(L):
     assert T.tdi_ip_plan_create(_noise(f_min=-1.0), T.TDI_FP32_BULK, 10.0, 4, 1000, 500)[0] == T.TDI_ERANGE
     assert T.tdi_ip_plan_create(_noise(), 7, 10.0, 4, 1000, 500)[0] == T.TDI_EUNSUPPORTED
     assert T.tdi_ip_plan_create(_noise(), T.TDI_FP32_BULK, 0.0, 4, 1000, 500)[0] == T.TDI_ERANGE
-    # longest supported source: 2^24 (FP32), 2^22 (FP64)
-    assert T.tdi_ip_plan_create(_noise(), T.TDI_FP64, 10.0, 4, 1 << 23, (1 << 22) + 1)[0] == T.TDI_ERANGE
+    # longest supported source: 2^25 (FP32), 2^23 (FP64)
+    assert T.tdi_ip_plan_create(_noise(), T.TDI_FP64, 10.0, 4, 1 << 24, (1 << 23) + 1)[0] == T.TDI_ERANGE
+    assert T.tdi_ip_plan_create(_noise(), T.TDI_FP32_BULK, 10.0, 4, 1 << 26, (1 << 25) + 1)[0] == T.TDI_ERANGE
+    assert T.tdi_ip_plan_create(_noise(), T.TDI_FP64, 10.0, 4, 1 << 24, 1 << 23)[0] == T.TDI_EDEVICE
+    assert T.tdi_ip_plan_create(_noise(), T.TDI_FP32_BULK, 10.0, 4, 1 << 26, 1 << 25)[0] == T.TDI_EDEVICE
     assert T.tdi_ip_run(None, 1, np.array([0, 5]), [0, 0, 0], [0, 0, 0], 0) == T.TDI_EINVAL
     assert T.lib().tdi_ip_plan_destroy(None) == T.TDI_EINVAL
     assert T.lib().tdi_ip_kernel_times(None, None, 0, None) == T.TDI_EINVAL

@@ -110,7 +110,7 @@ def test_inner_product_ragged(tdi, orc, prec, noise):
     two runs on one plan (the second smaller)."""
     dt = 10.0
     rng = np.random.default_rng(7 + prec)
-    lengths = [0, 1, 2, 3, 100, 4096, 4097, 8192, 8193, 20000, 65536, 100003]
+    lengths = [0, 1, 2, 3, 100, 4096, 4097, 8192, 8193, 16384, 16385, 20000, 65536, 100003]
     offsets = np.concatenate([[0], np.cumsum(lengths)]).astype(np.int64)
     total = int(offsets[-1])
     # chirps from the generator (x) and a perturbed copy plus white noise (y)
