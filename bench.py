@@ -379,6 +379,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n-sources", type=int, default=512)
+    ap.add_argument("--tile-chunks", type=int, default=0, choices=[0, 1, 2, 4],
+                    help="LFA tile shape of the fast path (chunks of 2304 outputs); 0 = autotuned")
     ap.add_argument("--orbit", default="analytic", choices=["analytic", "table"],
                     help="c4: the first-order analytic orbit (default) or flexing Keplerian orbits "
                          "read from an hourly position table")
@@ -418,6 +420,7 @@ def main():
     torch.cuda.set_device(dev)
     t_gen = time.perf_counter()
     batch, cfg, orb = W.config_c4(n_sources=args.n_sources, xp=torch, device=dev)
+    cfg = dict(cfg, fast_tile_chunks=args.tile_chunks)
     if args.orbit == "table":
         # eccentric Keplerian orbits sampled hourly, spanning the longest source
         span = float(np.max(np.diff(batch.offsets))) * 10.0

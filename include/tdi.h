@@ -124,7 +124,11 @@ typedef struct {
                                time its delay is applied, D_a D_b f(t) = f(t - T_a(t) -
                                T_b(t - T_a(t))).  No effect on the LFA or on tdi_run_links.
                                Other values give TDI_ERANGE. */
-  int32_t reserved2;        /* must be 0 */
+  int32_t fast_tile_chunks; /* FP32-bulk LFA and hybrid runs: outputs per LFA tile in chunks of 2304
+                               (1, 2 or 4); 0 = chosen by the autotuner (autotune = 1) or 4.
+                               Small tiles give single long sources enough tiles to fill the GPU;
+                               large ones amortise the per-tile geometry fit over big batches.
+                               Other values give TDI_ERANGE. */
 } tdi_config;
 
 typedef struct tdi_plan tdi_plan;

@@ -27,6 +27,7 @@ constexpr int kEvPerRun = 4;     // before the fit pre-pass, before / after the 
 struct Launch {
   int grid_lfa;      // 0 = one workgroup per tile
   int grid_full;
+  int chunks;        // fast LFA path: chunks of kFastChunk outputs per tile (1, 2 or 4)
 };
 
 struct OrbitBounds {
@@ -56,7 +57,8 @@ struct tdi_plan {
   hipStream_t graph_stream;      // private stream used for capture and replay
   // device memory
   tdi::KParams* d_params;        // KParams followed by SrcDev[max_sources]
-  void* d_ftiles;                // fast LFA path: per-tile records of the pre-pass
+  void* d_ftiles;
+  uint32_t* d_fix;               // work list of the fast path's second pass (16 entries per tile)                // fast LFA path: per-tile records of the pre-pass
   int64_t fit_tiles;             // their capacity (tiles)
   size_t params_bytes;
   int32_t* d_err;
@@ -117,7 +119,9 @@ tdi_status tdi_check_config(const tdi_config* c, const tdi_orbit* o) {
   if (c->channels != TDI_CHANNELS_XYZ && c->channels != TDI_CHANNELS_AET) return TDI_EUNSUPPORTED;
   if (c->lfa_terms < 0 || c->lfa_terms > 2) return TDI_ERANGE;
   if (c->nested_delays != 0 && c->nested_delays != 1) return TDI_ERANGE;
-  if (c->reserved2 != 0) return TDI_EINVAL;
+  if (c->fast_tile_chunks != 0 && c->fast_tile_chunks != 1 && c->fast_tile_chunks != 2 &&
+      c->fast_tile_chunks != 4)
+    return TDI_ERANGE;
   if (!(c->hyb_T_samples > 0.0) || !is_fin(c->hyb_T_samples)) return TDI_ERANGE;
   if (!(c->hyb_sigma_samples > 0.0) || !is_fin(c->hyb_sigma_samples)) return TDI_ERANGE;
   if (!(o->L_m > 0.0) || !is_fin(o->L_m)) return TDI_ERANGE;
@@ -257,6 +261,11 @@ bool table_covers(const tdi_plan* p, int64_t n_sources, const tdi_source* src, c
   return true;
 }
 
+// Outputs per LFA tile: the fast path takes the launch's chunk count.
+int lfa_tile(const Caps& caps, const Launch& ln) {
+  return caps.fast ? std::min(std::max(ln.chunks, 1), 4) * tdi::kFastChunk : caps.tile_lfa;
+}
+
 // Fill the pinned parameter image for one batch (work lists of both kernels).
 void stage_batch(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
                  const double* hp, const double* hc, void* X, void* Y, void* Z, const Caps& caps,
@@ -264,6 +273,7 @@ void stage_batch(tdi_plan* p, int64_t n_sources, const tdi_source* src, const in
   tdi::KParams* kp = p->h_params;
   tdi::SrcDev* sd = reinterpret_cast<tdi::SrcDev*>(kp + 1);
   const tdi_config& c = p->cfg;
+  const int tile_lfa = lfa_tile(caps, ln);
   int64_t tl = 0, tf = 0;
   for (int64_t i = 0; i < n_sources; ++i) {
     const tdi_source& s = src[i];
@@ -290,10 +300,11 @@ void stage_batch(tdi_plan* p, int64_t n_sources, const tdi_source* src, const in
     }
     d.lfa_kb = lb; d.lfa_ke = le; d.lfa_t0 = tl;
     d.full_kb = fb; d.full_ke = fe; d.full_t0 = tf;
-    if (le > lb) tl += (le - lb + caps.tile_lfa - 1) / caps.tile_lfa;
+    if (le > lb) tl += (le - lb + tile_lfa - 1) / tile_lfa;
     if (fe > fb) tf += (fe - fb + tdi::kTileFull - 1) / tdi::kTileFull;
   }
   kp->n_src = n_sources;
+  kp->tile_fast = caps.fast ? tile_lfa : 0;
   kp->n_tiles_lfa = tl;
   kp->n_tiles_full = tf;
   kp->hp = hp; kp->hc = hc; kp->X = X; kp->Y = Y; kp->Z = Z;
@@ -318,6 +329,9 @@ hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& c
   if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, caps.fast, gl, caps.lds_lfa, st) != 0)
     return hipErrorLaunchFailure;
   if (evs && (e = hipEventRecord(evs[2], st)) != hipSuccess) return e;
+  // fast path: uses whose split base is the neighbouring integer (timed with the full kernel)
+  if (gl > 0 && caps.fast && tdi::launch_lfa_shift_fix(p->d_params, taps, 2 * p->n_cu, st) != 0)
+    return hipErrorLaunchFailure;
   const int gf = ln.grid_full > 0 ? ln.grid_full : (int)std::max<int64_t>(0, tiles_full);
   if (gf > 0 && tdi::launch_full(p->d_params, taps, fp32, gf, caps.lds_full, st) != 0)
     return hipErrorLaunchFailure;
@@ -334,12 +348,13 @@ void destroy_graph(tdi_plan* p) {
 
 // Event-record nodes spliced into the captured chain (stream capture does not
 // record events): before the fit pre-pass, before and after the LFA kernel and
-// after the full kernel.  The chain is upload -> reset -> [fit] -> LFA -> full.
+// after the full kernel.  The chain is upload -> reset -> [fit] -> LFA -> [fix]
+// -> full (fit and fix on the fast path).
 bool add_graph_events(tdi_plan* p, hipGraph_t g, bool fast) {
   size_t n = 0, ne = 0;
   if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess || hipGraphGetEdges(g, nullptr, nullptr, &ne) != hipSuccess)
     return false;
-  const size_t want = fast ? 5 : 4;
+  const size_t want = fast ? 6 : 4;
   if (n != want || ne != want - 1) return false;
   std::vector<hipGraphNode_t> nodes(n), from(ne), to(ne);
   if (hipGraphGetNodes(g, nodes.data(), &n) != hipSuccess) return false;
@@ -368,14 +383,14 @@ bool add_graph_events(tdi_plan* p, hipGraph_t g, bool fast) {
     chain.insert(chain.begin() + at, *out);
     return true;
   };
-  // chain indices: 0 upload, 1 reset, then [fit], LFA, full
+  // chain indices: 0 upload, 1 reset, then [fit], LFA, [fix], full
   size_t at = 2;
   if (!splice(at, p->ev[0][0], &p->graph_ev_node[0])) return false;
   at += 1 + (fast ? 1 : 0);
   if (!splice(at, p->ev[0][1], &p->graph_ev_node[1])) return false;
   at += 2;
   if (!splice(at, p->ev[0][2], &p->graph_ev_node[2])) return false;
-  at += 2;
+  at += 2 + (fast ? 1 : 0);
   return splice(at, p->ev[0][3], &p->graph_ev_node[3]);
 }
 
@@ -450,7 +465,7 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
   if (!batch_caps(p, n_sources, src, offsets, &caps)) return TDI_OK;
   if (caps.lds_lfa > p->max_lds || caps.lds_full > p->max_lds) return TDI_ERANGE;
   p->last_fast = caps.fast;
-  p->last_tile_lfa = caps.tile_lfa;
+  p->last_tile_lfa = lfa_tile(caps, ln);
 
   // the previous upload must have left the pinned image before it is rewritten
   if (p->staged_pending) {
@@ -459,6 +474,9 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
   }
   stage_batch(p, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
   const int64_t tl = p->h_params->n_tiles_lfa, tf = p->h_params->n_tiles_full;
+  // per-tile records of the fast path: tiles hold at least kFastChunk outputs,
+  // so a batch within the plan's maxima always fits; checked all the same
+  if (caps.fast && tl > p->fit_tiles) return TDI_ESTATE;
   const size_t copy_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)n_sources;
   const int slot = p->ev_head;
 
@@ -520,11 +538,27 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
   if (!batch_caps(p, n_sources, src, offsets, &caps)) return;
   const int ol = tdi::occupancy_lfa(p->cfg.interp_taps, p->cfg.precision, caps.fast, caps.lds_lfa);
   const int of = tdi::occupancy_full(p->cfg.interp_taps, p->cfg.precision, caps.lds_full);
+  // grid candidates (persistent at the resident count, half and twice that, or
+  // one workgroup per tile), each with every tile shape of the fast LFA path:
+  // small tiles give single long sources enough tiles to fill the chip, large
+  // ones amortise the per-tile geometry fit over big batches
+  std::vector<Launch> grids;
+  grids.push_back({ol * p->n_cu, of * p->n_cu, 4});
+  grids.push_back({0, 0, 4});
+  if (ol > 1) grids.push_back({(ol / 2) * p->n_cu, of * p->n_cu, 4});
+  grids.push_back({2 * ol * p->n_cu, 2 * of * p->n_cu, 4});
   std::vector<Launch> cands;
-  cands.push_back({ol * p->n_cu, of * p->n_cu});
-  cands.push_back({0, 0});
-  if (ol > 1) cands.push_back({(ol / 2) * p->n_cu, of * p->n_cu});
-  cands.push_back({2 * ol * p->n_cu, 2 * of * p->n_cu});
+  for (const int ch : {4, 2, 1}) {
+    // the chunk count only matters on the fast path; a forced one is kept
+    const bool keep = caps.fast ? (p->cfg.fast_tile_chunks == 0 || ch == p->cfg.fast_tile_chunks) : ch == 4;
+    if (!keep) continue;
+    for (Launch g : grids) {
+      // graph replay needs persistent launches: with graphs only those are timed
+      if (p->cfg.use_graph && (g.grid_lfa == 0 || g.grid_full == 0)) continue;
+      g.chunks = ch;
+      cands.push_back(g);
+    }
+  }
   hipEvent_t a, b;
   hipEventCreate(&a);
   hipEventCreate(&b);
@@ -595,8 +629,9 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   ok = ok && hipMalloc((void**)&p->d_counters, 64) == hipSuccess;
   if (ok && cfg->precision == TDI_FP32_BULK && cfg->mode != TDI_MODE_FULL) {
     // records of the fast LFA path: at most one partial tile per source beyond the full ones
-    p->fit_tiles = max_total_samples / tdi::kTileLfaFast + max_sources + 1;
+    p->fit_tiles = max_total_samples / tdi::kFastChunk + max_sources + 1;
     ok = hipMalloc(&p->d_ftiles, (size_t)p->fit_tiles * tdi::fast_tile_bytes()) == hipSuccess;
+    ok = ok && hipMalloc((void**)&p->d_fix, (size_t)p->fit_tiles * 16 * sizeof(uint32_t)) == hipSuccess;
   }
   ok = ok && hipHostMalloc((void**)&p->h_params, p->params_bytes, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&p->staged_free, hipEventDisableTiming) == hipSuccess;
@@ -619,6 +654,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   tdi::KParams& kp = *p->h_params;
   kp.err = p->d_err;
   kp.lfa_tiles = p->d_ftiles;
+  kp.fix_items = p->d_fix;
   kp.counters = p->d_counters;
   tdi::OrbitDev& od = kp.orb;
   od.kind = orb->kind;
@@ -663,7 +699,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   kp.sigma_s = cfg->hyb_sigma_samples;
   kp.D2_bound = stage2_bound(*cfg, p->ob);
 
-  p->launch = {0, 0};
+  p->launch = {0, 0, cfg->fast_tile_chunks != 0 ? cfg->fast_tile_chunks : 4};
   p->tuned = cfg->autotune ? false : true;
   if (!cfg->autotune && cfg->use_graph) {
     // graph replay needs persistent launches: one full occupancy of the chip
@@ -690,6 +726,7 @@ tdi_status tdi_plan_destroy(tdi_plan* p) {
   if (p->d_err) hipFree(p->d_err);
   if (p->d_counters) hipFree(p->d_counters);
   if (p->d_ftiles) hipFree(p->d_ftiles);
+  if (p->d_fix) hipFree(p->d_fix);
   if (p->d_orbtab) hipFree(p->d_orbtab);
   if (p->h_params) hipHostFree(p->h_params);
   free(p);

@@ -18,7 +18,7 @@ constexpr int kWaveOut = 256;     // LFA FP32: outputs per wave (4 per lane, str
 // four chunks per tile (one geometry fit); its stencil pass covers up to
 // kFastStencilSpan elements in one sweep.
 constexpr int kFastChunk = 2304;
-constexpr int kTileLfaFast = 4 * kFastChunk;
+constexpr int kTileLfaFast = 4 * kFastChunk;   // largest fast-path tile (the record holds 4 chunks)
 constexpr int kFastStencilSpan = 11 * kBlock;
 constexpr int kFastOutPerLane = 9;
 constexpr int kWGrid = 16;                 // Lagrange Taylor table: rows per unit offset
@@ -69,11 +69,14 @@ struct KParams {
   // per plan
   int32_t* err;          // window-check report (8 ints)
   void* lfa_tiles;       // fast LFA path: per-tile records written by the pre-pass
-  uint32_t* counters;    // persistent work counters: [0] LFA, [1] full
+  uint32_t* fix_items;   // fast LFA path: waves with a flagged link (tile * 16 + chunk * 4 + wave)
+  uint32_t* counters;    // work counters: [0] LFA tiles, [1] full tiles (persistent kernels),
+                         // [2] entries of fix_items
   OrbitDev orb;
   int32_t gen, mode, equal_arms, stencil_m, stencil_p, persistent;
   int32_t aet, cap_lk;   // aet: store A, E, T instead of X, Y, Z; cap_lk: link-output window
-  int32_t nested, pad1;  // nested: time-nested stage-2 delays
+  int32_t nested;        // time-nested stage-2 delays
+  int32_t tile_fast;     // fast LFA path: outputs per tile (1, 2 or 4 chunks of kFastChunk)
   int64_t link_stride;   // link outputs: elements between the six link arrays (X is their base)
   double T_s, sigma_s;
   double D2_bound;       // upper bound of a stage-2 delay (s)
@@ -95,6 +98,9 @@ size_t links_lds_bytes(int cap, int fp32, int windows);
 // pre-pass of the fast LFA path: per-tile records (geometry fits, chunk
 // windows, wave models) for all LFA tiles (grid-stride over tiles)
 int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream);
+// second pass of the fast LFA path: the uses whose split base is the wave's
+// base shifted by one sample (grid-stride over the per-tile records)
+int launch_lfa_shift_fix(const KParams* dp, int taps, int grid, void* stream);
 size_t fast_tile_bytes();     // bytes of one per-tile record
 // LFA dynamic LDS: h window (FP64), reused for the FP32 wave tables, then the
 // derivative window; goff receives the byte offset of the latter.  Fast path:

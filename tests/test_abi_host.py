@@ -66,7 +66,9 @@ def test_status_strings(L):
     ("lfa_terms", -1, T.TDI_ERANGE),
     ("nested_delays", 2, T.TDI_ERANGE),
     ("nested_delays", -1, T.TDI_ERANGE),
-    ("reserved2", 1, T.TDI_EINVAL),
+    ("fast_tile_chunks", 3, T.TDI_ERANGE),
+    ("fast_tile_chunks", 8, T.TDI_ERANGE),
+    ("fast_tile_chunks", -1, T.TDI_ERANGE),
 ])
 def test_config_validation(L, field, value, code):
     c = _cfg()
