@@ -57,8 +57,7 @@ struct tdi_plan {
   hipStream_t graph_stream;      // private stream used for capture and replay
   // device memory
   tdi::KParams* d_params;        // KParams followed by SrcDev[max_sources]
-  void* d_ftiles;
-  uint32_t* d_fix;               // work list of the fast path's second pass (16 entries per tile)                // fast LFA path: per-tile records of the pre-pass
+  void* d_ftiles;                // fast LFA path: per-tile records of the pre-pass
   int64_t fit_tiles;             // their capacity (tiles)
   size_t params_bytes;
   int32_t* d_err;
@@ -329,9 +328,6 @@ hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& c
   if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, caps.fast, gl, caps.lds_lfa, st) != 0)
     return hipErrorLaunchFailure;
   if (evs && (e = hipEventRecord(evs[2], st)) != hipSuccess) return e;
-  // fast path: uses whose split base is the neighbouring integer (timed with the full kernel)
-  if (gl > 0 && caps.fast && tdi::launch_lfa_shift_fix(p->d_params, taps, 2 * p->n_cu, st) != 0)
-    return hipErrorLaunchFailure;
   const int gf = ln.grid_full > 0 ? ln.grid_full : (int)std::max<int64_t>(0, tiles_full);
   if (gf > 0 && tdi::launch_full(p->d_params, taps, fp32, gf, caps.lds_full, st) != 0)
     return hipErrorLaunchFailure;
@@ -348,13 +344,12 @@ void destroy_graph(tdi_plan* p) {
 
 // Event-record nodes spliced into the captured chain (stream capture does not
 // record events): before the fit pre-pass, before and after the LFA kernel and
-// after the full kernel.  The chain is upload -> reset -> [fit] -> LFA -> [fix]
-// -> full (fit and fix on the fast path).
+// after the full kernel.  The chain is upload -> reset -> [fit] -> LFA -> full.
 bool add_graph_events(tdi_plan* p, hipGraph_t g, bool fast) {
   size_t n = 0, ne = 0;
   if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess || hipGraphGetEdges(g, nullptr, nullptr, &ne) != hipSuccess)
     return false;
-  const size_t want = fast ? 6 : 4;
+  const size_t want = fast ? 5 : 4;
   if (n != want || ne != want - 1) return false;
   std::vector<hipGraphNode_t> nodes(n), from(ne), to(ne);
   if (hipGraphGetNodes(g, nodes.data(), &n) != hipSuccess) return false;
@@ -383,14 +378,14 @@ bool add_graph_events(tdi_plan* p, hipGraph_t g, bool fast) {
     chain.insert(chain.begin() + at, *out);
     return true;
   };
-  // chain indices: 0 upload, 1 reset, then [fit], LFA, [fix], full
+  // chain indices: 0 upload, 1 reset, then [fit], LFA, full
   size_t at = 2;
   if (!splice(at, p->ev[0][0], &p->graph_ev_node[0])) return false;
   at += 1 + (fast ? 1 : 0);
   if (!splice(at, p->ev[0][1], &p->graph_ev_node[1])) return false;
   at += 2;
   if (!splice(at, p->ev[0][2], &p->graph_ev_node[2])) return false;
-  at += 2 + (fast ? 1 : 0);
+  at += 2;
   return splice(at, p->ev[0][3], &p->graph_ev_node[3]);
 }
 
@@ -631,7 +626,6 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
     // records of the fast LFA path: at most one partial tile per source beyond the full ones
     p->fit_tiles = max_total_samples / tdi::kFastChunk + max_sources + 1;
     ok = hipMalloc(&p->d_ftiles, (size_t)p->fit_tiles * tdi::fast_tile_bytes()) == hipSuccess;
-    ok = ok && hipMalloc((void**)&p->d_fix, (size_t)p->fit_tiles * 16 * sizeof(uint32_t)) == hipSuccess;
   }
   ok = ok && hipHostMalloc((void**)&p->h_params, p->params_bytes, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&p->staged_free, hipEventDisableTiming) == hipSuccess;
@@ -654,7 +648,6 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   tdi::KParams& kp = *p->h_params;
   kp.err = p->d_err;
   kp.lfa_tiles = p->d_ftiles;
-  kp.fix_items = p->d_fix;
   kp.counters = p->d_counters;
   tdi::OrbitDev& od = kp.orb;
   od.kind = orb->kind;
@@ -726,7 +719,6 @@ tdi_status tdi_plan_destroy(tdi_plan* p) {
   if (p->d_err) hipFree(p->d_err);
   if (p->d_counters) hipFree(p->d_counters);
   if (p->d_ftiles) hipFree(p->d_ftiles);
-  if (p->d_fix) hipFree(p->d_fix);
   if (p->d_orbtab) hipFree(p->d_orbtab);
   if (p->h_params) hipHostFree(p->h_params);
   free(p);

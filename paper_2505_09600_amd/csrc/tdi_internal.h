@@ -69,9 +69,7 @@ struct KParams {
   // per plan
   int32_t* err;          // window-check report (8 ints)
   void* lfa_tiles;       // fast LFA path: per-tile records written by the pre-pass
-  uint32_t* fix_items;   // fast LFA path: waves with a flagged link (tile * 16 + chunk * 4 + wave)
-  uint32_t* counters;    // work counters: [0] LFA tiles, [1] full tiles (persistent kernels),
-                         // [2] entries of fix_items
+  uint32_t* counters;    // work counters of the persistent kernels: [0] LFA tiles, [1] full tiles
   OrbitDev orb;
   int32_t gen, mode, equal_arms, stencil_m, stencil_p, persistent;
   int32_t aet, cap_lk;   // aet: store A, E, T instead of X, Y, Z; cap_lk: link-output window
@@ -98,9 +96,6 @@ size_t links_lds_bytes(int cap, int fp32, int windows);
 // pre-pass of the fast LFA path: per-tile records (geometry fits, chunk
 // windows, wave models) for all LFA tiles (grid-stride over tiles)
 int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream);
-// second pass of the fast LFA path: the uses whose split base is the wave's
-// base shifted by one sample (grid-stride over the per-tile records)
-int launch_lfa_shift_fix(const KParams* dp, int taps, int grid, void* stream);
 size_t fast_tile_bytes();     // bytes of one per-tile record
 // LFA dynamic LDS: h window (FP64), reused for the FP32 wave tables, then the
 // derivative window; goff receives the byte offset of the latter.  Fast path:

@@ -1156,32 +1156,6 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
     }
     __syncthreads();
-    // waves with a flagged link go to the work list of the second pass
-    // (the three flags and the pad byte read as one word)
-    // (one counter update per wave, lanes placed by their rank among the flagged)
-    static_assert(kPrepTiles * 16 <= kBlock, "one work-list candidate per thread");
-    {
-      const int e = tid;
-      const int t = e >> 4, c = (e >> 2) & 3, w = e & 3;
-      bool flag = false;
-      if (e < kPrepTiles * 16 && sh.live[t] && min(kFChunk, sh.cnt[t] - c * kFChunk) > w * kFWave) {
-        const int32_t fl = *reinterpret_cast<const int32_t*>(TT[tb + t].C[c].W[w].cross);
-        flag = (fl & 0x00ffffff) != 0;
-      }
-      const uint64_t m = __ballot(flag);
-      if (m != 0) {
-        const int lane = tid & 63;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(P.counters + 2, (uint32_t)__popcll(m));
-        base = __shfl(base, leader, 64);
-        if (flag) {
-          const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-          P.fix_items[base + rank] = ((uint32_t)(tb + t) << 4) | ((uint32_t)e & 15u);
-        }
-      }
-    }
-    __syncthreads();
   }
 }
 
@@ -1350,10 +1324,52 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
 #pragma unroll
           for (int q = 0; q < kFR; ++q) Xa[q] = Xb[q] = Xc[q] = 0.0f;
           bool ok = true;
+          int l = 0, pass = 0;
 #pragma unroll 1
-          for (int l = 0; l < 3; ++l) {
-            const int64_t b64 = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1 - g0;
-            if (nl > 0 && (b64 < 0 || b64 + nl + N - 2 >= ng)) {
+          for (;;) {
+            // Near the ends of the series the zero extension makes F_l jump: the
+            // expansion in the offset does not hold for such broadband data, so a
+            // lane whose reads touch an end takes the exact split and weights.
+            const int64_t e_lo = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1;
+            const int64_t e_hi = e_lo + kFR + N - 2;
+            const bool edge = nl > 0 && ((e_lo <= hw + 1 && e_hi >= -hw - 2) ||
+                                         (e_lo <= n + hw + 1 && e_hi >= n - hw - 2));
+            // The split puts each use's integer base at ceil(q), i.e. its offset x
+            // from the base in [0, 1); the wave shares the base mbar (x = xbar + e).
+            // When a delay crosses an integer inside the wave (the pre-pass flags
+            // the link) the uses with x outside [0, 1) belong to the neighbouring
+            // base, whose node set is shifted by one sample.  A second pass takes
+            // them with that base's window and the table row at the integer end
+            // (x = 1 for base mbar + 1, x = 0 for mbar - 1); the first pass takes
+            // the rest.  For data the taps resolve the two interpolants agree;
+            // near a merger they do not.  Edge lanes are exact in the first pass.
+            const int gi = __builtin_amdgcn_readfirstlane(Wv.gi[l]);
+            const int npass = __builtin_amdgcn_readfirstlane((int)Wv.cross[l]) != 0 ? 2 : 1;
+            // x near 0 (gi <= kWGrid / 2): the neighbouring base is mbar + 1, else mbar - 1
+            const int s_alt = 2 * gi <= kWGrid ? 1 : -1;
+            uint32_t own = 0x3ffffu;           // bit side * kFR + q: the use is on base mbar
+            if (npass == 2 && !edge) {
+              const float xbar = (float)gi * (1.0f / (float)kWGrid);
+              own = 0u;
+#pragma unroll
+              for (int side = 0; side < 2; ++side) {
+                const int u = 2 * l + side;
+#pragma unroll
+                for (int q = 0; q < kFR; ++q) {
+                  const float r = rL + (float)(q - kFR / 2);
+                  const float x = xbar + (Wv.dl[u] - r * fmaf(Wv.a2[u], r, Wv.a1[u]));
+                  if (s_alt > 0 ? x >= 0.0f : x < 1.0f) own |= 1u << (side * kFR + q);
+                }
+              }
+            }
+            static_assert(2 * kFR <= 32, "use mask");
+            const int grow = pass ? (s_alt > 0 ? kWGrid : 0) : gi;
+            const float eoff =
+                pass ? (float)(gi - grow) * (1.0f / (float)kWGrid) + (float)s_alt : 0.0f;
+            const uint32_t take = pass ? ~own : own;
+            const int64_t b64 = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1 - g0 - (pass ? s_alt : 0);
+            const uint32_t live = nl > 0 ? take & (((1u << nl) - 1u) * ((1u << kFR) + 1u)) : 0u;
+            if (live != 0u && (b64 < 0 || b64 + nl + N - 2 >= ng)) {
               ok = false;
               report(P.err, 2, kw0 + kFR * lane, b64, ng);
             }
@@ -1365,9 +1381,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             const int u0 = 2 * l, u1 = 2 * l + 1;
             const float e0 = Wv.dl[u0] - rL * fmaf(Wv.a2[u0], rL, Wv.a1[u0]);
             const float e1 = Wv.dl[u1] - rL * fmaf(Wv.a2[u1], rL, Wv.a1[u1]);
-            const float eL = 0.5f * (e0 + e1);
-            // the wave's table row, read by scalar loads (SGPR operands)
-            const float4* row = wtab_row<N>(__builtin_amdgcn_readfirstlane(Wv.gi[l]));
+            const float eLm = 0.5f * (e0 + e1);
+            const float eL = eLm + eoff;
+            // the pass's table row, read by scalar loads (SGPR operands)
+            const float4* row = wtab_row<N>(grow);
             float A[kFR], B[kFR];
 #pragma unroll
             for (int q = 0; q < kFR; ++q) A[q] = B[q] = 0.0f;
@@ -1392,21 +1409,14 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
               const int u = 2 * l + side;
-              const float dl = Wv.dl[u] - eL, a1 = Wv.a1[u], a2 = Wv.a2[u];
+              const float dl = Wv.dl[u] - eLm, a1 = Wv.a1[u], a2 = Wv.a2[u];
 #pragma unroll
               for (int q = 0; q < kFR; ++q) {
                 const float r = rL + (float)(q - kFR / 2);
                 Iv[side][q] = fmaf(dl - r * fmaf(a2, r, a1), B[q], A[q]);
               }
             }
-            // Near the ends of the series the zero extension makes F_l jump: the
-            // expansion in the offset does not hold for such broadband data, so a
-            // lane whose reads touch an end takes the exact split and weights.
-            const int64_t e_lo = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1;
-            const int64_t e_hi = e_lo + kFR + N - 2;
-            const bool edge = nl > 0 && ((e_lo <= hw + 1 && e_hi >= -hw - 2) ||
-                                         (e_lo <= n + hw + 1 && e_hi >= n - hw - 2));
-            if (edge) {
+            if (edge && pass == 0) {
               // raw pairs with the coefficients at the output time: the
               // precombined F_l is exact only for band-limited data
               const double mq = (double)Wv.mbar[l] - (double)Wv.gi[l] / (double)kWGrid;
@@ -1451,10 +1461,14 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
               for (int q = 0; q < kFR; ++q) {
                 const float r = rL + (float)(q - kFR / 2);
                 const float cf = fmaf(r, c1, c0);
-                if (side == 0) Xa[q] = fmaf(cf, Iv[0][q], Xa[q]);
-                else Xb[q] = fmaf(cf, Iv[1][q], Xb[q]);
+                if ((take >> (side * kFR + q)) & 1u) {
+                  if (side == 0) Xa[q] = fmaf(cf, Iv[0][q], Xa[q]);
+                  else Xb[q] = fmaf(cf, Iv[1][q], Xb[q]);
+                }
               }
             }
+            if (++pass < npass) continue;
+            pass = 0;
             // the next link's (side 0, side 1) channels are this link's (Xc, Xa)
 #pragma unroll
             for (int q = 0; q < kFR; ++q) {
@@ -1463,6 +1477,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
               Xb[q] = Xa[q];
               Xa[q] = t;
             }
+            if (++l == 3) break;
           }
           // after three links: X = Xc, Y = Xb, Z = Xa.  Hybrid: w+ = 1/(1+e^z),
           // z = (k - kH)/sigma, zero beyond k - kH = T/2; a wave whose outputs all
@@ -1496,322 +1511,6 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
           store3<float>(P, off + kc0 + i, __builtin_nanf(""), __builtin_nanf(""), __builtin_nanf(""));
       }
       __syncthreads();
-    }
-  }
-}
-
-// Value of link l's precombined series F at element i of a chunk window (i
-// relative to g0), formed exactly as k_lfa_fast forms it: the FP64 central
-// stencil of h (zero outside [0, n)), rounded to FP32, combined with the
-// chunk's FP32 coefficient models.
-__device__ __forceinline__ float fast_F(const KParams& P, const FastChunk& R, int64_t off, int64_t n, int64_t i,
-                                        int l, const double* stn, int hw) {
-  const int64_t jj = R.g0 + i;
-  double ap = 0.0, ac = 0.0;
-#pragma unroll
-  for (int s = 0; s < 7; ++s) {
-    const int64_t smp = jj - hw + s;
-    const bool in = smp >= 0 && smp < n;
-    ap = fma(stn[s], in ? P.hp[off + smp] : 0.0, ap);
-    ac = fma(stn[s], in ? P.hc[off + smp] : 0.0, ac);
-  }
-  if (!(jj >= 0 && jj < n)) ap = ac = 0.0;
-  const float gp = (float)ap, gx = (float)ac;
-  const float u = (float)i - (float)(R.ec[l] - (double)R.g0);
-  const float cp = fmaf(u, fmaf(u, (float)R.pc[l][0][2], (float)R.pc[l][0][1]), (float)R.pc[l][0][0]);
-  const float cx = fmaf(u, fmaf(u, (float)R.pc[l][1][2], (float)R.pc[l][1][1]), (float)R.pc[l][1][0]);
-  return fmaf(cp, gp, cx * gx);
-}
-
-// The same from an LDS copy of the strain: hs_p[t], hs_c[t] hold samples slo + t
-// (zero outside [0, n)).
-__device__ __forceinline__ float fast_F_staged(const FastChunk& R, const double* hs_p, const double* hs_c,
-                                               int64_t slo, int64_t n, int64_t i, int l, const double* stn,
-                                               int hw) {
-  const int64_t jj = R.g0 + i;
-  double ap = 0.0, ac = 0.0;
-#pragma unroll
-  for (int s = 0; s < 7; ++s) {
-    const int t = (int)(jj - hw + s - slo);
-    ap = fma(stn[s], hs_p[t], ap);
-    ac = fma(stn[s], hs_c[t], ac);
-  }
-  if (!(jj >= 0 && jj < n)) ap = ac = 0.0;
-  const float gp = (float)ap, gx = (float)ac;
-  const float u = (float)i - (float)(R.ec[l] - (double)R.g0);
-  const float cp = fmaf(u, fmaf(u, (float)R.pc[l][0][2], (float)R.pc[l][0][1]), (float)R.pc[l][0][0]);
-  const float cx = fmaf(u, fmaf(u, (float)R.pc[l][1][2], (float)R.pc[l][1][1]), (float)R.pc[l][1][0]);
-  return fmaf(cp, gp, cx * gx);
-}
-
-constexpr int kFixStage = 768;    // strain samples staged per wave in the second pass
-// (-1)^(16-k) C(16, k): the sixteenth forward difference
-__constant__ double c_binom16[17] = {1, -16, 120, -560, 1820, -4368, 8008, -11440, 12870,
-                                     -11440, 8008, -4368, 1820, -560, 120, -16, 1};
-
-// A[q] += sum_j w_j(e) win[O + j + q], B[q] += sum_j w'_j(e) win[O + j + q] with the
-// weights of table row `row`, in the order and form of k_lfa_fast.
-template <int N, int O>
-__device__ __forceinline__ void fix_dot(const float (&win)[kFR + N], const float4* row, float e, float (&A)[kFR],
-                                        float (&B)[kFR]) {
-#pragma unroll
-  for (int q = 0; q < kFR; ++q) A[q] = B[q] = 0.0f;
-#pragma unroll
-  for (int j = 0; j < N; ++j) {
-    const float4 c = row[j];
-    const float b2 = fmaf(e, c.w, c.z);
-    const float b1 = fmaf(e, b2, c.y);
-    const float w = fmaf(e, b1, c.x);
-    const float wd = fmaf(e, b2, b1);
-#pragma unroll
-    for (int q = 0; q < kFR; ++q) {
-      A[q] = fmaf(w, win[O + j + q], A[q]);
-      B[q] = fmaf(wd, win[O + j + q], B[q]);
-    }
-  }
-}
-
-// Second pass of the fast LFA path over the wave records the pre-pass flagged.
-// The split puts each use's integer base at ceil(q), i.e. its offset x from
-// the base in [0, 1).  k_lfa_fast shares the wave's base mbar (x = xbar + e):
-// when a delay crosses an integer inside the wave, the uses with x outside
-// [0, 1) belong to the neighbouring base, whose node set is shifted by one
-// sample.  For data the taps resolve the two interpolants agree; near a merger
-// they do not.  For those uses this kernel adds to the stored outputs the
-// difference between the interpolant on their own node set (table row at the
-// integer end: x = 1 for base mbar + 1, x = 0 for mbar - 1) and the wave-base
-// value k_lfa_fast used, weighted as the stored output.  F is re-formed exactly
-// as k_lfa_fast forms it, so the wave-base value is reproduced to the bit.  One
-// wave per (tile, chunk, wave) record; lanes whose reads touch an end of the
-// series were exact in k_lfa_fast and take no part.
-template <int N>
-__global__ __launch_bounds__(kBlock) void k_lfa_fix(const KParams* __restrict__ Pp) {
-  const KParams& P = *Pp;
-  const FastTile* __restrict__ TT = static_cast<const FastTile*>(P.lfa_tiles);
-  // F over the union of a wave's windows (lane windows start kFR elements apart),
-  // formed from a staged copy of the strain the flagged links read
-  __shared__ float fwin[kBlock / 64][64 * kFR + 32];
-  __shared__ double hsp[kBlock / 64][kFixStage], hsc[kBlock / 64][kFixStage];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
-  const int hw = c_sthw[st];
-  double stn[7];
-#pragma unroll
-  for (int s = 0; s < 7; ++s) stn[s] = c_stnum[st][s];
-  const int64_t items = (int64_t)P.counters[2];
-  for (int64_t it = (int64_t)blockIdx.x * 4 + wave; it < items; it += (int64_t)gridDim.x * 4) {
-    const uint32_t item = P.fix_items[it];
-    const int64_t tile = item >> 4;
-    const int c = (int)((item >> 2) & 3), w = (int)(item & 3);
-    const FastTile& T = TT[tile];
-    if (c >= T.nch) continue;
-    const FastChunk& R = T.C[c];
-    if (R.bad) continue;
-    const FastWave& Wv = R.W[w];
-    const int wcnt = Wv.wcnt;
-    if (wcnt <= 0 || (Wv.cross[0] | Wv.cross[1] | Wv.cross[2]) == 0) continue;
-    const int64_t off = T.off, n = T.n;
-    const int ng = R.ng;
-    const int64_t kw0 = T.k0 + (int64_t)c * kFChunk + (int64_t)w * kFWave;
-    const int nl = min(max(wcnt - kFR * lane, 0), kFR);
-    const float rL = (float)(kFR * lane + kFR / 2) - Wv.hr;
-    float dX[3][kFR];
-#pragma unroll
-    for (int q = 0; q < kFR; ++q) dX[0][q] = dX[1][q] = dX[2][q] = 0.0f;
-    bool lane_any = false, ok = true;
-    // the strain samples of the union window and stencil halo of every link with
-    // uses on the shifted base (links whose crossing falls outside the wave's
-    // outputs add nothing)
-    int64_t slo = INT64_MAX, shi = INT64_MIN;
-    int links = 0;
-#pragma unroll 1
-    for (int l = 0; l < 3; ++l) {
-      if (Wv.cross[l] == 0) continue;
-      const float xb = (float)Wv.gi[l] * (1.0f / (float)kWGrid);
-      bool alt = false;
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        const int u = 2 * l + side;
-#pragma unroll
-        for (int q = 0; q < kFR; ++q) {
-          const float r = rL + (float)(q - kFR / 2);
-          const float x = xb + (Wv.dl[u] - r * fmaf(Wv.a2[u], r, Wv.a1[u]));
-          if (q < nl && !(x >= 0.0f && x < 1.0f)) alt = true;
-        }
-      }
-      if (__ballot(alt) == 0) continue;
-      links |= 1 << l;
-      const int64_t a = kw0 - Wv.mbar[l] - N / 2 + 1 - (2 * Wv.gi[l] <= kWGrid ? 1 : 0) - hw;
-      slo = min(slo, a);
-      shi = max(shi, a + 64 * kFR + N - 1 + 2 * hw);
-    }
-    if (links == 0) continue;
-    const bool staged = shi - slo + 1 <= kFixStage;
-    if (staged) {
-      const int slen = (int)(shi - slo + 1);
-      for (int t = lane; t < slen; t += 64) {
-        const int64_t smp = slo + t;
-        const bool in = smp >= 0 && smp < n;
-        hsp[wave][t] = in ? P.hp[off + smp] : 0.0;
-        hsc[wave][t] = in ? P.hc[off + smp] : 0.0;
-      }
-      wave_sync();
-      // Skip a wave whose strain is resolved by the taps.  The two interpolants
-      // of a use differ by 32 |x| |Delta^32 F| / 32! prod |p - s| over the 31
-      // common nodes, at most 3.6e-10 |x| |Delta^32 F| (|x| < 0.1 here), and
-      // Delta^32 F <= (|c+| + |cx|) sum|stencil| 2^16 max|Delta^16 h| (smooth
-      // coefficients).  With max|Delta^16 h| <= 1e-5 max|g| (g the stencil
-      // sums) the difference stays below 1e-9 of the window's scale
-      // (|c+| + |cx|) max|g|; the inspiral clears this by orders of magnitude
-      // (Delta^16 h ~ 2e-7 h at f dt = 0.06), a merger or a kink does not.  At
-      // low frequency g itself is tiny (a third derivative) and the sixteenth
-      // difference sits at its FP64 rounding level, ~1e-12 max|h|: below
-      // 1e-10 max|h| the bound is under 1e-14 max|h|, far below any channel
-      // peak, and the wave is skipped as well.  A kink moves 17 consecutive
-      // differences, so every fourth position is enough.
-      double d16 = 0.0, gmax = 0.0, hmax = 0.0;
-      for (int t = 4 * lane; t + 16 < slen; t += 256) {
-        double dp = 0.0, dc = 0.0;
-#pragma unroll
-        for (int k = 0; k <= 16; ++k) {
-          dp = fma(c_binom16[k], hsp[wave][t + k], dp);
-          dc = fma(c_binom16[k], hsc[wave][t + k], dc);
-        }
-        d16 = fmax(d16, fmax(fabs(dp), fabs(dc)));
-        hmax = fmax(hmax, fmax(fabs(hsp[wave][t + 8]), fabs(hsc[wave][t + 8])));
-        if (t + 2 * hw < slen) {
-          double gp = 0.0, gc = 0.0;
-#pragma unroll
-          for (int k = 0; k < 7; ++k) {
-            gp = fma(stn[k], hsp[wave][t + k], gp);
-            gc = fma(stn[k], hsc[wave][t + k], gc);
-          }
-          gmax = fmax(gmax, fmax(fabs(gp), fabs(gc)));
-        }
-      }
-      for (int o = 32; o > 0; o >>= 1) {
-        d16 = fmax(d16, __shfl_xor(d16, o, 64));
-        gmax = fmax(gmax, __shfl_xor(gmax, o, 64));
-        hmax = fmax(hmax, __shfl_xor(hmax, o, 64));
-      }
-      double ssum = 0.0;
-#pragma unroll
-      for (int k = 0; k < 7; ++k) ssum += fabs(stn[k]);
-      if (3.6e-11 * ssum * 65536.0 * d16 <= 1e-9 * gmax || d16 <= 1e-10 * hmax) continue;
-    }
-#pragma unroll 1
-    for (int l = 0; l < 3; ++l) {
-      if (!(links & (1 << l))) continue;
-      const int gi = Wv.gi[l];
-      const float xbar = (float)gi * (1.0f / (float)kWGrid);
-      const int s_alt = 2 * gi <= kWGrid ? 1 : -1;
-      const int64_t e_lo = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1;
-      const int64_t e_hi = e_lo + kFR + N - 2;
-      const bool edge = nl > 0 && ((e_lo <= hw + 1 && e_hi >= -hw - 2) ||
-                                   (e_lo <= n + hw + 1 && e_hi >= n - hw - 2));
-      bool need_alt = false;
-      if (!edge) {
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int u = 2 * l + side;
-#pragma unroll
-          for (int q = 0; q < kFR; ++q) {
-            const float r = rL + (float)(q - kFR / 2);
-            const float x = xbar + (Wv.dl[u] - r * fmaf(Wv.a2[u], r, Wv.a1[u]));
-            if (q < nl && !(x >= 0.0f && x < 1.0f)) need_alt = true;
-          }
-        }
-      }
-      if (__ballot(need_alt) == 0) continue;
-      // F over the wave's union window, formed once and shared by the lanes
-      const int64_t base0 = kw0 - Wv.mbar[l] - N / 2 + 1 - R.g0 - (s_alt > 0 ? 1 : 0);
-      static_assert(N <= 32, "window staging");
-#pragma unroll 1
-      for (int t = lane; t < 64 * kFR + N; t += 64)
-        fwin[wave][t] = staged ? fast_F_staged(R, hsp[wave], hsc[wave], slo, n, base0 + t, l, stn, hw)
-                               : fast_F(P, R, off, n, base0 + t, l, stn, hw);
-      wave_sync();
-      if (!need_alt) continue;
-      lane_any = true;
-      const int64_t bm = e_lo - R.g0;          // wave-base window (elements of the chunk window)
-      const int64_t ba = bm - s_alt;           // shifted window
-      if (bm < 0 || ba < 0 || bm + nl + N - 2 >= ng || ba + nl + N - 2 >= ng) {
-        ok = false;
-        report(P.err, 2, kw0 + kFR * lane, ba, ng);
-        continue;
-      }
-      const int64_t bu = s_alt > 0 ? ba : bm;
-      float win[kFR + N];
-#pragma unroll
-      for (int t = 0; t < kFR + N; ++t) win[t] = fwin[wave][(int)(bu - base0) + t];
-      const float e0 = Wv.dl[2 * l] - rL * fmaf(Wv.a2[2 * l], rL, Wv.a1[2 * l]);
-      const float e1 = Wv.dl[2 * l + 1] - rL * fmaf(Wv.a2[2 * l + 1], rL, Wv.a1[2 * l + 1]);
-      const float eL = 0.5f * (e0 + e1);
-      const int ga = s_alt > 0 ? kWGrid : 0;
-      const float eA = eL + (xbar + (float)s_alt - (float)ga * (1.0f / (float)kWGrid));
-      float Am[kFR], Bm[kFR], Aa[kFR], Ba[kFR];
-      if (s_alt > 0) {
-        fix_dot<N, 1>(win, wtab_row<N>(gi), eL, Am, Bm);
-        fix_dot<N, 0>(win, wtab_row<N>(ga), eA, Aa, Ba);
-      } else {
-        fix_dot<N, 0>(win, wtab_row<N>(gi), eL, Am, Bm);
-        fix_dot<N, 1>(win, wtab_row<N>(ga), eA, Aa, Ba);
-      }
-#pragma unroll
-      for (int side = 0; side < 2; ++side) {
-        const int u = 2 * l + side;
-        const float dl = Wv.dl[u] - eL, a1 = Wv.a1[u], a2 = Wv.a2[u];
-        const float c0 = Wv.c0[u], c1 = Wv.c1[u];
-        const int chn = side == 0 ? (l + 2) % 3 : (l + 1) % 3;
-#pragma unroll
-        for (int q = 0; q < kFR; ++q) {
-          const float r = rL + (float)(q - kFR / 2);
-          const float x = xbar + (Wv.dl[u] - r * fmaf(a2, r, a1));
-          if (q < nl && !(x >= 0.0f && x < 1.0f)) {
-            const float d = dl - r * fmaf(a2, r, a1);
-            const float vm = fmaf(d, Bm[q], Am[q]);
-            const float va = fmaf(d, Ba[q], Aa[q]);
-            const float cf = fmaf(r, c1, c0);
-            const float add = cf * (va - vm);
-            if (chn == 0) dX[0][q] += add;
-            else if (chn == 1) dX[1][q] += add;
-            else dX[2][q] += add;
-          }
-        }
-      }
-    }
-    if (!lane_any) continue;
-    // weight as k_lfa_fast weighs the stored output, map to A, E, T if asked,
-    // and add to the stored values
-    const double relL = (double)(kw0 + kFR * lane) - T.kH;
-    const double isg = 1.0 / P.sigma_s;
-    const bool weigh = P.mode == 2 && ((double)(kw0 + wcnt - 1) - T.kH) * isg > -17.0;
-    const int64_t o0 = off + kw0 + kFR * lane;
-#pragma unroll
-    for (int q = 0; q < kFR; ++q) {
-      if (q >= nl) continue;
-      float x = dX[0][q], y = dX[1][q], z = dX[2][q];
-      if (x == 0.0f && y == 0.0f && z == 0.0f) continue;
-      if (!ok) x = y = z = __builtin_nanf("");
-      if (weigh) {
-        const double rel = relL + (double)q;
-        if (rel <= 0.5 * P.T_s) {
-          const float zz = (float)(rel * isg);
-          if (zz > -17.0f) {
-            const float wgt = 1.0f / (1.0f + expf(zz));
-            x *= wgt; y *= wgt; z *= wgt;
-          }
-        } else {
-          continue;          // the LFA part is zero beyond the window
-        }
-      }
-      if (P.aet) to_aet<float>(x, y, z);
-      float* Xo = static_cast<float*>(P.X);
-      float* Yo = static_cast<float*>(P.Y);
-      float* Zo = static_cast<float*>(P.Z);
-      Xo[o0 + q] += x;
-      Yo[o0 + q] += y;
-      Zo[o0 + q] += z;
     }
   }
 }
@@ -2271,7 +1970,7 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
 }
 
 __global__ void k_reset(uint32_t* counters) {
-  if (threadIdx.x < 3) counters[threadIdx.x] = 0u;
+  if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
 }
 
 template <int N, typename TC>
@@ -2470,15 +2169,6 @@ int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t
   return -2;
 }
 
-template <int N>
-int launch_lfa_shift_fix_t(const KParams* dp, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_lfa_fix<N>), dim3(grid), dim3(kBlock), 0, st, dp);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-int launch_lfa_shift_fix(const KParams* dp, int taps, int grid, void* stream) {
-  TDI_DISPATCH_FAST(taps, launch_lfa_shift_fix_t, dp, grid, (hipStream_t)stream);
-  return -2;
-}
 int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream) {
   TDI_DISPATCH_FAST(taps, launch_lfa_fit_t, dp, grid, (hipStream_t)stream);
   return -2;

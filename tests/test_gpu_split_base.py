@@ -8,8 +8,8 @@ but right at a merger (a kink in the amplitude, broadband at the sample scale)
 the two interpolants differ by up to 4e-4 of the channel peak.  These sources
 put such a crossing on the merger: link 1's fractional delay there is 0.012
 samples (700-sample source) and 0.988 samples (4608-sample source, the
-neighbouring base below).  The second pass of the fast path must bring them to
-the FP32 bar, and in the hybrid the switch comes 31 samples before the merger,
+neighbouring base below).  The fast path's second pass over such links (the
+uses on the neighbouring base) must bring them to the FP32 bar, and in the hybrid the switch comes 31 samples before the merger,
 so the LFA still carries weight 0.15 there.
 """
 import numpy as np
