@@ -1329,7 +1329,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
           for (;;) {
             // Near the ends of the series the zero extension makes F_l jump: the
             // expansion in the offset does not hold for such broadband data, so a
-            // lane whose reads touch an end takes the exact split and weights.
+            // lane whose reads touch an end takes no use here; the exact split and
+            // weights give its uses after the link loop.
             const int64_t e_lo = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1;
             const int64_t e_hi = e_lo + kFR + N - 2;
             const bool edge = nl > 0 && ((e_lo <= hw + 1 && e_hi >= -hw - 2) ||
@@ -1347,7 +1348,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             const int npass = __builtin_amdgcn_readfirstlane((int)Wv.cross[l]) != 0 ? 2 : 1;
             // x near 0 (gi <= kWGrid / 2): the neighbouring base is mbar + 1, else mbar - 1
             const int s_alt = 2 * gi <= kWGrid ? 1 : -1;
-            uint32_t own = 0x3ffffu;           // bit side * kFR + q: the use is on base mbar
+            uint32_t own = edge ? 0u : 0x3ffffu;   // bit side * kFR + q: the use is on base mbar
             if (npass == 2 && !edge) {
               const float xbar = (float)gi * (1.0f / (float)kWGrid);
               own = 0u;
@@ -1366,7 +1367,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             const int grow = pass ? (s_alt > 0 ? kWGrid : 0) : gi;
             const float eoff =
                 pass ? (float)(gi - grow) * (1.0f / (float)kWGrid) + (float)s_alt : 0.0f;
-            const uint32_t take = pass ? ~own : own;
+            const uint32_t take = edge ? 0u : (pass ? ~own : own);
             const int64_t b64 = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1 - g0 - (pass ? s_alt : 0);
             const uint32_t live = nl > 0 ? take & (((1u << nl) - 1u) * ((1u << kFR) + 1u)) : 0u;
             if (live != 0u && (b64 < 0 || b64 + nl + N - 2 >= ng)) {
@@ -1416,42 +1417,6 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
                 Iv[side][q] = fmaf(dl - r * fmaf(a2, r, a1), B[q], A[q]);
               }
             }
-            if (edge && pass == 0) {
-              // raw pairs with the coefficients at the output time: the
-              // precombined F_l is exact only for band-limited data
-              const double mq = (double)Wv.mbar[l] - (double)Wv.gi[l] / (double)kWGrid;
-#pragma unroll 1
-              for (int side = 0; side < 2; ++side) {
-                const int u = 2 * l + side;
-                const float dl = Wv.dl[u], a1 = Wv.a1[u], a2 = Wv.a2[u];
-#pragma unroll 1
-                for (int q = 0; q < nl; ++q) {
-                  const float r = rL + (float)(q - kFR / 2);
-                  const int64_t k = kw0 + kFR * lane + q;
-                  const double qf = mq - (double)(dl - r * fmaf(a2, r, a1));   // delay in samples
-                  const double mc = ceil(qf);
-                  const int64_t j0 = k - (int64_t)mc - N / 2 + 1;
-                  double sp, sx;
-                  float v = __builtin_nanf("");
-                  if (!edge_read<N>(gedge, j0, n, ne, mc - qf, sp, sx)) {
-                    ok = false;
-                    report(P.err, 2, k, j0, n);
-                  } else {
-                    const double uu = ((double)k - qf) - ch.ec[l];
-                    const double cp = fma(uu, fma(uu, ch.pc[l][0][2], ch.pc[l][0][1]), ch.pc[l][0][0]);
-                    const double cx = fma(uu, fma(uu, ch.pc[l][1][2], ch.pc[l][1][1]), ch.pc[l][1][0]);
-                    v = (float)fma(cp, sp, cx * sx);
-                  }
-                  // constant indices into Iv keep it in registers
-#pragma unroll
-                  for (int qq = 0; qq < kFR; ++qq)
-                    if (qq == q) {
-                      if (side == 0) Iv[0][qq] = v;
-                      else Iv[1][qq] = v;
-                    }
-                }
-              }
-            }
             // side 0 feeds channel (l+2)%3 (Xa), side 1 channel (l+1)%3 (Xb)
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
@@ -1478,6 +1443,69 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
               Xa[q] = t;
             }
             if (++l == 3) break;
+          }
+          // Edge lanes: raw pairs with the coefficients at the output time (the
+          // precombined F_l is exact only for band-limited data).  A link's edge
+          // lanes hold 2 kFR uses each; they are spread over the 64 lanes of the
+          // wave, 64 per round, and each c * value goes back to its lane by a
+          // shuffle.  After the link loop X = Xc, Y = Xb, Z = Xa, and side 0 of
+          // link l feeds channel (l + 2) % 3, side 1 channel (l + 1) % 3.
+#pragma unroll
+          for (int l = 0; l < 3; ++l) {
+            const int64_t e_lo = kw0 + kFR * lane - Wv.mbar[l] - N / 2 + 1;
+            const int64_t e_hi = e_lo + kFR + N - 2;
+            const bool edge = nl > 0 && ((e_lo <= hw + 1 && e_hi >= -hw - 2) ||
+                                         (e_lo <= n + hw + 1 && e_hi >= n - hw - 2));
+            const uint64_t emask = __ballot(edge);
+            if (emask == 0) continue;
+            const double mq = (double)Wv.mbar[l] - (double)Wv.gi[l] / (double)kWGrid;
+            const int total = __popcll(emask) * (2 * kFR);
+            const int my_rank = edge ? __popcll(emask & ((1ull << lane) - 1ull)) : -1;
+#pragma unroll 1
+            for (int rb = 0; rb < total; rb += 64) {
+              const int id = rb + lane;
+              float v = 0.0f;
+              int good = 1;
+              if (id < total) {
+                const int rank = id / (2 * kFR), side = (id / kFR) % 2, q = id % kFR;
+                uint64_t mm = emask;
+                for (int i = 0; i < rank; ++i) mm &= mm - 1ull;
+                const int ol = __ffsll((unsigned long long)mm) - 1;      // the use's lane
+                if (q < min(max(wcnt - kFR * ol, 0), kFR)) {
+                  const int u = 2 * l + side;
+                  const float r = ((float)(kFR * ol + kFR / 2) - Wv.hr) + (float)(q - kFR / 2);
+                  const int64_t k = kw0 + kFR * ol + q;
+                  const double qf = mq - (double)(Wv.dl[u] - r * fmaf(Wv.a2[u], r, Wv.a1[u]));   // delay in samples
+                  const double mc = ceil(qf);
+                  const int64_t j0 = k - (int64_t)mc - N / 2 + 1;
+                  double sp, sx;
+                  if (!edge_read<N>(gedge, j0, n, ne, mc - qf, sp, sx)) {
+                    good = 0;
+                    report(P.err, 2, k, j0, n);
+                  } else {
+                    const double uu = ((double)k - qf) - ch.ec[l];
+                    const double cp = fma(uu, fma(uu, ch.pc[l][0][2], ch.pc[l][0][1]), ch.pc[l][0][0]);
+                    const double cx = fma(uu, fma(uu, ch.pc[l][1][2], ch.pc[l][1][1]), ch.pc[l][1][0]);
+                    v = fmaf(r, Wv.c1[u], Wv.c0[u]) * (float)fma(cp, sp, cx * sx);
+                  }
+                }
+              }
+              // constant indices keep the channels in registers
+#pragma unroll
+              for (int idx = 0; idx < 2 * kFR; ++idx) {
+                const int src = my_rank * (2 * kFR) + idx - rb;
+                const float got = __shfl(v, src & 63, 64);
+                const int gok = __shfl(good, src & 63, 64);
+                if (my_rank >= 0 && src >= 0 && src < 64) {
+                  const int q = idx % kFR;
+                  const int chn = idx < kFR ? (l + 2) % 3 : (l + 1) % 3;
+                  if (chn == 0) Xc[q] += got;
+                  else if (chn == 1) Xb[q] += got;
+                  else Xa[q] += got;
+                  if (!gok) ok = false;
+                }
+              }
+            }
           }
           // after three links: X = Xc, Y = Xb, Z = Xa.  Hybrid: w+ = 1/(1+e^z),
           // z = (k - kH)/sigma, zero beyond k - kH = T/2; a wave whose outputs all
