@@ -1417,18 +1417,34 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
                 Iv[side][q] = fmaf(dl - r * fmaf(a2, r, a1), B[q], A[q]);
               }
             }
-            // side 0 feeds channel (l+2)%3 (Xa), side 1 channel (l+1)%3 (Xb)
+            // side 0 feeds channel (l+2)%3 (Xa), side 1 channel (l+1)%3 (Xb); most
+            // waves take every use (no crossing, no edge) and skip the mask tests
+            if (__ballot(take != 0x3ffffu) == 0) {
 #pragma unroll
-            for (int side = 0; side < 2; ++side) {
-              const int u = 2 * l + side;
-              const float c0 = Wv.c0[u], c1 = Wv.c1[u];
+              for (int side = 0; side < 2; ++side) {
+                const int u = 2 * l + side;
+                const float c0 = Wv.c0[u], c1 = Wv.c1[u];
 #pragma unroll
-              for (int q = 0; q < kFR; ++q) {
-                const float r = rL + (float)(q - kFR / 2);
-                const float cf = fmaf(r, c1, c0);
-                if ((take >> (side * kFR + q)) & 1u) {
+                for (int q = 0; q < kFR; ++q) {
+                  const float r = rL + (float)(q - kFR / 2);
+                  const float cf = fmaf(r, c1, c0);
                   if (side == 0) Xa[q] = fmaf(cf, Iv[0][q], Xa[q]);
                   else Xb[q] = fmaf(cf, Iv[1][q], Xb[q]);
+                }
+              }
+            } else {
+#pragma unroll
+              for (int side = 0; side < 2; ++side) {
+                const int u = 2 * l + side;
+                const float c0 = Wv.c0[u], c1 = Wv.c1[u];
+#pragma unroll
+                for (int q = 0; q < kFR; ++q) {
+                  const float r = rL + (float)(q - kFR / 2);
+                  const float cf = fmaf(r, c1, c0);
+                  if ((take >> (side * kFR + q)) & 1u) {
+                    if (side == 0) Xa[q] = fmaf(cf, Iv[0][q], Xa[q]);
+                    else Xb[q] = fmaf(cf, Iv[1][q], Xb[q]);
+                  }
                 }
               }
             }
