@@ -42,10 +42,11 @@ def _sources():
     return W._assemble(parts, np)
 
 
+@pytest.mark.parametrize("taps", [8, 16, 32])
 @pytest.mark.parametrize("mode", [1, 2])
-def test_merger_on_an_integer_crossing(tdi, orc, mode):
+def test_merger_on_an_integer_crossing(tdi, orc, mode, taps):
     batch, orb = _sources(), W.default_orbit()
-    cfg = W.default_config(tdi_gen=20, mode=mode, taps=32, stencil_order=4, precision=1)
+    cfg = W.default_config(tdi_gen=20, mode=mode, taps=taps, stencil_order=4, precision=1)
     info = {}
     got = tdi.response(batch, cfg, orb, info=info)
     assert info["lfa_fast"] == 1
@@ -53,6 +54,6 @@ def test_merger_on_an_integer_crossing(tdi, orc, mode):
     for s in range(batch.n_sources):
         a, b = int(batch.offsets[s]), int(batch.offsets[s + 1])
         err = orc.peak_rel_err(got[:, a:b], ref[:, a:b])
-        print(f"[parity] integer crossing at the merger, mode{mode} n={b - a}: "
+        print(f"[parity] integer crossing at the merger, mode{mode} {taps} taps n={b - a}: "
               f"err X,Y,Z = {err[0]:.3e} {err[1]:.3e} {err[2]:.3e}", flush=True)
         assert np.all(err <= 1e-5), (s, err)
