@@ -1343,7 +1343,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             // them with that base's window and the table row at the integer end
             // (x = 1 for base mbar + 1, x = 0 for mbar - 1); the first pass takes
             // the rest.  For data the taps resolve the two interpolants agree;
-            // near a merger they do not.  Edge lanes are exact in the first pass.
+            // near a merger they do not.  Edge lanes take neither pass.
             const int gi = __builtin_amdgcn_readfirstlane(Wv.gi[l]);
             const int npass = __builtin_amdgcn_readfirstlane((int)Wv.cross[l]) != 0 ? 2 : 1;
             // x near 0 (gi <= kWGrid / 2): the neighbouring base is mbar + 1, else mbar - 1
