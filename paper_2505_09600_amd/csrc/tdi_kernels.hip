@@ -1822,7 +1822,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
 //           with two terms, the next term of Eq. (yslr_with_tau_derivatives),
 //           (T_l (1 - k.n_l) / 2)^2 / 6 times the third derivative, joins h';
 //   hybrid: Eq. (hybridized_yslr) with the windows and weights of the TDI hybrid.
-// One workgroup per tile of kTileLinks outputs, one output per thread.
+// One workgroup per tile of kTileLinks outputs (one geometry fit per tile), each
+// thread taking every kBlock-th output.
 // ---------------------------------------------------------------------------
 struct LinkShared {
   GeoFit F;
@@ -1899,8 +1900,8 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
   const int64_t stride = P.link_stride;
   TC* Yo = static_cast<TC*>(P.X);
   if (sh.bad) {
-    if (tid < cnt)
-      for (int a = 0; a < 6; ++a) Yo[a * stride + S.off + k0 + tid] = (TC)__builtin_nan("");
+    for (int o = tid; o < cnt; o += kBlock)
+      for (int a = 0; a < 6; ++a) Yo[a * stride + S.off + k0 + o] = (TC)__builtin_nan("");
     return;
   }
   // strain window (full part) and first-derivative window (LFA part), the
@@ -1949,67 +1950,68 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
     }
   }
   __syncthreads();
-  if (tid >= cnt) return;
-  const int64_t k = k0 + tid;
-  const double s = ((double)k - sh.F.kc) * sh.F.ikh;
-  const double rel = (double)k - sh.kH;
-  const bool lfa = P.mode == 1 || (P.mode == 2 && rel <= 0.5 * P.T_s);
-  const bool full = P.mode == 0 || (P.mode == 2 && rel >= -0.5 * P.T_s);
-  double wp = 1.0, wm = 1.0;
-  if (P.mode == 2) {
-    wp = 1.0 / (1.0 + exp(rel / P.sigma_s));
-    wm = 1.0 / (1.0 + exp(-rel / P.sigma_s));
-  }
-  const double kR[3] = {geo_eval(sh.F, qKR(0), s), geo_eval(sh.F, qKR(1), s), geo_eval(sh.F, qKR(2), s)};
-  const double c2 = sh.c2, s2 = sh.s2;
-#pragma unroll 1
-  for (int a = 0; a < 6; ++a) {
-    const double T = geo_eval(sh.F, qT(a), s);
-    const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
-    const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
-    const int sn = snd_of(a), rc = rcv_of(a);
-    TC y = (TC)0;
-    if (lfa) {
-      const double Tl = P.equal_arms ? P.orb.L_over_c : T;
-      int64_t i0;
-      double x;
-      split(k, 0.5 * Tl + 0.5 * (kR[sn] + kR[rc]), dt, i0, x);
-      const int64_t b = i0 - N / 2 + 1 - w0;
-      TC vp, vc, v3p = (TC)0, v3c = (TC)0;
-      if (b < 0 || b + N > nh) {
-        report(P.err, 16, k, b, nh);
-        vp = vc = (TC)__builtin_nan("");
-      } else {
-        interp2<N, TC>(gwin, b, x, vp, vc);
-        if (nlo) interp2<N, TC>(g3win, b, x, v3p, v3c);
-      }
-      TC lf = A * vp + B * vc;
-      if (nlo) {
-        // (T (1 - k.n) / 2)^2 / 6 with 1 - k.n = D / 2
-        const double e = 0.25 * Tl * geo_eval(sh.F, qD(a), s);
-        lf += (TC)(e * e / 6.0) * (A * v3p + B * v3c);
-      }
-      y += (TC)(wp * (-0.5 * Tl)) * lf;
+  for (int o = tid; o < cnt; o += kBlock) {
+    const int64_t k = k0 + o;
+    const double s = ((double)k - sh.F.kc) * sh.F.ikh;
+    const double rel = (double)k - sh.kH;
+    const bool lfa = P.mode == 1 || (P.mode == 2 && rel <= 0.5 * P.T_s);
+    const bool full = P.mode == 0 || (P.mode == 2 && rel >= -0.5 * P.T_s);
+    double wp = 1.0, wm = 1.0;
+    if (P.mode == 2) {
+      wp = 1.0 / (1.0 + exp(rel / P.sigma_s));
+      wm = 1.0 / (1.0 + exp(-rel / P.sigma_s));
     }
-    if (full) {
-      TC v[4];
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
+    const double kR[3] = {geo_eval(sh.F, qKR(0), s), geo_eval(sh.F, qKR(1), s), geo_eval(sh.F, qKR(2), s)};
+    const double c2 = sh.c2, s2 = sh.s2;
+#pragma unroll 1
+    for (int a = 0; a < 6; ++a) {
+      const double T = geo_eval(sh.F, qT(a), s);
+      const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
+      const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
+      const int sn = snd_of(a), rc = rcv_of(a);
+      TC y = (TC)0;
+      if (lfa) {
+        const double Tl = P.equal_arms ? P.orb.L_over_c : T;
         int64_t i0;
         double x;
-        split(k, e == 0 ? T + kR[sn] : kR[rc], dt, i0, x);
+        split(k, 0.5 * Tl + 0.5 * (kR[sn] + kR[rc]), dt, i0, x);
         const int64_t b = i0 - N / 2 + 1 - w0;
+        TC vp, vc, v3p = (TC)0, v3c = (TC)0;
         if (b < 0 || b + N > nh) {
           report(P.err, 16, k, b, nh);
-          v[2 * e] = v[2 * e + 1] = (TC)__builtin_nan("");
+          vp = vc = (TC)__builtin_nan("");
         } else {
-          interp2<N, TC>(hwin, b, x, v[2 * e], v[2 * e + 1]);
+          interp2<N, TC>(gwin, b, x, vp, vc);
+          if (nlo) interp2<N, TC>(g3win, b, x, v3p, v3c);
         }
+        TC lf = A * vp + B * vc;
+        if (nlo) {
+          // (T (1 - k.n) / 2)^2 / 6 with 1 - k.n = D / 2
+          const double e = 0.25 * Tl * geo_eval(sh.F, qD(a), s);
+          lf += (TC)(e * e / 6.0) * (A * v3p + B * v3c);
+        }
+        y += (TC)(wp * (-0.5 * Tl)) * lf;
       }
-      const TC Hs = A * v[0] + B * v[1], Hr = A * v[2] + B * v[3];
-      y += (TC)wm * ((Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s));
+      if (full) {
+        TC v[4];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          int64_t i0;
+          double x;
+          split(k, e == 0 ? T + kR[sn] : kR[rc], dt, i0, x);
+          const int64_t b = i0 - N / 2 + 1 - w0;
+          if (b < 0 || b + N > nh) {
+            report(P.err, 16, k, b, nh);
+            v[2 * e] = v[2 * e + 1] = (TC)__builtin_nan("");
+          } else {
+            interp2<N, TC>(hwin, b, x, v[2 * e], v[2 * e + 1]);
+          }
+        }
+        const TC Hs = A * v[0] + B * v[1], Hr = A * v[2] + B * v[3];
+        y += (TC)wm * ((Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s));
+      }
+      Yo[a * stride + S.off + k] = y;
     }
-    Yo[a * stride + S.off + k] = y;
   }
 }
 
