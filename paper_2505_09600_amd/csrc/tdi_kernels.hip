@@ -1276,12 +1276,15 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             const double* __restrict__ hpb = P.hp + off + (j0 - hw);
             const double* __restrict__ hcb = P.hc + off + (j0 - hw);
             double hp_[kSR + 6], hc_[kSR + 6];
+            // the strain loads go out ahead of the other waves' arithmetic
+            __builtin_amdgcn_s_setprio(1);
 #pragma unroll
             for (int m = 0; m < kSR + 6; ++m) {
               const bool in = m >= mlo && m < mhi;
               hp_[m] = in ? hpb[m] : 0.0;
               hc_[m] = in ? hcb[m] : 0.0;
             }
+            __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int e = 0; e < kSR; ++e) {
               // all seven taps: the coefficient rows are zero beyond 2 hw
