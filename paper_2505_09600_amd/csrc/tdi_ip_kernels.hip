@@ -353,6 +353,8 @@ __device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const
   const int cnt = B << S.logN2;
   {
     V z[kIt];
+    // the loads go out ahead of the transform of the other resident workgroup
+    __builtin_amdgcn_s_setprio(1);
     if (N1 == 1) {
       const void* xs = P->x[c];
       const void* ys = P->y[c];
@@ -373,6 +375,7 @@ __device__ __forceinline__ void pass2_task(const IpParams* __restrict__ P, const
         }
       }
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int it = 0; it < kIt; ++it) {
       const int e = threadIdx.x + it * TL::kBlock;
