@@ -1916,6 +1916,8 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
   stencil_coeffs(3, P.stencil_p, st3, hw3, den3);
   const double gscale = 1.0 / (den * dt), g3scale = 1.0 / (den3 * dt * dt * dt);
   const bool nlo = want_lfa && P.lfa_terms == 2;
+  // the window loads go out ahead of the other resident workgroups' arithmetic
+  __builtin_amdgcn_s_setprio(1);
   for (int i = tid; i < nh; i += kBlock) {
     const int64_t j = w0 + i;
     const bool in = j >= 0 && j < S.n;
@@ -1952,6 +1954,7 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
       g3win[2 * i + 1] = (TC)(gc * g3scale);
     }
   }
+  __builtin_amdgcn_s_setprio(0);
   __syncthreads();
   for (int o = tid; o < cnt; o += kBlock) {
     const int64_t k = k0 + o;
