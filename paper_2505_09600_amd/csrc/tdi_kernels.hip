@@ -507,7 +507,7 @@ constexpr size_t wave_tables_bytes() {
 }
 
 template <int N, typename TC>
-__global__ __launch_bounds__(kBlock, 4) void k_lfa(const KParams* __restrict__ Pp) {
+__global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ Pp) {
   const KParams& P = *Pp;
   const SrcDev* __restrict__ SS = sources_of(Pp);
   __shared__ LfaShared sh;
