@@ -1466,7 +1466,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
           // Edge lanes: raw pairs with the coefficients at the output time (the
           // precombined F_l is exact only for band-limited data).  A link's edge
           // lanes hold 2 kFR uses each; they are spread over the 64 lanes of the
-          // wave, 64 per round, and each c * value goes back to its lane by a
+          // wave, 64 at a time, and each c * value goes back to its lane by a
           // shuffle.  After the link loop X = Xc, Y = Xb, Z = Xa, and side 0 of
           // link l feeds channel (l + 2) % 3, side 1 channel (l + 1) % 3.
 #pragma unroll
