@@ -8,7 +8,14 @@ log-uniform chirp mass 1e5..1e7 Msun, synthetic Newtonian chirps with ringdown
 4th-order LFA stencils, hybrid switch where f_GW L / c reaches 0.05,
 T = 800 dt, sigma = T / 40.  Inputs are generated in device memory before the
 timed region.  One step = one tdi_run over the whole batch (graph replay of the
-persistent LFA and full-response kernels).
+persistent LFA and full-response kernels), synchronised after each step;
+ms_per_step is the median step and value = samples / median step.
+
+The line also carries the FP64 full, LFA and hybrid responses of the same batch,
+the roofline of the dominant kernel (algorithmic HBM bytes per launch over its
+median event-timed duration, with the VALU issue rate from the committed
+counter summary when it matches the kernel source) and the FP64 CPU oracle
+timed per mode on one core and on all cores.
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is not supported:
 the response has no multi-GPU path in this build (sources would be sharded
@@ -31,8 +38,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "TDI2 XYZ samples/s (batched, FP32-bulk vs FP64) at ≤1e-5 peak-rel error"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3              # published, with packed FP32
+FP32_NONPACKED_TFLOPS = 78.6          # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (packed FP32 is off)
 FP64_PEAK_TFLOPS = 78.6
+VALU_SIMDS = 256 * 4                  # a wave64 VALU instruction occupies one 16-lane SIMD for 4 cycles
+CLOCK_HZ = 2.4e9
 BYTES_PER_SAMPLE_FP32 = 16 + 12       # read h+, hx (FP64), write X, Y, Z (FP32)
 BYTES_PER_SAMPLE_FP64 = 16 + 24
 TAPS = 32
@@ -53,10 +63,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel_hash: str):
-    """HBM bytes per sample from committed rocprofv3 PMC summaries, if they were
-    taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", "k_lfa_c4_traffic.json")
+def load_counters(kernel_hash: str):
+    """HBM bytes and VALU instructions per launch of the dominant kernel, from the
+    committed rocprofv3 PMC summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "k_lfa_c4_counters.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -65,45 +75,64 @@ def load_traffic(kernel_hash: str):
     return d
 
 
-def cpu_baseline(host_sub, cfg, orb, budget_s: float):
-    """The FP64 oracle on a bounded seeded sample of the same workload: seeded
-    random output indices of a seeded subset of the sources, evaluated with the
-    oracle's sampled-output entry point (OpenMP across sources).  The sample is
-    grown until one timed evaluation takes about a third of the budget or more;
-    a single-source evaluation (one thread) gives the one-core rate."""
+def _oracle_run(oracle, cfg, orb, sub, m, rng):
+    """One oracle evaluation of a contiguous block of m outputs (at a seeded
+    random start) in each source of sub; returns (outputs, seconds)."""
+    lens = [int(sub.offsets[i + 1] - sub.offsets[i]) for i in range(sub.n_sources)]
+    ks = []
+    for n in lens:
+        mm = min(m, n)
+        a = int(rng.integers(0, n - mm + 1))
+        ks.append(np.arange(a, a + mm, dtype=np.int64))
+    t = time.perf_counter()
+    oracle.response_batch_at(cfg, orb, sub, ks)
+    return int(sum(len(k) for k in ks)), time.perf_counter() - t
+
+
+def _oracle_rate(oracle, cfg, orb, sub, target_s, reps, rng):
+    """Median samples/s of `reps` oracle runs, each sized to about target_s."""
+    m = 256
+    while True:
+        nout, el = _oracle_run(oracle, cfg, orb, sub, m, rng)
+        full = all(m >= int(sub.offsets[i + 1] - sub.offsets[i]) for i in range(sub.n_sources))
+        if el >= 0.5 * target_s or full:
+            break
+        m = int(m * min(16.0, max(1.5, target_s / max(el, 1e-3))))
+    rates = [nout / el]
+    for _ in range(reps - 1):
+        nout, el = _oracle_run(oracle, cfg, orb, sub, m, rng)
+        rates.append(nout / el)
+    return float(np.median(rates)), m, nout
+
+
+def cpu_baseline(host_sub, cfg, orb, budget_s: float, modes: dict):
+    """The FP64 oracle, as it stands, on a bounded seeded sample of the batch:
+    contiguous blocks of outputs at seeded random positions of seeded random
+    sources, evaluated with the oracle's sampled-output entry point (OpenMP
+    across sources; a single source runs on one thread).  Each mode is timed at
+    one core (one source) and on all cores (every source of the sample), as the
+    median of five runs; the headline entry is the hybrid TDI 2.0 on all cores."""
     import oracle
     oracle.build(force=False)
     threads = oracle.num_threads()
-    lens = [int(host_sub.offsets[i + 1] - host_sub.offsets[i]) for i in range(host_sub.n_sources)]
-    # one core: a single source runs on one OpenMP thread
     rng = np.random.default_rng(11)
-    probe = host_sub.subset([0])
-    m1 = 512
-    while True:
-        ks = [np.sort(rng.integers(0, lens[0], m1))]
-        t = time.perf_counter()
-        oracle.response_batch_at(cfg, orb, probe, ks)
-        el1 = time.perf_counter() - t
-        if el1 >= 1.0 or m1 >= lens[0]:
-            break
-        m1 = min(lens[0], int(m1 * max(2.0, 1.5 / max(el1, 1e-3))))
-    one_core = m1 / el1
-    # all cores: grow the per-source sample until the run is long enough
-    m = int(max(64, one_core * 0.5 / host_sub.n_sources * min(threads, host_sub.n_sources)))
-    while True:
-        ks = [np.sort(rng.integers(0, n, min(m, n))) for n in lens]
-        nout = int(sum(len(k) for k in ks))
-        t = time.perf_counter()
-        oracle.response_batch_at(cfg, orb, host_sub, ks)
-        el = time.perf_counter() - t
-        if el >= budget_s / 3.0 or m >= max(lens):
-            break
-        m = int(m * min(8.0, max(1.5, 0.5 * budget_s / max(el, 1e-3))))
-    return {"value": nout / el, "unit": "samples/s", "cores": threads, "kind": "oracle",
-            "value_1core": one_core,
-            "sample": f"{nout} seeded-random output samples of {host_sub.n_sources} seeded-random sources "
-                      f"of the batch (FP64 hybrid TDI 2.0 oracle, sampled-output entry point, OpenMP "
-                      f"across sources), {el:.1f} s wall; one core: {m1} samples of one source in {el1:.1f} s"}
+    one = host_sub.subset([0])
+    per = budget_s / (2.0 * 5.0 * len(modes))
+    table = {}
+    for name, c in modes.items():
+        r1, m1, _ = _oracle_rate(oracle, c, orb, one, per, 5, rng)
+        ra, ma, na = _oracle_rate(oracle, c, orb, host_sub, per, 5, rng)
+        table[name] = {"one_core": r1, "all_cores": ra, "block_one_core": m1, "block_all_cores": ma,
+                       "outputs_all_cores": na}
+        print(f"[bench] oracle {name}: {r1:.3g} samples/s on 1 core, {ra:.3g} on {threads}",
+              file=sys.stderr, flush=True)
+    h = table["hybrid tdi2.0"]
+    return {"value": h["all_cores"], "unit": "samples/s", "cores": threads, "kind": "oracle",
+            "value_1core": h["one_core"], "modes": table, "timing": "median of 5 runs per entry",
+            "sample": f"contiguous blocks of {h['block_all_cores']} outputs at seeded random positions in "
+                      f"each of {host_sub.n_sources} seeded random sources of the batch ({h['outputs_all_cores']} "
+                      f"outputs per run; one core: a block of {h['block_one_core']} outputs of one source), "
+                      f"FP64 oracle, sampled-output entry point, OpenMP across sources"}
 
 
 def time_plan(tdi, torch, hp, hc, recs, offsets, cfg, orb, steps, warmup, autotune=True):
@@ -386,7 +415,8 @@ def main():
                          "read from an hourly position table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=30.0, help="upper bound of the timed oracle run (s)")
+    ap.add_argument("--cpu-budget", type=float, default=40.0,
+                    help="about the total time of the timed oracle runs (s), over all modes")
     ap.add_argument("--steps-only", action="store_true", help="only the timed hybrid steps (profiling)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the steps, copy a float32 buffer of this size three times (a plain "
@@ -447,23 +477,28 @@ def main():
     if st != tdi.TDI_OK:
         raise RuntimeError(f"window check failed during warmup: {tdi.tdi_status_str(st)}")
     plan.kernel_times()                               # drop the warmup records
+    # K timed steps; each step is synchronised so that its own wall time is known
     torch.cuda.synchronize()
+    step_s = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
+        a = time.perf_counter()
         plan.run(src, batch.offsets, hp, hc, X, Y, Z)
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        step_s.append(time.perf_counter() - a)
     t1 = time.perf_counter()
     ktimes = plan.kernel_times()
     st = plan.sync()
     if st != tdi.TDI_OK:
         raise RuntimeError(f"window check failed: {tdi.tdi_status_str(st)}")
     launch = plan.describe()
-    finite = bool(torch.isfinite(X[:: max(1, total // 100000)]).all().item())
+    finite = bool(torch.isfinite(X).all().item() and torch.isfinite(Y).all().item()
+                  and torch.isfinite(Z).all().item())
     el = t1 - t0
-    value = total * args.steps / el
-    ms_step = 1e3 * el / args.steps
+    ms_step = 1e3 * float(np.median(step_s))
+    value = total / (ms_step * 1e-3)
     runs = len(ktimes) // 3                           # (fit pre-pass, LFA kernel, full kernel) per run
-    fit_ms, lfa_ms, full_ms = ((float(np.mean(ktimes[j::3][:runs])) for j in range(3)) if runs
+    fit_ms, lfa_ms, full_ms = ((float(np.median(ktimes[j::3][:runs])) for j in range(3)) if runs
                                else (float("nan"),) * 3)
     if args.calib_copy_mib > 0:
         nel = args.calib_copy_mib * (1 << 20) // 4
@@ -481,49 +516,67 @@ def main():
         return
     plan.close()
 
-    print(f"[bench] hybrid FP32-bulk: {ms_step:.2f} ms/step, fit pre-pass {fit_ms:.3f} ms, "
-          f"LFA kernel {lfa_ms:.3f} ms, full kernel {full_ms:.3f} ms, launch {launch}",
-          file=sys.stderr, flush=True)
-    # FP64 plain full response on the same batch (the reference this path must beat)
-    ref = None
+    print(f"[bench] hybrid FP32-bulk: {ms_step:.2f} ms/step (median; mean {1e3 * el / args.steps:.2f}), "
+          f"fit pre-pass {fit_ms:.3f} ms, LFA kernel {lfa_ms:.3f} ms, full kernel {full_ms:.3f} ms, "
+          f"launch {launch}", file=sys.stderr, flush=True)
+    # FP64 on the same batch: the plain full response (the reference this path
+    # must beat), and the FP64 LFA and hybrid of the same configuration
+    fp64 = {}
     if not args.no_fp64_reference:
-        cfg64 = dict(cfg, precision=0, mode=0, tdi_gen=20, taps=TAPS, stencil_order=4)
         X64 = torch.empty(total, dtype=torch.float64, device=dev)
         Y64 = torch.empty_like(X64)
         Z64 = torch.empty_like(X64)
-        p64 = tdi.Plan(cfg64, orb, batch.n_sources, total, autotune=True, use_graph=True)
-        p64.run(src, batch.offsets, hp, hc, X64, Y64, Z64)
-        p64.sync()
-        p64.kernel_times()
-        torch.cuda.synchronize()
-        r0 = time.perf_counter()
-        nref = 2
-        for _ in range(nref):
+        for name, mode in (("full", 0), ("lfa", 1), ("hybrid", 2)):
+            c64 = dict(cfg, precision=0, mode=mode, tdi_gen=20, taps=TAPS, stencil_order=4)
+            p64 = tdi.Plan(c64, orb, batch.n_sources, total, autotune=True, use_graph=True)
             p64.run(src, batch.offsets, hp, hc, X64, Y64, Z64)
-        torch.cuda.synchronize()
-        r1 = time.perf_counter()
-        print(f"[bench] FP64 full reference: {1e3 * (r1 - r0) / nref:.2f} ms/step", file=sys.stderr, flush=True)
-        ref = {"value": total * nref / (r1 - r0), "unit": "samples/s",
-               "ms_per_step": 1e3 * (r1 - r0) / nref,
-               "config": "plain full response, FP64, TDI 2.0, same batch"}
-        p64.close()
+            p64.sync()
+            p64.kernel_times()
+            reps = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                r0 = time.perf_counter()
+                p64.run(src, batch.offsets, hp, hc, X64, Y64, Z64)
+                torch.cuda.synchronize()
+                reps.append(time.perf_counter() - r0)
+            if p64.sync() != tdi.TDI_OK:
+                raise RuntimeError("window check failed (FP64)")
+            p64.close()
+            ms = 1e3 * float(np.median(reps))
+            fp64[name] = {"value": total / (ms * 1e-3), "unit": "samples/s", "ms_per_step": ms,
+                          "config": f"{name} response, FP64, TDI 2.0, same batch, median of 3"}
+            print(f"[bench] FP64 {name}: {ms:.2f} ms/step", file=sys.stderr, flush=True)
         del X64, Y64, Z64
+    ref = fp64.get("full")
 
-    flops = lfa_flops_per_sample(TAPS) * total
-    achieved_tflops = flops / (lfa_ms * 1e-3) / 1e12 if lfa_ms > 0 else float("nan")
+    # roofline of the dominant kernel: HBM (algorithmic 28 B per sample) is the
+    # roof the path is measured against; the VALU issue rate says what binds it
     achieved_gbs = BYTES_PER_SAMPLE_FP32 * total / (lfa_ms * 1e-3) / 1e9 if lfa_ms > 0 else float("nan")
     khash = kernel_source_hash()
-    traffic = load_traffic(khash)
-    roof = {"bound": "alu", "achieved": achieved_tflops, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved_tflops / FP32_PEAK_TFLOPS,
-            "traffic": (traffic["bytes_per_launch"] if traffic else None),
-            "kernel": (("k_lfa_fast<32>" if launch.get("lfa_fast") else "k_lfa<32,float>") +
-                       ("" if launch.get("graph_kernel_events") else " (+ k_full: whole graph replay)")),
-            "kernel_ms": lfa_ms, "fit_kernel_ms": fit_ms, "full_kernel_ms": full_ms,
-            "flops_per_sample": lfa_flops_per_sample(TAPS),
-            "hbm_achieved_gbs": achieved_gbs, "hbm_peak_gbs": HBM_PEAK_GBS,
-            "hbm_frac": achieved_gbs / HBM_PEAK_GBS,
-            "hbm_bytes_per_sample": BYTES_PER_SAMPLE_FP32, "kernel_hash": khash}
+    ctr = load_counters(khash)
+    kname = (("k_lfa_fast<32>" if launch.get("lfa_fast") else "k_lfa<32,float>") +
+             ("" if launch.get("graph_kernel_events") else " (+ k_full: whole graph replay)"))
+    valu = None
+    if ctr:
+        insts = float(ctr["valu_insts_per_launch"])
+        valu = {"insts_per_launch": insts, "lane_slots_per_sample": insts * 64.0 / total,
+                "issue_frac": insts * 4.0 / (VALU_SIMDS * CLOCK_HZ * lfa_ms * 1e-3),
+                "source": "profiles/k_lfa_c4_counters.json (SQ_INSTS_VALU, same kernel source)"}
+    flops = lfa_flops_per_sample(TAPS) * total
+    alg_tflops = flops / (lfa_ms * 1e-3) / 1e12 if lfa_ms > 0 else float("nan")
+    roof = {"bound": "hbm", "achieved": achieved_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved_gbs / HBM_PEAK_GBS,
+            "traffic": (ctr["hbm_bytes_per_launch"] if ctr else None),
+            "kernel": kname, "kernel_ms": lfa_ms, "fit_kernel_ms": fit_ms, "full_kernel_ms": full_ms,
+            "bytes_per_sample": BYTES_PER_SAMPLE_FP32, "samples_per_launch": total,
+            "valu": valu,
+            "algorithmic_fp32": {"flops_per_sample": lfa_flops_per_sample(TAPS), "tflops": alg_tflops,
+                                 "vs_nonpacked_peak": alg_tflops / FP32_NONPACKED_TFLOPS,
+                                 "note": "survey's per-sample count of six two-component 32-tap reads; "
+                                         "the kernel executes fewer flops (one precombined series per "
+                                         "link, shared table weights), so this ratio can exceed 1 and "
+                                         "is not a hardware rate"},
+            "kernel_hash": khash}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -531,11 +584,16 @@ def main():
         order = rng.permutation(batch.n_sources)[:32]
         host_sub = W.config_c4(n_sources=args.n_sources, only=[int(i) for i in order])[0]
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(host_sub, dict(cfg32, precision=0), orb, args.cpu_budget)
+        modes = {"full tdi1.5": dict(cfg32, precision=0, mode=0, tdi_gen=15),
+                 "full tdi2.0": dict(cfg32, precision=0, mode=0, tdi_gen=20),
+                 "lfa tdi2.0": dict(cfg32, precision=0, mode=1, tdi_gen=20),
+                 "hybrid tdi2.0": dict(cfg32, precision=0, mode=2, tdi_gen=20)}
+        cpu = cpu_baseline(host_sub, cfg32, orb, args.cpu_budget, modes)
 
     out = {
         "metric": METRIC, "value": value, "unit": "samples/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "ms_per_step_mean": 1e3 * el / args.steps,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "batched hybrid TDI 2.0, 512 sources, lengths log-uniform 2^18..2^22 at "
@@ -548,10 +606,11 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "fp64_full_reference": ref,
+        "fp64": fp64,
         "speedup_vs_fp64_full": (value / ref["value"]) if ref else None,
+        "speedup_vs_fp64_hybrid": (value / fp64["hybrid"]["value"]) if "hybrid" in fp64 else None,
     }
     print(json.dumps(out), flush=True)
-
 
 if __name__ == "__main__":
     main()

@@ -1,12 +1,16 @@
-"""GPU parity at the benchmark configurations' full sizes, on sampled outputs.
+"""GPU parity at the benchmark configurations' full sizes.
 
-The oracle evaluates the response at selected sample indices (uniform random
-plus a dense window around the peak of each channel and the hybrid switch);
-the HIP library computes every sample.  Per-channel error = max |diff| / max
-|X_oracle| over the sampled indices.  FP64 bar: max(1e-12, 64 u kappa) with the
-conditioning kappa measured by the oracle's absolute-value evaluation; FP32-bulk
-bar: 1e-5 for the LFA and hybrid (the plain FP32 full response is reported
-against max(1e-5, 64 u32 kappa), its own conditioning floor).
+The LFA and hybrid runs of the one-year source (c3) and 32 sources of the
+512-source batch (c4) are compared on every output sample; the plain full
+response of the one-year source (c2) and the sampler-scale subset (c5) on
+sampled outputs (uniform random plus a dense window around the peak of each
+channel, the series ends and the hybrid switch), where the oracle evaluates
+only the selected indices.  Per-channel error = max |diff| / max |X_oracle|
+over the compared samples.  FP64 bar: max(1e-12, 64 u kappa) with the
+conditioning kappa measured by the oracle's absolute-value evaluation on the
+sampled indices; FP32-bulk bar: 1e-5 for the LFA and hybrid.  The plain FP32
+full response of TDI 2.0 (c2) misses 1e-5 by its own conditioning (measured
+1.7e-5 to 1.8e-5 in X and Z): it is held to a fixed 3e-5 and reported.
 """
 import math
 
@@ -16,8 +20,6 @@ import pytest
 from paper_2505_09600_amd import workload as W
 
 pytestmark = pytest.mark.gpu
-
-U32 = 2.0 ** -24
 
 
 @pytest.fixture(scope="module")
@@ -46,25 +48,32 @@ def _sample_indices(n, X_gpu, rng, k_hyb=None, n_uniform=150, half=60):
     return np.array(sorted(k for k in ks if 0 <= k < n), dtype=np.int64)
 
 
-def _check_source(orc, name, cfg, orb, rec, hp, hc, X_gpu, fp32, rng, kappa_bar=False):
+def _check_source(orc, name, cfg, orb, rec, hp, hc, X_gpu, fp32, rng, fixed32=1e-5, every=False,
+                  ref_all=None):
+    """Compare one source; every=True compares all n outputs (ref_all, if given,
+    is the oracle's whole response, else it is computed here), otherwise the
+    sampled indices.  kappa comes from the sampled indices either way."""
     n = len(hp)
     kH = (rec["t_hyb"] - rec["t0"]) / rec["dt"] if cfg["mode"] == 2 else None
     ks = _sample_indices(n, X_gpu, rng, kH)
-    ref = orc.response_at(dict(cfg, precision=0), orb, rec, hp, hc, ks)
-    got = X_gpu[:, ks]
+    if every:
+        ref = ref_all if ref_all is not None else orc.response(dict(cfg, precision=0), orb, rec, hp, hc)
+        got = X_gpu
+        ref_ks = ref[:, ks]
+    else:
+        ref = ref_ks = orc.response_at(dict(cfg, precision=0), orb, rec, hp, hc, ks)
+        got = X_gpu[:, ks]
     peak = np.max(np.abs(ref), axis=1)
     err = np.max(np.abs(got - ref), axis=1) / np.where(peak > 0, peak, 1.0)
-    if fp32 and not kappa_bar:
-        tol = np.full(3, 1e-5)
+    if fp32:
+        tol = np.full(3, fixed32)
         kap = None
-    elif fp32:
-        t64, kap = orc.fp64_tolerance(dict(cfg, precision=0), orb, rec, hp, hc, ks, ref)
-        tol = np.maximum(1e-5, 64 * U32 * kap)
     else:
-        tol, kap = orc.fp64_tolerance(dict(cfg, precision=0), orb, rec, hp, hc, ks, ref)
+        tol, kap = orc.fp64_tolerance(dict(cfg, precision=0), orb, rec, hp, hc, ks, ref_ks)
     ks_txt = "" if kap is None else f" kappa {kap[0]:.1e} {kap[1]:.1e} {kap[2]:.1e}"
-    print(f"[parity] {name}: err X,Y,Z = {err[0]:.3e} {err[1]:.3e} {err[2]:.3e}  tol {tol.max():.1e}{ks_txt}"
-          f"  ({len(ks)} samples of {n})", flush=True)
+    cnt = f"all {n} samples" if every else f"{len(ks)} samples of {n}"
+    print(f"[parity] {name}: err X,Y,Z = {err[0]:.3e} {err[1]:.3e} {err[2]:.3e}  "
+          f"tol {tol[0]:.1e} {tol[1]:.1e} {tol[2]:.1e}{ks_txt}  ({cnt})", flush=True)
     assert np.all(np.isfinite(got))
     assert np.all(err <= tol), (err, tol)
     return err
@@ -87,7 +96,7 @@ def test_c2_full_response_one_year(tdi, orc, c2_batch, prec):
     X = _gpu_single(tdi, cfg, orb, c2_batch)
     rec, hp, hc = c2_batch.source(0)
     _check_source(orc, f"c2 full prec{prec}", cfg, orb, rec, hp, hc, X, prec == 1,
-                  np.random.default_rng(21), kappa_bar=True)
+                  np.random.default_rng(21), fixed32=3e-5)
 
 
 @pytest.mark.parametrize("gen,p,prec", [(15, 2, 0), (15, 4, 1), (20, 2, 1), (20, 4, 0), (20, 4, 1)])
@@ -97,7 +106,7 @@ def test_c3_lfa_one_year(tdi, orc, c2_batch, gen, p, prec):
     X = _gpu_single(tdi, cfg, orb, c2_batch)
     rec, hp, hc = c2_batch.source(0)
     _check_source(orc, f"c3 lfa tdi{gen} p{p} prec{prec}", cfg, orb, rec, hp, hc, X, prec == 1,
-                  np.random.default_rng(22))
+                  np.random.default_rng(22), every=True)
 
 
 @pytest.fixture(scope="module")
@@ -117,14 +126,16 @@ def test_c3_hybrid_one_year(tdi, orc, c3_hybrid_batch, gen, prec):
     X = _gpu_single(tdi, cfg, orb, c3_hybrid_batch)
     rec, hp, hc = c3_hybrid_batch.source(0)
     _check_source(orc, f"c3 hybrid tdi{gen} prec{prec}", cfg, orb, rec, hp, hc, X, prec == 1,
-                  np.random.default_rng(23))
+                  np.random.default_rng(23), every=True)
 
 
+@pytest.mark.timeout(900)
 def test_c4_batch_bench_launch(tdi, orc):
     """512 sources (7.3e8 samples), FP32-bulk hybrid TDI 2.0 with the benchmark's
     launch configuration (autotuned persistent kernels replayed from a graph);
-    sampled parity on a seeded subset of sources including every source whose
-    full-response region is non-empty among the first 64."""
+    every output sample of 32 seeded sources is compared, 24 drawn from the
+    whole batch and the first 8 of those whose full-response region is
+    non-empty."""
     import torch
     dev = torch.device("cuda:0")
     batch, cfg, orb = W.config_c4(xp=torch, device=dev)
@@ -139,15 +150,22 @@ def test_c4_batch_bench_launch(tdi, orc):
         desc = plan.describe()
     assert desc["graph"] == 1 and desc["grid_lfa"] > 0
     rng = np.random.default_rng(24)
-    hybrid_srcs = [i for i in range(64) if math.isfinite(batch.sources[i]["t_hyb"])]
-    chosen = sorted(set(rng.choice(batch.n_sources, 10, replace=False).tolist() + hybrid_srcs[:6]))
-    for i in chosen:
+    hybrid_srcs = [i for i in range(batch.n_sources) if math.isfinite(batch.sources[i]["t_hyb"])]
+    drawn = set(rng.choice(batch.n_sources, 24, replace=False).tolist())
+    chosen = sorted(drawn | set([i for i in hybrid_srcs if i not in drawn][:8]))
+    assert len(chosen) == 32 and sum(1 for i in chosen if i in hybrid_srcs) >= 8
+    sub = batch.subset(chosen)               # the same input arrays, copied to the host
+    print(f"[parity] c4: oracle over {sub.total} samples of {len(chosen)} sources", flush=True)
+    ref = orc.response_batch(dict(cfg, mode=2, precision=0), orb, sub)
+    for j, i in enumerate(chosen):
         a, b = int(batch.offsets[i]), int(batch.offsets[i + 1])
+        sa, sb = int(sub.offsets[j]), int(sub.offsets[j + 1])
         rec = batch.sources[i]
         out = np.stack([X[a:b].double().cpu().numpy(), Y[a:b].double().cpu().numpy(),
                         Z[a:b].double().cpu().numpy()])
-        _check_source(orc, f"c4 src{i} n={b - a}", dict(cfg, mode=2), orb, rec, hp[a:b].cpu().numpy(),
-                      hc[a:b].cpu().numpy(), out, True, rng)
+        _check_source(orc, f"c4 src{i} n={b - a}" + (" (full region)" if i in hybrid_srcs else ""),
+                      dict(cfg, mode=2), orb, rec, sub.hp[sa:sb], sub.hc[sa:sb], out, True, rng,
+                      every=True, ref_all=ref[:, sa:sb])
 
 
 @pytest.mark.parametrize("prec", [1, 0])
