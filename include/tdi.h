@@ -158,6 +158,27 @@ tdi_status tdi_run(tdi_plan* plan, int64_t n_sources, const tdi_source* src,
                    const int64_t* offsets, const double* hp, const double* hc,
                    void* X, void* Y, void* Z);
 
+/* Allocation-free variant of tdi_run, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): no plan, and no hipMalloc, hipFree or other allocating
+ * call.  The parameter block, work counters, window-check words and the fast
+ * LFA path's per-tile records live in a static device array of about 8.4 MB
+ * that each GPU holds from the first call on it until the process ends.
+ * Same computation, arguments and layouts as tdi_run, with the batch, config
+ * and orbit passed directly; hip_stream is a hipStream_t (NULL = default
+ * stream) on the current device, and the call is asynchronous on it.
+ * Limits: at most 256 sources and 2048 fast-LFA tiles (tiles of
+ * 2304 * fast_tile_chunks outputs, chunks 0 meaning 4), else TDI_ESTATE;
+ * TABLE orbits give TDI_EUNSUPPORTED.  autotune and use_graph are ignored
+ * (persistent grids at full occupancy, no graph).  A retarded-time window
+ * that leaves the staged range writes NaN outputs (there is no plan to
+ * report it through).  Every call on one GPU shares that GPU's array: calls
+ * whose device work overlaps (other streams, other host threads' streams)
+ * race and give undefined outputs; calls ordered on one stream are safe. */
+tdi_status tdi_run_noalloc(const tdi_config* cfg, const tdi_orbit* orb, int64_t n_sources,
+                           const tdi_source* src, const int64_t* offsets, const double* hp,
+                           const double* hc, void* X, void* Y, void* Z, void* hip_stream);
+
 /* Enqueue the six single-link outputs of one batch on the plan's stream
  * (asynchronous), in the plan's mode, precision, taps, stencil order and
  * hybrid window:

@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/tdi.h"
@@ -265,13 +266,50 @@ int lfa_tile(const Caps& caps, const Launch& ln) {
   return caps.fast ? std::min(std::max(ln.chunks, 1), 4) * tdi::kFastChunk : caps.tile_lfa;
 }
 
+// Constant part of the parameter block: orbit, TDI generation, mode, stencil,
+// hybrid window (dtab: device copy of a TABLE orbit's samples, else null).
+void fill_constants(tdi::KParams& kp, const tdi_config& c, const tdi_orbit& o, const OrbitBounds& ob,
+                    const double* dtab) {
+  tdi::OrbitDev& od = kp.orb;
+  od.kind = o.kind;
+  od.L = o.L_m;
+  od.R = o.R_m;
+  od.omega = o.omega;
+  od.kappa0 = o.kappa0;
+  od.t_freeze = o.t_freeze;
+  od.e = o.L_m / (2.0 * sqrt(3.0) * o.R_m);
+  for (int i = 0; i < 3; ++i) {
+    const double b = 2.0 * M_PI * (double)i / 3.0 + o.lambda0;
+    od.cb[i] = cos(b);
+    od.sb[i] = sin(b);
+  }
+  od.L_over_c = o.L_m / kC;
+  if (o.kind == TDI_ORBIT_TABLE) {
+    od.tab = dtab;
+    od.ntab = o.n_table;
+    od.tab_t0 = o.table_t0;
+    od.tab_idt = 1.0 / o.table_dt;
+    od.R = ob.rmax;
+    od.e = 0.0;
+  }
+  kp.gen = c.tdi_gen;
+  kp.mode = c.mode;
+  kp.aet = c.channels == TDI_CHANNELS_AET ? 1 : 0;
+  kp.lfa_terms = c.lfa_terms == 2 ? 2 : 1;
+  kp.nested = c.nested_delays;
+  kp.equal_arms = c.lfa_equal_arms;
+  kp.stencil_m = c.tdi_gen == 20 ? 3 : 2;
+  kp.stencil_p = c.stencil_order;
+  kp.T_s = c.hyb_T_samples;
+  kp.sigma_s = c.hyb_sigma_samples;
+  kp.D2_bound = stage2_bound(c, ob);
+}
+
 // Fill the pinned parameter image for one batch (work lists of both kernels).
-void stage_batch(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
-                 const double* hp, const double* hc, void* X, void* Y, void* Z, const Caps& caps,
-                 const Launch& ln) {
-  tdi::KParams* kp = p->h_params;
+void stage_batch(const tdi_config& c, tdi::KParams* kp, int64_t n_sources, const tdi_source* src,
+                 const int64_t* offsets, const double* hp, const double* hc, void* X, void* Y, void* Z,
+                 const Caps& caps, const Launch& ln) {
   tdi::SrcDev* sd = reinterpret_cast<tdi::SrcDev*>(kp + 1);
-  const tdi_config& c = p->cfg;
   const int tile_lfa = lfa_tile(caps, ln);
   int64_t tl = 0, tf = 0;
   for (int64_t i = 0; i < n_sources; ++i) {
@@ -440,8 +478,8 @@ void advance_ring(tdi_plan* p) {
 
 // Window capacities for a batch (smallest step) and the LFA kernel choice
 // (largest step); false for a batch without samples.
-bool batch_caps(const tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
-                Caps* caps) {
+bool batch_caps(const tdi_config& cfg, const OrbitBounds& ob, int64_t n_sources, const tdi_source* src,
+                const int64_t* offsets, Caps* caps) {
   double dt_min = INFINITY, dt_max = 0.0;
   for (int64_t i = 0; i < n_sources; ++i)
     if (offsets[i + 1] > offsets[i]) {
@@ -449,7 +487,7 @@ bool batch_caps(const tdi_plan* p, int64_t n_sources, const tdi_source* src, con
       dt_max = std::max(dt_max, src[i].dt);
     }
   if (!isfinite(dt_min)) return false;
-  *caps = window_caps(p->cfg, p->ob, dt_min, fast_lfa(p->cfg, p->ob, dt_max));
+  *caps = window_caps(cfg, ob, dt_min, fast_lfa(cfg, ob, dt_max));
   return true;
 }
 
@@ -457,7 +495,7 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
                     const int64_t* offsets, const double* hp, const double* hc, void* X, void* Y,
                     void* Z, bool record, bool allow_graph) {
   Caps caps;
-  if (!batch_caps(p, n_sources, src, offsets, &caps)) return TDI_OK;
+  if (!batch_caps(p->cfg, p->ob, n_sources, src, offsets, &caps)) return TDI_OK;
   if (caps.lds_lfa > p->max_lds || caps.lds_full > p->max_lds) return TDI_ERANGE;
   p->last_fast = caps.fast;
   p->last_tile_lfa = lfa_tile(caps, ln);
@@ -467,7 +505,7 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
     if (hipEventSynchronize(p->staged_free) != hipSuccess) return TDI_EDEVICE;
     p->staged_pending = false;
   }
-  stage_batch(p, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
+  stage_batch(p->cfg, p->h_params, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
   const int64_t tl = p->h_params->n_tiles_lfa, tf = p->h_params->n_tiles_full;
   // per-tile records of the fast path: tiles hold at least kFastChunk outputs,
   // so a batch within the plan's maxima always fits; checked all the same
@@ -530,7 +568,7 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
 void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
               const double* hp, const double* hc, void* X, void* Y, void* Z) {
   Caps caps;
-  if (!batch_caps(p, n_sources, src, offsets, &caps)) return;
+  if (!batch_caps(p->cfg, p->ob, n_sources, src, offsets, &caps)) return;
   const int ol = tdi::occupancy_lfa(p->cfg.interp_taps, p->cfg.precision, caps.fast, caps.lds_lfa);
   const int of = tdi::occupancy_full(p->cfg.interp_taps, p->cfg.precision, caps.lds_full);
   // grid candidates (persistent at the resident count, half and twice that, or
@@ -644,25 +682,6 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   }
   memset(p->h_params, 0, p->params_bytes);
 
-  // constant part of the parameter block
-  tdi::KParams& kp = *p->h_params;
-  kp.err = p->d_err;
-  kp.lfa_tiles = p->d_ftiles;
-  kp.counters = p->d_counters;
-  tdi::OrbitDev& od = kp.orb;
-  od.kind = orb->kind;
-  od.L = orb->L_m;
-  od.R = orb->R_m;
-  od.omega = orb->omega;
-  od.kappa0 = orb->kappa0;
-  od.t_freeze = orb->t_freeze;
-  od.e = orb->L_m / (2.0 * sqrt(3.0) * orb->R_m);
-  for (int i = 0; i < 3; ++i) {
-    const double b = 2.0 * M_PI * (double)i / 3.0 + orb->lambda0;
-    od.cb[i] = cos(b);
-    od.sb[i] = sin(b);
-  }
-  od.L_over_c = orb->L_m / kC;
   if (orb->kind == TDI_ORBIT_TABLE) {
     const size_t tb = sizeof(double) * 9 * (size_t)orb->n_table;
     if (hipMalloc((void**)&p->d_orbtab, tb) != hipSuccess) {
@@ -673,24 +692,11 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
       tdi_plan_destroy(p);
       return TDI_EDEVICE;
     }
-    od.tab = p->d_orbtab;
-    od.ntab = orb->n_table;
-    od.tab_t0 = orb->table_t0;
-    od.tab_idt = 1.0 / orb->table_dt;
-    od.R = p->ob.rmax;
-    od.e = 0.0;
   }
-  kp.gen = cfg->tdi_gen;
-  kp.mode = cfg->mode;
-  kp.aet = cfg->channels == TDI_CHANNELS_AET ? 1 : 0;
-  kp.lfa_terms = cfg->lfa_terms == 2 ? 2 : 1;
-  kp.nested = cfg->nested_delays;
-  kp.equal_arms = cfg->lfa_equal_arms;
-  kp.stencil_m = cfg->tdi_gen == 20 ? 3 : 2;
-  kp.stencil_p = cfg->stencil_order;
-  kp.T_s = cfg->hyb_T_samples;
-  kp.sigma_s = cfg->hyb_sigma_samples;
-  kp.D2_bound = stage2_bound(*cfg, p->ob);
+  fill_constants(*p->h_params, *cfg, *orb, p->ob, p->d_orbtab);
+  p->h_params->err = p->d_err;
+  p->h_params->lfa_tiles = p->d_ftiles;
+  p->h_params->counters = p->d_counters;
 
   p->launch = {0, 0, cfg->fast_tile_chunks != 0 ? cfg->fast_tile_chunks : 4};
   p->tuned = cfg->autotune ? false : true;
@@ -850,6 +856,146 @@ tdi_status tdi_plan_describe(const tdi_plan* p, char* buf, int32_t buflen) {
            (p->cfg.use_graph && p->launch.grid_lfa > 0 && p->launch.grid_full > 0) ? 1 : 0,
            p->graph_timed ? 1 : 0, p->n_cu,
            p->tuned ? 1 : 0, p->last_fast);
+  return TDI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free entry point.  The memory that a plan allocates for a run
+// (parameter block, window-check words, work counters, per-tile records of the
+// fast LFA path) lives instead in one file-scope device array, `scratch`, of
+// which every GPU holds its own copy.  Host code never passes the array's
+// name to a kernel: it takes each device's address once with
+// hipGetSymbolAddress and uses that.  The parameter block travels as kernel
+// arguments of a small copy kernel (no host staging buffer that must outlive
+// the call), and the counters and check words are cleared the same way.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int64_t kNaMaxSources = 256;
+constexpr int64_t kNaMaxTiles = 2048;
+constexpr int kNaMaxDevices = 64;
+constexpr size_t kNaErrOff = 0;            // 8 window-check words (int32)
+constexpr size_t kNaCntOff = 256;          // work counters of the persistent kernels
+constexpr size_t kNaParOff = 512;          // KParams followed by SrcDev[kNaMaxSources]
+constexpr size_t kNaParBytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)kNaMaxSources;
+constexpr size_t kNaTileOff = (kNaParOff + kNaParBytes + 255) / 256 * 256;
+constexpr size_t kNaBytes = kNaTileOff + (size_t)kNaMaxTiles * tdi::kFastTileBytesMax;
+constexpr int kPutWords = 512;             // 2 KB of payload per copy-kernel launch
+
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+struct PutArgs {
+  uint32_t w[kPutWords];
+  uint32_t n;                              // words to write
+};
+
+__global__ void k_put(uint32_t* __restrict__ dst, PutArgs a) {
+  for (uint32_t i = threadIdx.x; i < a.n; i += blockDim.x) dst[i] = a.w[i];
+}
+
+struct NaDevice {
+  bool ready;
+  unsigned char* ptr;                      // this device's address of scratch
+  int n_cu;
+  size_t max_lds;
+};
+
+NaDevice g_na[kNaMaxDevices];
+std::mutex g_na_mu;
+// host image of the cleared words and the parameter block, written under g_na_mu
+alignas(16) unsigned char g_na_image[kNaParOff + kNaParBytes];
+
+// Once per device, with that device current: gfx950 check, constant tables and
+// the device address of scratch.
+tdi_status na_setup(int dev) {
+  NaDevice& d = g_na[dev];
+  if (d.ready) return TDI_OK;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return TDI_EDEVICE;
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0) return TDI_EDEVICE;
+  if (tdi::set_constants() != 0) return TDI_EDEVICE;
+  void* ptr = nullptr;
+  if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return TDI_EDEVICE;
+  d.ptr = static_cast<unsigned char*>(ptr);
+  d.n_cu = prop.multiProcessorCount;
+  d.max_lds = prop.sharedMemPerBlock;
+  d.ready = true;
+  return TDI_OK;
+}
+
+// Copy `bytes` (a multiple of 4) of the host image to dst by kernel arguments.
+bool na_put(uint32_t* dst, const unsigned char* src, size_t bytes, hipStream_t st) {
+  PutArgs a;
+  const size_t words = bytes / 4;
+  for (size_t w0 = 0; w0 < words; w0 += kPutWords) {
+    a.n = (uint32_t)std::min<size_t>(kPutWords, words - w0);
+    memcpy(a.w, src + 4 * w0, 4 * (size_t)a.n);
+    hipLaunchKernelGGL(k_put, dim3(1), dim3(256), 0, st, dst + w0, a);
+    if (hipGetLastError() != hipSuccess) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdi_status tdi_run_noalloc(const tdi_config* cfg, const tdi_orbit* orb, int64_t n_sources,
+                           const tdi_source* src, const int64_t* offsets, const double* hp,
+                           const double* hc, void* X, void* Y, void* Z, void* hip_stream) {
+  tdi_status st = tdi_check_config(cfg, orb);
+  if (st != TDI_OK) return st;
+  if (orb->kind == TDI_ORBIT_TABLE) return TDI_EUNSUPPORTED;
+  if (cfg->lfa_terms == 2 && cfg->mode != TDI_MODE_FULL) return TDI_EUNSUPPORTED;
+  st = tdi_check_batch(cfg, n_sources, src, offsets);
+  if (st != TDI_OK) return st;
+  if (n_sources > kNaMaxSources) return TDI_ESTATE;
+  const int64_t total = offsets[n_sources];
+  if (total == 0) return TDI_OK;
+  if (!hp || !hc || !X || !Y || !Z) return TDI_EINVAL;
+  const uintptr_t al = cfg->precision == TDI_FP64 ? 8 : 4;
+  if (((uintptr_t)hp | (uintptr_t)hc) & 7) return TDI_EINVAL;
+  if ((((uintptr_t)X) | ((uintptr_t)Y) | ((uintptr_t)Z)) & (al - 1)) return TDI_EINVAL;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return TDI_EDEVICE;
+  if (dev >= kNaMaxDevices) return TDI_EUNSUPPORTED;
+
+  std::lock_guard<std::mutex> lock(g_na_mu);
+  st = na_setup(dev);
+  if (st != TDI_OK) return st;
+  const NaDevice& d = g_na[dev];
+  const OrbitBounds ob = orbit_bounds(*orb);
+  Caps caps;
+  if (!batch_caps(*cfg, ob, n_sources, src, offsets, &caps)) return TDI_OK;
+  if (caps.lds_lfa > d.max_lds || caps.lds_full > d.max_lds) return TDI_ERANGE;
+  const int taps = cfg->interp_taps, fp32 = cfg->precision;
+  Launch ln;
+  ln.grid_lfa = tdi::occupancy_lfa(taps, fp32, caps.fast, caps.lds_lfa) * d.n_cu;
+  ln.grid_full = tdi::occupancy_full(taps, fp32, caps.lds_full) * d.n_cu;
+  ln.chunks = cfg->fast_tile_chunks != 0 ? cfg->fast_tile_chunks : 4;
+
+  memset(g_na_image, 0, sizeof(g_na_image));
+  tdi::KParams* kp = reinterpret_cast<tdi::KParams*>(g_na_image + kNaParOff);
+  fill_constants(*kp, *cfg, *orb, ob, nullptr);
+  stage_batch(*cfg, kp, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
+  if (caps.fast && kp->n_tiles_lfa > kNaMaxTiles) return TDI_ESTATE;
+  kp->err = reinterpret_cast<int32_t*>(d.ptr + kNaErrOff);
+  kp->counters = reinterpret_cast<uint32_t*>(d.ptr + kNaCntOff);
+  kp->lfa_tiles = d.ptr + kNaTileOff;
+  const tdi::KParams* dp = reinterpret_cast<const tdi::KParams*>(d.ptr + kNaParOff);
+
+  // cleared check words and counters, then the parameter block, in one image
+  hipStream_t s = (hipStream_t)hip_stream;
+  const size_t bytes = kNaParOff + sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)n_sources;
+  if (!na_put(reinterpret_cast<uint32_t*>(d.ptr), g_na_image, (bytes + 3) / 4 * 4, s)) return TDI_EDEVICE;
+  if (kp->n_tiles_lfa > 0) {
+    if (caps.fast && tdi::launch_lfa_fit(dp, taps, 4 * d.n_cu, s) != 0) return TDI_EDEVICE;
+    if (tdi::launch_lfa(dp, taps, fp32, caps.fast, ln.grid_lfa, caps.lds_lfa, s) != 0) return TDI_EDEVICE;
+  }
+  if (kp->n_tiles_full > 0 && tdi::launch_full(dp, taps, fp32, ln.grid_full, caps.lds_full, s) != 0)
+    return TDI_EDEVICE;
   return TDI_OK;
 }
 

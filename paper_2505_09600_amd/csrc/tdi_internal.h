@@ -24,6 +24,7 @@ constexpr int kFastOutPerLane = 9;
 constexpr int kWGrid = 16;                 // Lagrange Taylor table: rows per unit offset
 constexpr double kFastDtMax = 40.0;        // s: quadratic chunk models stay below 1e-6 relative
 constexpr double kFastRateMax = 2.0e-4;    // bound of |d delay / dt| for the offset expansions
+constexpr size_t kFastTileBytesMax = 4096;  // bound of the fast path's per-tile record (checked in the kernels)
 constexpr int kTileLinks = 1024;           // link outputs: outputs per tile (kTileLinks / kBlock per thread)
 
 // Orbit constants prepared once per plan.

@@ -908,6 +908,7 @@ struct FastTile {
   FastChunk C[4];
 };
 static_assert(sizeof(FastChunk) % 8 == 0 && sizeof(FastTile) % 8 == 0, "record alignment");
+static_assert(sizeof(FastTile) <= kFastTileBytesMax, "tile record bound");
 constexpr int kChunkWords = (int)(sizeof(FastChunk) / 4);
 
 // Geometry sample points of a chunk: 0-11 the first, middle and last output

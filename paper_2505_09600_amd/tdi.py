@@ -23,7 +23,8 @@ TDI_MODE_FULL, TDI_MODE_LFA, TDI_MODE_HYBRID = 0, 1, 2
 TDI_FP64, TDI_FP32_BULK = 0, 1
 TDI_CHANNELS_XYZ, TDI_CHANNELS_AET = 0, 1
 
-EXPORTED = ["tdi_check_config", "tdi_check_batch", "tdi_plan_create", "tdi_run", "tdi_run_links",
+EXPORTED = ["tdi_check_config", "tdi_check_batch", "tdi_plan_create", "tdi_run", "tdi_run_noalloc",
+            "tdi_run_links",
             "tdi_plan_sync",
             "tdi_plan_kernel_times", "tdi_plan_describe", "tdi_plan_destroy", "tdi_status_str",
             "tdi_check_noise", "tdi_ip_plan_create", "tdi_ip_run", "tdi_ip_kernel_times",
@@ -87,6 +88,8 @@ def lib():
                                       C.c_int64, C.c_int64, P]
         L.tdi_run.argtypes = [P, C.c_int64, C.POINTER(tdi_source), C.POINTER(C.c_int64),
                               P, P, P, P, P]
+        L.tdi_run_noalloc.argtypes = [C.POINTER(tdi_config), C.POINTER(tdi_orbit), C.c_int64,
+                                      C.POINTER(tdi_source), C.POINTER(C.c_int64), P, P, P, P, P, P]
         L.tdi_run_links.argtypes = [P, C.c_int64, C.POINTER(tdi_source), C.POINTER(C.c_int64), P, P, P]
         L.tdi_plan_sync.argtypes = [P]
         L.tdi_plan_kernel_times.argtypes = [P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
@@ -135,6 +138,15 @@ def tdi_run(plan, n_sources: int, src, offsets, hp_ptr: int, hc_ptr: int, x_ptr:
     return lib().tdi_run(plan, int(n_sources), src, offs.ctypes.data_as(C.POINTER(C.c_int64)),
                          C.c_void_p(hp_ptr), C.c_void_p(hc_ptr), C.c_void_p(x_ptr),
                          C.c_void_p(y_ptr), C.c_void_p(z_ptr))
+
+
+def tdi_run_noalloc(cfg: tdi_config, orb: tdi_orbit, n_sources: int, src, offsets, hp_ptr: int,
+                    hc_ptr: int, x_ptr: int, y_ptr: int, z_ptr: int, stream: int = 0) -> int:
+    offs = np.ascontiguousarray(offsets, dtype=np.int64)
+    return lib().tdi_run_noalloc(C.byref(cfg), C.byref(orb), int(n_sources), src,
+                                 offs.ctypes.data_as(C.POINTER(C.c_int64)), C.c_void_p(hp_ptr),
+                                 C.c_void_p(hc_ptr), C.c_void_p(x_ptr), C.c_void_p(y_ptr),
+                                 C.c_void_p(z_ptr), C.c_void_p(stream))
 
 
 def tdi_run_links(plan, n_sources: int, src, offsets, hp_ptr: int, hc_ptr: int, y_ptr: int) -> int:

@@ -222,3 +222,31 @@ def test_table_orbit_validation(L):
     o = T.make_orbit(_table_orb())
     o.table = None
     assert T.tdi_check_config(c, o) == T.TDI_EINVAL
+
+
+def test_noalloc_host_checks_before_device(L):
+    """tdi_run_noalloc: every argument error and limit is reported before any
+    device call (fake device addresses are never touched)."""
+    src = T.make_sources(_recs(3))
+    offs = [0, 100, 200, 300]
+    fake = 1 << 20
+    cfg, orb = _cfg(), _orb()
+    run = T.tdi_run_noalloc
+    assert L.tdi_run_noalloc(None, None, 0, None, None, None, None, None, None, None, None) == T.TDI_EINVAL
+    assert run(_cfg(tdi_gen=7), orb, 3, src, offs, fake, fake, fake, fake, fake) == T.TDI_EUNSUPPORTED
+    assert run(cfg, orb, 3, src, [0, 100, 50, 300], fake, fake, fake, fake, fake) == T.TDI_EINVAL
+    assert run(cfg, orb, 3, src, offs, 0, fake, fake, fake, fake) == T.TDI_EINVAL
+    assert run(cfg, orb, 3, src, offs, fake + 4, fake, fake, fake, fake) == T.TDI_EINVAL
+    assert run(cfg, orb, 0, None, [0], 0, 0, 0, 0, 0) == T.TDI_OK
+    # the static scratch holds at most 256 sources
+    big = T.make_sources(_recs(257))
+    assert run(cfg, orb, 257, big, np.arange(258) * 10, fake, fake, fake, fake, fake) == T.TDI_ESTATE
+    # sampled orbits need a device table: not available without allocation
+    tab = W.keplerian_orbit_table(0.0, 1.0e4, 64)
+    torb = T.make_orbit(W.table_orbit(tab, 0.0, 1.0e4))
+    assert run(cfg, torb, 3, src, offs, fake, fake, fake, fake, fake) == T.TDI_EUNSUPPORTED
+    # the next term of the LFA is refused for X, Y, Z as by tdi_run
+    assert run(_cfg(lfa_terms=2), orb, 3, src, offs, fake, fake, fake, fake, fake) == T.TDI_EUNSUPPORTED
+    import torch
+    if not torch.cuda.is_available():
+        assert run(cfg, orb, 3, src, offs, fake, fake, fake, fake, fake) == T.TDI_EDEVICE
