@@ -217,6 +217,11 @@ double orc_lagrange(const double* s, int64_t n, int64_t i0, double x, int N) {
  * -h..h, numerator / denominator.
  * ------------------------------------------------------------------------- */
 static int stencil_coeffs(int m, int p, double* num, double* den) {
+  /* orders 4 and 5: the strain derivatives of the next LFA term */
+  if (m == 4 && p == 2) { double c[] = {1, -4, 6, -4, 1}; memcpy(num, c, sizeof c); *den = 1; return 2; }
+  if (m == 4 && p == 4) { double c[] = {-1, 12, -39, 56, -39, 12, -1}; memcpy(num, c, sizeof c); *den = 6; return 3; }
+  if (m == 5 && p == 2) { double c[] = {-1, 4, -5, 0, 5, -4, 1}; memcpy(num, c, sizeof c); *den = 2; return 3; }
+  if (m == 5 && p == 4) { double c[] = {1, -9, 26, -29, 0, 29, -26, 9, -1}; memcpy(num, c, sizeof c); *den = 6; return 4; }
   if (m == 1 && p == 2) { double c[] = {-1, 0, 1}; memcpy(num, c, sizeof c); *den = 2; return 1; }
   if (m == 1 && p == 4) { double c[] = {1, -8, 0, 8, -1}; memcpy(num, c, sizeof c); *den = 12; return 2; }
   if (m == 2 && p == 2) { double c[] = {1, -2, 1}; memcpy(num, c, sizeof c); *den = 1; return 1; }
@@ -236,7 +241,7 @@ static double stencil_at(const double* h, int64_t n, int64_t i, const double* nu
 }
 
 void orc_stencil(const double* h, int64_t n, int m, int p, double dt, double* g) {
-  double num[7], den;
+  double num[9], den;
   int hw = stencil_coeffs(m, p, num, &den);
   if (hw < 0) { for (int64_t i = 0; i < n; ++i) g[i] = NAN; return; }
   double scale = den * pow(dt, (double)m);
@@ -335,6 +340,7 @@ typedef struct {
   double* gc;
   unsigned char* g_ok;
   int m;              /* LFA derivative order */
+  void* nt;           /* LFA with the next term: context of derivative order m + 2 */
 } orc_ctx;
 
 static void ctx_init(orc_ctx* x, const orc_config* c, const orc_orbit* o, const orc_source* s,
@@ -350,11 +356,23 @@ static void ctx_init(orc_ctx* x, const orc_config* c, const orc_orbit* o, const 
   }
   x->y = NULL; x->y_ok = NULL; x->gp = NULL; x->gc = NULL; x->g_ok = NULL;
   x->m = (c->tdi_gen == 20) ? 3 : 2;
+  x->nt = NULL;
 }
 
 static void ctx_free(orc_ctx* x) {
   free(x->hp_ssb); free(x->hc_ssb); free(x->y); free(x->y_ok);
   free(x->gp); free(x->gc); free(x->g_ok);
+  if (x->nt) { ctx_free((orc_ctx*)x->nt); free(x->nt); }
+}
+
+/* X, Y, Z LFA with the next term (lfa_terms = 2): a second context holding the
+ * derivative series of order m + 2 of the same source. */
+static void ctx_next_term(orc_ctx* x, int64_t n, const double* hp, const double* hc) {
+  if (x->c->lfa_terms != 2 || x->c->mode == ORC_FULL) return;
+  orc_ctx* t = (orc_ctx*)malloc(sizeof(orc_ctx));
+  ctx_init(t, x->c, x->o, x->s, n, hp, hc);
+  t->m = x->m + 2;
+  x->nt = t;
 }
 
 static double t_of(const orc_ctx* x, int64_t k) { return x->s->t0 + (double)k * x->s->dt; }
@@ -487,7 +505,7 @@ static void ensure_g_range(orc_ctx* x, int64_t lo, int64_t hi) {
   ensure_g_alloc(x);
   if (lo < 0) lo = 0;
   if (hi > x->n) hi = x->n;
-  double num[7], den;
+  double num[9], den;
   int hw = stencil_coeffs(x->m, x->c->stencil_order, num, &den);
   double scale = den * pow(x->s->dt, (double)x->m);
   for (int64_t i = lo; i < hi; ++i) {
@@ -524,9 +542,31 @@ static double Xi(orc_ctx* x, const orc_geom* g, int l, int64_t k, double d) {
  * where Xi^(m) interpolates the m-th strain derivative taken on the grid by a
  * central stencil (derivative first, then fractional delay).  Equal arms set
  * every T_i to L/c.  Y, Z: links (2,3) -> (3,1) -> (1,2). */
+/* Next term (lfa_terms = 2), from the same central expansion carried one order
+ * further.  Expanding the eight terms of Eqs. (X1.5l2), (X1.5l3) about their
+ * group centres to third order in the delays, with the two-term link series of
+ * Eq. (yslr_with_tau_derivatives) and the link-reversal symmetry of the delays
+ * used for Eq. (X15_nonequal_timedelays), gives for the link-2 group of X
+ *   -2 T2 T3 [Xi_2^(2) + kappa_2 Xi_2^(4)](k; T2+T3+mu_2),
+ *   kappa_2 = T3^2/6 + T2^2/8 + T2^2 (1 + (k.n_2)^2)/24:
+ * T3^2/6 + T2^2/8 from the third-order terms of the TDI combination, the last
+ * term the m = 1 link term [T2 (1 -+ k.n_2)/2]^2/6 averaged over the two
+ * directions of arm 2.  TDI 2.0 follows from X2.0(t) = X1.5(t) - X1.5(t - D),
+ * D = 2(T2+T3) (constant link-symmetric delays), expanded about t - D/2 to
+ * third order: the same form with m = 3 and kappa + (T2+T3)^2/6.  The link-3
+ * group exchanges T2 and T3.  What remains is third order in 2 pi f L/c and
+ * proportional to k.n (the link asymmetry of the m = 1 terms), fourth order
+ * when k.n vanishes on both arms. */
+static double lfa_kappa(int gen, double Tl, double To, double kn) {
+  double kap = To * To / 6.0 + Tl * Tl / 8.0 + Tl * Tl * (1.0 + kn * kn) / 24.0;
+  if (gen == 20) kap += (Tl + To) * (Tl + To) / 6.0;
+  return kap;
+}
+
 static void lfa_at(orc_ctx* x, int64_t k, double out[3]) {
   orc_geom g;
   orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, k), &g);
+  orc_ctx* nt = (orc_ctx*)x->nt;
   for (int c = 0; c < 3; ++c) {
     int la = (c + 1) % 3 + 1, lb = (c + 2) % 3 + 1;
     double Ta = x->c->equal_arms ? x->o->L / ORC_C : g.T[la - 1];
@@ -534,7 +574,13 @@ static void lfa_at(orc_ctx* x, int64_t k, double out[3]) {
     double pref, d;
     if (x->c->tdi_gen == 20) { pref = -4.0 * Ta * Tb * (Ta + Tb); d = 2.0 * (Ta + Tb); }
     else { pref = -2.0 * Ta * Tb; d = Ta + Tb; }
-    out[c] = pref * (Xi(x, &g, la, k, d + g.mu[la - 1]) - Xi(x, &g, lb, k, d + g.mu[lb - 1]));
+    double va = Xi(x, &g, la, k, d + g.mu[la - 1]);
+    double vb = Xi(x, &g, lb, k, d + g.mu[lb - 1]);
+    if (nt) {
+      va += lfa_kappa(x->c->tdi_gen, Ta, Tb, g.kn[la - 1]) * Xi(nt, &g, la, k, d + g.mu[la - 1]);
+      vb += lfa_kappa(x->c->tdi_gen, Tb, Ta, g.kn[lb - 1]) * Xi(nt, &g, lb, k, d + g.mu[lb - 1]);
+    }
+    out[c] = pref * (va - vb);
   }
 }
 
@@ -695,9 +741,11 @@ void orc_response(const orc_config* c, const orc_orbit* o, const orc_source* s,
   if (n <= 0) return;
   orc_ctx x;
   ctx_init(&x, c, o, s, n, hp, hc);
+  ctx_next_term(&x, n, hp, hc);
   int64_t ylo = first_y_needed(&x);
   if (ylo < n) fill_y_from(&x, ylo);
   if (c->mode != ORC_FULL) fill_g_all(&x);
+  if (x.nt) fill_g_all((orc_ctx*)x.nt);
 #pragma omp parallel for schedule(static) if (n > 4096 && !in_parallel())
   for (int64_t k = 0; k < n; ++k) {
     double r[3];
@@ -712,6 +760,7 @@ void orc_response_at(const orc_config* c, const orc_orbit* o, const orc_source* 
                      int64_t nk, const int64_t* ks, double* X, double* Y, double* Z) {
   orc_ctx x;
   ctx_init(&x, c, o, s, n, hp, hc);
+  ctx_next_term(&x, n, hp, hc);
   for (int64_t q = 0; q < nk; ++q) {
     double r[3];
     output_at(&x, ks[q], r);
@@ -847,9 +896,9 @@ static void abs_ensure_g(orc_ctx* x, int64_t lo, int64_t hi) {
   ensure_g_alloc(x);
   if (lo < 0) lo = 0;
   if (hi > x->n) hi = x->n;
-  double num[7], den;
+  double num[9], den;
   int hw = stencil_coeffs(x->m, x->c->stencil_order, num, &den);
-  double anum[7];
+  double anum[9];
   for (int q = 0; q < 2 * hw + 1; ++q) anum[q] = fabs(num[q]);
   double scale = den * pow(x->s->dt, (double)x->m);
   for (int64_t i = lo; i < hi; ++i) {
@@ -873,6 +922,7 @@ static void abs_lfa_at(orc_ctx* x, int64_t k, double out[3]) {
     else { pref = 2.0 * Ta * Tb; d = Ta + Tb; }
     double acc = 0.0;
     int ls[2] = {la, lb};
+    orc_ctx* nt = (orc_ctx*)x->nt;
     for (int q = 0; q < 2; ++q) {
       int64_t i0; double fx;
       orc_split(k, d + g.mu[ls[q] - 1], x->s->dt, &i0, &fx);
@@ -880,6 +930,13 @@ static void abs_lfa_at(orc_ctx* x, int64_t k, double out[3]) {
       int a = link_slot(ls[q]);
       acc += fabs(g.xi_p[a]) * lagrange_abs(x->gp, x->n, i0, fx, N) +
              fabs(g.xi_c[a]) * lagrange_abs(x->gc, x->n, i0, fx, N);
+      if (nt) {
+        double Tl = q == 0 ? Ta : Tb, To = q == 0 ? Tb : Ta;
+        double kap = lfa_kappa(x->c->tdi_gen, Tl, To, g.kn[ls[q] - 1]);
+        abs_ensure_g(nt, i0 - N / 2 + 1, i0 + N / 2 + 1);
+        acc += kap * (fabs(g.xi_p[a]) * lagrange_abs(nt->gp, nt->n, i0, fx, N) +
+                      fabs(g.xi_c[a]) * lagrange_abs(nt->gc, nt->n, i0, fx, N));
+      }
     }
     out[c] = pref * acc;
   }
@@ -890,6 +947,12 @@ void orc_response_abs_at(const orc_config* c, const orc_orbit* o, const orc_sour
                          int64_t nk, const int64_t* ks, double* X, double* Y, double* Z) {
   orc_ctx x;
   abs_init(&x, c, o, s, n, hp, hc);
+  if (c->lfa_terms == 2 && c->mode != ORC_FULL) {
+    orc_ctx* t = (orc_ctx*)malloc(sizeof(orc_ctx));
+    abs_init(t, c, o, s, n, hp, hc);
+    t->m = x.m + 2;
+    x.nt = t;
+  }
   for (int64_t q = 0; q < nk; ++q) {
     int64_t k = ks[q];
     double r[3] = {0.0, 0.0, 0.0}, a[3];

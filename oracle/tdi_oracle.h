@@ -38,7 +38,7 @@ typedef struct {
   int32_t taps;           /* N, even */
   int32_t stencil_order;  /* p in {2, 4} */
   int32_t equal_arms;     /* LFA only: 1 = equal constant delays L/c */
-  int32_t lfa_terms;      /* single-link LFA: 2 = keep the next (m = 1) term of the central series */
+  int32_t lfa_terms;      /* LFA: 2 = keep the next term of the central series (links and X, Y, Z) */
   int32_t nested_delays;  /* full response: 1 = each delay at the time it is applied (time-nested),
                              0 = every delay at the output time (the paper's choice) */
   int32_t pad_;
