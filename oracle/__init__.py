@@ -43,7 +43,7 @@ class Orbit(C.Structure):
 class Config(C.Structure):
     _fields_ = [("tdi_gen", C.c_int32), ("mode", C.c_int32), ("taps", C.c_int32),
                 ("stencil_order", C.c_int32), ("equal_arms", C.c_int32),
-                ("lfa_terms", C.c_int32), ("nested_delays", C.c_int32), ("pad_", C.c_int32),
+                ("lfa_terms", C.c_int32), ("nested_delays", C.c_int32), ("x20_from_x15", C.c_int32),
                 ("T_samples", C.c_double),
                 ("sigma_samples", C.c_double)]
 
@@ -132,7 +132,7 @@ def make_orbit(d: dict) -> Orbit:
 def make_config(d: dict) -> Config:
     return Config(int(d["tdi_gen"]), int(d["mode"]), int(d["taps"]), int(d["stencil_order"]),
                   int(d.get("equal_arms", 0)), int(d.get("lfa_terms", 0)),
-                  int(d.get("nested_delays", 0)), 0, float(d["T_samples"]),
+                  int(d.get("nested_delays", 0)), int(d.get("x20_from_x15", 0)), float(d["T_samples"]),
                   float(d["sigma_samples"]))
 
 

@@ -341,6 +341,7 @@ typedef struct {
   unsigned char* g_ok;
   int m;              /* LFA derivative order */
   void* nt;           /* LFA with the next term: context of derivative order m + 2 */
+  void* sc;           /* TDI 2.0 LFA from TDI 1.5: the shortcut's series (orc_x20) */
 } orc_ctx;
 
 static void ctx_init(orc_ctx* x, const orc_config* c, const orc_orbit* o, const orc_source* s,
@@ -357,12 +358,16 @@ static void ctx_init(orc_ctx* x, const orc_config* c, const orc_orbit* o, const 
   x->y = NULL; x->y_ok = NULL; x->gp = NULL; x->gc = NULL; x->g_ok = NULL;
   x->m = (c->tdi_gen == 20) ? 3 : 2;
   x->nt = NULL;
+  x->sc = NULL;
 }
+
+static void sc_free(void* p);
 
 static void ctx_free(orc_ctx* x) {
   free(x->hp_ssb); free(x->hc_ssb); free(x->y); free(x->y_ok);
   free(x->gp); free(x->gc); free(x->g_ok);
   if (x->nt) { ctx_free((orc_ctx*)x->nt); free(x->nt); }
+  if (x->sc) sc_free(x->sc);
 }
 
 /* X, Y, Z LFA with the next term (lfa_terms = 2): a second context holding the
@@ -584,6 +589,99 @@ static void lfa_at(orc_ctx* x, int64_t k, double out[3]) {
   }
 }
 
+/* TDI 2.0 LFA from the TDI 1.5 LFA, Eq. (relation_X20_X15_nonequal_timedelays):
+ *   X2.0(t) = 2 (T2 + T3) dX1.5/dt (t - T2 - T3),
+ * in the stencil-first form used throughout: X1.5 is the LFA TDI 1.5 series on
+ * the grid (zero outside [0, n-1]), its first derivative is taken there by the
+ * central stencil of accuracy p, and that series is read at the fractional
+ * delay T2 + T3 by N-tap Lagrange, the light times at the output time (equal
+ * arms: 4L/c and 2L/c, Eq. relation_X20_X15_equal_timedelays).  Y, Z cyclic. */
+typedef struct {
+  orc_config c15;     /* the same configuration at TDI 1.5, LFA */
+  orc_ctx x15;        /* its context (derivative order 2) */
+  double* v;          /* X1.5, Y1.5, Z1.5 on the grid, 3 n */
+  double* d;          /* their first derivatives, 3 n */
+  unsigned char* v_ok;
+  unsigned char* d_ok;
+  int absmode;        /* rounding-scale evaluation: magnitudes throughout */
+} orc_x20;
+
+static void abs_lfa_at(orc_ctx* x, int64_t k, double out[3]);
+static double lagrange_abs(const double* s, int64_t n, int64_t i0, double x, int N);
+
+static void sc_free(void* p) {
+  orc_x20* s = (orc_x20*)p;
+  ctx_free(&s->x15);
+  free(s->v); free(s->d); free(s->v_ok); free(s->d_ok);
+  free(s);
+}
+
+static void ctx_shortcut(orc_ctx* x, int64_t n, const double* hp, const double* hc) {
+  if (!x->c->x20_from_x15 || x->c->tdi_gen != 20 || x->c->mode == ORC_FULL) return;
+  orc_x20* s = (orc_x20*)calloc(1, sizeof(orc_x20));
+  s->c15 = *x->c;
+  s->c15.tdi_gen = 15;
+  s->c15.mode = ORC_LFA;
+  s->c15.x20_from_x15 = 0;
+  ctx_init(&s->x15, &s->c15, x->o, x->s, n, hp, hc);
+  size_t m = (size_t)(n > 0 ? n : 1);
+  s->v = (double*)malloc(sizeof(double) * 3 * m);
+  s->d = (double*)malloc(sizeof(double) * 3 * m);
+  s->v_ok = (unsigned char*)calloc(m, 1);
+  s->d_ok = (unsigned char*)calloc(m, 1);
+  x->sc = s;
+}
+
+static void sc_ensure_v(orc_x20* s, int64_t n, int64_t lo, int64_t hi) {
+  if (lo < 0) lo = 0;
+  if (hi > n) hi = n;
+  for (int64_t i = lo; i < hi; ++i) {
+    if (s->v_ok[i]) continue;
+    double r[3];
+    if (s->absmode) abs_lfa_at(&s->x15, i, r);
+    else lfa_at(&s->x15, i, r);
+    for (int c = 0; c < 3; ++c) s->v[(size_t)c * n + i] = r[c];
+    s->v_ok[i] = 1;
+  }
+}
+
+static void sc_ensure_d(orc_x20* s, int64_t n, double dt, int p, int64_t lo, int64_t hi) {
+  double num[9], den;
+  int hw = stencil_coeffs(1, p, num, &den);
+  if (s->absmode)
+    for (int q = 0; q < 2 * hw + 1; ++q) num[q] = fabs(num[q]);
+  if (lo < 0) lo = 0;
+  if (hi > n) hi = n;
+  for (int64_t i = lo; i < hi; ++i) {
+    if (s->d_ok[i]) continue;
+    sc_ensure_v(s, n, i - hw, i + hw + 1);
+    for (int c = 0; c < 3; ++c) s->d[(size_t)c * n + i] = stencil_at(s->v + (size_t)c * n, n, i, num, hw, den * dt);
+    s->d_ok[i] = 1;
+  }
+}
+
+static void x20_at(orc_ctx* x, int64_t k, double out[3]) {
+  orc_x20* s = (orc_x20*)x->sc;
+  orc_geom g;
+  orc_geometry(x->o, x->s->beta, x->s->lam, t_of(x, k), &g);
+  int N = x->c->taps;
+  for (int c = 0; c < 3; ++c) {
+    int la = (c + 1) % 3 + 1, lb = (c + 2) % 3 + 1;
+    double Ta = x->c->equal_arms ? x->o->L / ORC_C : g.T[la - 1];
+    double Tb = x->c->equal_arms ? x->o->L / ORC_C : g.T[lb - 1];
+    int64_t i0; double fx;
+    orc_split(k, Ta + Tb, x->s->dt, &i0, &fx);
+    sc_ensure_d(s, x->n, x->s->dt, x->c->stencil_order, i0 - N / 2 + 1, i0 + N / 2 + 1);
+    const double* dc = s->d + (size_t)c * x->n;
+    out[c] = 2.0 * (Ta + Tb) * (s->absmode ? lagrange_abs(dc, x->n, i0, fx, N) : orc_lagrange(dc, x->n, i0, fx, N));
+  }
+}
+
+static void lfa_out(orc_ctx* x, int64_t k, double out[3]) {
+  if (x->sc) x20_at(x, k, out);
+  else lfa_at(x, k, out);
+}
+
 /* Hybrid weights and windows, Eqs. (sigmoid, hybridized_xs), in sample units:
  * z = (k - k_H)/sigma, w+ = 1/(1+e^z), w- = 1/(1+e^-z); LFA part where
  * k - k_H <= T/2, full part where k - k_H >= -T/2 (both inclusive, weights
@@ -591,7 +689,7 @@ static void lfa_at(orc_ctx* x, int64_t k, double out[3]) {
 static void output_at(orc_ctx* x, int64_t k, double out[3]) {
   int mode = x->c->mode;
   if (mode == ORC_FULL) { full_at(x, k, out, NULL); return; }
-  if (mode == ORC_LFA) { lfa_at(x, k, out); return; }
+  if (mode == ORC_LFA) { lfa_out(x, k, out); return; }
   double kH = (x->s->t_hyb - x->s->t0) / x->s->dt;
   double rel = (double)k - kH;
   double z = rel / x->c->sigma_samples;
@@ -600,7 +698,7 @@ static void output_at(orc_ctx* x, int64_t k, double out[3]) {
   double r[3] = {0.0, 0.0, 0.0};
   if (rel <= 0.5 * x->c->T_samples) {
     double a[3];
-    lfa_at(x, k, a);
+    lfa_out(x, k, a);
     for (int c = 0; c < 3; ++c) r[c] += wp * a[c];
   }
   if (rel >= -0.5 * x->c->T_samples) {
@@ -742,10 +840,19 @@ void orc_response(const orc_config* c, const orc_orbit* o, const orc_source* s,
   orc_ctx x;
   ctx_init(&x, c, o, s, n, hp, hc);
   ctx_next_term(&x, n, hp, hc);
+  ctx_shortcut(&x, n, hp, hc);
   int64_t ylo = first_y_needed(&x);
   if (ylo < n) fill_y_from(&x, ylo);
   if (c->mode != ORC_FULL) fill_g_all(&x);
   if (x.nt) fill_g_all((orc_ctx*)x.nt);
+  if (x.sc) {
+    /* every X1.5 sample, then its derivative, before the parallel reads */
+    orc_x20* sc = (orc_x20*)x.sc;
+    fill_g_all(&sc->x15);
+#pragma omp parallel for schedule(static) if (n > 4096 && !in_parallel())
+    for (int64_t i = 0; i < n; ++i) sc_ensure_v(sc, n, i, i + 1);
+    sc_ensure_d(sc, n, s->dt, c->stencil_order, 0, n);
+  }
 #pragma omp parallel for schedule(static) if (n > 4096 && !in_parallel())
   for (int64_t k = 0; k < n; ++k) {
     double r[3];
@@ -761,6 +868,7 @@ void orc_response_at(const orc_config* c, const orc_orbit* o, const orc_source* 
   orc_ctx x;
   ctx_init(&x, c, o, s, n, hp, hc);
   ctx_next_term(&x, n, hp, hc);
+  ctx_shortcut(&x, n, hp, hc);
   for (int64_t q = 0; q < nk; ++q) {
     double r[3];
     output_at(&x, ks[q], r);
@@ -953,19 +1061,28 @@ void orc_response_abs_at(const orc_config* c, const orc_orbit* o, const orc_sour
     t->m = x.m + 2;
     x.nt = t;
   }
+  if (c->x20_from_x15 && c->tdi_gen == 20 && c->mode != ORC_FULL) {
+    ctx_shortcut(&x, n, hp, hc);
+    orc_x20* sc = (orc_x20*)x.sc;
+    ctx_free(&sc->x15);
+    abs_init(&sc->x15, &sc->c15, o, s, n, hp, hc);
+    sc->absmode = 1;
+  }
   for (int64_t q = 0; q < nk; ++q) {
     int64_t k = ks[q];
     double r[3] = {0.0, 0.0, 0.0}, a[3];
     if (c->mode == ORC_FULL) {
       abs_full_at(&x, k, r);
     } else if (c->mode == ORC_LFA) {
-      abs_lfa_at(&x, k, r);
+      if (x.sc) x20_at(&x, k, r);
+      else abs_lfa_at(&x, k, r);
     } else {
       double kH = (s->t_hyb - s->t0) / s->dt;
       double rel = (double)k - kH, z = rel / c->sigma_samples;
       double wp = 1.0 / (1.0 + exp(z)), wm = 1.0 / (1.0 + exp(-z));
       if (rel <= 0.5 * c->T_samples) {
-        abs_lfa_at(&x, k, a);
+        if (x.sc) x20_at(&x, k, a);
+        else abs_lfa_at(&x, k, a);
         for (int i = 0; i < 3; ++i) r[i] += wp * a[i];
       }
       if (rel >= -0.5 * c->T_samples) {

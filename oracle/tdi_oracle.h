@@ -41,7 +41,8 @@ typedef struct {
   int32_t lfa_terms;      /* LFA: 2 = keep the next term of the central series (links and X, Y, Z) */
   int32_t nested_delays;  /* full response: 1 = each delay at the time it is applied (time-nested),
                              0 = every delay at the output time (the paper's choice) */
-  int32_t pad_;
+  int32_t x20_from_x15;   /* LFA, TDI 2.0: 1 = X2.0 from the TDI 1.5 LFA series by
+                             Eq. (relation_X20_X15_nonequal_timedelays) */
   double T_samples;       /* hybrid window length, samples */
   double sigma_samples;   /* sigmoid width, samples */
 } orc_config;

@@ -114,3 +114,98 @@ def test_higher_stencils_exact_on_polynomials(orc):
             sl = slice(5, n - 5)
             ref = np.polyval(d, t[sl])
             assert np.abs(g[sl] - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max()), (m, p)
+
+
+# --------------------------------------------------------------------------
+# TDI 2.0 LFA from the TDI 1.5 LFA (x20_from_x15 = 1),
+# Eq. (relation_X20_X15_nonequal_timedelays)
+# --------------------------------------------------------------------------
+def _stencil1(v, p, dt):
+    """First-derivative central stencil of accuracy p with zero extension,
+    written out independently of the oracle."""
+    w = {2: ([-1, 0, 1], 2.0), 4: ([1, -8, 0, 8, -1], 12.0)}[p]
+    hw = len(w[0]) // 2
+    z = np.concatenate([np.zeros(hw), v, np.zeros(hw)])
+    out = np.zeros_like(v)
+    for s, c in enumerate(w[0]):
+        out += c * z[s:s + len(v)]
+    return out / (w[1] * dt)
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_shortcut_integer_delay_is_scaled_shifted_derivative(orc, p):
+    """Equal arms with L/c = 10 s at dt = 1 s: the read of dX1.5/dt at 2L/c
+    falls on a grid point, so X2.0[k] = (4L/c) D1[X1.5][k - 20] exactly
+    (Eq. relation_X20_X15_equal_timedelays), edges included."""
+    orbit = W.default_orbit(W.ORBIT_FROZEN)
+    orbit["L"] = 10.0 * C
+    n, dt = 1500, 1.0
+    rec, hp, hc = _mono(n, dt, 3e-3, 0.4, 1.9)
+    cfg15 = W.default_config(tdi_gen=15, mode=1, taps=32, stencil_order=p, equal_arms=1)
+    x15 = orc.response(cfg15, orbit, rec, hp, hc)
+    cfg = W.default_config(tdi_gen=20, mode=1, taps=32, stencil_order=p, equal_arms=1)
+    cfg["x20_from_x15"] = 1
+    x20 = orc.response(cfg, orbit, rec, hp, hc)
+    for c in range(3):
+        d = _stencil1(x15[c], p, dt)
+        pred = np.zeros(n)
+        pred[20:] = 40.0 * d[:-20]
+        assert np.abs(pred - x20[c]).max() <= 1e-12 * np.abs(pred).max()
+
+
+@pytest.mark.parametrize("eq", [0, 1])
+def test_shortcut_matches_direct_lfa_to_stencil_order(orc, eq):
+    """Frozen constellation, monochromatic wave: the shortcut and the direct
+    TDI 2.0 LFA (Eq. X20_nonequal_timedelays) are the same relation with
+    different finite differences.  At accuracy 2 the first-derivative stencil
+    composed with the second-derivative one is exactly the third-derivative
+    stencil, so the two agree to rounding (and 32-tap interpolation error); at
+    accuracy 4 they differ by O((2 pi f dt)^4): halving dt divides the
+    difference by 16."""
+    orbit = W.default_orbit(W.ORBIT_FROZEN)
+    diffs = {2: [], 4: []}
+    for dt in (8.0, 4.0, 2.0):
+        n = int(16000 / dt)
+        rec, hp, hc = _mono(n, dt, 2e-3, 0.4, 1.9)
+        for p in (2, 4):
+            cfg = W.default_config(tdi_gen=20, mode=1, taps=32, stencil_order=p, equal_arms=eq)
+            direct = orc.response(cfg, orbit, rec, hp, hc)
+            sc = orc.response(dict(cfg, x20_from_x15=1), orbit, rec, hp, hc)
+            sl = slice(n // 4, 3 * n // 4)
+            diffs[p].append(np.abs(sc[0][sl] - direct[0][sl]).max() / np.abs(direct[0][sl]).max())
+    print("shortcut vs direct:", diffs)
+    assert max(diffs[2]) < 1e-8
+    r1, r2 = diffs[4][0] / diffs[4][1], diffs[4][1] / diffs[4][2]
+    assert 14.0 < r1 < 18.0 and 14.0 < r2 < 18.0
+    assert diffs[4][0] < 1e-4
+
+
+def test_shortcut_converges_to_full_as_x_squared(orc):
+    """Like the direct LFA, the shortcut misses the full response by O(x^2)."""
+    orbit = W.default_orbit(W.ORBIT_FROZEN)
+    errs = []
+    for f in (3e-3, 6e-3):
+        rec, hp, hc = _mono(3000, 1.0, f, 0.4, 1.9)
+        full = orc.response(W.default_config(tdi_gen=20, mode=0, taps=32), orbit, rec, hp, hc)
+        cfg = W.default_config(tdi_gen=20, mode=1, taps=32, stencil_order=4, equal_arms=1)
+        cfg["x20_from_x15"] = 1
+        sc = orc.response(cfg, orbit, rec, hp, hc)
+        sl = slice(500, 2500)
+        errs.append(np.abs(sc[0][sl] - full[0][sl]).max() / np.abs(full[0][sl]).max())
+    slope = math.log(errs[1] / errs[0]) / math.log(2.0)
+    assert abs(slope - 2.0) < 0.3, errs
+
+
+def test_shortcut_sampled_entry_point_matches_full_series(orc):
+    """Sampled outputs (lazy series) equal the whole-series evaluation, in the
+    LFA and the hybrid, on a moving orbit."""
+    orbit = W.default_orbit()
+    rec, hp, hc, meta = W.make_source(2e5, 0.7, 0.3, 2.0, 0.4, 6000, 10.0, t0=3e6)
+    assert math.isfinite(rec["t_hyb"])
+    for mode in (1, 2):
+        cfg = W.default_config(tdi_gen=20, mode=mode, taps=32, stencil_order=4)
+        cfg["x20_from_x15"] = 1
+        allv = orc.response(cfg, orbit, rec, hp, hc)
+        ks = np.array([0, 3, 17, 2999, 4500, 5998, 5999])
+        at = orc.response_at(cfg, orbit, rec, hp, hc, ks)
+        assert np.array_equal(allv[:, ks], at)
