@@ -415,6 +415,7 @@ def main():
                          "read from an hourly position table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-reference", action="store_true")
+    ap.add_argument("--no-variants", action="store_true", help="skip the LFA variant timings")
     ap.add_argument("--cpu-budget", type=float, default=40.0,
                     help="about the total time of the timed oracle runs (s), over all modes")
     ap.add_argument("--steps-only", action="store_true", help="only the timed hybrid steps (profiling)")
@@ -549,6 +550,42 @@ def main():
         del X64, Y64, Z64
     ref = fp64.get("full")
 
+    # LFA variants on the same batch and hybrid window: the next term of the
+    # central expansion (lfa_terms = 2, general LFA kernel) and TDI 2.0 from the
+    # TDI 1.5 LFA series (FP64 TDI 1.5 pass, then derivative and read)
+    variants = {}
+    if not args.no_variants:
+        for vname, extra in (("lfa_next_term", {"lfa_terms": 2}), ("x20_from_x15", {"x20_from_x15": 1})):
+            for prec in (1, 0):
+                cv = dict(cfg32, precision=prec, **extra)
+                dt_out = torch.float32 if prec else torch.float64
+                Xv = torch.empty(total, dtype=dt_out, device=dev)
+                Yv, Zv = torch.empty_like(Xv), torch.empty_like(Xv)
+                pv = tdi.Plan(cv, orb, batch.n_sources, total, autotune=True, use_graph=True)
+                pv.run(src, batch.offsets, hp, hc, Xv, Yv, Zv)
+                pv.sync()
+                pv.kernel_times()
+                reps = []
+                for _ in range(3):
+                    torch.cuda.synchronize()
+                    r0 = time.perf_counter()
+                    pv.run(src, batch.offsets, hp, hc, Xv, Yv, Zv)
+                    torch.cuda.synchronize()
+                    reps.append(time.perf_counter() - r0)
+                kv = pv.kernel_times()
+                if pv.sync() != tdi.TDI_OK:
+                    raise RuntimeError(f"window check failed ({vname})")
+                pv.close()
+                del Xv, Yv, Zv
+                ms = 1e3 * float(np.median(reps))
+                key = f"{vname}_{'fp32' if prec else 'fp64'}"
+                variants[key] = {"value": total / (ms * 1e-3), "unit": "samples/s", "ms_per_step": ms,
+                                 "kernel_ms": [round(float(np.median(kv[j::3])), 3) for j in range(3)],
+                                 "config": f"hybrid TDI 2.0, {vname}, {'FP32-bulk' if prec else 'FP64'}, "
+                                           "same batch, median of 3; kernel_ms = (pre-pass or TDI 1.5 "
+                                           "pass, LFA kernel, full kernel)"}
+                print(f"[bench] variant {key}: {ms:.2f} ms/step", file=sys.stderr, flush=True)
+
     # roofline of the dominant kernel: HBM (algorithmic 28 B per sample) is the
     # roof the path is measured against; the VALU issue rate says what binds it
     achieved_gbs = BYTES_PER_SAMPLE_FP32 * total / (lfa_ms * 1e-3) / 1e9 if lfa_ms > 0 else float("nan")
@@ -607,6 +644,7 @@ def main():
         "cpu_baseline": cpu,
         "fp64_full_reference": ref,
         "fp64": fp64,
+        "lfa_variants": variants,
         "speedup_vs_fp64_full": (value / ref["value"]) if ref else None,
         "speedup_vs_fp64_hybrid": (value / fp64["hybrid"]["value"]) if "hybrid" in fp64 else None,
     }

@@ -113,11 +113,20 @@ typedef struct {
                                noise-orthogonal combinations defined at the end of Sec. II.B instead,
                                A = (Z - X)/sqrt 2, E = (X - 2Y + Z)/sqrt 6, T = (X + Y + Z)/sqrt 3,
                                into the same three arrays (fused into the store) */
-  int32_t lfa_terms;        /* single-link LFA (tdi_run_links): 0 or 1 = the leading term of
-                               Eq. (yslr_with_tau_derivatives); 2 = also its next term,
-                               -(L/2c)(1/6)[L(1 - k.n)/(2c)]^2 times the third derivative of H.
-                               tdi_run supports only the leading term (2 gives
-                               TDI_EUNSUPPORTED in the LFA and hybrid modes) */
+  int32_t lfa_terms;        /* LFA terms.  0 or 1: the leading term of the central expansion
+                               (App. B).  2: also the next one.
+                               Single links (tdi_run_links): the m = 1 term of
+                               Eq. (yslr_with_tau_derivatives), -(L/2c)(1/6)[L(1 - k.n)/(2c)]^2
+                               times the third derivative of H.
+                               X, Y, Z (tdi_run, LFA and HYBRID modes): the expansion of the
+                               TDI combination, Eqs. (X1.5l2), (X1.5l3), carried to third order
+                               in the delays with that link term: each read Xi^(m) of
+                               Eqs. (X15/X20_nonequal_timedelays) becomes Xi^(m) + kappa
+                               Xi^(m+2), kappa = To^2/6 + Tl^2/8 + Tl^2 (1 + (k.n_l)^2)/24
+                               (+ (Tl + To)^2/6 for TDI 2.0), Tl the link's light time, To the
+                               channel's other arm; the derivative of order m + 2 comes from a
+                               central stencil of the same accuracy.  Runs on the general LFA
+                               kernel (not the FP32 fast path). */
   int32_t nested_delays;    /* full response (FULL mode and the full part of HYBRID): 0 = every
                                delay of Eqs. (X1.5), (X2.0) at the output time, as the paper does
                                (Sec. II.B); 1 = time-nested delays, each light time taken at the
@@ -129,6 +138,16 @@ typedef struct {
                                Small tiles give single long sources enough tiles to fill the GPU;
                                large ones amortise the per-tile geometry fit over big batches.
                                Other values give TDI_ERANGE. */
+  int32_t lfa_x20_from_x15; /* TDI 2.0 LFA and HYBRID modes: 1 = the LFA part from the TDI 1.5
+                               LFA series by Eq. (relation_X20_X15_nonequal_timedelays),
+                               X2.0(t) = 2 (T2 + T3) dX1.5/dt (t - T2 - T3): X1.5 is computed in
+                               FP64 on every sample into a plan-owned buffer (24 bytes per
+                               sample of max_total_samples), differentiated by the central
+                               stencil of the configured accuracy and read at the fractional
+                               delay with exact N-tap Lagrange weights; output in the plan's
+                               precision.  No graph replay for this option.  0 = the direct
+                               form of Eq. (X20_nonequal_timedelays).  1 with TDI 1.5 gives
+                               TDI_ERANGE; with lfa_terms = 2, TDI_EUNSUPPORTED. */
 } tdi_config;
 
 typedef struct tdi_plan tdi_plan;
@@ -169,7 +188,8 @@ tdi_status tdi_run(tdi_plan* plan, int64_t n_sources, const tdi_source* src,
  * stream) on the current device, and the call is asynchronous on it.
  * Limits: at most 256 sources and 2048 fast-LFA tiles (tiles of
  * 2304 * fast_tile_chunks outputs, chunks 0 meaning 4), else TDI_ESTATE;
- * TABLE orbits give TDI_EUNSUPPORTED.  autotune and use_graph are ignored
+ * TABLE orbits and lfa_x20_from_x15 (which needs a per-sample buffer) give
+ * TDI_EUNSUPPORTED.  autotune and use_graph are ignored
  * (persistent grids at full occupancy, no graph).  A retarded-time window
  * that leaves the staged range writes NaN outputs (there is no plan to
  * report it through).  Every call on one GPU shares that GPU's array: calls

@@ -40,6 +40,7 @@ struct Caps {
   size_t lds_lfa, lds_full;
   int goff;
   int fast;          // FP32 bulk LFA kernel
+  int nx;            // LFA with the next term (general LFA kernel)
   int tile_lfa;      // outputs per LFA tile
 };
 
@@ -63,6 +64,11 @@ struct tdi_plan {
   size_t params_bytes;
   int32_t* d_err;
   uint32_t* d_counters;
+  // TDI 2.0 LFA from TDI 1.5: the FP64 TDI 1.5 LFA series and its own parameter block
+  double* d_x15;
+  tdi::KParams* d_params15;
+  tdi::KParams* h_params15;
+  tdi_config cfg15;
   // pinned staging image of the parameter block
   tdi::KParams* h_params;
   hipEvent_t staged_free;        // recorded after the upload of the previous run
@@ -122,6 +128,9 @@ tdi_status tdi_check_config(const tdi_config* c, const tdi_orbit* o) {
   if (c->fast_tile_chunks != 0 && c->fast_tile_chunks != 1 && c->fast_tile_chunks != 2 &&
       c->fast_tile_chunks != 4)
     return TDI_ERANGE;
+  if (c->lfa_x20_from_x15 != 0 && c->lfa_x20_from_x15 != 1) return TDI_ERANGE;
+  if (c->lfa_x20_from_x15 && c->tdi_gen != 20) return TDI_ERANGE;
+  if (c->lfa_x20_from_x15 && c->lfa_terms == 2) return TDI_EUNSUPPORTED;
   if (!(c->hyb_T_samples > 0.0) || !is_fin(c->hyb_T_samples)) return TDI_ERANGE;
   if (!(c->hyb_sigma_samples > 0.0) || !is_fin(c->hyb_sigma_samples)) return TDI_ERANGE;
   if (!(o->L_m > 0.0) || !is_fin(o->L_m)) return TDI_ERANGE;
@@ -206,11 +215,14 @@ double stage2_bound(const tdi_config& c, const OrbitBounds& b) {
   return (c.tdi_gen == 20 ? 7.0 : 3.0) * b.tmax;
 }
 
+// TDI 2.0 LFA from the TDI 1.5 LFA series (lfa_x20_from_x15).
+bool x20_shortcut(const tdi_config& c) { return c.lfa_x20_from_x15 == 1 && c.mode != TDI_MODE_FULL; }
+
 // The FP32 bulk LFA kernel applies to steps up to kFastDtMax and to orbits whose
 // delays drift by at most kFastRateMax per unit time.
 bool fast_lfa(const tdi_config& c, const OrbitBounds& b, double dt_max) {
-  return c.precision == TDI_FP32_BULK && c.mode != TDI_MODE_FULL && dt_max <= tdi::kFastDtMax &&
-         b.rate <= tdi::kFastRateMax;
+  return c.precision == TDI_FP32_BULK && c.mode != TDI_MODE_FULL && c.lfa_terms != 2 &&
+         !x20_shortcut(c) && dt_max <= tdi::kFastDtMax && b.rate <= tdi::kFastRateMax;
 }
 
 // Worst-case staged window lengths (samples) at sampling step dt; the kernels
@@ -218,6 +230,7 @@ bool fast_lfa(const tdi_config& c, const OrbitBounds& b, double dt_max) {
 Caps window_caps(const tdi_config& c, const OrbitBounds& ob, double dt, bool fast) {
   Caps k;
   k.fast = fast ? 1 : 0;
+  k.nx = c.lfa_terms == 2 && c.mode != TDI_MODE_FULL ? 1 : 0;
   k.tile_lfa = fast ? tdi::kTileLfaFast : tdi::kTileLfa;
   const int lfa_span = fast ? tdi::kFastChunk : tdi::kTileLfa;   // outputs sharing one window
   const int N = c.interp_taps;
@@ -225,7 +238,9 @@ Caps window_caps(const tdi_config& c, const OrbitBounds& ob, double dt, bool fas
   const double Tmax = ob.tmax;
   const double Tmin = ob.tmin;
   const double Lc = Tmax;
-  const int hw = (c.tdi_gen == 20) ? (c.stencil_order == 4 ? 3 : 2) : (c.stencil_order == 4 ? 2 : 1);
+  // stencil half width (the next term's stencil, of derivative order m + 2, is wider)
+  const int hw = k.nx ? ((c.tdi_gen == 20) ? (c.stencil_order == 4 ? 4 : 3) : (c.stencil_order == 4 ? 3 : 2))
+                      : ((c.tdi_gen == 20) ? (c.stencil_order == 4 ? 3 : 2) : (c.stencil_order == 4 ? 2 : 1));
   auto margin = [](double cnt) { return 2 + (int)ceil(4e-4 * cnt); };
   // LFA: the six delays D_c + mu_l spread over half an arm plus arm differences
   const double mult = c.tdi_gen == 20 ? 2.0 : 1.0;
@@ -238,7 +253,15 @@ Caps window_caps(const tdi_config& c, const OrbitBounds& ob, double dt, bool fas
   const double spread_f = Tmax + Lc * 1.02 + 2.0 * rate * k.y * dt;
   k.hf = k.y + (int)ceil(spread_f / dt) + N + 2 * margin(k.y) + 4;
   const int fp32 = c.precision == TDI_FP32_BULK;
-  k.lds_lfa = tdi::lfa_lds_bytes(N, k.g, k.hl, fp32, k.fast, &k.goff);
+  k.lds_lfa = tdi::lfa_lds_bytes(N, k.g, k.hl, fp32, k.fast, k.nx, &k.goff);
+  if (x20_shortcut(c)) {
+    // the shortcut's window: the tile, the spread of T2 + T3 (delays at most two
+    // light times), the taps and the first-derivative stencil
+    k.g = tdi::kTileLfa + (int)ceil(2.04 * Tmax / dt) + N + 2 * margin(tdi::kTileLfa) + 4 + 2 * 2;
+    k.hl = k.g;
+    k.goff = 0;
+    k.lds_lfa = tdi::x20_lds_bytes(k.g);
+  }
   k.lds_full = tdi::full_lds_bytes(k.hf, k.y, fp32);
   return k;
 }
@@ -363,7 +386,7 @@ hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& c
   if (gl > 0 && caps.fast && tdi::launch_lfa_fit(p->d_params, taps, 4 * p->n_cu, st) != 0)
     return hipErrorLaunchFailure;
   if (evs && (e = hipEventRecord(evs[1], st)) != hipSuccess) return e;
-  if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, caps.fast, gl, caps.lds_lfa, st) != 0)
+  if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, caps.fast, caps.nx, gl, caps.lds_lfa, st) != 0)
     return hipErrorLaunchFailure;
   if (evs && (e = hipEventRecord(evs[2], st)) != hipSuccess) return e;
   const int gf = ln.grid_full > 0 ? ln.grid_full : (int)std::max<int64_t>(0, tiles_full);
@@ -491,9 +514,61 @@ bool batch_caps(const tdi_config& cfg, const OrbitBounds& ob, int64_t n_sources,
   return true;
 }
 
+// TDI 2.0 LFA from TDI 1.5: pass 1 runs the FP64 TDI 1.5 LFA over every sample
+// of each source into d_x15 (its own parameter block, counters 8..9), pass 2
+// (k_x20) forms the TDI 2.0 LFA part from it, then the full-response kernel
+// adds the hybrid's full part.  Plain stream launches, persistent grids.
+tdi_status run_x20(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
+                   const double* hp, const double* hc, void* X, void* Y, void* Z, bool record) {
+  Caps caps, caps15;
+  if (!batch_caps(p->cfg, p->ob, n_sources, src, offsets, &caps)) return TDI_OK;
+  if (!batch_caps(p->cfg15, p->ob, n_sources, src, offsets, &caps15)) return TDI_OK;
+  if (caps.lds_lfa > p->max_lds || caps.lds_full > p->max_lds || caps15.lds_lfa > p->max_lds) return TDI_ERANGE;
+  const int taps = p->cfg.interp_taps, fp32 = p->cfg.precision;
+  const int64_t total = offsets[n_sources];
+  Launch ln15 = {tdi::occupancy_lfa(taps, 0, 0, 0, caps15.lds_lfa) * p->n_cu, 0, 4};
+  Launch ln = {tdi::occupancy_x20(taps, fp32, caps.lds_lfa) * p->n_cu,
+               tdi::occupancy_full(taps, fp32, caps.lds_full) * p->n_cu, 4};
+  p->last_fast = 0;
+  p->last_tile_lfa = tdi::kTileLfa;
+  if (p->staged_pending) {
+    if (hipEventSynchronize(p->staged_free) != hipSuccess) return TDI_EDEVICE;
+    p->staged_pending = false;
+  }
+  stage_batch(p->cfg15, p->h_params15, n_sources, src, offsets, hp, hc, p->d_x15, p->d_x15 + total,
+              p->d_x15 + 2 * total, caps15, ln15);
+  stage_batch(p->cfg, p->h_params, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
+  p->h_params->x15 = p->d_x15;
+  p->h_params->x15_stride = total;
+  const size_t copy_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)n_sources;
+  hipStream_t st = p->user_stream;
+  const hipEvent_t* evs = record ? p->ev[p->ev_head] : nullptr;
+  if (hipMemcpyAsync(p->d_params15, p->h_params15, copy_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(p->d_params, p->h_params, copy_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+    return TDI_EDEVICE;
+  if (tdi::launch_reset(p->d_counters, st) != 0) return TDI_EDEVICE;
+  if (evs && hipEventRecord(evs[0], st) != hipSuccess) return TDI_EDEVICE;
+  if (p->h_params15->n_tiles_lfa > 0 &&
+      tdi::launch_lfa(p->d_params15, taps, 0, 0, 0, ln15.grid_lfa, caps15.lds_lfa, st) != 0)
+    return TDI_EDEVICE;
+  if (evs && hipEventRecord(evs[1], st) != hipSuccess) return TDI_EDEVICE;
+  if (p->h_params->n_tiles_lfa > 0 && tdi::launch_x20(p->d_params, taps, fp32, ln.grid_lfa, caps.lds_lfa, st) != 0)
+    return TDI_EDEVICE;
+  if (evs && hipEventRecord(evs[2], st) != hipSuccess) return TDI_EDEVICE;
+  if (p->h_params->n_tiles_full > 0 &&
+      tdi::launch_full(p->d_params, taps, fp32, ln.grid_full, caps.lds_full, st) != 0)
+    return TDI_EDEVICE;
+  if (evs && hipEventRecord(evs[3], st) != hipSuccess) return TDI_EDEVICE;
+  hipEventRecord(p->staged_free, st);
+  p->staged_pending = true;
+  if (record) advance_ring(p);
+  return TDI_OK;
+}
+
 tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_source* src,
                     const int64_t* offsets, const double* hp, const double* hc, void* X, void* Y,
                     void* Z, bool record, bool allow_graph) {
+  if (x20_shortcut(p->cfg)) return run_x20(p, n_sources, src, offsets, hp, hc, X, Y, Z, record);
   Caps caps;
   if (!batch_caps(p->cfg, p->ob, n_sources, src, offsets, &caps)) return TDI_OK;
   if (caps.lds_lfa > p->max_lds || caps.lds_full > p->max_lds) return TDI_ERANGE;
@@ -569,7 +644,7 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
               const double* hp, const double* hc, void* X, void* Y, void* Z) {
   Caps caps;
   if (!batch_caps(p->cfg, p->ob, n_sources, src, offsets, &caps)) return;
-  const int ol = tdi::occupancy_lfa(p->cfg.interp_taps, p->cfg.precision, caps.fast, caps.lds_lfa);
+  const int ol = tdi::occupancy_lfa(p->cfg.interp_taps, p->cfg.precision, caps.fast, caps.nx, caps.lds_lfa);
   const int of = tdi::occupancy_full(p->cfg.interp_taps, p->cfg.precision, caps.lds_full);
   // grid candidates (persistent at the resident count, half and twice that, or
   // one workgroup per tile), each with every tile shape of the fast LFA path:
@@ -666,6 +741,12 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
     ok = hipMalloc(&p->d_ftiles, (size_t)p->fit_tiles * tdi::fast_tile_bytes()) == hipSuccess;
   }
   ok = ok && hipHostMalloc((void**)&p->h_params, p->params_bytes, hipHostMallocDefault) == hipSuccess;
+  if (ok && x20_shortcut(*cfg)) {
+    ok = hipMalloc((void**)&p->d_x15, sizeof(double) * 3 * (size_t)std::max<int64_t>(1, max_total_samples)) ==
+         hipSuccess;
+    ok = ok && hipMalloc((void**)&p->d_params15, p->params_bytes) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&p->h_params15, p->params_bytes, hipHostMallocDefault) == hipSuccess;
+  }
   ok = ok && hipEventCreateWithFlags(&p->staged_free, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&p->handoff, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipStreamCreateWithFlags(&p->graph_stream, hipStreamNonBlocking) == hipSuccess;
@@ -697,13 +778,28 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   p->h_params->err = p->d_err;
   p->h_params->lfa_tiles = p->d_ftiles;
   p->h_params->counters = p->d_counters;
+  if (x20_shortcut(*cfg)) {
+    // pass 1: the same source set at TDI 1.5, LFA mode, FP64, over every sample
+    p->cfg15 = *cfg;
+    p->cfg15.tdi_gen = 15;
+    p->cfg15.mode = TDI_MODE_LFA;
+    p->cfg15.precision = TDI_FP64;
+    p->cfg15.lfa_terms = 0;
+    p->cfg15.lfa_x20_from_x15 = 0;
+    p->cfg15.channels = TDI_CHANNELS_XYZ;
+    memset(p->h_params15, 0, p->params_bytes);
+    fill_constants(*p->h_params15, p->cfg15, *orb, p->ob, p->d_orbtab);
+    p->h_params15->err = p->d_err;
+    p->h_params15->lfa_tiles = nullptr;
+    p->h_params15->counters = p->d_counters + 8;
+  }
 
   p->launch = {0, 0, cfg->fast_tile_chunks != 0 ? cfg->fast_tile_chunks : 4};
-  p->tuned = cfg->autotune ? false : true;
+  p->tuned = cfg->autotune && !x20_shortcut(*cfg) ? false : true;
   if (!cfg->autotune && cfg->use_graph) {
     // graph replay needs persistent launches: one full occupancy of the chip
     const Caps caps = window_caps(*cfg, p->ob, 1.0, fast_lfa(*cfg, p->ob, 1.0));
-    p->launch.grid_lfa = tdi::occupancy_lfa(cfg->interp_taps, cfg->precision, caps.fast, caps.lds_lfa) * p->n_cu;
+    p->launch.grid_lfa = tdi::occupancy_lfa(cfg->interp_taps, cfg->precision, caps.fast, caps.nx, caps.lds_lfa) * p->n_cu;
     p->launch.grid_full = tdi::occupancy_full(cfg->interp_taps, cfg->precision, caps.lds_full) * p->n_cu;
   }
   *out = p;
@@ -726,6 +822,9 @@ tdi_status tdi_plan_destroy(tdi_plan* p) {
   if (p->d_counters) hipFree(p->d_counters);
   if (p->d_ftiles) hipFree(p->d_ftiles);
   if (p->d_orbtab) hipFree(p->d_orbtab);
+  if (p->d_x15) hipFree(p->d_x15);
+  if (p->d_params15) hipFree(p->d_params15);
+  if (p->h_params15) hipHostFree(p->h_params15);
   if (p->h_params) hipHostFree(p->h_params);
   free(p);
   return TDI_OK;
@@ -743,7 +842,6 @@ tdi_status tdi_run(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   const uintptr_t al = p->cfg.precision == TDI_FP64 ? 8 : 4;
   if (((uintptr_t)hp | (uintptr_t)hc) & 7) return TDI_EINVAL;
   if ((((uintptr_t)X) | ((uintptr_t)Y) | ((uintptr_t)Z)) & (al - 1)) return TDI_EINVAL;
-  if (p->cfg.lfa_terms == 2 && p->cfg.mode != TDI_MODE_FULL) return TDI_EUNSUPPORTED;
   if (!table_covers(p, n_sources, src, offsets)) return TDI_ERANGE;
   if (!p->tuned) autotune(p, n_sources, src, offsets, hp, hc, X, Y, Z);
   return run_with(p, p->launch, n_sources, src, offsets, hp, hc, X, Y, Z, true, true);
@@ -851,11 +949,12 @@ tdi_status tdi_plan_describe(const tdi_plan* p, char* buf, int32_t buflen) {
   if (!p || !buf || buflen < 1) return TDI_EINVAL;
   snprintf(buf, (size_t)buflen,
            "{\"tile_lfa\": %d, \"tile_full\": %d, \"grid_lfa\": %d, \"grid_full\": %d, "
-           "\"graph\": %d, \"graph_kernel_events\": %d, \"cu\": %d, \"tuned\": %d, \"lfa_fast\": %d}",
+           "\"graph\": %d, \"graph_kernel_events\": %d, \"cu\": %d, \"tuned\": %d, \"lfa_fast\": %d, "
+           "\"x20_from_x15\": %d}",
            p->last_tile_lfa, tdi::kTileFull, p->launch.grid_lfa, p->launch.grid_full,
-           (p->cfg.use_graph && p->launch.grid_lfa > 0 && p->launch.grid_full > 0) ? 1 : 0,
+           (p->cfg.use_graph && !x20_shortcut(p->cfg) && p->launch.grid_lfa > 0 && p->launch.grid_full > 0) ? 1 : 0,
            p->graph_timed ? 1 : 0, p->n_cu,
-           p->tuned ? 1 : 0, p->last_fast);
+           p->tuned ? 1 : 0, p->last_fast, x20_shortcut(p->cfg) ? 1 : 0);
   return TDI_OK;
 }
 
@@ -948,7 +1047,7 @@ tdi_status tdi_run_noalloc(const tdi_config* cfg, const tdi_orbit* orb, int64_t 
   tdi_status st = tdi_check_config(cfg, orb);
   if (st != TDI_OK) return st;
   if (orb->kind == TDI_ORBIT_TABLE) return TDI_EUNSUPPORTED;
-  if (cfg->lfa_terms == 2 && cfg->mode != TDI_MODE_FULL) return TDI_EUNSUPPORTED;
+  if (x20_shortcut(*cfg)) return TDI_EUNSUPPORTED;
   st = tdi_check_batch(cfg, n_sources, src, offsets);
   if (st != TDI_OK) return st;
   if (n_sources > kNaMaxSources) return TDI_ESTATE;
@@ -972,7 +1071,7 @@ tdi_status tdi_run_noalloc(const tdi_config* cfg, const tdi_orbit* orb, int64_t 
   if (caps.lds_lfa > d.max_lds || caps.lds_full > d.max_lds) return TDI_ERANGE;
   const int taps = cfg->interp_taps, fp32 = cfg->precision;
   Launch ln;
-  ln.grid_lfa = tdi::occupancy_lfa(taps, fp32, caps.fast, caps.lds_lfa) * d.n_cu;
+  ln.grid_lfa = tdi::occupancy_lfa(taps, fp32, caps.fast, caps.nx, caps.lds_lfa) * d.n_cu;
   ln.grid_full = tdi::occupancy_full(taps, fp32, caps.lds_full) * d.n_cu;
   ln.chunks = cfg->fast_tile_chunks != 0 ? cfg->fast_tile_chunks : 4;
 
@@ -992,7 +1091,7 @@ tdi_status tdi_run_noalloc(const tdi_config* cfg, const tdi_orbit* orb, int64_t 
   if (!na_put(reinterpret_cast<uint32_t*>(d.ptr), g_na_image, (bytes + 3) / 4 * 4, s)) return TDI_EDEVICE;
   if (kp->n_tiles_lfa > 0) {
     if (caps.fast && tdi::launch_lfa_fit(dp, taps, 4 * d.n_cu, s) != 0) return TDI_EDEVICE;
-    if (tdi::launch_lfa(dp, taps, fp32, caps.fast, ln.grid_lfa, caps.lds_lfa, s) != 0) return TDI_EDEVICE;
+    if (tdi::launch_lfa(dp, taps, fp32, caps.fast, caps.nx, ln.grid_lfa, caps.lds_lfa, s) != 0) return TDI_EDEVICE;
   }
   if (kp->n_tiles_full > 0 && tdi::launch_full(dp, taps, fp32, ln.grid_full, caps.lds_full, s) != 0)
     return TDI_EDEVICE;

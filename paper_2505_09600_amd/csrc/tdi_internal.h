@@ -79,6 +79,8 @@ struct KParams {
   int64_t link_stride;   // link outputs: elements between the six link arrays (X is their base)
   double T_s, sigma_s;
   double D2_bound;       // upper bound of a stage-2 delay (s)
+  const double* x15;     // TDI 2.0 from TDI 1.5 (k_x20): the FP64 TDI 1.5 LFA series,
+  int64_t x15_stride;    // three channel arrays x15_stride apart (same offsets as the outputs)
 };
 
 __host__ __device__ inline const SrcDev* sources_of(const KParams* p) {
@@ -87,10 +89,15 @@ __host__ __device__ inline const SrcDev* sources_of(const KParams* p) {
 
 // Launch entry points (defined in tdi_kernels.hip).
 int set_constants();
-int launch_reset(uint32_t* counters, void* stream);
+int launch_reset(uint32_t* counters, void* stream);      // zeroes counters[0..15]
 // fast != 0 selects the FP32 bulk LFA kernel (fp32 must be 1)
-int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t lds_bytes, void* stream);
+// nx != 0: LFA with the next term (lfa_terms = 2; general kernel only)
+int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int nx, int grid, size_t lds_bytes, void* stream);
 int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
+// TDI 2.0 LFA from the TDI 1.5 LFA series in KParams::x15 (window capacity cap_g)
+int launch_x20(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
+int occupancy_x20(int taps, int fp32, size_t lds);
+size_t x20_lds_bytes(int cap);
 // link outputs: one workgroup per tile of kTileLinks samples (tile list in SrcDev::lfa_t0)
 int launch_links(const KParams* dp, int taps, int fp32, int64_t grid, size_t lds, void* stream);
 size_t links_lds_bytes(int cap, int fp32, int windows);
@@ -101,9 +108,9 @@ size_t fast_tile_bytes();     // bytes of one per-tile record
 // LFA dynamic LDS: h window (FP64), reused for the FP32 wave tables, then the
 // derivative window; goff receives the byte offset of the latter.  Fast path:
 // h window and the three F_l series, overlaid when one stencil sweep suffices.
-size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int* goff);
+size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int nx, int* goff);
 size_t full_lds_bytes(int cap_h, int cap_y, int fp32);
-int occupancy_lfa(int taps, int fp32, int fast, size_t lds);
+int occupancy_lfa(int taps, int fp32, int fast, int nx, size_t lds);
 int occupancy_full(int taps, int fp32, size_t lds);
 
 }  // namespace tdi

@@ -161,22 +161,24 @@ __device__ __forceinline__ void lag_weights(double x, double w[N]) {
 // Lagrange interpolation of NC interleaved series (element j*NC + c) at offset
 // x from the node block starting at b: prefix products forward, suffix products
 // and accumulation backward, so only the N prefix values are live.
-template <int N, int NC, typename TC>
-__device__ __forceinline__ void lag_interp(double x, const TC* __restrict__ b, TC out[NC]) {
+// Weights and sums in TA (the stored type by default; FP64 for exact reads of
+// FP32 series).
+template <int N, int NC, typename TC, typename TA = TC>
+__device__ __forceinline__ void lag_interp(double x, const TC* __restrict__ b, TA out[NC]) {
   double pre[N];
   pre[0] = 1.0;
 #pragma unroll
   for (int j = 1; j < N; ++j) pre[j] = pre[j - 1] * (x - (double)(j - N / 2));
   double suf = 1.0;
-  TC acc[NC];
+  TA acc[NC];
 #pragma unroll
-  for (int c = 0; c < NC; ++c) acc[c] = (TC)0;
+  for (int c = 0; c < NC; ++c) acc[c] = (TA)0;
 #pragma unroll
   for (int j = N - 1; j >= 0; --j) {
-    const TC w = (TC)(lag_norm<N>(j) * pre[j] * suf);
+    const TA w = (TA)(lag_norm<N>(j) * pre[j] * suf);
     suf *= (x - (double)(j + 1 - N / 2));
 #pragma unroll
-    for (int c = 0; c < NC; ++c) acc[c] += w * b[j * NC + c];
+    for (int c = 0; c < NC; ++c) acc[c] += w * (TA)b[j * NC + c];
   }
 #pragma unroll
   for (int c = 0; c < NC; ++c) out[c] = acc[c];
@@ -204,6 +206,17 @@ __constant__ double c_stnum[4][7] = {
 };
 __constant__ int c_sthw[4] = {1, 2, 2, 3};
 __constant__ double c_stden[4] = {1.0, 12.0, 2.0, 8.0};
+
+// Stencils of the next LFA term, derivative order m + 2 (4 for TDI 1.5, 5 for
+// TDI 2.0), same indexing and layout, zero padded to 9.
+__constant__ double c_stnum2[4][9] = {
+    {1, -4, 6, -4, 1, 0, 0, 0, 0},                // m + 2 = 4, p = 2
+    {-1, 12, -39, 56, -39, 12, -1, 0, 0},         // m + 2 = 4, p = 4
+    {-1, 4, -5, 0, 5, -4, 1, 0, 0},               // m + 2 = 5, p = 2
+    {1, -9, 26, -29, 0, 29, -26, 9, -1},          // m + 2 = 5, p = 4
+};
+__constant__ int c_sthw2[4] = {2, 3, 3, 4};
+__constant__ double c_stden2[4] = {1.0, 6.0, 2.0, 6.0};
 
 // Central stencil numerators (offsets -hw..hw) and denominators of derivative
 // order m (1, 2, 3) and accuracy p (2, 4).
@@ -440,6 +453,30 @@ __device__ __forceinline__ void lfa_use(const KParams& P, const double T3[3], co
   kx = sg * (xc3[l] * c2 - xp3[l] * s2);
 }
 
+// Coefficient of the next LFA term of use (l, side) (lfa_terms = 2): the read
+// of link l becomes Xi^(m) + kappa Xi^(m+2) with kappa = To^2/6 + Tl^2/8 +
+// Tl^2 (1 + (k.n_l)^2)/24, plus (Tl + To)^2/6 for TDI 2.0, To the other arm of
+// the use's channel.  This is the central expansion of App. B one order
+// further: the m = 1 term of Eq. (yslr_with_tau_derivatives) averaged over
+// the two directions of the arm, and the third-order terms of the TDI
+// combination of Eqs. (X1.5l2), (X1.5l3) (and of X2.0 = X1.5 - delayed X1.5).
+__device__ __forceinline__ double lfa_kappa(const KParams& P, const double T3[3], const double kn3[3],
+                                            int l, int side) {
+  const int c = chan_of_use(l, side);
+  const int o = side == 0 ? (c + 2) % 3 : (c + 1) % 3;   // the channel's other link
+  const double Tl = P.equal_arms ? P.orb.L_over_c : T3[l];
+  const double To = P.equal_arms ? P.orb.L_over_c : T3[o];
+  double kap = To * To / 6.0 + Tl * Tl / 8.0 + Tl * Tl * (1.0 + kn3[l] * kn3[l]) / 24.0;
+  if (P.gen == 20) kap += (Tl + To) * (Tl + To) / 6.0;
+  return kap;
+}
+
+// k.n of the positive links at sample k from the fit (D = 2 (1 - k.n)).
+__device__ __forceinline__ void lfa_kn(const GeoFit& F, double s, double kn3[3]) {
+#pragma unroll
+  for (int l = 0; l < 3; ++l) kn3[l] = 1.0 - 0.5 * geo_eval(F, qD(l), s);
+}
+
 // Positive-link geometry at sample k from the fit.
 __device__ __forceinline__ void lfa_geo(const GeoFit& F, double s, double T3[3], double xp3[3],
                                         double xc3[3], double mu3[3]) {
@@ -484,7 +521,7 @@ struct LfaShared {
   GeoFit F;
   int64_t src, k0, g0;
   int32_t cnt, ng, bad, nh;
-  double c2, s2, inv_scale, kH;
+  double c2, s2, inv_scale, inv_scale2, kH;
   double qext[2][2];
 };
 
@@ -496,7 +533,9 @@ struct WaveParams {
   float delta[6], a1[6], a2[6];       // eps_u(r) = delta - r (a1 + a2 r)
   float kp0[6], kp1[6], kp2[6];       // coefficient on g+ : kp0 + r (kp1 + r kp2)
   float kx0[6], kx1[6], kx2[6];
-  double vals[3][6][3];               // scratch: (point, use, {q, kp, kx})
+  float kq0[6], kq1[6], kq2[6];       // next term (lfa_terms = 2): coefficient on g+^(m+2)
+  float kz0[6], kz1[6], kz2[6];       // and on g_x^(m+2)
+  double vals[3][6][5];               // scratch: (point, use, {q, kp, kx, kq, kz})
 };
 
 constexpr size_t kWaveParamsBytes = align16(sizeof(WaveParams));
@@ -506,7 +545,64 @@ constexpr size_t wave_tables_bytes() {
   return 4 * kWaveParamsBytes + (size_t)4 * 3 * N * 16;
 }
 
-template <int N, typename TC>
+// One LFA output with exact FP64 Lagrange weights for each of its six reads
+// (the FP64 path, and the FP32 path next to the series ends, where the zero
+// extension makes the derivative series jump and an offset expansion fails).
+// The derivative window gwin holds NC components per element from g0 on.
+template <int N, typename TC, bool NX>
+__device__ __forceinline__ void lfa_exact_out(const KParams& P, const LfaShared& sh, const SrcDev& S,
+                                              const TC* __restrict__ gwin, int64_t g0, int ng, int64_t k,
+                                              double out[3]) {
+  constexpr int NC = NX ? 4 : 2;
+  const double s = ((double)k - sh.F.kc) * sh.F.ikh;
+  double T3[3], xp3[3], xc3[3], mu3[3], kn3[3];
+  lfa_geo(sh.F, s, T3, xp3, xc3, mu3);
+  if constexpr (NX) lfa_kn(sh.F, s, kn3);
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+#pragma unroll 1
+  for (int u = 0; u < 6; ++u) {
+    const int l = u >> 1, side = u & 1;
+    const int c = side == 0 ? (l + 2) % 3 : (l + 1) % 3;
+    const int a = (c + 1) % 3, bb = (c + 2) % 3;
+    const double Ta = P.equal_arms ? P.orb.L_over_c : sel3(T3[0], T3[1], T3[2], a);
+    const double Tb = P.equal_arms ? P.orb.L_over_c : sel3(T3[0], T3[1], T3[2], bb);
+    double pref, D;
+    if (P.gen == 20) { pref = -4.0 * Ta * Tb * (Ta + Tb); D = 2.0 * (Ta + Tb); }
+    else { pref = -2.0 * Ta * Tb; D = Ta + Tb; }
+    int64_t i0;
+    double x;
+    split(k, D + sel3(mu3[0], mu3[1], mu3[2], l), S.dt, i0, x);
+    const int64_t b = i0 - N / 2 + 1 - g0;
+    double v[NC];
+    if (b < 0 || b + N > ng) {
+      report(P.err, 2, k, b, ng);
+#pragma unroll
+      for (int q = 0; q < NC; ++q) v[q] = __builtin_nan("");
+    } else if (x == 0.0) {
+#pragma unroll
+      for (int q = 0; q < NC; ++q) v[q] = (double)gwin[NC * (b + N / 2 - 1) + q];
+    } else {
+      lag_interp<N, NC, TC, double>(x, gwin + NC * b, v);
+    }
+    double gp = (v[0] * sh.c2 - v[1] * sh.s2) * sh.inv_scale;   // rotation to the SSB frame
+    double gc = (v[0] * sh.s2 + v[1] * sh.c2) * sh.inv_scale;
+    if constexpr (NX) {
+      const double kap = lfa_kappa(P, T3, kn3, l, side) * sh.inv_scale2;
+      gp = fma(kap, v[NC - 2] * sh.c2 - v[NC - 1] * sh.s2, gp);
+      gc = fma(kap, v[NC - 2] * sh.s2 + v[NC - 1] * sh.c2, gc);
+    }
+    const double xi = sel3(xp3[0], xp3[1], xp3[2], l) * gp + sel3(xc3[0], xc3[1], xc3[2], l) * gc;
+    const double term = side == 0 ? pref * xi : -(pref * xi);
+    if (c == 0) acc0 += term; else if (c == 1) acc1 += term; else acc2 += term;
+  }
+  out[0] = acc0;
+  out[1] = acc1;
+  out[2] = acc2;
+}
+
+// NX: with the next term of the LFA (lfa_terms = 2); the derivative window then
+// holds four components per element, g+^(m), g_x^(m), g+^(m+2), g_x^(m+2).
+template <int N, typename TC, bool NX>
 __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ Pp) {
   const KParams& P = *Pp;
   const SrcDev* __restrict__ SS = sources_of(Pp);
@@ -515,10 +611,12 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
   extern __shared__ __align__(16) char dyn[];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   constexpr bool kF32 = sizeof(TC) == 4;
+  constexpr int NC = NX ? 4 : 2;                                 // components per element
   double* hwin = reinterpret_cast<double*>(dyn);                 // [nh][2], FP64
-  TC* gwin = reinterpret_cast<TC*>(dyn + P.lfa_goff);           // [ng][2]
+  TC* gwin = reinterpret_cast<TC*>(dyn + P.lfa_goff);           // [ng][NC]
   const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
-  const int hw = c_sthw[st];
+  const int hw1 = c_sthw[st];
+  const int hw = NX ? c_sthw2[st] : hw1;                         // half width of the h window margin
 
   int64_t iter = 0;
   for (;;) {
@@ -537,6 +635,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
       double sc = c_stden[st];
       for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
       sh.inv_scale = 1.0 / sc;
+      sh.inv_scale2 = 1.0 / (sc * (c_stden2[st] / c_stden[st]) * S.dt * S.dt);
       sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
     }
     __syncthreads();
@@ -592,21 +691,35 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
         hwin[2 * i + 1] = in ? P.hc[S.off + j] : 0.0;
       }
       __syncthreads();
-      // unscaled central stencil sum; 1/(den dt^m) is folded into the coefficients
+      // unscaled central stencil sums; 1/(den dt^m) is folded into the coefficients
       for (int i = tid; i < ng; i += kBlock) {
         const int64_t j = g0 + i;
-        double ap = 0.0, ac = 0.0;
+        double ap = 0.0, ac = 0.0, bp = 0.0, bc = 0.0;
         if (j >= 0 && j < S.n) {
+          const int c1 = i + hw - hw1;         // first sample of the order-m stencil
 #pragma unroll
           for (int s = 0; s < 7; ++s) {
-            if (s <= 2 * hw) {
-              ap = fma(c_stnum[st][s], hwin[2 * (i + s)], ap);
-              ac = fma(c_stnum[st][s], hwin[2 * (i + s) + 1], ac);
+            if (s <= 2 * hw1) {
+              ap = fma(c_stnum[st][s], hwin[2 * (c1 + s)], ap);
+              ac = fma(c_stnum[st][s], hwin[2 * (c1 + s) + 1], ac);
+            }
+          }
+          if constexpr (NX) {
+#pragma unroll
+            for (int s = 0; s < 9; ++s) {
+              if (s <= 2 * hw) {
+                bp = fma(c_stnum2[st][s], hwin[2 * (i + s)], bp);
+                bc = fma(c_stnum2[st][s], hwin[2 * (i + s) + 1], bc);
+              }
             }
           }
         }
-        gwin[2 * i] = (TC)ap;
-        gwin[2 * i + 1] = (TC)ac;
+        gwin[NC * i] = (TC)ap;
+        gwin[NC * i + 1] = (TC)ac;
+        if constexpr (NX) {
+          gwin[NC * i + 2] = (TC)bp;
+          gwin[NC * i + 3] = (TC)bc;
+        }
       }
     }
     __syncthreads();
@@ -629,8 +742,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
         if (lane < 3) {
           const double r = (double)(lane - 1) * hr;
           const double s = (kw + r - sh.F.kc) * sh.F.ikh;
-          double T3[3], xp3[3], xc3[3], mu3[3];
+          double T3[3], xp3[3], xc3[3], mu3[3], kn3[3];
           lfa_geo(sh.F, s, T3, xp3, xc3, mu3);
+          if constexpr (NX) lfa_kn(sh.F, s, kn3);
 #pragma unroll
           for (int l = 0; l < 3; ++l)
 #pragma unroll
@@ -641,11 +755,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
               wp->vals[lane][u][0] = d / S.dt;
               wp->vals[lane][u][1] = kp * sh.inv_scale;
               wp->vals[lane][u][2] = kx * sh.inv_scale;
+              if constexpr (NX) {
+                const double kap = lfa_kappa(P, T3, kn3, l, side) * sh.inv_scale2;
+                wp->vals[lane][u][3] = kp * kap;
+                wp->vals[lane][u][4] = kx * kap;
+              }
             }
         }
         wave_sync();
-        if (lane < 18) {
-          const int u = lane / 3, qi = lane % 3;
+        constexpr int NQ = NX ? 5 : 3;         // modelled quantities per use
+        if (lane < 6 * NQ) {
+          const int u = lane / NQ, qi = lane % NQ;
           const double v0 = wp->vals[0][u][qi], v1 = wp->vals[1][u][qi], v2 = wp->vals[2][u][qi];
           const double c1 = hr > 0.0 ? (v2 - v0) / (2.0 * hr) : 0.0;
           const double c2q = hr > 0.0 ? (v2 - 2.0 * v1 + v0) / (2.0 * hr * hr) : 0.0;
@@ -664,10 +784,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
             wp->kp0[u] = (float)v1;
             wp->kp1[u] = (float)c1;
             wp->kp2[u] = (float)c2q;
-          } else {
+          } else if (qi == 2) {
             wp->kx0[u] = (float)v1;
             wp->kx1[u] = (float)c1;
             wp->kx2[u] = (float)c2q;
+          } else if (qi == 3) {
+            wp->kq0[u] = (float)v1;
+            wp->kq1[u] = (float)c1;
+            wp->kq2[u] = (float)c2q;
+          } else {
+            wp->kz0[u] = (float)v1;
+            wp->kz1[u] = (float)c1;
+            wp->kz2[u] = (float)c2q;
           }
         }
         wave_sync();
@@ -688,9 +816,13 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
         wave_sync();
 
         float X0[4], X1[4], X2[4];
+        bool near_end[4];                      // some read's nodes touch a series end
 #pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) X0[s4] = X1[s4] = X2[s4] = 0.0f;
-        const float2* g2 = reinterpret_cast<const float2*>(gwin);
+        for (int s4 = 0; s4 < 4; ++s4) {
+          X0[s4] = X1[s4] = X2[s4] = 0.0f;
+          near_end[s4] = false;
+        }
+        const float* gf = reinterpret_cast<const float*>(gwin);
         bool okall = true;
 #pragma unroll 1
         for (int l = 0; l < 3; ++l) {
@@ -704,25 +836,30 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
             const bool inwin = b >= 0 && b + N <= ng;
             if (live && !inwin) { okall = false; report(P.err, 2, k, b, ng); }
             base[s4] = inwin ? (int)b : 0;
+            // nodes j0 .. j0 + N - 1 (one more either side for the offset spread)
+            // against the elements where the zero-extended stencil output jumps
+            const int64_t j0 = k - mb - N / 2 + 1;
+            near_end[s4] = near_end[s4] || (j0 - 1 <= hw + 1 && j0 + N >= -hw - 2) ||
+                           (j0 - 1 <= S.n + hw + 1 && j0 + N >= S.n - hw - 2);
           }
-          float A[4][2], B[4][2], Cc[4][2];
+          float A[4][NC], B[4][NC], Cc[4][NC];
 #pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) {
-            A[s4][0] = A[s4][1] = B[s4][0] = B[s4][1] = Cc[s4][0] = Cc[s4][1] = 0.0f;
-          }
+          for (int s4 = 0; s4 < 4; ++s4)
+#pragma unroll
+            for (int q = 0; q < NC; ++q) A[s4][q] = B[s4][q] = Cc[s4][q] = 0.0f;
           const float4* wl = wts + l * N;
 #pragma unroll 2
           for (int j = 0; j < N; ++j) {
             const float4 w = wl[j];
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
-              const float2 g = g2[base[s4] + j];
-              A[s4][0] = fmaf(w.x, g.x, A[s4][0]);
-              A[s4][1] = fmaf(w.x, g.y, A[s4][1]);
-              B[s4][0] = fmaf(w.y, g.x, B[s4][0]);
-              B[s4][1] = fmaf(w.y, g.y, B[s4][1]);
-              Cc[s4][0] = fmaf(w.z, g.x, Cc[s4][0]);
-              Cc[s4][1] = fmaf(w.z, g.y, Cc[s4][1]);
+#pragma unroll
+              for (int q = 0; q < NC; ++q) {
+                const float g = gf[NC * (base[s4] + j) + q];
+                A[s4][q] = fmaf(w.x, g, A[s4][q]);
+                B[s4][q] = fmaf(w.y, g, B[s4][q]);
+                Cc[s4][q] = fmaf(w.z, g, Cc[s4][q]);
+              }
             }
           }
 #pragma unroll
@@ -737,11 +874,17 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
               const float r = (float)(lane + 64 * s4) - (float)hr;
               const float eps = dl - r * fmaf(a2, r, a1);
               const float hh = 0.5f * eps;
-              const float Ip = fmaf(eps, fmaf(hh, Cc[s4][0], B[s4][0]), A[s4][0]);
-              const float Ix = fmaf(eps, fmaf(hh, Cc[s4][1], B[s4][1]), A[s4][1]);
+              float I[NC];
+#pragma unroll
+              for (int q = 0; q < NC; ++q) I[q] = fmaf(eps, fmaf(hh, Cc[s4][q], B[s4][q]), A[s4][q]);
               const float kp = fmaf(r, fmaf(r, p2, p1), p0);
               const float kx = fmaf(r, fmaf(r, x2, x1), x0);
-              const float v = fmaf(kp, Ip, kx * Ix);
+              float v = fmaf(kp, I[0], kx * I[1]);
+              if constexpr (NX) {
+                const float kq = fmaf(r, fmaf(r, wp->kq2[u], wp->kq1[u]), wp->kq0[u]);
+                const float kz = fmaf(r, fmaf(r, wp->kz2[u], wp->kz1[u]), wp->kz0[u]);
+                v = fmaf(kq, I[NC - 2], fmaf(kz, I[NC - 1], v));
+              }
               if (c == 0) X0[s4] += v;
               else if (c == 1) X1[s4] += v;
               else X2[s4] += v;
@@ -754,6 +897,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
           if (i >= wcnt) continue;
           const int64_t k = kw0 + i;
           float x = X0[s4], y = X1[s4], z = X2[s4];
+          if (near_end[s4]) {
+            // the expansion in the offset needs smooth data: exact weights here
+            double o[3];
+            lfa_exact_out<N, TC, NX>(P, sh, S, gwin, g0, ng, k, o);
+            x = (float)o[0];
+            y = (float)o[1];
+            z = (float)o[2];
+          }
           if (!okall) x = y = z = __builtin_nanf("");
           if (P.mode == 2) {
             const double rel = (double)k - kH;
@@ -784,43 +935,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
         if (bad) {
           out[0] = out[1] = out[2] = __builtin_nan("");
         } else {
-          const double s = ((double)k - sh.F.kc) * sh.F.ikh;
-          double T3[3], xp3[3], xc3[3], mu3[3];
-          lfa_geo(sh.F, s, T3, xp3, xc3, mu3);
-          double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
-#pragma unroll 1
-          for (int u = 0; u < 6; ++u) {
-            const int l = u >> 1, side = u & 1;
-            const int c = side == 0 ? (l + 2) % 3 : (l + 1) % 3;
-            const int a = (c + 1) % 3, bb = (c + 2) % 3;
-            const double Ta = P.equal_arms ? P.orb.L_over_c : sel3(T3[0], T3[1], T3[2], a);
-            const double Tb = P.equal_arms ? P.orb.L_over_c : sel3(T3[0], T3[1], T3[2], bb);
-            double pref, D;
-            if (P.gen == 20) { pref = -4.0 * Ta * Tb * (Ta + Tb); D = 2.0 * (Ta + Tb); }
-            else { pref = -2.0 * Ta * Tb; D = Ta + Tb; }
-            int64_t i0;
-            double x;
-            split(k, D + sel3(mu3[0], mu3[1], mu3[2], l), S.dt, i0, x);
-            const int64_t b = i0 - N / 2 + 1 - g0;
-            double v[2];
-            if (b < 0 || b + N > ng) {
-              report(P.err, 2, k, b, ng);
-              v[0] = v[1] = __builtin_nan("");
-            } else if (x == 0.0) {
-              v[0] = (double)gwin[2 * (b + N / 2 - 1)];
-              v[1] = (double)gwin[2 * (b + N / 2 - 1) + 1];
-            } else {
-              lag_interp<N, 2, TC>(x, gwin + 2 * b, v);
-            }
-            const double gp = (v[0] * sh.c2 - v[1] * sh.s2) * sh.inv_scale;   // rotation to the SSB frame
-            const double gc = (v[0] * sh.s2 + v[1] * sh.c2) * sh.inv_scale;
-            const double xi = sel3(xp3[0], xp3[1], xp3[2], l) * gp + sel3(xc3[0], xc3[1], xc3[2], l) * gc;
-            const double term = side == 0 ? pref * xi : -(pref * xi);
-            if (c == 0) acc0 += term; else if (c == 1) acc1 += term; else acc2 += term;
-          }
-          out[0] = acc0;
-          out[1] = acc1;
-          out[2] = acc2;
+          lfa_exact_out<N, TC, NX>(P, sh, S, gwin, g0, ng, k, out);
         }
         if (P.mode == 2) {
           const double rel = (double)k - kH;
@@ -1220,9 +1335,12 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
   float* Fw = reinterpret_cast<float*>(dyn);                        // [3][ngp], FP32
   const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
   const int hw = c_sthw[st];
-  double stn[7];
+  // the stencil as a centre weight and three pair weights (offsets +-1..3,
+  // zero beyond hw): even orders sum the pairs, odd orders difference them
+  const bool odd = (P.stencil_m & 1) != 0;
+  double stc[4];
 #pragma unroll
-  for (int s = 0; s < 7; ++s) stn[s] = c_stnum[st][s];
+  for (int k = 0; k < 4; ++k) stc[k] = k <= hw ? c_stnum[st][hw + k] : 0.0;
   const int ne = N + kFR + 2 * hw + 8;          // raw pairs kept at each end
 
   int64_t iter = 0;
@@ -1259,6 +1377,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
 #pragma unroll
             for (int m = 0; m < 3; ++m) pcv[l][q][m] = (float)R.pc[l][q][m];
         }
+        constexpr int kSM = kSR / 2;                 // middle element of a thread's run
         for (int base = 0; base < ng; base += kSR * kBlock) {
           const int i0 = base + kSR * tid;
           if (i0 < ng) {
@@ -1270,12 +1389,23 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             const int es0 = (int)min(max((int64_t)ne - j0, (int64_t)0), (int64_t)kSR);
             const int es1 = (int)min(max(n - ne - j0, (int64_t)0), (int64_t)kSR);
             const bool near_end = es0 > 0 || es1 < kSR;
-            const float uf0 = (float)i0;
-            // samples j0 - hw + m, m < kSR + 6, inside the series for m in [mlo, mhi)
-            const int mlo = (int)min(max((int64_t)hw - j0, (int64_t)0), (int64_t)(kSR + 6));
-            const int mhi = (int)min(max(n - j0 + hw, (int64_t)0), (int64_t)(kSR + 6));
-            const double* __restrict__ hpb = P.hp + off + (j0 - hw);
-            const double* __restrict__ hcb = P.hc + off + (j0 - hw);
+            // the coefficients over the thread's kSR elements: tangent lines of the
+            // chunk's quadratics at the middle element (the curvature term over
+            // +-5 samples is ~1e-10 of the coefficient)
+            float cpm[3], cpd[3], cxm[3], cxd[3];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+              const float u = (float)(i0 + kSM) - ecv[l];
+              cpm[l] = fmaf(u, fmaf(u, pcv[l][0][2], pcv[l][0][1]), pcv[l][0][0]);
+              cpd[l] = fmaf(2.0f * u, pcv[l][0][2], pcv[l][0][1]);
+              cxm[l] = fmaf(u, fmaf(u, pcv[l][1][2], pcv[l][1][1]), pcv[l][1][0]);
+              cxd[l] = fmaf(2.0f * u, pcv[l][1][2], pcv[l][1][1]);
+            }
+            // samples j0 - 3 + m, m < kSR + 6, inside the series for m in [mlo, mhi)
+            const int mlo = (int)min(max((int64_t)3 - j0, (int64_t)0), (int64_t)(kSR + 6));
+            const int mhi = (int)min(max(n - j0 + 3, (int64_t)0), (int64_t)(kSR + 6));
+            const double* __restrict__ hpb = P.hp + off + (j0 - 3);
+            const double* __restrict__ hcb = P.hc + off + (j0 - 3);
             double hp_[kSR + 6], hc_[kSR + 6];
             // the strain loads go out ahead of the other waves' arithmetic
             __builtin_amdgcn_s_setprio(1);
@@ -1288,12 +1418,23 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int e = 0; e < kSR; ++e) {
-              // all seven taps: the coefficient rows are zero beyond 2 hw
-              double ap = 0.0, ac = 0.0;
+              // element e sits at hp_[e + 3]; pair weights are zero beyond hw
+              double ap, ac;
+              if (odd) {
+                ap = stc[1] * (hp_[e + 4] - hp_[e + 2]);
+                ac = stc[1] * (hc_[e + 4] - hc_[e + 2]);
+                ap = fma(stc[2], hp_[e + 5] - hp_[e + 1], ap);
+                ac = fma(stc[2], hc_[e + 5] - hc_[e + 1], ac);
+                ap = fma(stc[3], hp_[e + 6] - hp_[e], ap);
+                ac = fma(stc[3], hc_[e + 6] - hc_[e], ac);
+              } else {
+                ap = stc[0] * hp_[e + 3];
+                ac = stc[0] * hc_[e + 3];
 #pragma unroll
-              for (int s = 0; s < 7; ++s) {
-                ap = fma(stn[s], hp_[e + s], ap);
-                ac = fma(stn[s], hc_[e + s], ac);
+                for (int k = 1; k < 4; ++k) {
+                  ap = fma(stc[k], hp_[e + 3 + k] + hp_[e + 3 - k], ap);
+                  ac = fma(stc[k], hc_[e + 3 + k] + hc_[e + 3 - k], ac);
+                }
               }
               const bool in = e >= elo && e < ehi;
               if (!in) ap = ac = 0.0;
@@ -1304,9 +1445,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
               }
 #pragma unroll
               for (int l = 0; l < 3; ++l) {
-                const float u = (uf0 + (float)e) - ecv[l];
-                const float cp = fmaf(u, fmaf(u, pcv[l][0][2], pcv[l][0][1]), pcv[l][0][0]);
-                const float cx = fmaf(u, fmaf(u, pcv[l][1][2], pcv[l][1][1]), pcv[l][1][0]);
+                const float cp = fmaf((float)(e - kSM), cpd[l], cpm[l]);
+                const float cx = fmaf((float)(e - kSM), cxd[l], cxm[l]);
                 if (i0 + e < ng) Fw[l * ngp + i0 + e] = fmaf(cp, gp, cx * gx);
               }
             }
@@ -1399,7 +1539,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
               // w = p(e) = c.x + c.y e + c.z e^2 + c.w e^3 by Horner; its slope
               // p'(e) = c.y + 2 c.z e + 3 c.w e^2 is taken as b1 + e b2 = c.y + 2 c.z e
               // + 2 c.w e^2: it only multiplies the per-use offset delta (<= 1e-3),
-              // so the dropped c.w e^2 delta is of fifth order in the offsets
+              // so the dropped c.w e^2 delta is of fifth order in the offsets.  The
+              // slope must be that of the same N-node interpolant: a shorter stencil
+              // differs from it by O(1) of the local jump where the data have a kink
+              // (a merger cut), and parity with the oracle's exact read is lost there.
               const float b2 = fmaf(eL, c.w, c.z);
               const float b1 = fmaf(eL, b2, c.y);
               const float w = fmaf(eL, b1, c.x);
@@ -1410,16 +1553,19 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
                 B[q] = fmaf(wd, win[j + q], B[q]);
               }
             }
+            // per use: I = A + delta B, delta linear in the output index over
+            // the lane's kFR outputs (the offset's curvature over 2 kFR samples
+            // is below 1e-8 samples)
             float Iv[2][kFR];
 #pragma unroll
             for (int side = 0; side < 2; ++side) {
               const int u = 2 * l + side;
-              const float dl = Wv.dl[u] - eLm, a1 = Wv.a1[u], a2 = Wv.a2[u];
+              const float a1 = Wv.a1[u], a2 = Wv.a2[u];
+              const float d0 = (side == 0 ? e0 : e1) - eLm;
+              const float sl = fmaf(2.0f * a2, rL, a1);
 #pragma unroll
-              for (int q = 0; q < kFR; ++q) {
-                const float r = rL + (float)(q - kFR / 2);
-                Iv[side][q] = fmaf(dl - r * fmaf(a2, r, a1), B[q], A[q]);
-              }
+              for (int q = 0; q < kFR; ++q)
+                Iv[side][q] = fmaf(fmaf((float)(kFR / 2 - q), sl, d0), B[q], A[q]);
             }
             // side 0 feeds channel (l+2)%3 (Xa), side 1 channel (l+1)%3 (Xb); most
             // waves take every use (no crossing, no edge) and skip the mask tests
@@ -1427,11 +1573,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
 #pragma unroll
               for (int side = 0; side < 2; ++side) {
                 const int u = 2 * l + side;
-                const float c0 = Wv.c0[u], c1 = Wv.c1[u];
+                const float c1 = Wv.c1[u], cL = fmaf(rL, c1, Wv.c0[u]);
 #pragma unroll
                 for (int q = 0; q < kFR; ++q) {
-                  const float r = rL + (float)(q - kFR / 2);
-                  const float cf = fmaf(r, c1, c0);
+                  const float cf = fmaf((float)(q - kFR / 2), c1, cL);
                   if (side == 0) Xa[q] = fmaf(cf, Iv[0][q], Xa[q]);
                   else Xb[q] = fmaf(cf, Iv[1][q], Xb[q]);
                 }
@@ -1440,11 +1585,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
 #pragma unroll
               for (int side = 0; side < 2; ++side) {
                 const int u = 2 * l + side;
-                const float c0 = Wv.c0[u], c1 = Wv.c1[u];
+                const float c1 = Wv.c1[u], cL = fmaf(rL, c1, Wv.c0[u]);
 #pragma unroll
                 for (int q = 0; q < kFR; ++q) {
-                  const float r = rL + (float)(q - kFR / 2);
-                  const float cf = fmaf(r, c1, c0);
+                  const float cf = fmaf((float)(q - kFR / 2), c1, cL);
                   if ((take >> (side * kFR + q)) & 1u) {
                     if (side == 0) Xa[q] = fmaf(cf, Iv[0][q], Xa[q]);
                     else Xb[q] = fmaf(cf, Iv[1][q], Xb[q]);
@@ -1560,6 +1704,153 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
       }
       __syncthreads();
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// TDI 2.0 LFA from the TDI 1.5 LFA series, Eq. (relation_X20_X15_nonequal_
+// timedelays): X2.0(t_k) = 2 (T2+T3)(t_k) I_N[D1 X1.5](k - (T2+T3)(t_k)/dt),
+// Y and Z by cyclic relabelling (equal arms: 4L/c and 2L/c).  The TDI 1.5 LFA
+// series of every sample of each source comes from an earlier FP64 launch of
+// the LFA kernel into P.x15 (three channel arrays of P.x15_stride doubles).
+// Per tile of kTileLfa outputs its window is staged in LDS, differentiated by
+// the central first-derivative stencil of accuracy p (zero outside the series),
+// and read at the fractional delay with exact FP64 Lagrange weights.
+// ---------------------------------------------------------------------------
+struct X20Shared {
+  GeoFit F;
+  int64_t src, k0, g0;
+  int32_t cnt, nw, bad;
+  double kH;
+  double qext[2][2];
+};
+
+template <int N, typename TC>
+__global__ __launch_bounds__(kBlock, 2) void k_x20(const KParams* __restrict__ Pp) {
+  const KParams& P = *Pp;
+  const SrcDev* __restrict__ SS = sources_of(Pp);
+  __shared__ X20Shared sh;
+  __shared__ int64_t s_next;
+  extern __shared__ __align__(16) char dyn[];
+  const int cap = P.cap_g;
+  double* xw = reinterpret_cast<double*>(dyn);            // [3][cap]: X1.5 window
+  double* dw = xw + 3 * (size_t)cap;                       // [3][cap]: its first derivative
+  const int tid = threadIdx.x;
+  double sc[7], den;
+  int hw;
+  stencil_coeffs(1, P.stencil_p, sc, hw, den);
+
+  int64_t iter = 0;
+  for (;;) {
+    const int64_t tile = next_tile(P, P.counters + 0, P.n_tiles_lfa, iter, &s_next);
+    if (tile >= P.n_tiles_lfa) break;
+    if (tid == 0) {
+      const int64_t s = find_source(SS, P.n_src, tile, true);
+      const SrcDev& S = SS[s];
+      sh.src = s;
+      sh.k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfa;
+      sh.cnt = (int32_t)min((int64_t)kTileLfa, S.lfa_ke - sh.k0);
+      sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+    }
+    __syncthreads();
+    const SrcDev& S = SS[sh.src];
+    const int64_t k0 = sh.k0;
+    const int cnt = sh.cnt;
+    fit_geometry(P, S, (double)k0, (double)(k0 + cnt - 1), sh.F);
+    // window of the derivative series from the three channel delays at both ends
+    if (tid < 2) {
+      const int64_t k = tid == 0 ? k0 : k0 + cnt - 1;
+      const double s = ((double)k - sh.F.kc) * sh.F.ikh;
+      double qmin = 1e300, qmax = -1e300;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double Ta = P.equal_arms ? P.orb.L_over_c : geo_eval(sh.F, qT((c + 1) % 3), s);
+        const double Tb = P.equal_arms ? P.orb.L_over_c : geo_eval(sh.F, qT((c + 2) % 3), s);
+        qmin = fmin(qmin, (Ta + Tb) / S.dt);
+        qmax = fmax(qmax, (Ta + Tb) / S.dt);
+      }
+      sh.qext[tid][0] = qmin;
+      sh.qext[tid][1] = qmax;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      const double qmin = fmin(sh.qext[0][0], sh.qext[1][0]);
+      const double qmax = fmax(sh.qext[0][1], sh.qext[1][1]);
+      const int margin = 2 + (int)ceil(4e-4 * (double)cnt);
+      sh.g0 = k0 - (int64_t)ceil(qmax) - N / 2 + 1 - margin;
+      const int64_t g1 = k0 + cnt - 1 - (int64_t)floor(qmin) + N / 2 + margin;
+      sh.nw = (int32_t)(g1 - sh.g0 + 1);
+      sh.bad = sh.nw + 2 * hw > cap ? 1 : 0;
+      if (sh.bad) report(P.err, 1, k0, sh.nw, cap);
+    }
+    __syncthreads();
+    const int64_t g0 = sh.g0;
+    const int nw = sh.nw;
+    const bool bad = sh.bad != 0;
+    const double kH = sh.kH;
+    if (!bad) {
+      for (int i = tid; i < nw + 2 * hw; i += kBlock) {
+        const int64_t j = g0 - hw + i;
+        const bool in = j >= 0 && j < S.n;
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          xw[c * cap + i] = in ? P.x15[(size_t)c * P.x15_stride + S.off + j] : 0.0;
+      }
+      __syncthreads();
+      const double iden = 1.0 / (den * S.dt);
+      for (int i = tid; i < nw; i += kBlock) {
+        const int64_t j = g0 + i;
+        const bool in = j >= 0 && j < S.n;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double a = 0.0;
+          for (int q = 0; q <= 2 * hw; ++q) a = fma(sc[q], xw[c * cap + i + q], a);
+          dw[c * cap + i] = in ? a * iden : 0.0;
+        }
+      }
+      __syncthreads();
+    }
+    for (int i = tid; i < cnt; i += kBlock) {
+      const int64_t k = k0 + i;
+      double out[3];
+      if (bad) {
+        out[0] = out[1] = out[2] = __builtin_nan("");
+      } else {
+        const double s = ((double)k - sh.F.kc) * sh.F.ikh;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double Ta = P.equal_arms ? P.orb.L_over_c : geo_eval(sh.F, qT((c + 1) % 3), s);
+          const double Tb = P.equal_arms ? P.orb.L_over_c : geo_eval(sh.F, qT((c + 2) % 3), s);
+          int64_t i0;
+          double x;
+          split(k, Ta + Tb, S.dt, i0, x);
+          const int64_t b = i0 - N / 2 + 1 - g0;
+          double v;
+          if (b < 0 || b + N > nw) {
+            report(P.err, 2, k, b, nw);
+            v = __builtin_nan("");
+          } else if (x == 0.0) {
+            v = dw[c * cap + b + N / 2 - 1];
+          } else {
+            lag_interp<N, 1, double>(x, dw + c * cap + b, &v);
+          }
+          out[c] = 2.0 * (Ta + Tb) * v;
+        }
+      }
+      if (P.mode == 2) {
+        const double rel = (double)k - kH;
+        if (rel <= 0.5 * P.T_s) {
+          const double w = 1.0 / (1.0 + exp(rel / P.sigma_s));
+          out[0] *= w;
+          out[1] *= w;
+          out[2] *= w;
+        } else {
+          out[0] = out[1] = out[2] = 0.0;
+        }
+      }
+      store3<TC>(P, S.off + k, (TC)out[0], (TC)out[1], (TC)out[2]);
+    }
+    __syncthreads();
   }
 }
 
@@ -2023,13 +2314,27 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
 }
 
 __global__ void k_reset(uint32_t* counters) {
-  if (threadIdx.x < 2) counters[threadIdx.x] = 0u;
+  if (threadIdx.x < 16) counters[threadIdx.x] = 0u;
 }
 
 template <int N, typename TC>
-int launch_lfa_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((k_lfa<N, TC>), dim3(grid), dim3(kBlock), lds, st, dp);
+int launch_lfa_t(const KParams* dp, int nx, int grid, size_t lds, hipStream_t st) {
+  if (nx) hipLaunchKernelGGL((k_lfa<N, TC, true>), dim3(grid), dim3(kBlock), lds, st, dp);
+  else hipLaunchKernelGGL((k_lfa<N, TC, false>), dim3(grid), dim3(kBlock), lds, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, typename TC>
+int launch_x20_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
+  hipLaunchKernelGGL((k_x20<N, TC>), dim3(grid), dim3(kBlock), lds, st, dp);
+  return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, typename TC>
+int occ_x20_t(size_t lds) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_x20<N, TC>), kBlock, lds) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
 }
 
 template <int N, typename TC>
@@ -2064,9 +2369,11 @@ int occ_lfa_fast_t(size_t lds) {
 }
 
 template <int N, typename TC>
-int occ_lfa_t(size_t lds) {
+int occ_lfa_t(int nx, size_t lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_lfa<N, TC>), kBlock, lds) != hipSuccess) return 1;
+  const void* f = nx ? reinterpret_cast<const void*>(&k_lfa<N, TC, true>)
+                     : reinterpret_cast<const void*>(&k_lfa<N, TC, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, lds) != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 
@@ -2188,7 +2495,7 @@ int set_constants() {
 
 size_t fast_tile_bytes() { return sizeof(FastTile); }
 
-size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int* goff) {
+size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int nx, int* goff) {
   if (fast) {                                // the three F_l series only
     if (goff) *goff = 0;
     return align16((size_t)3 * (cap_g + kFR + 1) * sizeof(float));
@@ -2198,7 +2505,7 @@ size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int* go
   const size_t wb = align16(wave_bytes(taps, fp32));
   if (wb > hb) hb = wb;
   if (goff) *goff = (int)hb;
-  return hb + align16((size_t)cap_g * 2 * tcs);
+  return hb + align16((size_t)cap_g * (nx ? 4 : 2) * tcs);
 }
 
 size_t full_lds_bytes(int cap_h, int cap_y, int fp32) {
@@ -2212,13 +2519,13 @@ int launch_reset(uint32_t* counters, void* stream) {
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int grid, size_t lds, void* stream) {
+int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int nx, int grid, size_t lds, void* stream) {
   if (fast) {
-    if (!fp32) return -2;
+    if (!fp32 || nx) return -2;
     TDI_DISPATCH_FAST(taps, launch_lfa_fast_t, dp, grid, lds, (hipStream_t)stream);
     return -2;
   }
-  TDI_DISPATCH(taps, fp32, launch_lfa_t, dp, grid, lds, (hipStream_t)stream);
+  TDI_DISPATCH(taps, fp32, launch_lfa_t, dp, nx, grid, lds, (hipStream_t)stream);
   return -2;
 }
 
@@ -2226,6 +2533,18 @@ int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream) {
   TDI_DISPATCH_FAST(taps, launch_lfa_fit_t, dp, grid, (hipStream_t)stream);
   return -2;
 }
+
+int launch_x20(const KParams* dp, int taps, int fp32, int grid, size_t lds, void* stream) {
+  TDI_DISPATCH(taps, fp32, launch_x20_t, dp, grid, lds, (hipStream_t)stream);
+  return -2;
+}
+
+int occupancy_x20(int taps, int fp32, size_t lds) {
+  TDI_DISPATCH(taps, fp32, occ_x20_t, lds);
+  return 1;
+}
+
+size_t x20_lds_bytes(int cap) { return (size_t)6 * cap * sizeof(double); }
 
 int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds, void* stream) {
   TDI_DISPATCH(taps, fp32, launch_full_t, dp, grid, lds, (hipStream_t)stream);
@@ -2243,12 +2562,12 @@ size_t links_lds_bytes(int cap, int fp32, int windows) {
   return align16((size_t)cap * 2 * e) * (size_t)windows;
 }
 
-int occupancy_lfa(int taps, int fp32, int fast, size_t lds) {
+int occupancy_lfa(int taps, int fp32, int fast, int nx, size_t lds) {
   if (fast) {
     TDI_DISPATCH_FAST(taps, occ_lfa_fast_t, lds);
     return 1;
   }
-  TDI_DISPATCH(taps, fp32, occ_lfa_t, lds);
+  TDI_DISPATCH(taps, fp32, occ_lfa_t, nx, lds);
   return 1;
 }
 

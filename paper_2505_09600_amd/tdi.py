@@ -56,7 +56,8 @@ class tdi_config(C.Structure):
                 ("precision", C.c_int32), ("hyb_T_samples", C.c_double),
                 ("hyb_sigma_samples", C.c_double), ("autotune", C.c_int32),
                 ("use_graph", C.c_int32), ("channels", C.c_int32), ("lfa_terms", C.c_int32),
-                ("nested_delays", C.c_int32), ("fast_tile_chunks", C.c_int32)]
+                ("nested_delays", C.c_int32), ("fast_tile_chunks", C.c_int32),
+                ("lfa_x20_from_x15", C.c_int32)]
 
 
 class tdi_noise(C.Structure):
@@ -195,7 +196,8 @@ def make_config(d: dict, autotune: int = 0, use_graph: int = 0) -> tdi_config:
                       int(d.get("equal_arms", 0)), int(d.get("precision", 0)),
                       float(d["T_samples"]), float(d["sigma_samples"]), int(autotune), int(use_graph),
                       int(d.get("channels", 0)), int(d.get("lfa_terms", 0)),
-                      int(d.get("nested_delays", 0)), int(d.get("fast_tile_chunks", 0)))
+                      int(d.get("nested_delays", 0)), int(d.get("fast_tile_chunks", 0)),
+                      int(d.get("x20_from_x15", 0)))
 
 
 def make_sources(records) -> C.Array:

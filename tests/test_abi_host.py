@@ -69,6 +69,8 @@ def test_status_strings(L):
     ("fast_tile_chunks", 3, T.TDI_ERANGE),
     ("fast_tile_chunks", 8, T.TDI_ERANGE),
     ("fast_tile_chunks", -1, T.TDI_ERANGE),
+    ("lfa_x20_from_x15", 2, T.TDI_ERANGE),
+    ("lfa_x20_from_x15", -1, T.TDI_ERANGE),
 ])
 def test_config_validation(L, field, value, code):
     c = _cfg()
@@ -245,8 +247,19 @@ def test_noalloc_host_checks_before_device(L):
     tab = W.keplerian_orbit_table(0.0, 1.0e4, 64)
     torb = T.make_orbit(W.table_orbit(tab, 0.0, 1.0e4))
     assert run(cfg, torb, 3, src, offs, fake, fake, fake, fake, fake) == T.TDI_EUNSUPPORTED
-    # the next term of the LFA is refused for X, Y, Z as by tdi_run
-    assert run(_cfg(lfa_terms=2), orb, 3, src, offs, fake, fake, fake, fake, fake) == T.TDI_EUNSUPPORTED
     import torch
     if not torch.cuda.is_available():
         assert run(cfg, orb, 3, src, offs, fake, fake, fake, fake, fake) == T.TDI_EDEVICE
+
+
+def test_x20_shortcut_validation(L):
+    """The TDI 2.0-from-1.5 LFA exists for TDI 2.0 only, is not combined with the
+    next LFA term, and is not offered without allocation."""
+    c = _cfg(x20_from_x15=1)
+    assert T.tdi_check_config(c, _orb()) == T.TDI_OK
+    assert T.tdi_check_config(_cfg(x20_from_x15=1, tdi_gen=15), _orb()) == T.TDI_ERANGE
+    assert T.tdi_check_config(_cfg(x20_from_x15=1, lfa_terms=2), _orb()) == T.TDI_EUNSUPPORTED
+    src = T.make_sources(_recs(3))
+    fake = 1 << 20
+    assert T.tdi_run_noalloc(c, _orb(), 3, src, [0, 100, 200, 300], fake, fake, fake, fake,
+                             fake) == T.TDI_EUNSUPPORTED

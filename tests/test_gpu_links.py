@@ -128,16 +128,3 @@ def test_links_next_term(tdi, orc, mode, prec):
     orb = W.default_orbit()
     got = _gpu_links(tdi, batch, cfg, orb)
     _check(orc, f"links lfa two terms mode{mode} prec{prec}", batch, cfg, orb, got, TOL[prec])
-
-
-def test_tdi_run_refuses_the_next_term(tdi):
-    import torch
-    batch = _ragged()
-    cfg = W.default_config(tdi_gen=20, mode=1, taps=32, stencil_order=4, precision=1)
-    cfg["lfa_terms"] = 2
-    hp = torch.as_tensor(np.asarray(batch.hp), dtype=torch.float64, device="cuda:0")
-    hc = torch.as_tensor(np.asarray(batch.hc), dtype=torch.float64, device="cuda:0")
-    with tdi.Plan(cfg, W.default_orbit(), batch.n_sources, batch.total) as p:
-        with pytest.raises(tdi.TdiError) as e:
-            p.run(batch.sources, batch.offsets, hp, hc)
-        assert e.value.status == tdi.TDI_EUNSUPPORTED
