@@ -23,7 +23,8 @@ namespace {
 
 constexpr double kC = 299792458.0;
 constexpr int kEventRing = 256;
-constexpr int kEvPerRun = 4;     // before the fit pre-pass, before / after the LFA kernel, after the full kernel
+constexpr int kEvPerRun = 4;
+constexpr size_t kCtrBytes = 256;     // counters in front of a parameter block     // before the fit pre-pass, before / after the LFA kernel, after the full kernel
 
 struct Launch {
   int grid_lfa;      // 0 = one workgroup per tile
@@ -63,17 +64,33 @@ struct tdi_plan {
   int64_t fit_tiles;             // their capacity (tiles)
   size_t params_bytes;
   int32_t* d_err;
-  uint32_t* d_counters;
+  // parameter blocks are allocated with kCtrBytes in front for the work
+  // counters of the persistent kernels; the upload of each run copies that
+  // prefix as zeros, so no separate reset is launched
+  unsigned char* d_block;
+  unsigned char* h_block;        // the staging image in use (one of h_blk)
+  unsigned char* d_block15;
+  unsigned char* h_block15;
   // TDI 2.0 LFA from TDI 1.5: the FP64 TDI 1.5 LFA series and its own parameter block
   double* d_x15;
   tdi::KParams* d_params15;
   tdi::KParams* h_params15;
   tdi_config cfg15;
   // pinned staging image of the parameter block
-  tdi::KParams* h_params;
-  hipEvent_t staged_free;        // recorded after the upload of the previous run
+  tdi::KParams* h_params;        // its parameter block
+  // two pinned staging images, used in turn, so that the host stages run i + 1
+  // while the device still runs run i; an image is rewritten only after the
+  // work that uploaded it has completed (its event)
+  unsigned char* h_blk[2];
+  tdi::KParams* h_par[2];
+  hipEvent_t stage_ev[2];
+  bool stage_pending[2];
+  int stage_slot;                // slot of the next run
+  bool double_buffer;            // false if the graph's upload node cannot be retargeted
+  hipGraphNode_t graph_mnode;    // the upload (memcpy) node of the graph
+  hipEvent_t staged_free;        // recorded after the work of the latest run
   hipEvent_t handoff;            // orders the private stream after the caller's
-  bool staged_pending;
+  bool staged_pending;           // (x15 pass image; see stage_ev for the main images)
   // launch choice
   Launch launch;
   bool tuned;
@@ -85,6 +102,12 @@ struct tdi_plan {
   int graph_fast;
   hipGraphNode_t graph_ev_node[kEvPerRun];   // event records around the kernels inside the graph
   bool graph_timed;                  // those nodes are retargeted to the timing ring per replay
+  // kernel nodes of the graph (fit pre-pass, LFA, full; null if absent), their
+  // captured parameters and the grid each replay last used: every replay trims
+  // the persistent grids to the batch's tile counts
+  hipGraphNode_t graph_knode[3];
+  hipKernelNodeParams graph_kparams[3];
+  unsigned graph_kgrid[3];
   // timing: per recorded run, events before the fit pre-pass, before and after
   // the LFA kernel and after the full kernel
   hipEvent_t ev[kEventRing][kEvPerRun];
@@ -284,9 +307,32 @@ bool table_covers(const tdi_plan* p, int64_t n_sources, const tdi_source* src, c
   return true;
 }
 
+// Outputs per full-response tile: the hybrid's full regions are short (about a
+// thousand samples per source), so small tiles spread them over more workgroups.
+int full_tile(const tdi_config& c) { return c.mode == TDI_MODE_HYBRID ? tdi::kTileFullHybrid : tdi::kTileFull; }
+
 // Outputs per LFA tile: the fast path takes the launch's chunk count.
 int lfa_tile(const Caps& caps, const Launch& ln) {
   return caps.fast ? std::min(std::max(ln.chunks, 1), 4) * tdi::kFastChunk : caps.tile_lfa;
+}
+
+// Wait until staging image `slot` may be rewritten and make it current.
+bool acquire_stage(tdi_plan* p, int slot) {
+  if (p->stage_pending[slot]) {
+    if (hipEventSynchronize(p->stage_ev[slot]) != hipSuccess) return false;
+    p->stage_pending[slot] = false;
+  }
+  p->h_block = p->h_blk[slot];
+  p->h_params = p->h_par[slot];
+  return true;
+}
+
+// Mark image `slot` as read by the work enqueued so far on `st` and move on.
+bool release_stage(tdi_plan* p, int slot, hipStream_t st) {
+  if (hipEventRecord(p->stage_ev[slot], st) != hipSuccess) return false;
+  p->stage_pending[slot] = true;
+  p->stage_slot = p->double_buffer ? slot ^ 1 : slot;
+  return true;
 }
 
 // Constant part of the parameter block: orbit, TDI generation, mode, stencil,
@@ -334,6 +380,7 @@ void stage_batch(const tdi_config& c, tdi::KParams* kp, int64_t n_sources, const
                  const Caps& caps, const Launch& ln) {
   tdi::SrcDev* sd = reinterpret_cast<tdi::SrcDev*>(kp + 1);
   const int tile_lfa = lfa_tile(caps, ln);
+  const int tile_full = full_tile(c);
   int64_t tl = 0, tf = 0;
   for (int64_t i = 0; i < n_sources; ++i) {
     const tdi_source& s = src[i];
@@ -361,10 +408,11 @@ void stage_batch(const tdi_config& c, tdi::KParams* kp, int64_t n_sources, const
     d.lfa_kb = lb; d.lfa_ke = le; d.lfa_t0 = tl;
     d.full_kb = fb; d.full_ke = fe; d.full_t0 = tf;
     if (le > lb) tl += (le - lb + tile_lfa - 1) / tile_lfa;
-    if (fe > fb) tf += (fe - fb + tdi::kTileFull - 1) / tdi::kTileFull;
+    if (fe > fb) tf += (fe - fb + tile_full - 1) / tile_full;
   }
   kp->n_src = n_sources;
   kp->tile_fast = caps.fast ? tile_lfa : 0;
+  kp->tile_full = tile_full;
   kp->n_tiles_lfa = tl;
   kp->n_tiles_full = tf;
   kp->hp = hp; kp->hc = hc; kp->X = X; kp->Y = Y; kp->Z = Z;
@@ -373,13 +421,13 @@ void stage_batch(const tdi_config& c, tdi::KParams* kp, int64_t n_sources, const
   kp->persistent = (ln.grid_lfa > 0 ? 1 : 0) | (ln.grid_full > 0 ? 2 : 0);
 }
 
-// Upload, counter reset, the fit pre-pass (fast LFA path) and both kernels;
-// evs (optional, kEvPerRun) are recorded between the steps.
+// Upload (counters and parameter block), the fit pre-pass (fast LFA path) and
+// both kernels; evs (optional, kEvPerRun) are recorded between the steps.
 hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& caps, const Launch& ln,
                    int64_t tiles_lfa, int64_t tiles_full, const hipEvent_t* evs) {
-  hipError_t e = hipMemcpyAsync(p->d_params, p->h_params, copy_bytes, hipMemcpyHostToDevice, st);
+  // counters (zero) and parameter block in one copy
+  hipError_t e = hipMemcpyAsync(p->d_block, p->h_block, kCtrBytes + copy_bytes, hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return e;
-  if (tdi::launch_reset(p->d_counters, st) != 0) return hipErrorLaunchFailure;
   const int taps = p->cfg.interp_taps, fp32 = p->cfg.precision;
   if (evs && (e = hipEventRecord(evs[0], st)) != hipSuccess) return e;
   const int gl = ln.grid_lfa > 0 ? ln.grid_lfa : (int)std::max<int64_t>(0, tiles_lfa);
@@ -403,14 +451,35 @@ void destroy_graph(tdi_plan* p) {
   p->graph = nullptr;
 }
 
+// The nodes of a captured single chain, from its root to its end.
+bool graph_chain(hipGraph_t g, std::vector<hipGraphNode_t>& chain) {
+  size_t n = 0, ne = 0;
+  if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess || hipGraphGetEdges(g, nullptr, nullptr, &ne) != hipSuccess)
+    return false;
+  if (n == 0 || ne != n - 1) return false;
+  std::vector<hipGraphNode_t> nodes(n), from(ne), to(ne);
+  if (hipGraphGetNodes(g, nodes.data(), &n) != hipSuccess) return false;
+  if (ne > 0 && hipGraphGetEdges(g, from.data(), to.data(), &ne) != hipSuccess) return false;
+  chain.clear();
+  for (size_t i = 0; i < n; ++i)
+    if (std::find(to.begin(), to.end(), nodes[i]) == to.end()) chain.push_back(nodes[i]);
+  if (chain.size() != 1) return false;
+  while (chain.size() < n) {
+    const auto it = std::find(from.begin(), from.end(), chain.back());
+    if (it == from.end()) return false;
+    chain.push_back(to[it - from.begin()]);
+  }
+  return true;
+}
+
 // Event-record nodes spliced into the captured chain (stream capture does not
 // record events): before the fit pre-pass, before and after the LFA kernel and
-// after the full kernel.  The chain is upload -> reset -> [fit] -> LFA -> full.
+// after the full kernel.  The chain is upload -> [fit] -> LFA -> full.
 bool add_graph_events(tdi_plan* p, hipGraph_t g, bool fast) {
   size_t n = 0, ne = 0;
   if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess || hipGraphGetEdges(g, nullptr, nullptr, &ne) != hipSuccess)
     return false;
-  const size_t want = fast ? 5 : 4;
+  const size_t want = fast ? 4 : 3;
   if (n != want || ne != want - 1) return false;
   std::vector<hipGraphNode_t> nodes(n), from(ne), to(ne);
   if (hipGraphGetNodes(g, nodes.data(), &n) != hipSuccess) return false;
@@ -439,8 +508,8 @@ bool add_graph_events(tdi_plan* p, hipGraph_t g, bool fast) {
     chain.insert(chain.begin() + at, *out);
     return true;
   };
-  // chain indices: 0 upload, 1 reset, then [fit], LFA, full
-  size_t at = 2;
+  // chain indices: 0 upload, then [fit], LFA, full
+  size_t at = 1;
   if (!splice(at, p->ev[0][0], &p->graph_ev_node[0])) return false;
   at += 1 + (fast ? 1 : 0);
   if (!splice(at, p->ev[0][1], &p->graph_ev_node[1])) return false;
@@ -450,7 +519,7 @@ bool add_graph_events(tdi_plan* p, hipGraph_t g, bool fast) {
   return splice(at, p->ev[0][3], &p->graph_ev_node[3]);
 }
 
-// Capture (upload of the whole parameter block, counter reset, the fit
+// Capture (upload of the counters and the whole parameter block, the fit
 // pre-pass and both persistent kernels) once; replays pick up new batches from
 // the block.  With timed = true, event-record nodes are added around the
 // kernels (using the events of ring slot 0 as placeholders) so that each
@@ -468,6 +537,32 @@ bool capture_graph_once(tdi_plan* p, const Caps& caps, const Launch& ln, bool ti
     return false;
   }
   p->graph = g;
+  // the kernel nodes in chain order: [fit pre-pass], LFA, full
+  {
+    for (int j = 0; j < 3; ++j) p->graph_knode[j] = nullptr;
+    p->graph_mnode = nullptr;
+    std::vector<hipGraphNode_t> chain, kn;
+    if (!graph_chain(g, chain)) chain.clear();
+    if (!chain.empty()) {
+      hipGraphNodeType t;
+      if (hipGraphNodeGetType(chain[0], &t) == hipSuccess && t == hipGraphNodeTypeMemcpy) p->graph_mnode = chain[0];
+    }
+    for (hipGraphNode_t nd : chain) {
+      hipGraphNodeType t;
+      if (hipGraphNodeGetType(nd, &t) == hipSuccess && t == hipGraphNodeTypeKernel) kn.push_back(nd);
+    }
+    const size_t want = caps.fast ? 3 : 2;
+    if (kn.size() == want) {
+      for (size_t j = 0; j < kn.size(); ++j) {
+        const int slot = caps.fast ? (int)j : (int)j + 1;   // 0 fit, 1 LFA, 2 full
+        if (hipGraphKernelNodeGetParams(kn[j], &p->graph_kparams[slot]) == hipSuccess) {
+          p->graph_knode[slot] = kn[j];
+          p->graph_kgrid[slot] = p->graph_kparams[slot].gridDim.x;
+        }
+      }
+    }
+    (void)hipGetLastError();
+  }
   if (timed) {
     const bool added = add_graph_events(p, g, caps.fast != 0);
     (void)hipGetLastError();
@@ -515,7 +610,7 @@ bool batch_caps(const tdi_config& cfg, const OrbitBounds& ob, int64_t n_sources,
 }
 
 // TDI 2.0 LFA from TDI 1.5: pass 1 runs the FP64 TDI 1.5 LFA over every sample
-// of each source into d_x15 (its own parameter block, counters 8..9), pass 2
+// of each source into d_x15 (its own parameter block and counters), pass 2
 // (k_x20) forms the TDI 2.0 LFA part from it, then the full-response kernel
 // adds the hybrid's full part.  Plain stream launches, persistent grids.
 tdi_status run_x20(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
@@ -535,6 +630,8 @@ tdi_status run_x20(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
     if (hipEventSynchronize(p->staged_free) != hipSuccess) return TDI_EDEVICE;
     p->staged_pending = false;
   }
+  const int slot = p->stage_slot;
+  if (!acquire_stage(p, slot)) return TDI_EDEVICE;
   stage_batch(p->cfg15, p->h_params15, n_sources, src, offsets, hp, hc, p->d_x15, p->d_x15 + total,
               p->d_x15 + 2 * total, caps15, ln15);
   stage_batch(p->cfg, p->h_params, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
@@ -543,10 +640,9 @@ tdi_status run_x20(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   const size_t copy_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)n_sources;
   hipStream_t st = p->user_stream;
   const hipEvent_t* evs = record ? p->ev[p->ev_head] : nullptr;
-  if (hipMemcpyAsync(p->d_params15, p->h_params15, copy_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
-      hipMemcpyAsync(p->d_params, p->h_params, copy_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
+  if (hipMemcpyAsync(p->d_block15, p->h_block15, kCtrBytes + copy_bytes, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(p->d_block, p->h_block, kCtrBytes + copy_bytes, hipMemcpyHostToDevice, st) != hipSuccess)
     return TDI_EDEVICE;
-  if (tdi::launch_reset(p->d_counters, st) != 0) return TDI_EDEVICE;
   if (evs && hipEventRecord(evs[0], st) != hipSuccess) return TDI_EDEVICE;
   if (p->h_params15->n_tiles_lfa > 0 &&
       tdi::launch_lfa(p->d_params15, taps, 0, 0, 0, ln15.grid_lfa, caps15.lds_lfa, st) != 0)
@@ -561,6 +657,7 @@ tdi_status run_x20(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   if (evs && hipEventRecord(evs[3], st) != hipSuccess) return TDI_EDEVICE;
   hipEventRecord(p->staged_free, st);
   p->staged_pending = true;
+  if (!release_stage(p, slot, st)) return TDI_EDEVICE;
   if (record) advance_ring(p);
   return TDI_OK;
 }
@@ -575,11 +672,9 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
   p->last_fast = caps.fast;
   p->last_tile_lfa = lfa_tile(caps, ln);
 
-  // the previous upload must have left the pinned image before it is rewritten
-  if (p->staged_pending) {
-    if (hipEventSynchronize(p->staged_free) != hipSuccess) return TDI_EDEVICE;
-    p->staged_pending = false;
-  }
+  // the image of this staging slot must have been uploaded by its earlier run
+  const int sslot = p->stage_slot;
+  if (!acquire_stage(p, sslot)) return TDI_EDEVICE;
   stage_batch(p->cfg, p->h_params, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
   const int64_t tl = p->h_params->n_tiles_lfa, tf = p->h_params->n_tiles_full;
   // per-tile records of the fast path: tiles hold at least kFastChunk outputs,
@@ -619,6 +714,37 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
       hipEventRecord(p->ev[slot][0], p->graph_stream);
       hipEventRecord(p->ev[slot][1], p->graph_stream);
     }
+    // persistent grids no larger than the batch's tiles (a short batch is not
+    // charged for launching and retiring a full chip's worth of idle workgroups)
+    {
+      const int64_t tiles[3] = {(tl + 5) / 6, tl, tf};     // the fit pre-pass takes six tiles per pass
+      for (int j = 0; j < 3; ++j) {
+        if (!p->graph_knode[j]) continue;
+        const unsigned full_grid = j == 0 ? (unsigned)(4 * p->n_cu)
+                                          : (unsigned)(j == 1 ? ln.grid_lfa : ln.grid_full);
+        const unsigned want = (unsigned)std::max<int64_t>(1, std::min<int64_t>(full_grid, tiles[j]));
+        if (want == p->graph_kgrid[j]) continue;
+        hipKernelNodeParams kp = p->graph_kparams[j];
+        kp.gridDim.x = want;
+        if (hipGraphExecKernelNodeSetParams(p->graph_exec, p->graph_knode[j], &kp) == hipSuccess) {
+          p->graph_kgrid[j] = want;
+        } else {
+          (void)hipGetLastError();
+          p->graph_knode[j] = nullptr;      // keep the captured grid from now on
+        }
+      }
+    }
+    // the upload node reads this run's image
+    if (p->double_buffer &&
+        (!p->graph_mnode ||
+         hipGraphExecMemcpyNodeSetParams1D(p->graph_exec, p->graph_mnode, p->d_block, p->h_block,
+                                           kCtrBytes + p->params_bytes, hipMemcpyHostToDevice) != hipSuccess)) {
+      (void)hipGetLastError();
+      // the upload cannot be retargeted: capture again from this image and keep
+      // to it from now on (one image, each run waiting for the previous one)
+      p->double_buffer = false;
+      if (!capture_graph(p, caps, ln)) return TDI_EDEVICE;
+    }
     if (hipGraphLaunch(p->graph_exec, p->graph_stream) != hipSuccess) return TDI_EDEVICE;
     if (record) {
       if (!inner) {
@@ -628,14 +754,13 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
       advance_ring(p);
     }
     hipEventRecord(p->staged_free, p->graph_stream);
-    p->staged_pending = true;
+    if (!release_stage(p, sslot, p->graph_stream)) return TDI_EDEVICE;
     if (hipStreamWaitEvent(p->user_stream, p->staged_free, 0) != hipSuccess) return TDI_EDEVICE;
     return TDI_OK;
   }
   hipError_t e = enqueue(p, p->user_stream, copy_bytes, caps, ln, tl, tf, record ? p->ev[slot] : nullptr);
   if (e != hipSuccess) return TDI_EDEVICE;
-  hipEventRecord(p->staged_free, p->user_stream);
-  p->staged_pending = true;
+  if (!release_stage(p, sslot, p->user_stream)) return TDI_EDEVICE;
   if (record) advance_ring(p);
   return TDI_OK;
 }
@@ -732,20 +857,34 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   p->last_tile_lfa = tdi::kTileLfa;
   p->user_stream = (hipStream_t)hip_stream;
   p->params_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)max_sources;
-  bool ok = hipMalloc((void**)&p->d_params, p->params_bytes) == hipSuccess;
+  bool ok = hipMalloc((void**)&p->d_block, kCtrBytes + p->params_bytes) == hipSuccess;
   ok = ok && hipMalloc((void**)&p->d_err, 64) == hipSuccess;
-  ok = ok && hipMalloc((void**)&p->d_counters, 64) == hipSuccess;
   if (ok && cfg->precision == TDI_FP32_BULK && cfg->mode != TDI_MODE_FULL) {
     // records of the fast LFA path: at most one partial tile per source beyond the full ones
     p->fit_tiles = max_total_samples / tdi::kFastChunk + max_sources + 1;
     ok = hipMalloc(&p->d_ftiles, (size_t)p->fit_tiles * tdi::fast_tile_bytes()) == hipSuccess;
   }
-  ok = ok && hipHostMalloc((void**)&p->h_params, p->params_bytes, hipHostMallocDefault) == hipSuccess;
+  for (int j = 0; j < 2 && ok; ++j) {
+    ok = hipHostMalloc((void**)&p->h_blk[j], kCtrBytes + p->params_bytes, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipEventCreateWithFlags(&p->stage_ev[j], hipEventDisableTiming) == hipSuccess;
+    if (ok) p->h_par[j] = reinterpret_cast<tdi::KParams*>(p->h_blk[j] + kCtrBytes);
+  }
+  if (ok) {
+    p->d_params = reinterpret_cast<tdi::KParams*>(p->d_block + kCtrBytes);
+    p->h_block = p->h_blk[0];
+    p->h_params = p->h_par[0];
+    p->stage_slot = 0;
+    p->double_buffer = true;
+  }
   if (ok && x20_shortcut(*cfg)) {
     ok = hipMalloc((void**)&p->d_x15, sizeof(double) * 3 * (size_t)std::max<int64_t>(1, max_total_samples)) ==
          hipSuccess;
-    ok = ok && hipMalloc((void**)&p->d_params15, p->params_bytes) == hipSuccess;
-    ok = ok && hipHostMalloc((void**)&p->h_params15, p->params_bytes, hipHostMallocDefault) == hipSuccess;
+    ok = ok && hipMalloc((void**)&p->d_block15, kCtrBytes + p->params_bytes) == hipSuccess;
+    ok = ok && hipHostMalloc((void**)&p->h_block15, kCtrBytes + p->params_bytes, hipHostMallocDefault) == hipSuccess;
+    if (ok) {
+      p->d_params15 = reinterpret_cast<tdi::KParams*>(p->d_block15 + kCtrBytes);
+      p->h_params15 = reinterpret_cast<tdi::KParams*>(p->h_block15 + kCtrBytes);
+    }
   }
   ok = ok && hipEventCreateWithFlags(&p->staged_free, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&p->handoff, hipEventDisableTiming) == hipSuccess;
@@ -756,12 +895,12 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
     tdi_plan_destroy(p);
     return TDI_ENOMEM;
   }
-  if (hipMemset(p->d_err, 0, 64) != hipSuccess || hipMemset(p->d_counters, 0, 64) != hipSuccess ||
+  if (hipMemset(p->d_err, 0, 64) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     tdi_plan_destroy(p);
     return TDI_EDEVICE;
   }
-  memset(p->h_params, 0, p->params_bytes);
+  for (int j = 0; j < 2; ++j) memset(p->h_blk[j], 0, kCtrBytes + p->params_bytes);
 
   if (orb->kind == TDI_ORBIT_TABLE) {
     const size_t tb = sizeof(double) * 9 * (size_t)orb->n_table;
@@ -774,10 +913,12 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
       return TDI_EDEVICE;
     }
   }
-  fill_constants(*p->h_params, *cfg, *orb, p->ob, p->d_orbtab);
-  p->h_params->err = p->d_err;
-  p->h_params->lfa_tiles = p->d_ftiles;
-  p->h_params->counters = p->d_counters;
+  for (int j = 0; j < 2; ++j) {
+    fill_constants(*p->h_par[j], *cfg, *orb, p->ob, p->d_orbtab);
+    p->h_par[j]->err = p->d_err;
+    p->h_par[j]->lfa_tiles = p->d_ftiles;
+    p->h_par[j]->counters = reinterpret_cast<uint32_t*>(p->d_block);
+  }
   if (x20_shortcut(*cfg)) {
     // pass 1: the same source set at TDI 1.5, LFA mode, FP64, over every sample
     p->cfg15 = *cfg;
@@ -787,11 +928,11 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
     p->cfg15.lfa_terms = 0;
     p->cfg15.lfa_x20_from_x15 = 0;
     p->cfg15.channels = TDI_CHANNELS_XYZ;
-    memset(p->h_params15, 0, p->params_bytes);
+    memset(p->h_block15, 0, kCtrBytes + p->params_bytes);
     fill_constants(*p->h_params15, p->cfg15, *orb, p->ob, p->d_orbtab);
     p->h_params15->err = p->d_err;
     p->h_params15->lfa_tiles = nullptr;
-    p->h_params15->counters = p->d_counters + 8;
+    p->h_params15->counters = reinterpret_cast<uint32_t*>(p->d_block15);
   }
 
   p->launch = {0, 0, cfg->fast_tile_chunks != 0 ? cfg->fast_tile_chunks : 4};
@@ -817,15 +958,17 @@ tdi_status tdi_plan_destroy(tdi_plan* p) {
   if (p->staged_free) hipEventDestroy(p->staged_free);
   if (p->handoff) hipEventDestroy(p->handoff);
   if (p->graph_stream) hipStreamDestroy(p->graph_stream);
-  if (p->d_params) hipFree(p->d_params);
+  if (p->d_block) hipFree(p->d_block);
   if (p->d_err) hipFree(p->d_err);
-  if (p->d_counters) hipFree(p->d_counters);
   if (p->d_ftiles) hipFree(p->d_ftiles);
   if (p->d_orbtab) hipFree(p->d_orbtab);
   if (p->d_x15) hipFree(p->d_x15);
-  if (p->d_params15) hipFree(p->d_params15);
-  if (p->h_params15) hipHostFree(p->h_params15);
-  if (p->h_params) hipHostFree(p->h_params);
+  if (p->d_block15) hipFree(p->d_block15);
+  if (p->h_block15) hipHostFree(p->h_block15);
+  for (int j = 0; j < 2; ++j) {
+    if (p->h_blk[j]) hipHostFree(p->h_blk[j]);
+    if (p->stage_ev[j]) hipEventDestroy(p->stage_ev[j]);
+  }
   free(p);
   return TDI_OK;
 }
@@ -870,10 +1013,8 @@ tdi_status tdi_run_links(tdi_plan* p, int64_t n_sources, const tdi_source* src, 
     cap = std::max(cap, tdi::kTileLinks + (int)ceil(spread / src[i].dt) + N + 2 * margin + 8);
   const size_t lds = tdi::links_lds_bytes(cap, fp32, p->cfg.lfa_terms == 2 ? 3 : 2);
   if (lds > p->max_lds) return TDI_ERANGE;
-  if (p->staged_pending) {
-    if (hipEventSynchronize(p->staged_free) != hipSuccess) return TDI_EDEVICE;
-    p->staged_pending = false;
-  }
+  const int slot = p->stage_slot;
+  if (!acquire_stage(p, slot)) return TDI_EDEVICE;
   tdi::KParams* kp = p->h_params;
   tdi::SrcDev* sd = reinterpret_cast<tdi::SrcDev*>(kp + 1);
   int64_t tiles = 0;
@@ -898,10 +1039,9 @@ tdi_status tdi_run_links(tdi_plan* p, int64_t n_sources, const tdi_source* src, 
   kp->persistent = 0;
   const size_t copy_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)n_sources;
   hipStream_t s = p->user_stream;
-  if (hipMemcpyAsync(p->d_params, p->h_params, copy_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+  if (hipMemcpyAsync(p->d_block, p->h_block, kCtrBytes + copy_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
     return TDI_EDEVICE;
-  if (hipEventRecord(p->staged_free, s) != hipSuccess) return TDI_EDEVICE;
-  p->staged_pending = true;
+  if (!release_stage(p, slot, s)) return TDI_EDEVICE;
   if (tdi::launch_links(p->d_params, N, fp32, tiles, lds, s) != 0) return TDI_EDEVICE;
   return TDI_OK;
 }
@@ -951,7 +1091,7 @@ tdi_status tdi_plan_describe(const tdi_plan* p, char* buf, int32_t buflen) {
            "{\"tile_lfa\": %d, \"tile_full\": %d, \"grid_lfa\": %d, \"grid_full\": %d, "
            "\"graph\": %d, \"graph_kernel_events\": %d, \"cu\": %d, \"tuned\": %d, \"lfa_fast\": %d, "
            "\"x20_from_x15\": %d}",
-           p->last_tile_lfa, tdi::kTileFull, p->launch.grid_lfa, p->launch.grid_full,
+           p->last_tile_lfa, full_tile(p->cfg), p->launch.grid_lfa, p->launch.grid_full,
            (p->cfg.use_graph && !x20_shortcut(p->cfg) && p->launch.grid_lfa > 0 && p->launch.grid_full > 0) ? 1 : 0,
            p->graph_timed ? 1 : 0, p->n_cu,
            p->tuned ? 1 : 0, p->last_fast, x20_shortcut(p->cfg) ? 1 : 0);

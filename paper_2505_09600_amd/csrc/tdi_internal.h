@@ -12,7 +12,8 @@ constexpr int kNodes = 7;         // Chebyshev nodes of the per-tile geometry fi
 constexpr int kNQ = 27;           // fitted geometry quantities per tile
 constexpr int kFitLen = kNQ * kNodes;   // coefficients of one tile fit
 constexpr int kTileLfa = 1024;    // outputs per LFA tile (4 waves x 256)
-constexpr int kTileFull = 256;    // outputs per full-response tile
+constexpr int kTileFull = 256;    // outputs per full-response tile (FULL mode; the largest)
+constexpr int kTileFullHybrid = 64;   // the hybrid's short full regions: small tiles, more workgroups
 constexpr int kWaveOut = 256;     // LFA FP32: outputs per wave (4 per lane, stride 64)
 // FP32 bulk LFA path (k_lfa_fast): chunks of 4 waves x 64 lanes x 9 outputs,
 // four chunks per tile (one geometry fit); its stencil pass covers up to
@@ -70,12 +71,14 @@ struct KParams {
   // per plan
   int32_t* err;          // window-check report (8 ints)
   void* lfa_tiles;       // fast LFA path: per-tile records written by the pre-pass
-  uint32_t* counters;    // work counters of the persistent kernels: [0] LFA tiles, [1] full tiles
+  uint32_t* counters;    // work counters of the persistent kernels, zero at launch: [0] LFA tiles,
+                         // [1] full tiles (the plan keeps them in front of the parameter block)
   OrbitDev orb;
   int32_t gen, mode, equal_arms, stencil_m, stencil_p, persistent;
   int32_t aet, cap_lk;   // aet: store A, E, T instead of X, Y, Z; cap_lk: link-output window
   int32_t nested;        // time-nested stage-2 delays
   int32_t tile_fast;     // fast LFA path: outputs per tile (1, 2 or 4 chunks of kFastChunk)
+  int32_t tile_full;     // full-response outputs per tile (at most kTileFull)
   int64_t link_stride;   // link outputs: elements between the six link arrays (X is their base)
   double T_s, sigma_s;
   double D2_bound;       // upper bound of a stage-2 delay (s)
@@ -89,7 +92,6 @@ __host__ __device__ inline const SrcDev* sources_of(const KParams* p) {
 
 // Launch entry points (defined in tdi_kernels.hip).
 int set_constants();
-int launch_reset(uint32_t* counters, void* stream);      // zeroes counters[0..15]
 // fast != 0 selects the FP32 bulk LFA kernel (fp32 must be 1)
 // nx != 0: LFA with the next term (lfa_terms = 2; general kernel only)
 int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int nx, int grid, size_t lds_bytes, void* stream);

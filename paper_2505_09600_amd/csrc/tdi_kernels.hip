@@ -977,6 +977,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
 constexpr int kFR = 9;                 // outputs per lane (odd: conflict-free LDS stride)
 constexpr int kFWave = 64 * kFR;       // outputs per wave
 constexpr int kFChunk = 4 * kFWave;    // outputs per chunk (one per workgroup pass)
+constexpr uint32_t kAllUses = (1u << (2 * kFR)) - 1u;   // both uses of each of a lane's outputs
 constexpr int kSR = 11;                // stencil elements per thread (odd: conflict-free 16-byte stride)
 static_assert(kFChunk == kFastChunk && kFR == kFastOutPerLane, "chunk shape");
 static_assert(kSR * kBlock == kFastStencilSpan, "stencil sweep");
@@ -1492,7 +1493,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             const int npass = __builtin_amdgcn_readfirstlane((int)Wv.cross[l]) != 0 ? 2 : 1;
             // x near 0 (gi <= kWGrid / 2): the neighbouring base is mbar + 1, else mbar - 1
             const int s_alt = 2 * gi <= kWGrid ? 1 : -1;
-            uint32_t own = edge ? 0u : 0x3ffffu;   // bit side * kFR + q: the use is on base mbar
+            uint32_t own = edge ? 0u : kAllUses;   // bit side * kFR + q: the use is on base mbar
             if (npass == 2 && !edge) {
               const float xbar = (float)gi * (1.0f / (float)kWGrid);
               own = 0u;
@@ -1569,7 +1570,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             }
             // side 0 feeds channel (l+2)%3 (Xa), side 1 channel (l+1)%3 (Xb); most
             // waves take every use (no crossing, no edge) and skip the mask tests
-            if (__ballot(take != 0x3ffffu) == 0) {
+            if (__ballot(take != kAllUses) == 0) {
 #pragma unroll
               for (int side = 0; side < 2; ++side) {
                 const int u = 2 * l + side;
@@ -1878,6 +1879,24 @@ __device__ __forceinline__ void interp2(const TC* win, int64_t b, double x, TC& 
   vc = v[1];
 }
 
+// Channel c of full-response output o.  Hybrid: add w- X^Full to the LFA part
+// that the LFA kernel wrote inside its window (k - kH <= T/2), else store.
+template <typename TC>
+__device__ __forceinline__ void full_store(const KParams& P, int64_t o, int c, double v, double rel) {
+  TC* out = static_cast<TC*>(c == 0 ? P.X : (c == 1 ? P.Y : P.Z));
+  if (P.mode == 2) {
+    const double w = 1.0 / (1.0 + exp(-rel / P.sigma_s));
+    const bool has_lfa = rel <= 0.5 * P.T_s;
+    if constexpr (sizeof(TC) == 8) {
+      out[o] = (has_lfa ? out[o] : 0.0) + w * v;
+    } else {
+      out[o] = (has_lfa ? out[o] : 0.0f) + (float)w * (float)v;
+    }
+  } else {
+    out[o] = (TC)v;
+  }
+}
+
 template <int N, typename TC>
 __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ Pp) {
   const KParams& P = *Pp;
@@ -1900,8 +1919,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
       const int64_t s = find_source(SS, P.n_src, tile, false);
       const SrcDev& S = SS[s];
       sh.src = s;
-      sh.k0 = S.full_kb + (tile - S.full_t0) * kTileFull;
-      sh.cnt = (int32_t)min((int64_t)kTileFull, S.full_ke - sh.k0);
+      sh.k0 = S.full_kb + (tile - S.full_t0) * P.tile_full;
+      sh.cnt = (int32_t)min((int64_t)P.tile_full, S.full_ke - sh.k0);
       const int margin = 2 + (int)ceil(4e-4 * (double)sh.cnt);
       sh.y0 = sh.k0 - (int64_t)ceil(P.D2_bound / S.dt) - N / 2 + 1 - margin;
       sh.ny = (int32_t)(sh.k0 + sh.cnt - 1 + N / 2 + margin - sh.y0 + 1);
@@ -1961,78 +1980,62 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
       }
       __syncthreads();
       // Stage 1: y_l[i] = [H_l(t_i - ds) - H_l(t_i - dr)] / (2 (1 - k.n)), zero
-      // outside the series; antenna patterns at the reception time t_i.
+      // outside the series; antenna patterns at the reception time t_i.  One
+      // work item per (sample, link), so that a small tile still spreads over
+      // the workgroup (each item takes its sender and its receiver read).
       const double c2 = sh.c2, s2 = sh.s2;
-      for (int ii = tid; ii < ny; ii += kBlock) {
+      for (int it = tid; it < ny * 6; it += kBlock) {
+        const int ii = it / 6, a = it - 6 * ii;
         const int64_t i = y0 + ii;
         if (!(i >= 0 && i < S.n)) {
-#pragma unroll
-          for (int a = 0; a < 6; ++a) ywin[a * cap_y + ii] = (TC)0;
+          ywin[a * cap_y + ii] = (TC)0;
           continue;
         }
         const double s = ((double)i - sh.F.kc) * sh.F.ikh;
-        const double kR0 = geo_eval(sh.F, qKR(0), s), kR1 = geo_eval(sh.F, qKR(1), s),
-                     kR2 = geo_eval(sh.F, qKR(2), s);
-        // the receiver read is shared by the two links into each spacecraft
-        TC hr[6];
+        const double kRs = geo_eval(sh.F, qKR(snd_of(a)), s), kRr = geo_eval(sh.F, qKR(rcv_of(a)), s);
+        const double T = geo_eval(sh.F, qT(a), s);
+        if (i >= k0 && i < k0 + cnt) Tc[a * kTileFull + (int)(i - k0)] = T;
+        TC v[4];
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
+        for (int q = 0; q < 2; ++q) {
           int64_t i0;
           double x;
-          split(i, sel3(kR0, kR1, kR2, q), dt, i0, x);
+          split(i, q == 0 ? T + kRs : kRr, dt, i0, x);
           const int64_t b = i0 - N / 2 + 1 - w0;
           if (b < 0 || b + N > nh) {
             report(P.err, 8, i, b, nh);
-            hr[2 * q] = hr[2 * q + 1] = (TC)__builtin_nan("");
+            v[2 * q] = v[2 * q + 1] = (TC)__builtin_nan("");
           } else {
-            interp2<N, TC>(hwin, b, x, hr[2 * q], hr[2 * q + 1]);
+            interp2<N, TC>(hwin, b, x, v[2 * q], v[2 * q + 1]);
           }
         }
-#pragma unroll 1
-        for (int a = 0; a < 6; ++a) {
-          const double T = geo_eval(sh.F, qT(a), s);
-          if (i >= k0 && i < k0 + cnt) Tc[a * kTileFull + (int)(i - k0)] = T;
-          int64_t i0;
-          double x;
-          split(i, T + sel3(kR0, kR1, kR2, snd_of(a)), dt, i0, x);
-          const int64_t b = i0 - N / 2 + 1 - w0;
-          TC vp, vc;
-          if (b < 0 || b + N > nh) {
-            report(P.err, 8, i, b, nh);
-            vp = vc = (TC)__builtin_nan("");
-          } else {
-            interp2<N, TC>(hwin, b, x, vp, vc);
-          }
-          const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
-          const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
-          const int r = rcv_of(a);
-          const TC hrp = r == 0 ? hr[0] : (r == 1 ? hr[2] : hr[4]);
-          const TC hrc = r == 0 ? hr[1] : (r == 1 ? hr[3] : hr[5]);
-          const TC Hs = A * vp + B * vc;
-          const TC Hr = A * hrp + B * hrc;
-          ywin[a * cap_y + ii] = (Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s);
-        }
+        const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
+        const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
+        const TC Hs = A * v[0] + B * v[1];
+        const TC Hr = A * v[2] + B * v[3];
+        ywin[a * cap_y + ii] = (Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s);
       }
     }
     __syncthreads();
 
     // Stage 2: sum of +-y_l at the term delays, light times at the output time
     // (or time-nested: each light time from the fit at its retarded sample).
+    // One work item per (output, channel).
     const int nterms = P.gen == 20 ? 16 : 8;
     const double kH = sh.kH;
-    for (int i = tid; i < cnt; i += kBlock) {
+    for (int it = tid; it < cnt * 3; it += kBlock) {
+      const int i = it / 3, c = it - 3 * i;
       const int64_t k = k0 + i;
       const double rel = (double)k - kH;
       if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
-      double out[3];
+      double outc;
       if (bad) {
-        out[0] = out[1] = out[2] = __builtin_nan("");
+        outc = __builtin_nan("");
       } else {
         double T6[6];
 #pragma unroll
         for (int a = 0; a < 6; ++a) T6[a] = Tc[a * kTileFull + i];
-#pragma unroll 1
-        for (int c = 0; c < 3; ++c) {
+        {
           TC sum = (TC)0;
 #pragma unroll 1
           for (int t = 0; t < nterms; ++t) {
@@ -2074,32 +2077,26 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
             }
             sum += sign > 0 ? v : -v;
           }
-          if (c == 0) out[0] = (double)sum; else if (c == 1) out[1] = (double)sum; else out[2] = (double)sum;
+          outc = (double)sum;
         }
       }
-      const int64_t o = S.off + k;
-      if (P.mode == 2) {
-        // add w- X^Full to the LFA part written by k_lfa inside the LFA window
-        const double w = 1.0 / (1.0 + exp(-rel / P.sigma_s));
-        const bool has_lfa = rel <= 0.5 * P.T_s;
-        if (P.aet) to_aet<double>(out[0], out[1], out[2]);
-        TC* Xo = static_cast<TC*>(P.X);
-        TC* Yo = static_cast<TC*>(P.Y);
-        TC* Zo = static_cast<TC*>(P.Z);
-        if constexpr (sizeof(TC) == 8) {
-          const double xa = has_lfa ? Xo[o] : 0.0, ya = has_lfa ? Yo[o] : 0.0, za = has_lfa ? Zo[o] : 0.0;
-          Xo[o] = xa + w * out[0];
-          Yo[o] = ya + w * out[1];
-          Zo[o] = za + w * out[2];
-        } else {
-          const float wf = (float)w;
-          const float xa = has_lfa ? Xo[o] : 0.0f, ya = has_lfa ? Yo[o] : 0.0f, za = has_lfa ? Zo[o] : 0.0f;
-          Xo[o] = xa + wf * (float)out[0];
-          Yo[o] = ya + wf * (float)out[1];
-          Zo[o] = za + wf * (float)out[2];
-        }
-      } else {
-        store3<TC>(P, o, (TC)out[0], (TC)out[1], (TC)out[2]);
+      if (P.aet) {
+        // A, E, T mix the channels: the three items of an output meet in LDS
+        Tc[(6 + c) * kTileFull + i] = outc;
+        continue;
+      }
+      full_store<TC>(P, S.off + k, c, outc, rel);
+    }
+    if (P.aet) {
+      __syncthreads();
+      for (int i = tid; i < cnt; i += kBlock) {
+        const int64_t k = k0 + i;
+        const double rel = (double)k - kH;
+        if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
+        double o3[3] = {Tc[6 * kTileFull + i], Tc[7 * kTileFull + i], Tc[8 * kTileFull + i]};
+        to_aet<double>(o3[0], o3[1], o3[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) full_store<TC>(P, S.off + k, c, o3[c], rel);
       }
     }
     __syncthreads();
@@ -2313,10 +2310,6 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
   }
 }
 
-__global__ void k_reset(uint32_t* counters) {
-  if (threadIdx.x < 16) counters[threadIdx.x] = 0u;
-}
-
 template <int N, typename TC>
 int launch_lfa_t(const KParams* dp, int nx, int grid, size_t lds, hipStream_t st) {
   if (nx) hipLaunchKernelGGL((k_lfa<N, TC, true>), dim3(grid), dim3(kBlock), lds, st, dp);
@@ -2510,13 +2503,9 @@ size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int nx,
 
 size_t full_lds_bytes(int cap_h, int cap_y, int fp32) {
   const size_t tcs = fp32 ? sizeof(float) : sizeof(double);
+  // light times of the tile's outputs (6 rows) and, for A, E, T, the three channels
   return align16((size_t)cap_h * 2 * tcs) + align16((size_t)cap_y * 6 * tcs) +
-         (size_t)6 * kTileFull * sizeof(double);
-}
-
-int launch_reset(uint32_t* counters, void* stream) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, (hipStream_t)stream, counters);
-  return hipGetLastError() == hipSuccess ? 0 : -1;
+         (size_t)9 * kTileFull * sizeof(double);
 }
 
 int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int nx, int grid, size_t lds, void* stream) {
