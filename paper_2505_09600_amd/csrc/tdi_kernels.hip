@@ -1336,12 +1336,11 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
   float* Fw = reinterpret_cast<float*>(dyn);                        // [3][ngp], FP32
   const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
   const int hw = c_sthw[st];
-  // the stencil as a centre weight and three pair weights (offsets +-1..3,
-  // zero beyond hw): even orders sum the pairs, odd orders difference them
-  const bool odd = (P.stencil_m & 1) != 0;
-  double stc[4];
+  // all seven stencil weights, zero beyond 2 hw (a pair-summed form saves
+  // FP64 FMAs but costs registers, and measured slower)
+  double stn[7];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) stc[k] = k <= hw ? c_stnum[st][hw + k] : 0.0;
+  for (int s = 0; s < 7; ++s) stn[s] = c_stnum[st][s];
   const int ne = N + kFR + 2 * hw + 8;          // raw pairs kept at each end
 
   int64_t iter = 0;
@@ -1403,10 +1402,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
               cxd[l] = fmaf(2.0f * u, pcv[l][1][2], pcv[l][1][1]);
             }
             // samples j0 - 3 + m, m < kSR + 6, inside the series for m in [mlo, mhi)
-            const int mlo = (int)min(max((int64_t)3 - j0, (int64_t)0), (int64_t)(kSR + 6));
-            const int mhi = (int)min(max(n - j0 + 3, (int64_t)0), (int64_t)(kSR + 6));
-            const double* __restrict__ hpb = P.hp + off + (j0 - 3);
-            const double* __restrict__ hcb = P.hc + off + (j0 - 3);
+            const int mlo = (int)min(max((int64_t)hw - j0, (int64_t)0), (int64_t)(kSR + 6));
+            const int mhi = (int)min(max(n - j0 + hw, (int64_t)0), (int64_t)(kSR + 6));
+            const double* __restrict__ hpb = P.hp + off + (j0 - hw);
+            const double* __restrict__ hcb = P.hc + off + (j0 - hw);
             double hp_[kSR + 6], hc_[kSR + 6];
             // the strain loads go out ahead of the other waves' arithmetic
             __builtin_amdgcn_s_setprio(1);
@@ -1419,23 +1418,11 @@ __global__ __launch_bounds__(kBlock, 3) void k_lfa_fast(const KParams* __restric
             __builtin_amdgcn_s_setprio(0);
 #pragma unroll
             for (int e = 0; e < kSR; ++e) {
-              // element e sits at hp_[e + 3]; pair weights are zero beyond hw
-              double ap, ac;
-              if (odd) {
-                ap = stc[1] * (hp_[e + 4] - hp_[e + 2]);
-                ac = stc[1] * (hc_[e + 4] - hc_[e + 2]);
-                ap = fma(stc[2], hp_[e + 5] - hp_[e + 1], ap);
-                ac = fma(stc[2], hc_[e + 5] - hc_[e + 1], ac);
-                ap = fma(stc[3], hp_[e + 6] - hp_[e], ap);
-                ac = fma(stc[3], hc_[e + 6] - hc_[e], ac);
-              } else {
-                ap = stc[0] * hp_[e + 3];
-                ac = stc[0] * hc_[e + 3];
+              double ap = 0.0, ac = 0.0;
 #pragma unroll
-                for (int k = 1; k < 4; ++k) {
-                  ap = fma(stc[k], hp_[e + 3 + k] + hp_[e + 3 - k], ap);
-                  ac = fma(stc[k], hc_[e + 3 + k] + hc_[e + 3 - k], ac);
-                }
+              for (int s = 0; s < 7; ++s) {
+                ap = fma(stn[s], hp_[e + s], ap);
+                ac = fma(stn[s], hc_[e + s], ac);
               }
               const bool in = e >= elo && e < ehi;
               if (!in) ap = ac = 0.0;
@@ -1981,39 +1968,56 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
       __syncthreads();
       // Stage 1: y_l[i] = [H_l(t_i - ds) - H_l(t_i - dr)] / (2 (1 - k.n)), zero
       // outside the series; antenna patterns at the reception time t_i.  One
-      // work item per (sample, link), so that a small tile still spreads over
-      // the workgroup (each item takes its sender and its receiver read).
+      // work item per (sample, receiving spacecraft): the receiver read is
+      // shared by the two links into that spacecraft, and a small tile still
+      // spreads over the workgroup.
       const double c2 = sh.c2, s2 = sh.s2;
-      for (int it = tid; it < ny * 6; it += kBlock) {
-        const int ii = it / 6, a = it - 6 * ii;
+      for (int it = tid; it < ny * 3; it += kBlock) {
+        const int ii = it / 3, r = it - 3 * ii;
         const int64_t i = y0 + ii;
+        // the links received by spacecraft r (slots with rcv_of(a) == r)
+        const int la = r == 0 ? 2 : (r == 1 ? 0 : 1), lb = r == 0 ? 4 : (r == 1 ? 5 : 3);
         if (!(i >= 0 && i < S.n)) {
-          ywin[a * cap_y + ii] = (TC)0;
+          ywin[la * cap_y + ii] = (TC)0;
+          ywin[lb * cap_y + ii] = (TC)0;
           continue;
         }
         const double s = ((double)i - sh.F.kc) * sh.F.ikh;
-        const double kRs = geo_eval(sh.F, qKR(snd_of(a)), s), kRr = geo_eval(sh.F, qKR(rcv_of(a)), s);
-        const double T = geo_eval(sh.F, qT(a), s);
-        if (i >= k0 && i < k0 + cnt) Tc[a * kTileFull + (int)(i - k0)] = T;
-        TC v[4];
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
+        TC hr[2];
+        {
           int64_t i0;
           double x;
-          split(i, q == 0 ? T + kRs : kRr, dt, i0, x);
+          split(i, geo_eval(sh.F, qKR(r), s), dt, i0, x);
           const int64_t b = i0 - N / 2 + 1 - w0;
           if (b < 0 || b + N > nh) {
             report(P.err, 8, i, b, nh);
-            v[2 * q] = v[2 * q + 1] = (TC)__builtin_nan("");
+            hr[0] = hr[1] = (TC)__builtin_nan("");
           } else {
-            interp2<N, TC>(hwin, b, x, v[2 * q], v[2 * q + 1]);
+            interp2<N, TC>(hwin, b, x, hr[0], hr[1]);
           }
         }
-        const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
-        const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
-        const TC Hs = A * v[0] + B * v[1];
-        const TC Hr = A * v[2] + B * v[3];
-        ywin[a * cap_y + ii] = (Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s);
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+          const int a = q == 0 ? la : lb;
+          const double T = geo_eval(sh.F, qT(a), s);
+          if (i >= k0 && i < k0 + cnt) Tc[a * kTileFull + (int)(i - k0)] = T;
+          int64_t i0;
+          double x;
+          split(i, T + geo_eval(sh.F, qKR(snd_of(a)), s), dt, i0, x);
+          const int64_t b = i0 - N / 2 + 1 - w0;
+          TC vp, vc;
+          if (b < 0 || b + N > nh) {
+            report(P.err, 8, i, b, nh);
+            vp = vc = (TC)__builtin_nan("");
+          } else {
+            interp2<N, TC>(hwin, b, x, vp, vc);
+          }
+          const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
+          const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
+          const TC Hs = A * vp + B * vc;
+          const TC Hr = A * hr[0] + B * hr[1];
+          ywin[a * cap_y + ii] = (Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s);
+        }
       }
     }
     __syncthreads();
