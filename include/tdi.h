@@ -108,7 +108,11 @@ typedef struct {
   double hyb_T_samples;     /* hybrid window length T in samples (paper default 800), > 0 */
   double hyb_sigma_samples; /* sigmoid width sigma in samples (paper default T/40), > 0 */
   int32_t autotune;         /* 1: time the launch candidates on the first run and keep the best */
-  int32_t use_graph;        /* 1: capture the run sequence in a hipGraph and replay it */
+  int32_t use_graph;        /* 1: capture the run sequence in a hipGraph and replay it.  With
+                               autotune = 1 the first run also times replays against plain
+                               stream launches over back-to-back runs and keeps the faster
+                               (short runs, where a replay costs the host more than the
+                               launches it replaces); tdi_plan_describe reports the choice */
   int32_t channels;         /* TDI_CHANNELS_XYZ: write X, Y, Z.  TDI_CHANNELS_AET: write the
                                noise-orthogonal combinations defined at the end of Sec. II.B instead,
                                A = (Z - X)/sqrt 2, E = (X - 2Y + Z)/sqrt 6, T = (X + Y + Z)/sqrt 3,

@@ -94,6 +94,7 @@ struct tdi_plan {
   // launch choice
   Launch launch;
   bool tuned;
+  bool stream_pick;              // the autotuner found stream launches faster than graph replay
   // graph
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
@@ -795,8 +796,8 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
   hipEvent_t a, b;
   hipEventCreate(&a);
   hipEventCreate(&b);
-  float best = INFINITY;
-  Launch best_l = cands[0];
+  float best = INFINITY, best_p = INFINITY;
+  Launch best_l = cands[0], best_pl = cands[0];
   for (const Launch& ln : cands) {
     float ms_sum = 0.0f;
     bool ok = true;
@@ -813,12 +814,39 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
       best = ms_sum;
       best_l = ln;
     }
+    if (ok && ln.grid_lfa > 0 && ln.grid_full > 0 && ms_sum < best_p) {
+      best_p = ms_sum;
+      best_pl = ln;
+    }
+  }
+  p->launch = best_l;
+  p->stream_pick = false;
+  if (p->cfg.use_graph) {
+    // Graph replay needs persistent launches.  It saves host work per run, but
+    // on short runs a replay can cost the host more than the stream launches
+    // it replaces: time both over back-to-back runs and keep the faster.
+    auto batch_ms = [&](const Launch& ln, bool graph) -> float {
+      hipEventRecord(a, p->user_stream);
+      for (int rep = 0; rep < 8; ++rep)
+        if (run_with(p, ln, n_sources, src, offsets, hp, hc, X, Y, Z, false, graph) != TDI_OK) return INFINITY;
+      hipEventRecord(b, p->user_stream);
+      if (hipEventSynchronize(b) != hipSuccess) return INFINITY;
+      float ms = 0.0f;
+      hipEventElapsedTime(&ms, a, b);
+      return ms;
+    };
+    p->launch = best_pl;
+    (void)batch_ms(best_pl, true);                       // capture and warm the graph
+    const float tg = batch_ms(best_pl, true);
+    const float ts = batch_ms(best_l, false);
+    (void)hipGetLastError();
+    if (ts < 0.97f * tg) {
+      p->launch = best_l;
+      p->stream_pick = true;
+    }
   }
   hipEventDestroy(a);
   hipEventDestroy(b);
-  // graph replay needs persistent launches
-  if (p->cfg.use_graph && (best_l.grid_lfa == 0 || best_l.grid_full == 0)) best_l = cands[0];
-  p->launch = best_l;
   p->tuned = true;
 }
 
@@ -987,7 +1015,7 @@ tdi_status tdi_run(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   if ((((uintptr_t)X) | ((uintptr_t)Y) | ((uintptr_t)Z)) & (al - 1)) return TDI_EINVAL;
   if (!table_covers(p, n_sources, src, offsets)) return TDI_ERANGE;
   if (!p->tuned) autotune(p, n_sources, src, offsets, hp, hc, X, Y, Z);
-  return run_with(p, p->launch, n_sources, src, offsets, hp, hc, X, Y, Z, true, true);
+  return run_with(p, p->launch, n_sources, src, offsets, hp, hc, X, Y, Z, true, !p->stream_pick);
 }
 
 tdi_status tdi_run_links(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
@@ -1092,7 +1120,8 @@ tdi_status tdi_plan_describe(const tdi_plan* p, char* buf, int32_t buflen) {
            "\"graph\": %d, \"graph_kernel_events\": %d, \"cu\": %d, \"tuned\": %d, \"lfa_fast\": %d, "
            "\"x20_from_x15\": %d}",
            p->last_tile_lfa, full_tile(p->cfg), p->launch.grid_lfa, p->launch.grid_full,
-           (p->cfg.use_graph && !x20_shortcut(p->cfg) && p->launch.grid_lfa > 0 && p->launch.grid_full > 0) ? 1 : 0,
+           (p->cfg.use_graph && !p->stream_pick && !x20_shortcut(p->cfg) && p->launch.grid_lfa > 0 &&
+            p->launch.grid_full > 0) ? 1 : 0,
            p->graph_timed ? 1 : 0, p->n_cu,
            p->tuned ? 1 : 0, p->last_fast, x20_shortcut(p->cfg) ? 1 : 0);
   return TDI_OK;

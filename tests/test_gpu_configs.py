@@ -132,7 +132,7 @@ def test_c3_hybrid_one_year(tdi, orc, c3_hybrid_batch, gen, prec):
 @pytest.mark.timeout(900)
 def test_c4_batch_bench_launch(tdi, orc):
     """512 sources (7.3e8 samples), FP32-bulk hybrid TDI 2.0 with the benchmark's
-    launch configuration (autotuned persistent kernels replayed from a graph);
+    launch configuration (autotuned, with graph replay allowed);
     every output sample of 32 seeded sources is compared, 24 drawn from the
     whole batch and the first 8 of those whose full-response region is
     non-empty."""
@@ -148,7 +148,9 @@ def test_c4_batch_bench_launch(tdi, orc):
             plan.run(tdi.make_sources(batch.sources), batch.offsets, hp, hc, X, Y, Z)
         assert plan.sync() == tdi.TDI_OK
         desc = plan.describe()
-    assert desc["graph"] == 1 and desc["grid_lfa"] > 0
+    # the autotuner keeps graph replay (persistent grids) unless stream launches
+    # time faster over back-to-back runs
+    assert desc["tuned"] == 1 and (desc["graph"] == 0 or desc["grid_lfa"] > 0)
     rng = np.random.default_rng(24)
     hybrid_srcs = [i for i in range(batch.n_sources) if math.isfinite(batch.sources[i]["t_hyb"])]
     drawn = set(rng.choice(batch.n_sources, 24, replace=False).tolist())
