@@ -56,6 +56,7 @@ struct tdi_plan {
   int device, n_cu;
   size_t max_lds;                // LDS bytes available to one workgroup
   int last_fast, last_tile_lfa;  // LFA kernel choice of the latest run
+  int last_tile_full;            // full-response tile of the latest run
   hipStream_t user_stream;
   hipStream_t graph_stream;      // private stream used for capture and replay
   // device memory
@@ -286,7 +287,7 @@ Caps window_caps(const tdi_config& c, const OrbitBounds& ob, double dt, bool fas
     k.goff = 0;
     k.lds_lfa = tdi::x20_lds_bytes(k.g);
   }
-  k.lds_full = tdi::full_lds_bytes(k.hf, k.y, fp32);
+  k.lds_full = tdi::full_lds_bytes(k.hf, k.y, fp32, c.mode == TDI_MODE_HYBRID ? 1 : 0);
   return k;
 }
 
@@ -311,6 +312,16 @@ bool table_covers(const tdi_plan* p, int64_t n_sources, const tdi_source* src, c
 // Outputs per full-response tile: the hybrid's full regions are short (about a
 // thousand samples per source), so small tiles spread them over more workgroups.
 int full_tile(const tdi_config& c) { return c.mode == TDI_MODE_HYBRID ? tdi::kTileFullHybrid : tdi::kTileFull; }
+
+// Full-response tile for a batch: the FULL mode's kTileFull; in the hybrid,
+// whose full regions are short, kTileFullHybrid, or kTileFullSmall when the
+// batch's full samples would not give every compute unit a tile (one source:
+// the region's latency then sets the run time, and small tiles spread it).
+int full_tile_for(const tdi_config& c, int64_t full_samples, int n_cu) {
+  if (c.mode != TDI_MODE_HYBRID) return tdi::kTileFull;
+  const int64_t tiles = (full_samples + tdi::kTileFullHybrid - 1) / tdi::kTileFullHybrid;
+  return tiles < n_cu ? tdi::kTileFullSmall : tdi::kTileFullHybrid;
+}
 
 // Outputs per LFA tile: the fast path takes the launch's chunk count.
 int lfa_tile(const Caps& caps, const Launch& ln) {
@@ -375,13 +386,39 @@ void fill_constants(tdi::KParams& kp, const tdi_config& c, const tdi_orbit& o, c
   kp.D2_bound = stage2_bound(c, ob);
 }
 
+// Sample ranges of the two kernels for one source ([lb, le) LFA, [fb, fe)
+// full); the kernels apply the exact window predicates per sample, these
+// ranges only need to contain them.
+void kernel_ranges(const tdi_config& c, const tdi_source& s, int64_t n, int64_t& lb, int64_t& le, int64_t& fb,
+                   int64_t& fe) {
+  lb = le = fb = fe = 0;
+  if (c.mode == TDI_MODE_FULL) {
+    fe = n;
+  } else if (c.mode == TDI_MODE_LFA) {
+    le = n;
+  } else {
+    const double kH = (s.t_hyb - s.t0) / s.dt;
+    const double lhi = kH + 0.5 * c.hyb_T_samples;     // LFA where k - kH <= T/2
+    const double flo = kH - 0.5 * c.hyb_T_samples;     // full where k - kH >= -T/2
+    le = !(lhi < (double)n) ? n : (lhi < 0.0 ? 0 : std::min<int64_t>(n, (int64_t)floor(lhi) + 2));
+    fb = !(flo > 0.0) ? 0 : (flo >= (double)n ? n : std::max<int64_t>(0, (int64_t)ceil(flo) - 2));
+    fe = n;
+  }
+}
+
 // Fill the pinned parameter image for one batch (work lists of both kernels).
 void stage_batch(const tdi_config& c, tdi::KParams* kp, int64_t n_sources, const tdi_source* src,
                  const int64_t* offsets, const double* hp, const double* hc, void* X, void* Y, void* Z,
-                 const Caps& caps, const Launch& ln) {
+                 const Caps& caps, const Launch& ln, int n_cu) {
   tdi::SrcDev* sd = reinterpret_cast<tdi::SrcDev*>(kp + 1);
   const int tile_lfa = lfa_tile(caps, ln);
-  const int tile_full = full_tile(c);
+  int64_t full_samples = 0;
+  for (int64_t i = 0; i < n_sources; ++i) {
+    int64_t lb, le, fb, fe;
+    kernel_ranges(c, src[i], offsets[i + 1] - offsets[i], lb, le, fb, fe);
+    full_samples += fe - fb;
+  }
+  const int tile_full = full_tile_for(c, full_samples, n_cu);
   int64_t tl = 0, tf = 0;
   for (int64_t i = 0; i < n_sources; ++i) {
     const tdi_source& s = src[i];
@@ -391,21 +428,8 @@ void stage_batch(const tdi_config& c, tdi::KParams* kp, int64_t n_sources, const
     d.s2psi = sin(2.0 * s.psi);
     d.off = offsets[i];
     d.n = offsets[i + 1] - offsets[i];
-    // sample ranges of the two kernels; the kernels apply the exact window
-    // predicates per sample, these ranges only need to contain them
-    int64_t lb = 0, le = 0, fb = 0, fe = 0;
-    if (c.mode == TDI_MODE_FULL) {
-      fe = d.n;
-    } else if (c.mode == TDI_MODE_LFA) {
-      le = d.n;
-    } else {
-      const double kH = (s.t_hyb - s.t0) / s.dt;
-      const double lhi = kH + 0.5 * c.hyb_T_samples;     // LFA where k - kH <= T/2
-      const double flo = kH - 0.5 * c.hyb_T_samples;     // full where k - kH >= -T/2
-      le = !(lhi < (double)d.n) ? d.n : (lhi < 0.0 ? 0 : std::min<int64_t>(d.n, (int64_t)floor(lhi) + 2));
-      fb = !(flo > 0.0) ? 0 : (flo >= (double)d.n ? d.n : std::max<int64_t>(0, (int64_t)ceil(flo) - 2));
-      fe = d.n;
-    }
+    int64_t lb, le, fb, fe;
+    kernel_ranges(c, s, d.n, lb, le, fb, fe);
     d.lfa_kb = lb; d.lfa_ke = le; d.lfa_t0 = tl;
     d.full_kb = fb; d.full_ke = fe; d.full_t0 = tf;
     if (le > lb) tl += (le - lb + tile_lfa - 1) / tile_lfa;
@@ -634,8 +658,8 @@ tdi_status run_x20(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   const int slot = p->stage_slot;
   if (!acquire_stage(p, slot)) return TDI_EDEVICE;
   stage_batch(p->cfg15, p->h_params15, n_sources, src, offsets, hp, hc, p->d_x15, p->d_x15 + total,
-              p->d_x15 + 2 * total, caps15, ln15);
-  stage_batch(p->cfg, p->h_params, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
+              p->d_x15 + 2 * total, caps15, ln15, p->n_cu);
+  stage_batch(p->cfg, p->h_params, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln, p->n_cu);
   p->h_params->x15 = p->d_x15;
   p->h_params->x15_stride = total;
   const size_t copy_bytes = sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)n_sources;
@@ -676,7 +700,8 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
   // the image of this staging slot must have been uploaded by its earlier run
   const int sslot = p->stage_slot;
   if (!acquire_stage(p, sslot)) return TDI_EDEVICE;
-  stage_batch(p->cfg, p->h_params, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
+  stage_batch(p->cfg, p->h_params, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln, p->n_cu);
+  p->last_tile_full = p->h_params->tile_full;
   const int64_t tl = p->h_params->n_tiles_lfa, tf = p->h_params->n_tiles_full;
   // per-tile records of the fast path: tiles hold at least kFastChunk outputs,
   // so a batch within the plan's maxima always fits; checked all the same
@@ -1119,7 +1144,8 @@ tdi_status tdi_plan_describe(const tdi_plan* p, char* buf, int32_t buflen) {
            "{\"tile_lfa\": %d, \"tile_full\": %d, \"grid_lfa\": %d, \"grid_full\": %d, "
            "\"graph\": %d, \"graph_kernel_events\": %d, \"cu\": %d, \"tuned\": %d, \"lfa_fast\": %d, "
            "\"x20_from_x15\": %d}",
-           p->last_tile_lfa, full_tile(p->cfg), p->launch.grid_lfa, p->launch.grid_full,
+           p->last_tile_lfa, p->last_tile_full > 0 ? p->last_tile_full : full_tile(p->cfg), p->launch.grid_lfa,
+           p->launch.grid_full,
            (p->cfg.use_graph && !p->stream_pick && !x20_shortcut(p->cfg) && p->launch.grid_lfa > 0 &&
             p->launch.grid_full > 0) ? 1 : 0,
            p->graph_timed ? 1 : 0, p->n_cu,
@@ -1247,7 +1273,7 @@ tdi_status tdi_run_noalloc(const tdi_config* cfg, const tdi_orbit* orb, int64_t 
   memset(g_na_image, 0, sizeof(g_na_image));
   tdi::KParams* kp = reinterpret_cast<tdi::KParams*>(g_na_image + kNaParOff);
   fill_constants(*kp, *cfg, *orb, ob, nullptr);
-  stage_batch(*cfg, kp, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln);
+  stage_batch(*cfg, kp, n_sources, src, offsets, hp, hc, X, Y, Z, caps, ln, d.n_cu);
   if (caps.fast && kp->n_tiles_lfa > kNaMaxTiles) return TDI_ESTATE;
   kp->err = reinterpret_cast<int32_t*>(d.ptr + kNaErrOff);
   kp->counters = reinterpret_cast<uint32_t*>(d.ptr + kNaCntOff);

@@ -14,6 +14,7 @@ constexpr int kFitLen = kNQ * kNodes;   // coefficients of one tile fit
 constexpr int kTileLfa = 1024;    // outputs per LFA tile (4 waves x 256)
 constexpr int kTileFull = 256;    // outputs per full-response tile (FULL mode; the largest)
 constexpr int kTileFullHybrid = 64;   // the hybrid's short full regions: small tiles, more workgroups
+constexpr int kTileFullSmall = 16;    // hybrid batches with fewer full tiles than compute units
 constexpr int kWaveOut = 256;     // LFA FP32: outputs per wave (4 per lane, stride 64)
 // FP32 bulk LFA path (k_lfa_fast): chunks of 4 waves x 64 lanes x 9 outputs,
 // four chunks per tile (one geometry fit); its stencil pass covers up to
@@ -111,7 +112,9 @@ size_t fast_tile_bytes();     // bytes of one per-tile record
 // derivative window; goff receives the byte offset of the latter.  Fast path:
 // h window and the three F_l series, overlaid when one stencil sweep suffices.
 size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int nx, int* goff);
-size_t full_lds_bytes(int cap_h, int cap_y, int fp32);
+// hybrid != 0 adds the per-term values of the term-parallel stage 2 (tiles of at
+// most kTileFullHybrid outputs)
+size_t full_lds_bytes(int cap_h, int cap_y, int fp32, int hybrid);
 int occupancy_lfa(int taps, int fp32, int fast, int nx, size_t lds);
 int occupancy_full(int taps, int fp32, size_t lds);
 

@@ -1896,7 +1896,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
   TC* hwin = reinterpret_cast<TC*>(dyn);                                        // [cap_hf][2]
   TC* ywin = reinterpret_cast<TC*>(dyn + align16((size_t)P.cap_hf * 2 * sizeof(TC)));  // [6][cap_y]
   double* Tc = reinterpret_cast<double*>(dyn + align16((size_t)P.cap_hf * 2 * sizeof(TC)) +
-                                         align16((size_t)cap_y * 6 * sizeof(TC)));       // [6][tile]
+                                         align16((size_t)cap_y * 6 * sizeof(TC)));       // [9][kTileFull]
+  TC* tv = reinterpret_cast<TC*>(Tc + 9 * kTileFull);   // hybrid: [tile * 3][terms] signed term values
 
   int64_t iter = 0;
   for (;;) {
@@ -2024,9 +2025,63 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
 
     // Stage 2: sum of +-y_l at the term delays, light times at the output time
     // (or time-nested: each light time from the fit at its retarded sample).
-    // One work item per (output, channel).
     const int nterms = P.gen == 20 ? 16 : 8;
     const double kH = sh.kH;
+    // the signed value of term t of channel c at output i
+    auto term = [&](int i, int c, int t) -> TC {
+      const int64_t k = k0 + i;
+      double d = 0.0;
+      int slot, sign;
+      if (P.nested) {
+#pragma unroll 1
+        for (int q = 0; q < c_nlen[t]; ++q) {
+          const double sq = ((double)k - d / dt - sh.F.kc) * sh.F.ikh;
+          d += geo_eval(sh.F, qT(rot_slot(c_nseq[t][q], c)), sq);
+        }
+        slot = c_nlink[t];
+        sign = c_nsign[t];
+      } else {
+#pragma unroll
+        for (int a = 0; a < 6; ++a) d += (double)c_tcoef[t][unrot_slot(a, c)] * Tc[a * kTileFull + i];
+        slot = c_tlink[t];
+        sign = c_tsign[t];
+      }
+      const TC* ys = ywin + rot_slot(slot, c) * cap_y;
+      TC v;
+      if (d == 0.0) {
+        v = ys[k - y0];
+      } else {
+        int64_t i0;
+        double x;
+        split(k, d, dt, i0, x);
+        const int64_t b = i0 - N / 2 + 1 - y0;
+        if (b < 0 || b + N > ny) {
+          report(P.err, 16, k, b, ny);
+          v = (TC)__builtin_nan("");
+        } else if (x == 0.0) {
+          v = ys[b + N / 2 - 1];
+        } else {
+          TC vv[1];
+          lag_interp<N, 1, TC>(x, ys + b, vv);
+          v = vv[0];
+        }
+      }
+      return sign > 0 ? v : -v;
+    };
+    // Hybrid tiles (at most kTileFullHybrid outputs) take one work item per
+    // (output, channel, term), so that a tile's latency is a few reads rather
+    // than all of a channel's terms in sequence; the terms are then summed in
+    // their order, as the per-(output, channel) loop below does.
+    const bool tpar = P.tile_full <= kTileFullHybrid && !bad;
+    if (tpar) {
+      for (int it = tid; it < cnt * 3 * nterms; it += kBlock) {
+        const int t = it % nterms, ic = it / nterms, i = ic / 3, c = ic - 3 * i;
+        const double rel = (double)(k0 + i) - kH;
+        if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
+        tv[it] = term(i, c, t);
+      }
+      __syncthreads();
+    }
     for (int it = tid; it < cnt * 3; it += kBlock) {
       const int i = it / 3, c = it - 3 * i;
       const int64_t k = k0 + i;
@@ -2036,53 +2091,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
       if (bad) {
         outc = __builtin_nan("");
       } else {
-        double T6[6];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) T6[a] = Tc[a * kTileFull + i];
-        {
-          TC sum = (TC)0;
+        TC sum = (TC)0;
+        if (tpar) {
+          for (int t = 0; t < nterms; ++t) sum += tv[it * nterms + t];
+        } else {
 #pragma unroll 1
-          for (int t = 0; t < nterms; ++t) {
-            double d = 0.0;
-            int slot, sign;
-            if (P.nested) {
-#pragma unroll 1
-              for (int q = 0; q < c_nlen[t]; ++q) {
-                const double sq = ((double)k - d / dt - sh.F.kc) * sh.F.ikh;
-                d += geo_eval(sh.F, qT(rot_slot(c_nseq[t][q], c)), sq);
-              }
-              slot = c_nlink[t];
-              sign = c_nsign[t];
-            } else {
-#pragma unroll
-              for (int a = 0; a < 6; ++a) d += (double)c_tcoef[t][unrot_slot(a, c)] * T6[a];
-              slot = c_tlink[t];
-              sign = c_tsign[t];
-            }
-            const TC* ys = ywin + rot_slot(slot, c) * cap_y;
-            TC v;
-            if (d == 0.0) {
-              v = ys[k - y0];
-            } else {
-              int64_t i0;
-              double x;
-              split(k, d, dt, i0, x);
-              const int64_t b = i0 - N / 2 + 1 - y0;
-              if (b < 0 || b + N > ny) {
-                report(P.err, 16, k, b, ny);
-                v = (TC)__builtin_nan("");
-              } else if (x == 0.0) {
-                v = ys[b + N / 2 - 1];
-              } else {
-                TC vv[1];
-                lag_interp<N, 1, TC>(x, ys + b, vv);
-                v = vv[0];
-              }
-            }
-            sum += sign > 0 ? v : -v;
-          }
-          outc = (double)sum;
+          for (int t = 0; t < nterms; ++t) sum += term(i, c, t);
         }
+        outc = (double)sum;
       }
       if (P.aet) {
         // A, E, T mix the channels: the three items of an output meet in LDS
@@ -2505,11 +2521,12 @@ size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int nx,
   return hb + align16((size_t)cap_g * (nx ? 4 : 2) * tcs);
 }
 
-size_t full_lds_bytes(int cap_h, int cap_y, int fp32) {
+size_t full_lds_bytes(int cap_h, int cap_y, int fp32, int hybrid) {
   const size_t tcs = fp32 ? sizeof(float) : sizeof(double);
-  // light times of the tile's outputs (6 rows) and, for A, E, T, the three channels
+  // light times of the tile's outputs (6 rows) and, for A, E, T, the three
+  // channels; the hybrid's term-parallel stage 2 keeps every term's value
   return align16((size_t)cap_h * 2 * tcs) + align16((size_t)cap_y * 6 * tcs) +
-         (size_t)9 * kTileFull * sizeof(double);
+         (size_t)9 * kTileFull * sizeof(double) + (hybrid ? (size_t)kTileFullHybrid * 3 * 16 * tcs : 0);
 }
 
 int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int nx, int grid, size_t lds, void* stream) {
