@@ -43,6 +43,7 @@ struct Caps {
   int fast;          // FP32 bulk LFA kernel
   int nx;            // LFA with the next term (general LFA kernel)
   int tile_lfa;      // outputs per LFA tile
+  int hyb;           // HYBRID mode: term-parallel full-response kernel
 };
 
 }  // namespace
@@ -287,7 +288,8 @@ Caps window_caps(const tdi_config& c, const OrbitBounds& ob, double dt, bool fas
     k.goff = 0;
     k.lds_lfa = tdi::x20_lds_bytes(k.g);
   }
-  k.lds_full = tdi::full_lds_bytes(k.hf, k.y, fp32, c.mode == TDI_MODE_HYBRID ? 1 : 0);
+  k.hyb = c.mode == TDI_MODE_HYBRID ? 1 : 0;
+  k.lds_full = tdi::full_lds_bytes(k.hf, k.y, fp32, k.hyb);
   return k;
 }
 
@@ -463,7 +465,7 @@ hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& c
     return hipErrorLaunchFailure;
   if (evs && (e = hipEventRecord(evs[2], st)) != hipSuccess) return e;
   const int gf = ln.grid_full > 0 ? ln.grid_full : (int)std::max<int64_t>(0, tiles_full);
-  if (gf > 0 && tdi::launch_full(p->d_params, taps, fp32, gf, caps.lds_full, st) != 0)
+  if (gf > 0 && tdi::launch_full(p->d_params, taps, fp32, caps.hyb, gf, caps.lds_full, st) != 0)
     return hipErrorLaunchFailure;
   if (evs && (e = hipEventRecord(evs[3], st)) != hipSuccess) return e;
   return hipSuccess;
@@ -648,7 +650,7 @@ tdi_status run_x20(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   const int64_t total = offsets[n_sources];
   Launch ln15 = {tdi::occupancy_lfa(taps, 0, 0, 0, caps15.lds_lfa) * p->n_cu, 0, 4};
   Launch ln = {tdi::occupancy_x20(taps, fp32, caps.lds_lfa) * p->n_cu,
-               tdi::occupancy_full(taps, fp32, caps.lds_full) * p->n_cu, 4};
+               tdi::occupancy_full(taps, fp32, caps.hyb, caps.lds_full) * p->n_cu, 4};
   p->last_fast = 0;
   p->last_tile_lfa = tdi::kTileLfa;
   if (p->staged_pending) {
@@ -677,7 +679,7 @@ tdi_status run_x20(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
     return TDI_EDEVICE;
   if (evs && hipEventRecord(evs[2], st) != hipSuccess) return TDI_EDEVICE;
   if (p->h_params->n_tiles_full > 0 &&
-      tdi::launch_full(p->d_params, taps, fp32, ln.grid_full, caps.lds_full, st) != 0)
+      tdi::launch_full(p->d_params, taps, fp32, caps.hyb, ln.grid_full, caps.lds_full, st) != 0)
     return TDI_EDEVICE;
   if (evs && hipEventRecord(evs[3], st) != hipSuccess) return TDI_EDEVICE;
   hipEventRecord(p->staged_free, st);
@@ -796,7 +798,7 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
   Caps caps;
   if (!batch_caps(p->cfg, p->ob, n_sources, src, offsets, &caps)) return;
   const int ol = tdi::occupancy_lfa(p->cfg.interp_taps, p->cfg.precision, caps.fast, caps.nx, caps.lds_lfa);
-  const int of = tdi::occupancy_full(p->cfg.interp_taps, p->cfg.precision, caps.lds_full);
+  const int of = tdi::occupancy_full(p->cfg.interp_taps, p->cfg.precision, caps.hyb, caps.lds_full);
   // grid candidates (persistent at the resident count, half and twice that, or
   // one workgroup per tile), each with every tile shape of the fast LFA path:
   // small tiles give single long sources enough tiles to fill the chip, large
@@ -994,7 +996,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
     // graph replay needs persistent launches: one full occupancy of the chip
     const Caps caps = window_caps(*cfg, p->ob, 1.0, fast_lfa(*cfg, p->ob, 1.0));
     p->launch.grid_lfa = tdi::occupancy_lfa(cfg->interp_taps, cfg->precision, caps.fast, caps.nx, caps.lds_lfa) * p->n_cu;
-    p->launch.grid_full = tdi::occupancy_full(cfg->interp_taps, cfg->precision, caps.lds_full) * p->n_cu;
+    p->launch.grid_full = tdi::occupancy_full(cfg->interp_taps, cfg->precision, caps.hyb, caps.lds_full) * p->n_cu;
   }
   *out = p;
   return TDI_OK;
@@ -1267,7 +1269,7 @@ tdi_status tdi_run_noalloc(const tdi_config* cfg, const tdi_orbit* orb, int64_t 
   const int taps = cfg->interp_taps, fp32 = cfg->precision;
   Launch ln;
   ln.grid_lfa = tdi::occupancy_lfa(taps, fp32, caps.fast, caps.nx, caps.lds_lfa) * d.n_cu;
-  ln.grid_full = tdi::occupancy_full(taps, fp32, caps.lds_full) * d.n_cu;
+  ln.grid_full = tdi::occupancy_full(taps, fp32, caps.hyb, caps.lds_full) * d.n_cu;
   ln.chunks = cfg->fast_tile_chunks != 0 ? cfg->fast_tile_chunks : 4;
 
   memset(g_na_image, 0, sizeof(g_na_image));
@@ -1288,7 +1290,7 @@ tdi_status tdi_run_noalloc(const tdi_config* cfg, const tdi_orbit* orb, int64_t 
     if (caps.fast && tdi::launch_lfa_fit(dp, taps, 4 * d.n_cu, s) != 0) return TDI_EDEVICE;
     if (tdi::launch_lfa(dp, taps, fp32, caps.fast, caps.nx, ln.grid_lfa, caps.lds_lfa, s) != 0) return TDI_EDEVICE;
   }
-  if (kp->n_tiles_full > 0 && tdi::launch_full(dp, taps, fp32, ln.grid_full, caps.lds_full, s) != 0)
+  if (kp->n_tiles_full > 0 && tdi::launch_full(dp, taps, fp32, caps.hyb, ln.grid_full, caps.lds_full, s) != 0)
     return TDI_EDEVICE;
   return TDI_OK;
 }

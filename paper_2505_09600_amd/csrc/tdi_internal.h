@@ -96,7 +96,9 @@ int set_constants();
 // fast != 0 selects the FP32 bulk LFA kernel (fp32 must be 1)
 // nx != 0: LFA with the next term (lfa_terms = 2; general kernel only)
 int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int nx, int grid, size_t lds_bytes, void* stream);
-int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
+// hybrid != 0: the term-parallel stage 2 (tiles of at most kTileFullHybrid, LDS from
+// full_lds_bytes(..., hybrid = 1))
+int launch_full(const KParams* dp, int taps, int fp32, int hybrid, int grid, size_t lds_bytes, void* stream);
 // TDI 2.0 LFA from the TDI 1.5 LFA series in KParams::x15 (window capacity cap_g)
 int launch_x20(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes, void* stream);
 int occupancy_x20(int taps, int fp32, size_t lds);
@@ -116,6 +118,6 @@ size_t lfa_lds_bytes(int taps, int cap_g, int cap_h, int fp32, int fast, int nx,
 // most kTileFullHybrid outputs)
 size_t full_lds_bytes(int cap_h, int cap_y, int fp32, int hybrid);
 int occupancy_lfa(int taps, int fp32, int fast, int nx, size_t lds);
-int occupancy_full(int taps, int fp32, size_t lds);
+int occupancy_full(int taps, int fp32, int hybrid, size_t lds);
 
 }  // namespace tdi

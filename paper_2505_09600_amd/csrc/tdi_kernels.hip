@@ -1884,7 +1884,10 @@ __device__ __forceinline__ void full_store(const KParams& P, int64_t o, int c, d
   }
 }
 
-template <int N, typename TC>
+// TP: term-parallel stage 2 (the hybrid's tiles of at most kTileFullHybrid
+// outputs, with the term buffer in LDS); the FULL mode's larger tiles sum each
+// channel's terms in one work item.
+template <int N, typename TC, bool TP>
 __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ Pp) {
   const KParams& P = *Pp;
   const SrcDev* __restrict__ SS = sources_of(Pp);
@@ -2027,85 +2030,151 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
     // (or time-nested: each light time from the fit at its retarded sample).
     const int nterms = P.gen == 20 ? 16 : 8;
     const double kH = sh.kH;
-    // the signed value of term t of channel c at output i
-    auto term = [&](int i, int c, int t) -> TC {
-      const int64_t k = k0 + i;
-      double d = 0.0;
-      int slot, sign;
-      if (P.nested) {
+    if constexpr (TP) {
+      // the signed value of term t of channel c at output i (T6: the light times
+      // at the output)
+      auto term = [&](int i, int c, int t, const double (&T6)[6]) -> TC {
+        const int64_t k = k0 + i;
+        double d = 0.0;
+        int slot, sign;
+        if (P.nested) {
 #pragma unroll 1
-        for (int q = 0; q < c_nlen[t]; ++q) {
-          const double sq = ((double)k - d / dt - sh.F.kc) * sh.F.ikh;
-          d += geo_eval(sh.F, qT(rot_slot(c_nseq[t][q], c)), sq);
-        }
-        slot = c_nlink[t];
-        sign = c_nsign[t];
-      } else {
+          for (int q = 0; q < c_nlen[t]; ++q) {
+            const double sq = ((double)k - d / dt - sh.F.kc) * sh.F.ikh;
+            d += geo_eval(sh.F, qT(rot_slot(c_nseq[t][q], c)), sq);
+          }
+          slot = c_nlink[t];
+          sign = c_nsign[t];
+        } else {
 #pragma unroll
-        for (int a = 0; a < 6; ++a) d += (double)c_tcoef[t][unrot_slot(a, c)] * Tc[a * kTileFull + i];
-        slot = c_tlink[t];
-        sign = c_tsign[t];
-      }
-      const TC* ys = ywin + rot_slot(slot, c) * cap_y;
-      TC v;
-      if (d == 0.0) {
-        v = ys[k - y0];
-      } else {
-        int64_t i0;
-        double x;
-        split(k, d, dt, i0, x);
-        const int64_t b = i0 - N / 2 + 1 - y0;
-        if (b < 0 || b + N > ny) {
-          report(P.err, 16, k, b, ny);
-          v = (TC)__builtin_nan("");
-        } else if (x == 0.0) {
-          v = ys[b + N / 2 - 1];
-        } else {
-          TC vv[1];
-          lag_interp<N, 1, TC>(x, ys + b, vv);
-          v = vv[0];
+          for (int a = 0; a < 6; ++a) d += (double)c_tcoef[t][unrot_slot(a, c)] * T6[a];
+          slot = c_tlink[t];
+          sign = c_tsign[t];
         }
+        const TC* ys = ywin + rot_slot(slot, c) * cap_y;
+        TC v;
+        if (d == 0.0) {
+          v = ys[k - y0];
+        } else {
+          int64_t i0;
+          double x;
+          split(k, d, dt, i0, x);
+          const int64_t b = i0 - N / 2 + 1 - y0;
+          if (b < 0 || b + N > ny) {
+            report(P.err, 16, k, b, ny);
+            v = (TC)__builtin_nan("");
+          } else if (x == 0.0) {
+            v = ys[b + N / 2 - 1];
+          } else {
+            TC vv[1];
+            lag_interp<N, 1, TC>(x, ys + b, vv);
+            v = vv[0];
+          }
+        }
+        return sign > 0 ? v : -v;
+      };
+      // Hybrid tiles (at most kTileFullHybrid outputs) take one work item per
+      // (output, channel, term), so that a tile's latency is a few reads rather
+      // than all of a channel's terms in sequence; the terms are then summed in
+      // their order, as the per-(output, channel) loop below does.
+      if (!bad) {
+        for (int it = tid; it < cnt * 3 * nterms; it += kBlock) {
+          const int t = it % nterms, ic = it / nterms, i = ic / 3, c = ic - 3 * i;
+          const double rel = (double)(k0 + i) - kH;
+          if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
+          double T6[6];
+#pragma unroll
+          for (int a = 0; a < 6; ++a) T6[a] = Tc[a * kTileFull + i];
+          tv[it] = term(i, c, t, T6);
+        }
+        __syncthreads();
       }
-      return sign > 0 ? v : -v;
-    };
-    // Hybrid tiles (at most kTileFullHybrid outputs) take one work item per
-    // (output, channel, term), so that a tile's latency is a few reads rather
-    // than all of a channel's terms in sequence; the terms are then summed in
-    // their order, as the per-(output, channel) loop below does.
-    const bool tpar = P.tile_full <= kTileFullHybrid && !bad;
-    if (tpar) {
-      for (int it = tid; it < cnt * 3 * nterms; it += kBlock) {
-        const int t = it % nterms, ic = it / nterms, i = ic / 3, c = ic - 3 * i;
-        const double rel = (double)(k0 + i) - kH;
+      for (int it = tid; it < cnt * 3; it += kBlock) {
+        const int i = it / 3, c = it - 3 * i;
+        const int64_t k = k0 + i;
+        const double rel = (double)k - kH;
         if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
-        tv[it] = term(i, c, t);
-      }
-      __syncthreads();
-    }
-    for (int it = tid; it < cnt * 3; it += kBlock) {
-      const int i = it / 3, c = it - 3 * i;
-      const int64_t k = k0 + i;
-      const double rel = (double)k - kH;
-      if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
-      double outc;
-      if (bad) {
-        outc = __builtin_nan("");
-      } else {
-        TC sum = (TC)0;
-        if (tpar) {
-          for (int t = 0; t < nterms; ++t) sum += tv[it * nterms + t];
+        double outc;
+        if (bad) {
+          outc = __builtin_nan("");
         } else {
-#pragma unroll 1
-          for (int t = 0; t < nterms; ++t) sum += term(i, c, t);
+          TC sum = (TC)0;
+          for (int t = 0; t < nterms; ++t) sum += tv[it * nterms + t];
+          outc = (double)sum;
         }
-        outc = (double)sum;
+        if (P.aet) {
+          // A, E, T mix the channels: the three items of an output meet in LDS
+          Tc[(6 + c) * kTileFull + i] = outc;
+          continue;
+        }
+        full_store<TC>(P, S.off + k, c, outc, rel);
       }
-      if (P.aet) {
-        // A, E, T mix the channels: the three items of an output meet in LDS
-        Tc[(6 + c) * kTileFull + i] = outc;
-        continue;
+    } else {
+      // One work item per (output, channel).
+      for (int it = tid; it < cnt * 3; it += kBlock) {
+        const int i = it / 3, c = it - 3 * i;
+        const int64_t k = k0 + i;
+        const double rel = (double)k - kH;
+        if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
+        double outc;
+        if (bad) {
+          outc = __builtin_nan("");
+        } else {
+          double T6[6];
+#pragma unroll
+          for (int a = 0; a < 6; ++a) T6[a] = Tc[a * kTileFull + i];
+          {
+            TC sum = (TC)0;
+#pragma unroll 1
+            for (int t = 0; t < nterms; ++t) {
+              double d = 0.0;
+              int slot, sign;
+              if (P.nested) {
+#pragma unroll 1
+                for (int q = 0; q < c_nlen[t]; ++q) {
+                  const double sq = ((double)k - d / dt - sh.F.kc) * sh.F.ikh;
+                  d += geo_eval(sh.F, qT(rot_slot(c_nseq[t][q], c)), sq);
+                }
+                slot = c_nlink[t];
+                sign = c_nsign[t];
+              } else {
+#pragma unroll
+                for (int a = 0; a < 6; ++a) d += (double)c_tcoef[t][unrot_slot(a, c)] * T6[a];
+                slot = c_tlink[t];
+                sign = c_tsign[t];
+              }
+              const TC* ys = ywin + rot_slot(slot, c) * cap_y;
+              TC v;
+              if (d == 0.0) {
+                v = ys[k - y0];
+              } else {
+                int64_t i0;
+                double x;
+                split(k, d, dt, i0, x);
+                const int64_t b = i0 - N / 2 + 1 - y0;
+                if (b < 0 || b + N > ny) {
+                  report(P.err, 16, k, b, ny);
+                  v = (TC)__builtin_nan("");
+                } else if (x == 0.0) {
+                  v = ys[b + N / 2 - 1];
+                } else {
+                  TC vv[1];
+                  lag_interp<N, 1, TC>(x, ys + b, vv);
+                  v = vv[0];
+                }
+              }
+              sum += sign > 0 ? v : -v;
+            }
+            outc = (double)sum;
+          }
+        }
+        if (P.aet) {
+          // A, E, T mix the channels: the three items of an output meet in LDS
+          Tc[(6 + c) * kTileFull + i] = outc;
+          continue;
+        }
+        full_store<TC>(P, S.off + k, c, outc, rel);
       }
-      full_store<TC>(P, S.off + k, c, outc, rel);
     }
     if (P.aet) {
       __syncthreads();
@@ -2351,8 +2420,9 @@ int occ_x20_t(size_t lds) {
 }
 
 template <int N, typename TC>
-int launch_full_t(const KParams* dp, int grid, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((k_full<N, TC>), dim3(grid), dim3(kBlock), lds, st, dp);
+int launch_full_t(const KParams* dp, int tp, int grid, size_t lds, hipStream_t st) {
+  if (tp) hipLaunchKernelGGL((k_full<N, TC, true>), dim3(grid), dim3(kBlock), lds, st, dp);
+  else hipLaunchKernelGGL((k_full<N, TC, false>), dim3(grid), dim3(kBlock), lds, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -2391,9 +2461,11 @@ int occ_lfa_t(int nx, size_t lds) {
 }
 
 template <int N, typename TC>
-int occ_full_t(size_t lds) {
+int occ_full_t(int tp, size_t lds) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_full<N, TC>), kBlock, lds) != hipSuccess) return 1;
+  const void* f = tp ? reinterpret_cast<const void*>(&k_full<N, TC, true>)
+                     : reinterpret_cast<const void*>(&k_full<N, TC, false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, kBlock, lds) != hipSuccess) return 1;
   return n > 0 ? n : 1;
 }
 
@@ -2556,8 +2628,8 @@ int occupancy_x20(int taps, int fp32, size_t lds) {
 
 size_t x20_lds_bytes(int cap) { return (size_t)6 * cap * sizeof(double); }
 
-int launch_full(const KParams* dp, int taps, int fp32, int grid, size_t lds, void* stream) {
-  TDI_DISPATCH(taps, fp32, launch_full_t, dp, grid, lds, (hipStream_t)stream);
+int launch_full(const KParams* dp, int taps, int fp32, int hybrid, int grid, size_t lds, void* stream) {
+  TDI_DISPATCH(taps, fp32, launch_full_t, dp, hybrid, grid, lds, (hipStream_t)stream);
   return -2;
 }
 
@@ -2581,8 +2653,8 @@ int occupancy_lfa(int taps, int fp32, int fast, int nx, size_t lds) {
   return 1;
 }
 
-int occupancy_full(int taps, int fp32, size_t lds) {
-  TDI_DISPATCH(taps, fp32, occ_full_t, lds);
+int occupancy_full(int taps, int fp32, int hybrid, size_t lds) {
+  TDI_DISPATCH(taps, fp32, occ_full_t, hybrid, lds);
   return 1;
 }
 
