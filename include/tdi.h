@@ -238,6 +238,14 @@ tdi_status tdi_plan_sync(tdi_plan* plan);
  * the plan's work; the record is cleared afterwards. */
 tdi_status tdi_plan_kernel_times(tdi_plan* plan, float* ms, int32_t cap, int32_t* count);
 
+/* Per-kernel timing of tdi_run on (on = 1, the default) or off (on = 0).
+ * Each timed run records device events around its kernels, and each such
+ * record is a marker in the device queue that costs microseconds of device
+ * time: for short runs (one source, ~0.1 ms) turning it off shortens the run;
+ * untimed runs add nothing to tdi_plan_kernel_times.  TDI_EINVAL for other
+ * values of on, TDI_ESTATE for a null plan. */
+tdi_status tdi_plan_set_timing(tdi_plan* plan, int32_t on);
+
 /* Launch parameters chosen for the plan as a JSON object in buf (tile
  * lengths, persistent grid sizes, graph use, compute units, tuned flag). */
 tdi_status tdi_plan_describe(const tdi_plan* plan, char* buf, int32_t buflen);

@@ -97,6 +97,7 @@ struct tdi_plan {
   Launch launch;
   bool tuned;
   bool stream_pick;              // the autotuner found stream launches faster than graph replay
+  bool timing;                   // runs record the per-kernel events (tdi_plan_set_timing)
   // graph
   hipGraph_t graph;
   hipGraphExec_t graph_exec;
@@ -990,6 +991,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
     p->h_params15->counters = reinterpret_cast<uint32_t*>(p->d_block15);
   }
 
+  p->timing = true;
   p->launch = {0, 0, cfg->fast_tile_chunks != 0 ? cfg->fast_tile_chunks : 4};
   p->tuned = cfg->autotune && !x20_shortcut(*cfg) ? false : true;
   if (!cfg->autotune && cfg->use_graph) {
@@ -1042,7 +1044,14 @@ tdi_status tdi_run(tdi_plan* p, int64_t n_sources, const tdi_source* src, const 
   if ((((uintptr_t)X) | ((uintptr_t)Y) | ((uintptr_t)Z)) & (al - 1)) return TDI_EINVAL;
   if (!table_covers(p, n_sources, src, offsets)) return TDI_ERANGE;
   if (!p->tuned) autotune(p, n_sources, src, offsets, hp, hc, X, Y, Z);
-  return run_with(p, p->launch, n_sources, src, offsets, hp, hc, X, Y, Z, true, !p->stream_pick);
+  return run_with(p, p->launch, n_sources, src, offsets, hp, hc, X, Y, Z, p->timing, !p->stream_pick);
+}
+
+tdi_status tdi_plan_set_timing(tdi_plan* p, int32_t on) {
+  if (!p) return TDI_ESTATE;
+  if (on != 0 && on != 1) return TDI_EINVAL;
+  p->timing = on != 0;
+  return TDI_OK;
 }
 
 tdi_status tdi_run_links(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,

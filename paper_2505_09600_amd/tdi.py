@@ -26,7 +26,8 @@ TDI_CHANNELS_XYZ, TDI_CHANNELS_AET = 0, 1
 EXPORTED = ["tdi_check_config", "tdi_check_batch", "tdi_plan_create", "tdi_run", "tdi_run_noalloc",
             "tdi_run_links",
             "tdi_plan_sync",
-            "tdi_plan_kernel_times", "tdi_plan_describe", "tdi_plan_destroy", "tdi_status_str",
+            "tdi_plan_kernel_times", "tdi_plan_set_timing", "tdi_plan_describe", "tdi_plan_destroy",
+            "tdi_status_str",
             "tdi_check_noise", "tdi_ip_plan_create", "tdi_ip_run", "tdi_ip_kernel_times",
             "tdi_ip_plan_destroy"]
 
@@ -95,6 +96,7 @@ def lib():
         L.tdi_plan_sync.argtypes = [P]
         L.tdi_plan_kernel_times.argtypes = [P, C.POINTER(C.c_float), C.c_int32, C.POINTER(C.c_int32)]
         L.tdi_plan_describe.argtypes = [P, C.c_char_p, C.c_int32]
+        L.tdi_plan_set_timing.argtypes = [P, C.c_int32]
         L.tdi_plan_destroy.argtypes = [P]
         L.tdi_check_noise.argtypes = [C.POINTER(tdi_noise)]
         L.tdi_ip_plan_create.argtypes = [C.POINTER(P), C.POINTER(tdi_noise), C.c_int32, C.c_double,
@@ -165,6 +167,10 @@ def tdi_plan_kernel_times(plan, cap: int = 256):
     n = C.c_int32()
     st = lib().tdi_plan_kernel_times(plan, buf, cap, C.byref(n))
     return st, [buf[i] for i in range(n.value)]
+
+
+def tdi_plan_set_timing(plan, on: int) -> int:
+    return lib().tdi_plan_set_timing(plan, int(on))
 
 
 def tdi_plan_describe(plan) -> dict:
@@ -282,6 +288,11 @@ class Plan:
         if st != TDI_OK:
             raise TdiError(st, "tdi_plan_kernel_times")
         return v
+
+    def set_timing(self, on: bool):
+        st = tdi_plan_set_timing(self.handle, int(bool(on)))
+        if st != TDI_OK:
+            raise TdiError(st, "tdi_plan_set_timing")
 
     def describe(self) -> dict:
         return tdi_plan_describe(self.handle)

@@ -102,6 +102,7 @@ def test_null_arguments(L):
     assert L.tdi_plan_destroy(None) == T.TDI_EINVAL
     n = C.c_int32()
     assert L.tdi_plan_kernel_times(None, None, 0, C.byref(n)) == T.TDI_EINVAL
+    assert L.tdi_plan_set_timing(None, 1) == T.TDI_ESTATE
 
 
 def _recs(n=3, **kw):

@@ -192,3 +192,38 @@ def test_graph_and_persistent_match_plain_launch(tdi, orc):
     a = _run_gpu(tdi, batch, cfg, orb)
     b = _run_gpu(tdi, batch, cfg, orb, autotune=True, use_graph=True)
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_untimed_runs_match_timed_runs(tdi, orc, graph):
+    """tdi_plan_set_timing(0): the runs record no kernel events and give the
+    same outputs, bit for bit, as timed runs; timing can be turned back on."""
+    import torch
+    batch = _small_analytic(n=30011, seed=17)
+    orb = W.default_orbit()
+    cfg = W.default_config(tdi_gen=20, mode=2, taps=32, stencil_order=4, precision=1)
+    dev = torch.device("cuda:0")
+    hp = torch.as_tensor(batch.hp, device=dev)
+    hc = torch.as_tensor(batch.hc, device=dev)
+    outs = [torch.empty(batch.total, dtype=torch.float32, device=dev) for _ in range(6)]
+    src = tdi.make_sources(batch.sources)
+    with tdi.Plan(cfg, orb, 1, batch.total, autotune=True, use_graph=graph) as plan:
+        plan.run(src, batch.offsets, hp, hc, *outs[:3])
+        assert plan.sync() == tdi.TDI_OK
+        assert len(plan.kernel_times()) == 3
+        plan.set_timing(False)
+        for _ in range(3):
+            plan.run(src, batch.offsets, hp, hc, *outs[3:])
+        assert plan.sync() == tdi.TDI_OK
+        assert len(plan.kernel_times()) == 0
+        plan.set_timing(True)
+        plan.run(src, batch.offsets, hp, hc, *outs[3:])
+        assert plan.sync() == tdi.TDI_OK
+        assert len(plan.kernel_times()) == 3
+    for a, b in zip(outs[:3], outs[3:]):
+        assert torch.equal(a, b)
+    ref = _run_orc(orc, batch, cfg, orb)
+    got = np.stack([o.double().cpu().numpy() for o in outs[3:]])
+    err = _err(orc, got, ref)
+    _report(f"untimed graph={graph}", err, 1e-5)
+    assert np.all(err <= 1e-5)
