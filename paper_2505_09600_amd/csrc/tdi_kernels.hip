@@ -1971,56 +1971,111 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
       }
       __syncthreads();
       // Stage 1: y_l[i] = [H_l(t_i - ds) - H_l(t_i - dr)] / (2 (1 - k.n)), zero
-      // outside the series; antenna patterns at the reception time t_i.  One
-      // work item per (sample, receiving spacecraft): the receiver read is
-      // shared by the two links into that spacecraft, and a small tile still
-      // spreads over the workgroup.
+      // outside the series; antenna patterns at the reception time t_i.  The
+      // receiver read is shared by the two links into each spacecraft.
       const double c2 = sh.c2, s2 = sh.s2;
-      for (int it = tid; it < ny * 3; it += kBlock) {
-        const int ii = it / 3, r = it - 3 * ii;
-        const int64_t i = y0 + ii;
-        // the links received by spacecraft r (slots with rcv_of(a) == r)
-        const int la = r == 0 ? 2 : (r == 1 ? 0 : 1), lb = r == 0 ? 4 : (r == 1 ? 5 : 3);
-        if (!(i >= 0 && i < S.n)) {
-          ywin[la * cap_y + ii] = (TC)0;
-          ywin[lb * cap_y + ii] = (TC)0;
-          continue;
-        }
-        const double s = ((double)i - sh.F.kc) * sh.F.ikh;
-        TC hr[2];
-        {
-          int64_t i0;
-          double x;
-          split(i, geo_eval(sh.F, qKR(r), s), dt, i0, x);
-          const int64_t b = i0 - N / 2 + 1 - w0;
-          if (b < 0 || b + N > nh) {
-            report(P.err, 8, i, b, nh);
-            hr[0] = hr[1] = (TC)__builtin_nan("");
-          } else {
-            interp2<N, TC>(hwin, b, x, hr[0], hr[1]);
+      if constexpr (TP) {
+        // hybrid tiles: one work item per (sample, receiving spacecraft), so
+        // that a small tile still spreads over the workgroup
+        for (int it = tid; it < ny * 3; it += kBlock) {
+          const int ii = it / 3, r = it - 3 * ii;
+          const int64_t i = y0 + ii;
+          // the links received by spacecraft r (slots with rcv_of(a) == r)
+          const int la = r == 0 ? 2 : (r == 1 ? 0 : 1), lb = r == 0 ? 4 : (r == 1 ? 5 : 3);
+          if (!(i >= 0 && i < S.n)) {
+            ywin[la * cap_y + ii] = (TC)0;
+            ywin[lb * cap_y + ii] = (TC)0;
+            continue;
+          }
+          const double s = ((double)i - sh.F.kc) * sh.F.ikh;
+          TC hr[2];
+          {
+            int64_t i0;
+            double x;
+            split(i, geo_eval(sh.F, qKR(r), s), dt, i0, x);
+            const int64_t b = i0 - N / 2 + 1 - w0;
+            if (b < 0 || b + N > nh) {
+              report(P.err, 8, i, b, nh);
+              hr[0] = hr[1] = (TC)__builtin_nan("");
+            } else {
+              interp2<N, TC>(hwin, b, x, hr[0], hr[1]);
+            }
+          }
+  #pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int a = q == 0 ? la : lb;
+            const double T = geo_eval(sh.F, qT(a), s);
+            if (i >= k0 && i < k0 + cnt) Tc[a * kTileFull + (int)(i - k0)] = T;
+            int64_t i0;
+            double x;
+            split(i, T + geo_eval(sh.F, qKR(snd_of(a)), s), dt, i0, x);
+            const int64_t b = i0 - N / 2 + 1 - w0;
+            TC vp, vc;
+            if (b < 0 || b + N > nh) {
+              report(P.err, 8, i, b, nh);
+              vp = vc = (TC)__builtin_nan("");
+            } else {
+              interp2<N, TC>(hwin, b, x, vp, vc);
+            }
+            const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
+            const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
+            const TC Hs = A * vp + B * vc;
+            const TC Hr = A * hr[0] + B * hr[1];
+            ywin[a * cap_y + ii] = (Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s);
           }
         }
+      } else {
+        // FULL tiles: one work item per sample (its three receiver reads and
+        // six links), the geometry evaluated once per sample
+        for (int ii = tid; ii < ny; ii += kBlock) {
+          const int64_t i = y0 + ii;
+          if (!(i >= 0 && i < S.n)) {
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
-          const int a = q == 0 ? la : lb;
-          const double T = geo_eval(sh.F, qT(a), s);
-          if (i >= k0 && i < k0 + cnt) Tc[a * kTileFull + (int)(i - k0)] = T;
-          int64_t i0;
-          double x;
-          split(i, T + geo_eval(sh.F, qKR(snd_of(a)), s), dt, i0, x);
-          const int64_t b = i0 - N / 2 + 1 - w0;
-          TC vp, vc;
-          if (b < 0 || b + N > nh) {
-            report(P.err, 8, i, b, nh);
-            vp = vc = (TC)__builtin_nan("");
-          } else {
-            interp2<N, TC>(hwin, b, x, vp, vc);
+            for (int a = 0; a < 6; ++a) ywin[a * cap_y + ii] = (TC)0;
+            continue;
           }
-          const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
-          const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
-          const TC Hs = A * vp + B * vc;
-          const TC Hr = A * hr[0] + B * hr[1];
-          ywin[a * cap_y + ii] = (Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s);
+          const double s = ((double)i - sh.F.kc) * sh.F.ikh;
+          const double kR0 = geo_eval(sh.F, qKR(0), s), kR1 = geo_eval(sh.F, qKR(1), s),
+                       kR2 = geo_eval(sh.F, qKR(2), s);
+          // the receiver read is shared by the two links into each spacecraft
+          TC hr[6];
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            int64_t i0;
+            double x;
+            split(i, sel3(kR0, kR1, kR2, q), dt, i0, x);
+            const int64_t b = i0 - N / 2 + 1 - w0;
+            if (b < 0 || b + N > nh) {
+              report(P.err, 8, i, b, nh);
+              hr[2 * q] = hr[2 * q + 1] = (TC)__builtin_nan("");
+            } else {
+              interp2<N, TC>(hwin, b, x, hr[2 * q], hr[2 * q + 1]);
+            }
+          }
+#pragma unroll 1
+          for (int a = 0; a < 6; ++a) {
+            const double T = geo_eval(sh.F, qT(a), s);
+            if (i >= k0 && i < k0 + cnt) Tc[a * kTileFull + (int)(i - k0)] = T;
+            int64_t i0;
+            double x;
+            split(i, T + sel3(kR0, kR1, kR2, snd_of(a)), dt, i0, x);
+            const int64_t b = i0 - N / 2 + 1 - w0;
+            TC vp, vc;
+            if (b < 0 || b + N > nh) {
+              report(P.err, 8, i, b, nh);
+              vp = vc = (TC)__builtin_nan("");
+            } else {
+              interp2<N, TC>(hwin, b, x, vp, vc);
+            }
+            const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
+            const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
+            const int r = rcv_of(a);
+            const TC hrp = r == 0 ? hr[0] : (r == 1 ? hr[2] : hr[4]);
+            const TC hrc = r == 0 ? hr[1] : (r == 1 ? hr[3] : hr[5]);
+            const TC Hs = A * vp + B * vc;
+            const TC Hr = A * hrp + B * hrc;
+            ywin[a * cap_y + ii] = (Hs - Hr) / (TC)geo_eval(sh.F, qD(a), s);
+          }
         }
       }
     }
@@ -2110,20 +2165,20 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
         full_store<TC>(P, S.off + k, c, outc, rel);
       }
     } else {
-      // One work item per (output, channel).
-      for (int it = tid; it < cnt * 3; it += kBlock) {
-        const int i = it / 3, c = it - 3 * i;
+      // FULL tiles: one work item per output, its three channels in turn
+      for (int i = tid; i < cnt; i += kBlock) {
         const int64_t k = k0 + i;
         const double rel = (double)k - kH;
         if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
-        double outc;
+        double out[3];
         if (bad) {
-          outc = __builtin_nan("");
+          out[0] = out[1] = out[2] = __builtin_nan("");
         } else {
           double T6[6];
 #pragma unroll
           for (int a = 0; a < 6; ++a) T6[a] = Tc[a * kTileFull + i];
-          {
+#pragma unroll 1
+          for (int c = 0; c < 3; ++c) {
             TC sum = (TC)0;
 #pragma unroll 1
             for (int t = 0; t < nterms; ++t) {
@@ -2165,27 +2220,27 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
               }
               sum += sign > 0 ? v : -v;
             }
-            outc = (double)sum;
+            if (c == 0) out[0] = (double)sum; else if (c == 1) out[1] = (double)sum; else out[2] = (double)sum;
           }
         }
-        if (P.aet) {
-          // A, E, T mix the channels: the three items of an output meet in LDS
-          Tc[(6 + c) * kTileFull + i] = outc;
-          continue;
-        }
-        full_store<TC>(P, S.off + k, c, outc, rel);
+        if (P.aet) to_aet<double>(out[0], out[1], out[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) full_store<TC>(P, S.off + k, c, out[c], rel);
       }
     }
-    if (P.aet) {
-      __syncthreads();
-      for (int i = tid; i < cnt; i += kBlock) {
-        const int64_t k = k0 + i;
-        const double rel = (double)k - kH;
-        if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
-        double o3[3] = {Tc[6 * kTileFull + i], Tc[7 * kTileFull + i], Tc[8 * kTileFull + i]};
-        to_aet<double>(o3[0], o3[1], o3[2]);
+    if constexpr (TP) {
+      // A, E, T of the term-parallel items
+      if (P.aet) {
+        __syncthreads();
+        for (int i = tid; i < cnt; i += kBlock) {
+          const int64_t k = k0 + i;
+          const double rel = (double)k - kH;
+          if (P.mode == 2 && !(rel >= -0.5 * P.T_s)) continue;
+          double o3[3] = {Tc[6 * kTileFull + i], Tc[7 * kTileFull + i], Tc[8 * kTileFull + i]};
+          to_aet<double>(o3[0], o3[1], o3[2]);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) full_store<TC>(P, S.off + k, c, o3[c], rel);
+          for (int c = 0; c < 3; ++c) full_store<TC>(P, S.off + k, c, o3[c], rel);
+        }
       }
     }
     __syncthreads();
