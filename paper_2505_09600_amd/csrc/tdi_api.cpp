@@ -1106,7 +1106,8 @@ tdi_status tdi_run_links(tdi_plan* p, int64_t n_sources, const tdi_source* src, 
   if (hipMemcpyAsync(p->d_block, p->h_block, kCtrBytes + copy_bytes, hipMemcpyHostToDevice, s) != hipSuccess)
     return TDI_EDEVICE;
   if (!release_stage(p, slot, s)) return TDI_EDEVICE;
-  if (tdi::launch_links(p->d_params, N, fp32, tiles, lds, s) != 0) return TDI_EDEVICE;
+  const int arm = fp32 && p->cfg.mode != TDI_MODE_FULL && p->cfg.lfa_terms != 2 ? 1 : 0;
+  if (tdi::launch_links(p->d_params, N, fp32, arm, tiles, lds, s) != 0) return TDI_EDEVICE;
   return TDI_OK;
 }
 

@@ -27,7 +27,7 @@ constexpr int kWGrid = 16;                 // Lagrange Taylor table: rows per un
 constexpr double kFastDtMax = 40.0;        // s: quadratic chunk models stay below 1e-6 relative
 constexpr double kFastRateMax = 2.0e-4;    // bound of |d delay / dt| for the offset expansions
 constexpr size_t kFastTileBytesMax = 4096;  // bound of the fast path's per-tile record (checked in the kernels)
-constexpr int kTileLinks = 1024;           // link outputs: outputs per tile (kTileLinks / kBlock per thread)
+constexpr int kTileLinks = 2048;           // link outputs: outputs per tile (kTileLinks / kBlock per thread)
 
 // Orbit constants prepared once per plan.
 struct OrbitDev {
@@ -104,7 +104,8 @@ int launch_x20(const KParams* dp, int taps, int fp32, int grid, size_t lds_bytes
 int occupancy_x20(int taps, int fp32, size_t lds);
 size_t x20_lds_bytes(int cap);
 // link outputs: one workgroup per tile of kTileLinks samples (tile list in SrcDev::lfa_t0)
-int launch_links(const KParams* dp, int taps, int fp32, int64_t grid, size_t lds, void* stream);
+// arm != 0 (FP32, LFA or hybrid, leading term): the per-arm read of the LFA part
+int launch_links(const KParams* dp, int taps, int fp32, int arm, int64_t grid, size_t lds, void* stream);
 size_t links_lds_bytes(int cap, int fp32, int windows);
 // pre-pass of the fast LFA path: per-tile records (geometry fits, chunk
 // windows, wave models) for all LFA tiles (grid-stride over tiles)

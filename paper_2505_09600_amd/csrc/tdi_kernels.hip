@@ -2260,6 +2260,16 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
 //   hybrid: Eq. (hybridized_yslr) with the windows and weights of the TDI hybrid.
 // One workgroup per tile of kTileLinks outputs (one geometry fit per tile), each
 // thread taking every kBlock-th output.
+// FP32-bulk LFA (leading term): the two links of an arm (l and -l) read the
+// derivative series at delays that differ by (T_l - T_-l) / 2, ~1e-4 samples.
+// Per arm the two components are read once, at the mean offset of the two
+// links, with weights from the Taylor table (a row shared by the wave,
+// re-expanded per lane): values A+-, slopes B+-; each link takes A + (its
+// offset - the mean) B with its own polarisation factors (those of l and -l
+// differ by ~1e-4 through aberration, so the components are not precombined
+// per arm).  Reads whose nodes touch a series end, whose two offsets straddle
+// an integer, or whose lane is far from the wave's table row take the exact
+// two-component path.
 // ---------------------------------------------------------------------------
 struct LinkShared {
   GeoFit F;
@@ -2269,8 +2279,10 @@ struct LinkShared {
   double dext[4];
 };
 
-template <int N, typename TC>
-__global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp) {
+// ARM: the FP32 per-arm read of the leading-term LFA (launched for the LFA and
+// hybrid modes in FP32-bulk); without it the kernel is the exact path alone.
+template <int N, typename TC, bool ARM>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ARM ? 2 : 1))) void k_links(const KParams* __restrict__ Pp) {
   const KParams& P = *Pp;
   const SrcDev* __restrict__ SS = sources_of(Pp);
   __shared__ LinkShared sh;
@@ -2283,6 +2295,9 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
   const int64_t tile = blockIdx.x;
   if (tile >= P.n_tiles_lfa) return;
   const bool want_lfa = P.mode != 0, want_full = P.mode != 1;
+  // the per-arm read: FP32, leading LFA term
+  static_assert(!ARM || sizeof(TC) == 4, "the per-arm read is FP32");
+  const bool arm_fast = ARM && want_lfa && P.lfa_terms != 2;
   if (tid == 0) {
     const int64_t s = find_source(SS, P.n_src, tile, true);
     const SrcDev& S = SS[s];
@@ -2348,6 +2363,15 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
   stencil_coeffs(1, P.stencil_p, st, hw, den);
   stencil_coeffs(3, P.stencil_p, st3, hw3, den3);
   const double gscale = 1.0 / (den * dt), g3scale = 1.0 / (den3 * dt * dt * dt);
+  // the stencils on the seven offsets -3..3 (zero beyond the half width), so
+  // that the tap loops index them with constants
+  double sc1[7], sc3[7];
+#pragma unroll
+  for (int o = 0; o < 7; ++o) {
+    sc1[o] = hw == 3 ? st[o] : (hw == 2 ? (o >= 1 && o <= 5 ? st[o - 1] : 0.0) : (o >= 2 && o <= 4 ? st[o - 2] : 0.0));
+    sc3[o] = hw3 == 3 ? st3[o]
+                      : (hw3 == 2 ? (o >= 1 && o <= 5 ? st3[o - 1] : 0.0) : (o >= 2 && o <= 4 ? st3[o - 2] : 0.0));
+  }
   const bool nlo = want_lfa && P.lfa_terms == 2;
   // the window loads go out ahead of the other resident workgroups' arithmetic
   __builtin_amdgcn_s_setprio(1);
@@ -2361,11 +2385,12 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
     if (want_lfa) {
       double gp = 0.0, gc = 0.0;
       if (in) {
-        for (int q = -hw; q <= hw; ++q) {
-          const int64_t jj = j + q;
-          if (jj >= 0 && jj < S.n) {
-            gp += st[q + hw] * P.hp[S.off + jj];
-            gc += st[q + hw] * P.hc[S.off + jj];
+#pragma unroll
+        for (int o = 0; o < 7; ++o) {
+          const int64_t jj = j + o - 3;
+          if (sc1[o] != 0.0 && jj >= 0 && jj < S.n) {
+            gp += sc1[o] * P.hp[S.off + jj];
+            gc += sc1[o] * P.hc[S.off + jj];
           }
         }
       }
@@ -2375,11 +2400,12 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
     if (nlo) {
       double gp = 0.0, gc = 0.0;
       if (in) {
-        for (int q = -hw3; q <= hw3; ++q) {
-          const int64_t jj = j + q;
-          if (jj >= 0 && jj < S.n) {
-            gp += st3[q + hw3] * P.hp[S.off + jj];
-            gc += st3[q + hw3] * P.hc[S.off + jj];
+#pragma unroll
+        for (int o = 0; o < 7; ++o) {
+          const int64_t jj = j + o - 3;
+          if (sc3[o] != 0.0 && jj >= 0 && jj < S.n) {
+            gp += sc3[o] * P.hp[S.off + jj];
+            gc += sc3[o] * P.hc[S.off + jj];
           }
         }
       }
@@ -2402,14 +2428,84 @@ __global__ __launch_bounds__(kBlock) void k_links(const KParams* __restrict__ Pp
     }
     const double kR[3] = {geo_eval(sh.F, qKR(0), s), geo_eval(sh.F, qKR(1), s), geo_eval(sh.F, qKR(2), s)};
     const double c2 = sh.c2, s2 = sh.s2;
+    // LFA values of the six links from the per-arm reads (bit a of xmask set:
+    // link a takes the exact two-component read below instead)
+    float yl[6];
+    uint32_t xmask = 0x3fu;
+#pragma unroll
+    for (int a = 0; a < 6; ++a) yl[a] = 0.0f;
+    if (arm_fast && lfa) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double Tp = P.equal_arms ? P.orb.L_over_c : geo_eval(sh.F, qT(a), s);
+        const double Tm = P.equal_arms ? P.orb.L_over_c : geo_eval(sh.F, qT(a + 3), s);
+        const double mu = 0.5 * (kR[snd_of(a)] + kR[rcv_of(a)]);
+        const double qp = (0.5 * Tp + mu) / dt, qm = (0.5 * Tm + mu) / dt;
+        const double qbar = 0.5 * (qp + qm), hd = 0.5 * (qp - qm);
+        int64_t i0;
+        double xbar;
+        split(k, qbar * dt, dt, i0, xbar);
+        const int64_t b = i0 - N / 2 + 1 - w0;
+        const int64_t jlo = i0 - N / 2 + 1, jhi = i0 + N / 2;
+        const bool edge = (jlo <= hw + 1 && jhi >= -hw - 2) || (jlo <= S.n + hw + 1 && jhi >= S.n - hw - 2);
+        // the wave's table row, and this lane's expansion offset from it
+        const int gl = min(max((int)rint(xbar * (double)kWGrid), 0), kWGrid);
+        const int g = __builtin_amdgcn_readfirstlane(gl);
+        const float e = (float)(xbar - (double)g / (double)kWGrid);
+        const bool ok = !edge && b >= 0 && b + N <= nh && fabsf(e) <= 0.04f && xbar - fabs(hd) >= 0.0 &&
+                        xbar + fabs(hd) < 1.0;
+        if (__ballot(ok) == 0) continue;
+        if (ok) {
+          float Ap = 0.0f, Ac = 0.0f, Bp = 0.0f, Bc = 0.0f;
+          const float4* row = wtab_row<N>(g);
+          const float* Ga = reinterpret_cast<const float*>(gwin) + 2 * b;
+#pragma unroll
+          for (int j2 = 0; j2 < N; ++j2) {
+            const float4 c = row[j2];
+            const float b2 = fmaf(e, c.w, c.z);
+            const float b1 = fmaf(e, b2, c.y);
+            const float w = fmaf(e, b1, c.x);
+            const float wd = fmaf(e, b2, b1);
+            const float gp = Ga[2 * j2], gc = Ga[2 * j2 + 1];
+            Ap = fmaf(w, gp, Ap);
+            Ac = fmaf(w, gc, Ac);
+            Bp = fmaf(wd, gp, Bp);
+            Bc = fmaf(wd, gc, Bc);
+          }
+          // link a reads at xbar - hd, link a + 3 at xbar + hd, each with its
+          // own polarisation factors at the output time
+#pragma unroll
+          for (int side = 0; side < 2; ++side) {
+            const int l = a + 3 * side;
+            const double xp = geo_eval(sh.F, qXp(l), s), xc = geo_eval(sh.F, qXc(l), s);
+            const float cp = (float)(xp * c2 + xc * s2), cx = (float)(xc * c2 - xp * s2);
+            const float dl = side == 0 ? -(float)hd : (float)hd;
+            const float v = fmaf(cp, fmaf(dl, Bp, Ap), cx * fmaf(dl, Bc, Ac));
+            yl[l] = (float)(wp * (-0.5 * (side == 0 ? Tp : Tm))) * v;
+          }
+          xmask &= ~((1u << a) | (1u << (a + 3)));
+        }
+      }
+    }
 #pragma unroll 1
     for (int a = 0; a < 6; ++a) {
+      TC y = (TC)0;
+      const bool exact = ((xmask >> a) & 1u) != 0;
+      if (lfa && !exact) {
+        float ysel = yl[0];
+#pragma unroll
+        for (int q = 1; q < 6; ++q) ysel = a == q ? yl[q] : ysel;
+        y = (TC)ysel;
+        if (!full) {
+          Yo[a * stride + S.off + k] = y;
+          continue;
+        }
+      }
       const double T = geo_eval(sh.F, qT(a), s);
       const double xp = geo_eval(sh.F, qXp(a), s), xc = geo_eval(sh.F, qXc(a), s);
       const TC A = (TC)(xp * c2 + xc * s2), B = (TC)(xc * c2 - xp * s2);
       const int sn = snd_of(a), rc = rcv_of(a);
-      TC y = (TC)0;
-      if (lfa) {
+      if (lfa && exact) {
         const double Tl = P.equal_arms ? P.orb.L_over_c : T;
         int64_t i0;
         double x;
@@ -2482,8 +2578,14 @@ int launch_full_t(const KParams* dp, int tp, int grid, size_t lds, hipStream_t s
 }
 
 template <int N, typename TC>
-int launch_links_t(const KParams* dp, int64_t grid, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((k_links<N, TC>), dim3((unsigned)grid), dim3(kBlock), lds, st, dp);
+int launch_links_t(const KParams* dp, int arm, int64_t grid, size_t lds, hipStream_t st) {
+  if constexpr (sizeof(TC) == 4) {
+    if (arm) {
+      hipLaunchKernelGGL((k_links<N, TC, true>), dim3((unsigned)grid), dim3(kBlock), lds, st, dp);
+      return hipGetLastError() == hipSuccess ? 0 : -1;
+    }
+  }
+  hipLaunchKernelGGL((k_links<N, TC, false>), dim3((unsigned)grid), dim3(kBlock), lds, st, dp);
   return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -2688,9 +2790,9 @@ int launch_full(const KParams* dp, int taps, int fp32, int hybrid, int grid, siz
   return -2;
 }
 
-int launch_links(const KParams* dp, int taps, int fp32, int64_t grid, size_t lds, void* stream) {
+int launch_links(const KParams* dp, int taps, int fp32, int arm, int64_t grid, size_t lds, void* stream) {
   if (grid <= 0) return 0;
-  TDI_DISPATCH(taps, fp32, launch_links_t, dp, grid, lds, (hipStream_t)stream);
+  TDI_DISPATCH(taps, fp32, launch_links_t, dp, arm, grid, lds, (hipStream_t)stream);
   return -2;
 }
 
