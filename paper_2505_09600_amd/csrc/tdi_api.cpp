@@ -824,8 +824,8 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
   hipEvent_t a, b;
   hipEventCreate(&a);
   hipEventCreate(&b);
-  float best = INFINITY, best_p = INFINITY;
-  Launch best_l = cands[0], best_pl = cands[0];
+  float best = INFINITY;
+  Launch best_l = cands[0];
   for (const Launch& ln : cands) {
     float ms_sum = 0.0f;
     bool ok = true;
@@ -842,17 +842,14 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
       best = ms_sum;
       best_l = ln;
     }
-    if (ok && ln.grid_lfa > 0 && ln.grid_full > 0 && ms_sum < best_p) {
-      best_p = ms_sum;
-      best_pl = ln;
-    }
   }
   p->launch = best_l;
   p->stream_pick = false;
   if (p->cfg.use_graph) {
-    // Graph replay needs persistent launches.  It saves host work per run, but
-    // on short runs a replay can cost the host more than the stream launches
-    // it replaces: time both over back-to-back runs and keep the faster.
+    // With graphs the candidates are persistent launches, which replay.  A
+    // replay saves host work per run, but on short runs it can cost the host
+    // more than the stream launches it replaces: time both over back-to-back
+    // runs and keep the faster.
     auto batch_ms = [&](const Launch& ln, bool graph) -> float {
       hipEventRecord(a, p->user_stream);
       for (int rep = 0; rep < 8; ++rep)
@@ -863,15 +860,11 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
       hipEventElapsedTime(&ms, a, b);
       return ms;
     };
-    p->launch = best_pl;
-    (void)batch_ms(best_pl, true);                       // capture and warm the graph
-    const float tg = batch_ms(best_pl, true);
+    (void)batch_ms(best_l, true);                        // capture and warm the graph
+    const float tg = batch_ms(best_l, true);
     const float ts = batch_ms(best_l, false);
     (void)hipGetLastError();
-    if (ts < 0.97f * tg) {
-      p->launch = best_l;
-      p->stream_pick = true;
-    }
+    p->stream_pick = ts < 0.97f * tg;
   }
   hipEventDestroy(a);
   hipEventDestroy(b);
