@@ -1884,9 +1884,10 @@ __device__ __forceinline__ void full_store(const KParams& P, int64_t o, int c, d
   }
 }
 
-// TP: term-parallel stage 2 (the hybrid's tiles of at most kTileFullHybrid
-// outputs, with the term buffer in LDS); the FULL mode's larger tiles sum each
-// channel's terms in one work item.
+// TP: the hybrid's variant (tiles of at most kTileFullHybrid outputs): stage 1
+// per (sample, receiving spacecraft), stage 2 per (output, channel, term) with
+// the term values in LDS.  The FULL mode's variant (larger tiles) takes one
+// work item per sample in stage 1 and one per output in stage 2.
 template <int N, typename TC, bool TP>
 __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ Pp) {
   const KParams& P = *Pp;
@@ -2266,8 +2267,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
 // links, with weights from the Taylor table (a row shared by the wave,
 // re-expanded per lane): values A+-, slopes B+-; each link takes A + (its
 // offset - the mean) B with its own polarisation factors (those of l and -l
-// differ by ~1e-4 through aberration, so the components are not precombined
-// per arm).  Reads whose nodes touch a series end, whose two offsets straddle
+// differ through aberration, so the components are not precombined per arm).  Reads whose nodes touch a series end, whose two offsets straddle
 // an integer, or whose lane is far from the wave's table row take the exact
 // two-component path.
 // ---------------------------------------------------------------------------
