@@ -151,6 +151,7 @@ def test_c4_batch_bench_launch(tdi, orc):
     # the autotuner keeps graph replay (persistent grids) unless stream launches
     # time faster over back-to-back runs
     assert desc["tuned"] == 1 and (desc["graph"] == 0 or desc["grid_lfa"] > 0)
+    assert desc["tile_full"] == 64          # thousands of full-region tiles: the hybrid's usual size
     rng = np.random.default_rng(24)
     hybrid_srcs = [i for i in range(batch.n_sources) if math.isfinite(batch.sources[i]["t_hyb"])]
     drawn = set(rng.choice(batch.n_sources, 24, replace=False).tolist())

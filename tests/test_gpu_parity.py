@@ -220,6 +220,8 @@ def test_untimed_runs_match_timed_runs(tdi, orc, graph):
         plan.run(src, batch.offsets, hp, hc, *outs[3:])
         assert plan.sync() == tdi.TDI_OK
         assert len(plan.kernel_times()) == 3
+        # one source: fewer full-region tiles than compute units, so 16-output tiles
+        assert plan.describe()["tile_full"] == 16
     for a, b in zip(outs[:3], outs[3:]):
         assert torch.equal(a, b)
     ref = _run_orc(orc, batch, cfg, orb)
