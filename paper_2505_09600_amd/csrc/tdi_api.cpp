@@ -44,6 +44,7 @@ struct Caps {
   int nx;            // LFA with the next term (general LFA kernel)
   int tile_lfa;      // outputs per LFA tile
   int hyb;           // HYBRID mode: term-parallel full-response kernel
+  int fit_cu;        // fast path: resident pre-pass workgroups per CU (its grid-stride grid)
 };
 
 }  // namespace
@@ -257,6 +258,7 @@ bool fast_lfa(const tdi_config& c, const OrbitBounds& b, double dt_max) {
 Caps window_caps(const tdi_config& c, const OrbitBounds& ob, double dt, bool fast) {
   Caps k;
   k.fast = fast ? 1 : 0;
+  k.fit_cu = fast ? tdi::occupancy_lfa_fit(c.interp_taps) : 0;
   k.nx = c.lfa_terms == 2 && c.mode != TDI_MODE_FULL ? 1 : 0;
   k.tile_lfa = fast ? tdi::kTileLfaFast : tdi::kTileLfa;
   const int lfa_span = fast ? tdi::kFastChunk : tdi::kTileLfa;   // outputs sharing one window
@@ -459,7 +461,7 @@ hipError_t enqueue(tdi_plan* p, hipStream_t st, size_t copy_bytes, const Caps& c
   const int taps = p->cfg.interp_taps, fp32 = p->cfg.precision;
   if (evs && (e = hipEventRecord(evs[0], st)) != hipSuccess) return e;
   const int gl = ln.grid_lfa > 0 ? ln.grid_lfa : (int)std::max<int64_t>(0, tiles_lfa);
-  if (gl > 0 && caps.fast && tdi::launch_lfa_fit(p->d_params, taps, 4 * p->n_cu, st) != 0)
+  if (gl > 0 && caps.fast && tdi::launch_lfa_fit(p->d_params, taps, caps.fit_cu * p->n_cu, st) != 0)
     return hipErrorLaunchFailure;
   if (evs && (e = hipEventRecord(evs[1], st)) != hipSuccess) return e;
   if (gl > 0 && tdi::launch_lfa(p->d_params, taps, fp32, caps.fast, caps.nx, gl, caps.lds_lfa, st) != 0)
@@ -746,10 +748,10 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
     // persistent grids no larger than the batch's tiles (a short batch is not
     // charged for launching and retiring a full chip's worth of idle workgroups)
     {
-      const int64_t tiles[3] = {(tl + 5) / 6, tl, tf};     // the fit pre-pass takes six tiles per pass
+      const int64_t tiles[3] = {(tl + tdi::kPrepTiles - 1) / tdi::kPrepTiles, tl, tf};   // pre-pass: workgroup passes
       for (int j = 0; j < 3; ++j) {
         if (!p->graph_knode[j]) continue;
-        const unsigned full_grid = j == 0 ? (unsigned)(4 * p->n_cu)
+        const unsigned full_grid = j == 0 ? (unsigned)(caps.fit_cu * p->n_cu)
                                           : (unsigned)(j == 1 ? ln.grid_lfa : ln.grid_full);
         const unsigned want = (unsigned)std::max<int64_t>(1, std::min<int64_t>(full_grid, tiles[j]));
         if (want == p->graph_kgrid[j]) continue;
@@ -1290,7 +1292,7 @@ tdi_status tdi_run_noalloc(const tdi_config* cfg, const tdi_orbit* orb, int64_t 
   const size_t bytes = kNaParOff + sizeof(tdi::KParams) + sizeof(tdi::SrcDev) * (size_t)n_sources;
   if (!na_put(reinterpret_cast<uint32_t*>(d.ptr), g_na_image, (bytes + 3) / 4 * 4, s)) return TDI_EDEVICE;
   if (kp->n_tiles_lfa > 0) {
-    if (caps.fast && tdi::launch_lfa_fit(dp, taps, 4 * d.n_cu, s) != 0) return TDI_EDEVICE;
+    if (caps.fast && tdi::launch_lfa_fit(dp, taps, caps.fit_cu * d.n_cu, s) != 0) return TDI_EDEVICE;
     if (tdi::launch_lfa(dp, taps, fp32, caps.fast, caps.nx, ln.grid_lfa, caps.lds_lfa, s) != 0) return TDI_EDEVICE;
   }
   if (kp->n_tiles_full > 0 && tdi::launch_full(dp, taps, fp32, caps.hyb, ln.grid_full, caps.lds_full, s) != 0)

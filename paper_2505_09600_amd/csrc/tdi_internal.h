@@ -27,6 +27,7 @@ constexpr int kWGrid = 16;                 // Lagrange Taylor table: rows per un
 constexpr double kFastDtMax = 40.0;        // s: quadratic chunk models stay below 1e-6 relative
 constexpr double kFastRateMax = 2.0e-4;    // bound of |d delay / dt| for the offset expansions
 constexpr size_t kFastTileBytesMax = 4096;  // bound of the fast path's per-tile record (checked in the kernels)
+constexpr int kPrepTiles = 7;              // fast path pre-pass: tiles per workgroup pass
 constexpr int kTileLinks = 2048;           // link outputs: outputs per tile (kTileLinks / kBlock per thread)
 
 // Orbit constants prepared once per plan.
@@ -110,6 +111,7 @@ size_t links_lds_bytes(int cap, int fp32, int windows);
 // pre-pass of the fast LFA path: per-tile records (geometry fits, chunk
 // windows, wave models) for all LFA tiles (grid-stride over tiles)
 int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream);
+int occupancy_lfa_fit(int taps);   // resident pre-pass workgroups per CU
 size_t fast_tile_bytes();     // bytes of one per-tile record
 // LFA dynamic LDS: h window (FP64), reused for the FP32 wave tables, then the
 // derivative window; goff receives the byte offset of the latter.  Fast path:

@@ -374,7 +374,8 @@ __device__ __forceinline__ void fit_node(const KParams& P, const SrcDev& S, doub
 }
 
 // Monomial coefficient e = q * kNodes + m from the node values.
-__device__ __forceinline__ double fit_coef(const double vals[kNodes][kNQ], int e) {
+template <int NQ>
+__device__ __forceinline__ double fit_coef(const double vals[kNodes][NQ], int e) {
   const int q = e / kNodes, m = e % kNodes;
   if (m == 0) return vals[kNodes / 2][q];    // the centre node is s = 0
   double c = 0.0;
@@ -393,7 +394,7 @@ __device__ void fit_geometry(const KParams& P, const SrcDev& S, double ka, doubl
     F.ikh = 1.0 / kh;
   }
   __syncthreads();
-  if (tid < kNQ * kNodes) F.coef[tid / kNodes][tid % kNodes] = fit_coef(F.vals, tid);
+  if (tid < kNQ * kNodes) F.coef[tid / kNodes][tid % kNodes] = fit_coef<kNQ>(F.vals, tid);
   __syncthreads();
 }
 
@@ -404,6 +405,25 @@ __device__ __forceinline__ int64_t find_source(const SrcDev* S, int64_t n_src, i
     const int64_t mid = (lo + hi + 1) >> 1;
     const int64_t t0 = lfa ? S[mid].lfa_t0 : S[mid].full_t0;
     if (t0 <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The same search for an LFA tile by one whole wave (t uniform, all 64 lanes
+// active): each round tests 64 evenly spaced candidates at once, so 512
+// sources take two rounds of loads instead of nine.
+__device__ __forceinline__ int64_t find_source_lfa_wave(const SrcDev* S, int64_t n_src, int64_t t) {
+  const int lane = (int)(threadIdx.x & 63);
+  int64_t lo = 0, hi = n_src - 1;
+  while (lo < hi) {
+    const int64_t step = (hi - lo + 63) / 64;
+    const int64_t c = lo + (int64_t)(lane + 1) * step;
+    const bool ok = c <= hi && S[c].lfa_t0 <= t;
+    // first tiles are nondecreasing in the source index: the passing
+    // candidates are a prefix of the lanes
+    const int64_t nlo = lo + (int64_t)__popcll(__ballot(ok)) * step;
+    hi = min(hi, nlo + step - 1);
+    lo = nlo;
   }
   return lo;
 }
@@ -1057,14 +1077,21 @@ __host__ __device__ constexpr int kFitPad() { return N / 2 + 8; }
 // Pre-pass of the fast LFA kernel.  Per tile: the degree-6 geometry fit (in
 // LDS only) over the tile and the elements read around it, and from it every
 // chunk's window, each wave's offset and prefactor models and the per-link
-// precombination quadratics, written to P.lfa_tiles.  Six tiles per pass
-// (6 x 42 node evaluations).
+// precombination quadratics, written to P.lfa_tiles.  The fit holds only what
+// the fast path reads: T, xi+ and xi_x of the three positive links and k.R/c
+// of the three spacecraft (21 node evaluations per tile).  Seven tiles per
+// pass (kPrepTiles), three workgroups per CU.
 // ---------------------------------------------------------------------------
-constexpr int kPrepTiles = kBlock / (kNodes * 6);
+constexpr int kPQ = 12;
+constexpr int kPrepNodes = kNodes * 3;
+__host__ __device__ constexpr int pT(int l) { return l; }
+__host__ __device__ constexpr int pXp(int l) { return 3 + l; }
+__host__ __device__ constexpr int pXc(int l) { return 6 + l; }
+__host__ __device__ constexpr int pKR(int i) { return 9 + i; }
 
 struct PrepShared {
-  double vals[kPrepTiles][kNodes][kNQ];
-  double coef[kPrepTiles][kNQ][kNodes];
+  double vals[kPrepTiles][kNodes][kPQ];
+  double coef[kPrepTiles][kPQ][kNodes];
   double kc[kPrepTiles], ikh[kPrepTiles];
   double c2[kPrepTiles], s2[kPrepTiles], isc[kPrepTiles], idt[kPrepTiles];
   int64_t src[kPrepTiles], k0[kPrepTiles];
@@ -1074,7 +1101,7 @@ struct PrepShared {
   double pe[kPrepTiles][4][3][3][3];      // tile, chunk, link, point, {element, c+, c_x}
 };
 
-__device__ __forceinline__ double prep_eval(const double c[kNQ][kNodes], int q, double s) {
+__device__ __forceinline__ double prep_eval(const double c[kPQ][kNodes], int q, double s) {
   double v = c[q][kNodes - 1];
 #pragma unroll
   for (int m = kNodes - 2; m >= 0; --m) v = fma(v, s, c[q][m]);
@@ -1082,7 +1109,7 @@ __device__ __forceinline__ double prep_eval(const double c[kNQ][kNodes], int q, 
 }
 
 template <int N>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) void k_lfa_prep(const KParams* __restrict__ Pp) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) void k_lfa_prep(const KParams* __restrict__ Pp) {
   const KParams& P = *Pp;
   const SrcDev* __restrict__ SS = sources_of(Pp);
   FastTile* __restrict__ TT = static_cast<FastTile*>(P.lfa_tiles);
@@ -1091,28 +1118,29 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
   const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
   for (int64_t tb = (int64_t)blockIdx.x * kPrepTiles; tb < P.n_tiles_lfa;
        tb += (int64_t)gridDim.x * kPrepTiles) {
-    // tile headers
-    if (tid < kPrepTiles) {
-      const int64_t tile = tb + tid;
-      sh.live[tid] = tile < P.n_tiles_lfa ? 1 : 0;
-      if (tile < P.n_tiles_lfa) {
-        const int64_t s = find_source(SS, P.n_src, tile, true);
+    // tile headers: one wave per tile
+    for (int lt = tid >> 6; lt < kPrepTiles; lt += kBlock / 64) {
+      const int64_t tile = tb + lt;
+      const bool live = tile < P.n_tiles_lfa;
+      const int64_t s = live ? find_source_lfa_wave(SS, P.n_src, tile) : 0;
+      if ((tid & 63) == 0) sh.live[lt] = live ? 1 : 0;
+      if (live && (tid & 63) == 0) {
         const SrcDev& S = SS[s];
         const int64_t k0 = S.lfa_kb + (tile - S.lfa_t0) * P.tile_fast;
         const int32_t cnt = (int32_t)min((int64_t)P.tile_fast, S.lfa_ke - k0);
         double kc, kh;
         fit_span((double)(k0 - kFitPad<N>()), (double)(k0 + cnt - 1 + kFitPad<N>()), kc, kh);
-        sh.kc[tid] = kc;
-        sh.ikh[tid] = 1.0 / kh;
-        sh.src[tid] = s;
-        sh.k0[tid] = k0;
-        sh.cnt[tid] = cnt;
-        sh.c2[tid] = S.c2psi;
-        sh.s2[tid] = S.s2psi;
+        sh.kc[lt] = kc;
+        sh.ikh[lt] = 1.0 / kh;
+        sh.src[lt] = s;
+        sh.k0[lt] = k0;
+        sh.cnt[lt] = cnt;
+        sh.c2[lt] = S.c2psi;
+        sh.s2[lt] = S.s2psi;
         double sc = c_stden[st];
         for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
-        sh.isc[tid] = 1.0 / sc;
-        sh.idt[tid] = 1.0 / S.dt;
+        sh.isc[lt] = 1.0 / sc;
+        sh.idt[lt] = 1.0 / S.dt;
         FastTile& T = TT[tile];
         T.off = S.off;
         T.n = S.n;
@@ -1123,18 +1151,24 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       }
     }
     __syncthreads();
-    // node values and fit
-    {
-      const int lt = tid / (kNodes * 6), r = tid % (kNodes * 6);
-      if (lt < kPrepTiles && sh.live[lt]) {
-        const double kh = 1.0 / sh.ikh[lt];
-        fit_node(P, SS[sh.src[lt]], sh.kc[lt], kh, r, sh.vals[lt]);
-      }
+    // node values (node j, positive link l) and fit
+    for (int e = tid; e < kPrepTiles * kPrepNodes; e += kBlock) {
+      const int lt = e / kPrepNodes, j = (e % kPrepNodes) / 3, l = e % 3;
+      if (!sh.live[lt]) continue;
+      const SrcDev& S = SS[sh.src[lt]];
+      const double kh = 1.0 / sh.ikh[lt];
+      const double t = S.t0 + (sh.kc[lt] + c_snode[j] * kh) * S.dt;
+      double g[5];
+      node_geometry(P.orb, S.beta, S.lam, t, l, g);
+      sh.vals[lt][j][pT(l)] = g[0];
+      sh.vals[lt][j][pXp(l)] = g[1];
+      sh.vals[lt][j][pXc(l)] = g[2];
+      sh.vals[lt][j][pKR(l)] = g[4];
     }
     __syncthreads();
-    for (int e = tid; e < kPrepTiles * kFitLen; e += kBlock) {
-      const int t = e / kFitLen, c = e % kFitLen;
-      if (sh.live[t]) sh.coef[t][c / kNodes][c % kNodes] = fit_coef(sh.vals[t], c);
+    for (int e = tid; e < kPrepTiles * kPQ * kNodes; e += kBlock) {
+      const int t = e / (kPQ * kNodes), c = e % (kPQ * kNodes);
+      if (sh.live[t]) sh.coef[t][c / kNodes][c % kNodes] = fit_coef<kPQ>(sh.vals[t], c);
     }
     __syncthreads();
     // geometry, delays and prefactors at the sample points of every chunk
@@ -1148,14 +1182,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       const double kq = fast_point(pt, kc0, ccnt, N, live);
       if (!live) continue;
       const double s = (kq - sh.kc[t]) * sh.ikh[t];
-      double kR[3], T3[3], xp3[3], xc3[3], mu3[3];
+      double kR[3], T3[3], mu3[3];
 #pragma unroll
-      for (int i = 0; i < 3; ++i) kR[i] = prep_eval(sh.coef[t], qKR(i), s);
+      for (int i = 0; i < 3; ++i) kR[i] = prep_eval(sh.coef[t], pKR(i), s);
 #pragma unroll
       for (int l = 0; l < 3; ++l) {
-        T3[l] = prep_eval(sh.coef[t], qT(l), s);
-        xp3[l] = prep_eval(sh.coef[t], qXp(l), s);
-        xc3[l] = prep_eval(sh.coef[t], qXc(l), s);
+        T3[l] = prep_eval(sh.coef[t], pT(l), s);
         mu3[l] = 0.5 * (kR[snd_of(l)] + kR[rcv_of(l)]);
       }
       double qd[6], sp[6];
@@ -1187,7 +1219,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2))) voi
       } else {
         const int l = (pt - 14) / 3, p = (pt - 14) % 3;
         const double ql = 0.5 * (sel3(qd[0], qd[2], qd[4], l) + sel3(qd[1], qd[3], qd[5], l));
-        const double xp = sel3(xp3[0], xp3[1], xp3[2], l), xc = sel3(xc3[0], xc3[1], xc3[2], l);
+        const double xp = prep_eval(sh.coef[t], pXp(l), s), xc = prep_eval(sh.coef[t], pXc(l), s);
         sh.pe[t][c][l][p][0] = kq - ql;
         sh.pe[t][c][l][p][1] = xp * sh.c2[t] + xc * sh.s2[t];
         sh.pe[t][c][l][p][2] = xc * sh.c2[t] - xp * sh.s2[t];
@@ -2602,6 +2634,13 @@ int launch_lfa_fit_t(const KParams* dp, int grid, hipStream_t st) {
 }
 
 template <int N>
+int occ_lfa_fit_t() {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_lfa_prep<N>), kBlock, 0) != hipSuccess) return 1;
+  return n > 0 ? n : 1;
+}
+
+template <int N>
 int occ_lfa_fast_t(size_t lds) {
   int n = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, reinterpret_cast<const void*>(&k_lfa_fast<N>), kBlock, lds) != hipSuccess) return 1;
@@ -2771,6 +2810,11 @@ int launch_lfa(const KParams* dp, int taps, int fp32, int fast, int nx, int grid
 int launch_lfa_fit(const KParams* dp, int taps, int grid, void* stream) {
   TDI_DISPATCH_FAST(taps, launch_lfa_fit_t, dp, grid, (hipStream_t)stream);
   return -2;
+}
+
+int occupancy_lfa_fit(int taps) {
+  TDI_DISPATCH_FAST(taps, occ_lfa_fit_t);
+  return 1;
 }
 
 int launch_x20(const KParams* dp, int taps, int fp32, int grid, size_t lds, void* stream) {
