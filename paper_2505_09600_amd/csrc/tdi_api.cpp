@@ -443,6 +443,13 @@ void stage_batch(const tdi_config& c, tdi::KParams* kp, int64_t n_sources, const
   kp->n_src = n_sources;
   kp->tile_fast = caps.fast ? tile_lfa : 0;
   kp->tile_full = tile_full;
+  // pre-pass: the fewest tiles per workgroup pass that cover the batch in one
+  // pass of the resident workgroups (a short batch gets short passes), at most
+  // kPrepTiles with several passes beyond that
+  {
+    const int64_t resident = std::max<int64_t>(1, (int64_t)std::max(caps.fit_cu, 1) * n_cu);
+    kp->prep_tiles = (int32_t)std::min<int64_t>(tdi::kPrepTiles, std::max<int64_t>(1, (tl + resident - 1) / resident));
+  }
   kp->n_tiles_lfa = tl;
   kp->n_tiles_full = tf;
   kp->hp = hp; kp->hc = hc; kp->X = X; kp->Y = Y; kp->Z = Z;
@@ -748,7 +755,8 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
     // persistent grids no larger than the batch's tiles (a short batch is not
     // charged for launching and retiring a full chip's worth of idle workgroups)
     {
-      const int64_t tiles[3] = {(tl + tdi::kPrepTiles - 1) / tdi::kPrepTiles, tl, tf};   // pre-pass: workgroup passes
+      const int64_t ptl = p->h_params->prep_tiles;
+      const int64_t tiles[3] = {(tl + ptl - 1) / ptl, tl, tf};   // pre-pass: workgroup passes
       for (int j = 0; j < 3; ++j) {
         if (!p->graph_knode[j]) continue;
         const unsigned full_grid = j == 0 ? (unsigned)(caps.fit_cu * p->n_cu)

@@ -27,7 +27,7 @@ constexpr int kWGrid = 16;                 // Lagrange Taylor table: rows per un
 constexpr double kFastDtMax = 40.0;        // s: quadratic chunk models stay below 1e-6 relative
 constexpr double kFastRateMax = 2.0e-4;    // bound of |d delay / dt| for the offset expansions
 constexpr size_t kFastTileBytesMax = 4096;  // bound of the fast path's per-tile record (checked in the kernels)
-constexpr int kPrepTiles = 7;              // fast path pre-pass: tiles per workgroup pass
+constexpr int kPrepTiles = 7;              // fast path pre-pass: most tiles per workgroup pass
 constexpr int kTileLinks = 2048;           // link outputs: outputs per tile (kTileLinks / kBlock per thread)
 
 // Orbit constants prepared once per plan.
@@ -81,6 +81,7 @@ struct KParams {
   int32_t nested;        // time-nested stage-2 delays
   int32_t tile_fast;     // fast LFA path: outputs per tile (1, 2 or 4 chunks of kFastChunk)
   int32_t tile_full;     // full-response outputs per tile (at most kTileFull)
+  int32_t prep_tiles;    // fast LFA pre-pass: tiles per workgroup pass (1..kPrepTiles)
   int64_t link_stride;   // link outputs: elements between the six link arrays (X is their base)
   double T_s, sigma_s;
   double D2_bound;       // upper bound of a stage-2 delay (s)

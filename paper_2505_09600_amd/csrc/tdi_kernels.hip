@@ -1079,8 +1079,8 @@ __host__ __device__ constexpr int kFitPad() { return N / 2 + 8; }
 // chunk's window, each wave's offset and prefactor models and the per-link
 // precombination quadratics, written to P.lfa_tiles.  The fit holds only what
 // the fast path reads: T, xi+ and xi_x of the three positive links and k.R/c
-// of the three spacecraft (21 node evaluations per tile).  Seven tiles per
-// pass (kPrepTiles), three workgroups per CU.
+// of the three spacecraft (21 node evaluations per tile).  Up to seven tiles
+// per pass (P.prep_tiles, fewer for short batches), three workgroups per CU.
 // ---------------------------------------------------------------------------
 constexpr int kPQ = 12;
 constexpr int kPrepNodes = kNodes * 3;
@@ -1116,10 +1116,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
   __shared__ PrepShared sh;
   const int tid = threadIdx.x;
   const int st = 2 * (P.stencil_m == 3 ? 1 : 0) + (P.stencil_p == 4 ? 1 : 0);
-  for (int64_t tb = (int64_t)blockIdx.x * kPrepTiles; tb < P.n_tiles_lfa;
-       tb += (int64_t)gridDim.x * kPrepTiles) {
+  const int ntp = min(max(P.prep_tiles, 1), kPrepTiles);   // tiles per pass
+  for (int64_t tb = (int64_t)blockIdx.x * ntp; tb < P.n_tiles_lfa; tb += (int64_t)gridDim.x * ntp) {
     // tile headers: one wave per tile
-    for (int lt = tid >> 6; lt < kPrepTiles; lt += kBlock / 64) {
+    for (int lt = tid >> 6; lt < ntp; lt += kBlock / 64) {
       const int64_t tile = tb + lt;
       const bool live = tile < P.n_tiles_lfa;
       const int64_t s = live ? find_source_lfa_wave(SS, P.n_src, tile) : 0;
@@ -1152,7 +1152,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
     __syncthreads();
     // node values (node j, positive link l) and fit
-    for (int e = tid; e < kPrepTiles * kPrepNodes; e += kBlock) {
+    for (int e = tid; e < ntp * kPrepNodes; e += kBlock) {
       const int lt = e / kPrepNodes, j = (e % kPrepNodes) / 3, l = e % 3;
       if (!sh.live[lt]) continue;
       const SrcDev& S = SS[sh.src[lt]];
@@ -1166,13 +1166,13 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
       sh.vals[lt][j][pKR(l)] = g[4];
     }
     __syncthreads();
-    for (int e = tid; e < kPrepTiles * kPQ * kNodes; e += kBlock) {
+    for (int e = tid; e < ntp * kPQ * kNodes; e += kBlock) {
       const int t = e / (kPQ * kNodes), c = e % (kPQ * kNodes);
       if (sh.live[t]) sh.coef[t][c / kNodes][c % kNodes] = fit_coef<kPQ>(sh.vals[t], c);
     }
     __syncthreads();
     // geometry, delays and prefactors at the sample points of every chunk
-    for (int e = tid; e < kPrepTiles * 4 * kFPts; e += kBlock) {
+    for (int e = tid; e < ntp * 4 * kFPts; e += kBlock) {
       const int t = e / (4 * kFPts), c = (e / kFPts) % 4, pt = e % kFPts;
       if (!sh.live[t]) continue;
       const int ccnt = min(kFChunk, sh.cnt[t] - c * kFChunk);
@@ -1227,7 +1227,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     }
     __syncthreads();
     // chunk records: window (kind 0), wave models (1..12), precombination (13..15)
-    for (int e = tid; e < kPrepTiles * 4 * 16; e += kBlock) {
+    for (int e = tid; e < ntp * 4 * 16; e += kBlock) {
       const int t = e / 64, c = (e / 16) % 4, kind = e % 16;
       if (!sh.live[t]) continue;
       const int ccnt = min(kFChunk, sh.cnt[t] - c * kFChunk);
