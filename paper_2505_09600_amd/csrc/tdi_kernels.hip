@@ -398,27 +398,17 @@ __device__ void fit_geometry(const KParams& P, const SrcDev& S, double ka, doubl
   __syncthreads();
 }
 
-// Source of global tile t: last source whose first tile is <= t.
-__device__ __forceinline__ int64_t find_source(const SrcDev* S, int64_t n_src, int64_t t, bool lfa) {
-  int64_t lo = 0, hi = n_src - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    const int64_t t0 = lfa ? S[mid].lfa_t0 : S[mid].full_t0;
-    if (t0 <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
-
-// The same search for an LFA tile by one whole wave (t uniform, all 64 lanes
-// active): each round tests 64 evenly spaced candidates at once, so 512
-// sources take two rounds of loads instead of nine.
-__device__ __forceinline__ int64_t find_source_lfa_wave(const SrcDev* S, int64_t n_src, int64_t t) {
+// Source of global tile t: the last source whose first tile is <= t.  Called
+// by one whole wave (t uniform, all 64 lanes active): each round tests 64
+// evenly spaced candidates at once, so 512 sources take two rounds of
+// dependent loads where a binary search takes nine.
+__device__ __forceinline__ int64_t find_source_wave(const SrcDev* S, int64_t n_src, int64_t t, bool lfa) {
   const int lane = (int)(threadIdx.x & 63);
   int64_t lo = 0, hi = n_src - 1;
   while (lo < hi) {
     const int64_t step = (hi - lo + 63) / 64;
     const int64_t c = lo + (int64_t)(lane + 1) * step;
-    const bool ok = c <= hi && S[c].lfa_t0 <= t;
+    const bool ok = c <= hi && (lfa ? S[c].lfa_t0 : S[c].full_t0) <= t;
     // first tiles are nondecreasing in the source index: the passing
     // candidates are a prefix of the lanes
     const int64_t nlo = lo + (int64_t)__popcll(__ballot(ok)) * step;
@@ -642,21 +632,23 @@ __global__ __launch_bounds__(kBlock, 2) void k_lfa(const KParams* __restrict__ P
   for (;;) {
     const int64_t tile = next_tile(P, P.counters + 0, P.n_tiles_lfa, iter, &s_next);
     if (tile >= P.n_tiles_lfa) break;
-    if (tid == 0) {
-      const int64_t s = find_source(SS, P.n_src, tile, true);
-      const SrcDev& S = SS[s];
-      sh.src = s;
-      sh.k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfa;
-      sh.cnt = (int32_t)min((int64_t)kTileLfa, S.lfa_ke - sh.k0);
-      double sn, cs;
-      sincos(2.0 * S.psi, &sn, &cs);
-      sh.c2 = cs;
-      sh.s2 = sn;
-      double sc = c_stden[st];
-      for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
-      sh.inv_scale = 1.0 / sc;
-      sh.inv_scale2 = 1.0 / (sc * (c_stden2[st] / c_stden[st]) * S.dt * S.dt);
-      sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+    if (tid < 64) {
+      const int64_t s = find_source_wave(SS, P.n_src, tile, true);
+      if (tid == 0) {
+        const SrcDev& S = SS[s];
+        sh.src = s;
+        sh.k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfa;
+        sh.cnt = (int32_t)min((int64_t)kTileLfa, S.lfa_ke - sh.k0);
+        double sn, cs;
+        sincos(2.0 * S.psi, &sn, &cs);
+        sh.c2 = cs;
+        sh.s2 = sn;
+        double sc = c_stden[st];
+        for (int q = 0; q < P.stencil_m; ++q) sc *= S.dt;
+        sh.inv_scale = 1.0 / sc;
+        sh.inv_scale2 = 1.0 / (sc * (c_stden2[st] / c_stden[st]) * S.dt * S.dt);
+        sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+      }
     }
     __syncthreads();
     const SrcDev& S = SS[sh.src];
@@ -1122,7 +1114,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(3))) voi
     for (int lt = tid >> 6; lt < ntp; lt += kBlock / 64) {
       const int64_t tile = tb + lt;
       const bool live = tile < P.n_tiles_lfa;
-      const int64_t s = live ? find_source_lfa_wave(SS, P.n_src, tile) : 0;
+      const int64_t s = live ? find_source_wave(SS, P.n_src, tile, true) : 0;
       if ((tid & 63) == 0) sh.live[lt] = live ? 1 : 0;
       if (live && (tid & 63) == 0) {
         const SrcDev& S = SS[s];
@@ -1764,13 +1756,15 @@ __global__ __launch_bounds__(kBlock, 2) void k_x20(const KParams* __restrict__ P
   for (;;) {
     const int64_t tile = next_tile(P, P.counters + 0, P.n_tiles_lfa, iter, &s_next);
     if (tile >= P.n_tiles_lfa) break;
-    if (tid == 0) {
-      const int64_t s = find_source(SS, P.n_src, tile, true);
-      const SrcDev& S = SS[s];
-      sh.src = s;
-      sh.k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfa;
-      sh.cnt = (int32_t)min((int64_t)kTileLfa, S.lfa_ke - sh.k0);
-      sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+    if (tid < 64) {
+      const int64_t s = find_source_wave(SS, P.n_src, tile, true);
+      if (tid == 0) {
+        const SrcDev& S = SS[s];
+        sh.src = s;
+        sh.k0 = S.lfa_kb + (tile - S.lfa_t0) * kTileLfa;
+        sh.cnt = (int32_t)min((int64_t)kTileLfa, S.lfa_ke - sh.k0);
+        sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+      }
     }
     __syncthreads();
     const SrcDev& S = SS[sh.src];
@@ -1939,20 +1933,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_full(const KParams* __restrict__ 
   for (;;) {
     const int64_t tile = next_tile(P, P.counters + 1, P.n_tiles_full, iter, &s_next);
     if (tile >= P.n_tiles_full) break;
-    if (tid == 0) {
-      const int64_t s = find_source(SS, P.n_src, tile, false);
-      const SrcDev& S = SS[s];
-      sh.src = s;
-      sh.k0 = S.full_kb + (tile - S.full_t0) * P.tile_full;
-      sh.cnt = (int32_t)min((int64_t)P.tile_full, S.full_ke - sh.k0);
-      const int margin = 2 + (int)ceil(4e-4 * (double)sh.cnt);
-      sh.y0 = sh.k0 - (int64_t)ceil(P.D2_bound / S.dt) - N / 2 + 1 - margin;
-      sh.ny = (int32_t)(sh.k0 + sh.cnt - 1 + N / 2 + margin - sh.y0 + 1);
-      double sn, cs;
-      sincos(2.0 * S.psi, &sn, &cs);
-      sh.c2 = cs;
-      sh.s2 = sn;
-      sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+    if (tid < 64) {
+      const int64_t s = find_source_wave(SS, P.n_src, tile, false);
+      if (tid == 0) {
+        const SrcDev& S = SS[s];
+        sh.src = s;
+        sh.k0 = S.full_kb + (tile - S.full_t0) * P.tile_full;
+        sh.cnt = (int32_t)min((int64_t)P.tile_full, S.full_ke - sh.k0);
+        const int margin = 2 + (int)ceil(4e-4 * (double)sh.cnt);
+        sh.y0 = sh.k0 - (int64_t)ceil(P.D2_bound / S.dt) - N / 2 + 1 - margin;
+        sh.ny = (int32_t)(sh.k0 + sh.cnt - 1 + N / 2 + margin - sh.y0 + 1);
+        double sn, cs;
+        sincos(2.0 * S.psi, &sn, &cs);
+        sh.c2 = cs;
+        sh.s2 = sn;
+        sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : -INFINITY;
+      }
     }
     __syncthreads();
     const SrcDev& S = SS[sh.src];
@@ -2330,15 +2326,17 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(ARM ? 2 
   // the per-arm read: FP32, leading LFA term
   static_assert(!ARM || sizeof(TC) == 4, "the per-arm read is FP32");
   const bool arm_fast = ARM && want_lfa && P.lfa_terms != 2;
-  if (tid == 0) {
-    const int64_t s = find_source(SS, P.n_src, tile, true);
-    const SrcDev& S = SS[s];
-    sh.src = s;
-    sh.k0 = (tile - S.lfa_t0) * kTileLinks;
-    sh.cnt = (int32_t)min((int64_t)kTileLinks, S.n - sh.k0);
-    sh.c2 = S.c2psi;
-    sh.s2 = S.s2psi;
-    sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : 0.0;
+  if (tid < 64) {
+    const int64_t s = find_source_wave(SS, P.n_src, tile, true);
+    if (tid == 0) {
+      const SrcDev& S = SS[s];
+      sh.src = s;
+      sh.k0 = (tile - S.lfa_t0) * kTileLinks;
+      sh.cnt = (int32_t)min((int64_t)kTileLinks, S.n - sh.k0);
+      sh.c2 = S.c2psi;
+      sh.s2 = S.s2psi;
+      sh.kH = P.mode == 2 ? (S.t_hyb - S.t0) / S.dt : 0.0;
+    }
   }
   __syncthreads();
   const SrcDev& S = SS[sh.src];
