@@ -107,7 +107,14 @@ typedef struct {
   int32_t precision;        /* TDI_FP64 or TDI_FP32_BULK */
   double hyb_T_samples;     /* hybrid window length T in samples (paper default 800), > 0 */
   double hyb_sigma_samples; /* sigmoid width sigma in samples (paper default T/40), > 0 */
-  int32_t autotune;         /* 1: time the launch candidates on the first run and keep the best */
+  int32_t autotune;         /* 1: time the launch candidates on the first run and keep the best.
+                               If the environment variable TDI_AUTOTUNE_CACHE names a file, each
+                               decision is appended to it (one JSON object per line, keyed by the
+                               device architecture and compute units, the options that change the
+                               kernels, and the batch's source and sample counts as powers of
+                               two), and a plan whose key is found there takes the stored launch
+                               without timing; unreadable lines are skipped.  TDI_LOG=1 reports
+                               each decision on stderr, TDI_LOG=2 also every candidate's time. */
   int32_t use_graph;        /* 1: capture the run sequence in a hipGraph and replay it.  With
                                autotune = 1 the first run also times replays against plain
                                stream launches over back-to-back runs and keeps the faster
@@ -247,7 +254,8 @@ tdi_status tdi_plan_kernel_times(tdi_plan* plan, float* ms, int32_t cap, int32_t
 tdi_status tdi_plan_set_timing(tdi_plan* plan, int32_t on);
 
 /* Launch parameters chosen for the plan as a JSON object in buf (tile
- * lengths, persistent grid sizes, graph use, compute units, tuned flag). */
+ * lengths, persistent grid sizes, graph use, compute units, tuned flag, and
+ * tune_cache = 1 when the launch came from the autotune cache). */
 tdi_status tdi_plan_describe(const tdi_plan* plan, char* buf, int32_t buflen);
 
 /* Wait for the plan's outstanding work and release everything it owns

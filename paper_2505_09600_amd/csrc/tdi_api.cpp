@@ -13,6 +13,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <vector>
 
@@ -56,6 +57,7 @@ struct tdi_plan {
   double* d_orbtab;              // TABLE: device copy of the sampled positions
   int64_t max_sources, max_total;
   int device, n_cu;
+  char arch[64];                 // device architecture name (autotune cache key)
   size_t max_lds;                // LDS bytes available to one workgroup
   int last_fast, last_tile_lfa;  // LFA kernel choice of the latest run
   int last_tile_full;            // full-response tile of the latest run
@@ -97,6 +99,7 @@ struct tdi_plan {
   // launch choice
   Launch launch;
   bool tuned;
+  bool tune_cached;              // the launch came from the autotune cache file
   bool stream_pick;              // the autotuner found stream launches faster than graph replay
   bool timing;                   // runs record the per-kernel events (tdi_plan_set_timing)
   // graph
@@ -804,10 +807,90 @@ tdi_status run_with(tdi_plan* p, const Launch& ln, int64_t n_sources, const tdi_
   return TDI_OK;
 }
 
+// Diagnostics on stderr, by the TDI_LOG environment variable: 1 reports each
+// autotune decision, 2 also every candidate's time.
+int log_level() {
+  const char* s = getenv("TDI_LOG");
+  return s ? atoi(s) : 0;
+}
+
+// Autotune cache.  With TDI_AUTOTUNE_CACHE naming a file, each decision of the
+// autotuner is appended to it as one JSON object per line, and a later plan
+// whose key matches takes the stored launch without timing.  The key holds the
+// device architecture and compute-unit count, every option that changes the
+// kernels or their windows (including the LDS sizes the batch needs), and the
+// batch shape as powers of two of the source and sample counts.  Lines that do
+// not parse are skipped; the last matching line wins.
+void tune_key(const tdi_plan* p, const Caps& caps, int64_t n_sources, int64_t total, char* key, size_t n) {
+  auto lg2 = [](int64_t v) {
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << b) < v) ++b;
+    return b;
+  };
+  const tdi_config& c = p->cfg;
+  snprintf(key, n,
+           "%s,cu=%d,gen=%d,mode=%d,prec=%d,taps=%d,p=%d,equal=%d,terms=%d,x20_from_x15=%d,channels=%d,"
+           "nested=%d,chunks=%d,graph=%d,orbit=%d,lds=%zu+%zu,sources=2^%d,samples=2^%d",
+           p->arch, p->n_cu, c.tdi_gen, c.mode, c.precision, c.interp_taps, c.stencil_order, c.lfa_equal_arms,
+           c.lfa_terms, c.lfa_x20_from_x15, c.channels, c.nested_delays, c.fast_tile_chunks, c.use_graph,
+           p->orb.kind, caps.lds_lfa, caps.lds_full, lg2(n_sources), lg2(total));
+}
+
+bool tune_cache_get(const tdi_plan* p, const char* path, const char* key, Launch* ln, bool* stream) {
+  FILE* f = fopen(path, "r");
+  if (!f) return false;
+  char head[320];
+  snprintf(head, sizeof(head), "{\"key\": \"%s\", ", key);
+  const size_t hn = strlen(head);
+  char line[512];
+  bool hit = false;
+  while (fgets(line, sizeof(line), f)) {
+    if (strncmp(line, head, hn) != 0) continue;
+    int gl = -1, gf = -1, ch = 0, sp = -1;
+    if (sscanf(line + hn, "\"grid_lfa\": %d, \"grid_full\": %d, \"chunks\": %d, \"stream\": %d}", &gl, &gf,
+               &ch, &sp) != 4)
+      continue;
+    const int gmax = 64 * p->n_cu;
+    if (gl < 0 || gf < 0 || gl > gmax || gf > gmax || (ch != 1 && ch != 2 && ch != 4) || (sp != 0 && sp != 1))
+      continue;
+    *ln = {gl, gf, ch};
+    *stream = sp == 1;
+    hit = true;
+  }
+  fclose(f);
+  return hit;
+}
+
+void tune_cache_put(const char* path, const char* key, const Launch& ln, bool stream) {
+  FILE* f = fopen(path, "a");
+  if (!f) return;
+  fprintf(f, "{\"key\": \"%s\", \"grid_lfa\": %d, \"grid_full\": %d, \"chunks\": %d, \"stream\": %d}\n", key,
+          ln.grid_lfa, ln.grid_full, ln.chunks, stream ? 1 : 0);
+  fclose(f);
+}
+
 void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64_t* offsets,
               const double* hp, const double* hc, void* X, void* Y, void* Z) {
   Caps caps;
   if (!batch_caps(p->cfg, p->ob, n_sources, src, offsets, &caps)) return;
+  const int verbose = log_level();
+  const char* cache = getenv("TDI_AUTOTUNE_CACHE");
+  char key[256];
+  tune_key(p, caps, n_sources, offsets[n_sources], key, sizeof(key));
+  if (cache && *cache) {
+    Launch ln;
+    bool sp = false;
+    if (tune_cache_get(p, cache, key, &ln, &sp)) {
+      p->launch = ln;
+      p->stream_pick = p->cfg.use_graph && sp;
+      p->tuned = true;
+      p->tune_cached = true;
+      if (verbose >= 1)
+        fprintf(stderr, "[tdi] autotune %s: from cache, grid_lfa %d grid_full %d chunks %d stream %d\n", key,
+                ln.grid_lfa, ln.grid_full, ln.chunks, sp ? 1 : 0);
+      return;
+    }
+  }
   const int ol = tdi::occupancy_lfa(p->cfg.interp_taps, p->cfg.precision, caps.fast, caps.nx, caps.lds_lfa);
   const int of = tdi::occupancy_full(p->cfg.interp_taps, p->cfg.precision, caps.hyb, caps.lds_full);
   // grid candidates (persistent at the resident count, half and twice that, or
@@ -848,6 +931,9 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
       hipEventElapsedTime(&ms, a, b);
       if (rep > 0) ms_sum += ms;
     }
+    if (verbose >= 2)
+      fprintf(stderr, "[tdi] autotune candidate grid_lfa %d grid_full %d chunks %d: %.4f ms%s\n", ln.grid_lfa,
+              ln.grid_full, ln.chunks, 0.5f * ms_sum, ok ? "" : " (failed)");
     if (ok && ms_sum < best) {
       best = ms_sum;
       best_l = ln;
@@ -875,10 +961,16 @@ void autotune(tdi_plan* p, int64_t n_sources, const tdi_source* src, const int64
     const float ts = batch_ms(best_l, false);
     (void)hipGetLastError();
     p->stream_pick = ts < 0.97f * tg;
+    if (verbose >= 2)
+      fprintf(stderr, "[tdi] autotune 8 runs: graph %.4f ms, stream %.4f ms\n", tg, ts);
   }
   hipEventDestroy(a);
   hipEventDestroy(b);
   p->tuned = true;
+  if (verbose >= 1)
+    fprintf(stderr, "[tdi] autotune %s: grid_lfa %d grid_full %d chunks %d stream %d\n", key, best_l.grid_lfa,
+            best_l.grid_full, best_l.chunks, p->stream_pick ? 1 : 0);
+  if (cache && *cache && std::isfinite(best)) tune_cache_put(cache, key, best_l, p->stream_pick);
 }
 
 }  // namespace
@@ -911,6 +1003,7 @@ tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbi
   p->max_total = max_total_samples;
   p->device = dev;
   p->n_cu = prop.multiProcessorCount;
+  snprintf(p->arch, sizeof(p->arch), "%s", prop.gcnArchName);
   p->max_lds = prop.sharedMemPerBlock;
   p->last_fast = 0;
   p->last_tile_lfa = tdi::kTileLfa;
@@ -1158,13 +1251,13 @@ tdi_status tdi_plan_describe(const tdi_plan* p, char* buf, int32_t buflen) {
   snprintf(buf, (size_t)buflen,
            "{\"tile_lfa\": %d, \"tile_full\": %d, \"grid_lfa\": %d, \"grid_full\": %d, "
            "\"graph\": %d, \"graph_kernel_events\": %d, \"cu\": %d, \"tuned\": %d, \"lfa_fast\": %d, "
-           "\"x20_from_x15\": %d}",
+           "\"x20_from_x15\": %d, \"tune_cache\": %d}",
            p->last_tile_lfa, p->last_tile_full > 0 ? p->last_tile_full : full_tile(p->cfg), p->launch.grid_lfa,
            p->launch.grid_full,
            (p->cfg.use_graph && !p->stream_pick && !x20_shortcut(p->cfg) && p->launch.grid_lfa > 0 &&
             p->launch.grid_full > 0) ? 1 : 0,
            p->graph_timed ? 1 : 0, p->n_cu,
-           p->tuned ? 1 : 0, p->last_fast, x20_shortcut(p->cfg) ? 1 : 0);
+           p->tuned ? 1 : 0, p->last_fast, x20_shortcut(p->cfg) ? 1 : 0, p->tune_cached ? 1 : 0);
   return TDI_OK;
 }
 
