@@ -174,12 +174,21 @@ tdi_status tdi_check_batch(const tdi_config* cfg, int64_t n_sources,
                            const tdi_source* src, const int64_t* offsets);
 
 /* Create a plan on the current HIP device for batches of at most max_sources
- * sources and max_total_samples samples.  hip_stream is a hipStream_t (NULL =
- * default stream).  Returns TDI_EDEVICE when no gfx950 device is present. */
+ * sources and max_total_samples samples: the device state for the response of
+ * tdi_run (Secs. II-IV): the orbit of Sec. II.A (light times and link
+ * directions of Eqs. (yslr), (delta_s), (delta_r)), the parameter block and,
+ * with use_graph, the captured launch sequence.  hip_stream is a hipStream_t
+ * (NULL = default stream).  Returns TDI_EDEVICE when no gfx950 device is
+ * present. */
 tdi_status tdi_plan_create(tdi_plan** out, const tdi_config* cfg, const tdi_orbit* orb,
                            int64_t max_sources, int64_t max_total_samples, void* hip_stream);
 
-/* Enqueue the response of one batch on the plan's stream (asynchronous).
+/* Enqueue the response of one batch on the plan's stream (asynchronous):
+ * X, Y, Z (or A, E, T) of each source by the plan's mode: the full response
+ * (Sec. II.B, Eqs. (yslr), (X1.5), (X2.0)), the LFA (Sec. III and App. B,
+ * Eqs. (X15_with_strain_derivatives), (X20_with_strain_derivatives),
+ * (X15_nonequal_timedelays), (X20_nonequal_timedelays)) or the hybrid
+ * (Sec. IV, Eqs. (sigmoid), (hybridized_xs)).
  * src, offsets: host arrays (copied before return).  hp, hc: device arrays of
  * offsets[n_sources] doubles (8-byte aligned).  X, Y, Z: device arrays of
  * offsets[n_sources] doubles (TDI_FP64) or floats (TDI_FP32_BULK).
