@@ -321,12 +321,16 @@ bool table_covers(const tdi_plan* p, int64_t n_sources, const tdi_source* src, c
 // thousand samples per source), so small tiles spread them over more workgroups.
 int full_tile(const tdi_config& c) { return c.mode == TDI_MODE_HYBRID ? tdi::kTileFullHybrid : tdi::kTileFull; }
 
-// Full-response tile for a batch: the FULL mode's kTileFull; in the hybrid,
-// whose full regions are short, kTileFullHybrid, or kTileFullSmall when the
-// batch's full samples would not give every compute unit a tile (one source:
-// the region's latency then sets the run time, and small tiles spread it).
+// Full-response tile for a batch: the FULL mode's kTileFull, or kTileFullHybrid
+// when kTileFull would not give every compute unit a tile; in the hybrid, whose
+// full regions are short, kTileFullHybrid, or kTileFullSmall when the batch's
+// full samples would not give every compute unit a tile (one source: the
+// region's latency then sets the run time, and small tiles spread it).
 int full_tile_for(const tdi_config& c, int64_t full_samples, int n_cu) {
-  if (c.mode != TDI_MODE_HYBRID) return tdi::kTileFull;
+  if (c.mode != TDI_MODE_HYBRID) {
+    const int64_t tiles = (full_samples + tdi::kTileFull - 1) / tdi::kTileFull;
+    return tiles < n_cu ? tdi::kTileFullHybrid : tdi::kTileFull;
+  }
   const int64_t tiles = (full_samples + tdi::kTileFullHybrid - 1) / tdi::kTileFullHybrid;
   return tiles < n_cu ? tdi::kTileFullSmall : tdi::kTileFullHybrid;
 }
