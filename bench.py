@@ -633,7 +633,7 @@ def main():
             "valu": valu,
             "algorithmic_fp32": {"flops_per_sample": lfa_flops_per_sample(TAPS), "tflops": alg_tflops,
                                  "vs_nonpacked_peak": alg_tflops / FP32_NONPACKED_TFLOPS,
-                                 "note": "survey's per-sample count of six two-component 32-tap reads; "
+                                 "note": "per-sample count of six two-component 32-tap reads (4N + 4N flops each); "
                                          "the kernel executes fewer flops (one precombined series per "
                                          "link, shared table weights), so this ratio can exceed 1 and "
                                          "is not a hardware rate"},
